@@ -1,0 +1,187 @@
+/*
+ * fdirw.h -- C ABI of the MI355X (gfx950) FDiRW fast-diffusion library.
+ *
+ * The method (arXiv 2408.11376, Sec. 3.1, Eqs. 8-9): over one big time step
+ * the concentration field is advanced by superposition, c(t + dt_big) = P c(t),
+ * where column j of the proportion matrix P is the mass that a unit point
+ * source at cell j spreads to every other cell.  The paper obtains each column
+ * by an explicit finite-difference solution started from that point source
+ * (Sec. 3.1, text after Eq. 9) and applies the matrix-vector product on the GPU
+ * (Sec. 3.2), optionally with P stored in reduced precision and FP32
+ * accumulation (Sec. 3.3).
+ *
+ * This library computes the columns on the fly, per source cell, on a local
+ * window [s - r, s + r]^3 of the fine grid, and scatter-adds c(s) * G_s into
+ * the new field:
+ *   - explicit 7-point scheme, sub-step dt (given, or 0.9 h^2 / (6 Dmax));
+ *   - face coefficient lambda_f = D_f dt / h^2 with D_f the harmonic mean
+ *     2 Da Db / (Da + Db) of the two cells (0 if either is 0);
+ *   - no flux through domain walls, impermeable (D = 0) cells or the window
+ *     walls; cells of the window outside the domain hold 0;
+ *   - superposition accumulated in FP64.
+ *
+ * Conventions for every entry point:
+ *   - Grids are [nz][ny][nx] with x fastest; the linear index of (x, y, z) is
+ *     (z*ny + y)*nx + x (int64).
+ *   - Pointers are DEVICE pointers (memory of the current HIP device) unless
+ *     marked (host).  All buffers belong to the caller; the library never frees
+ *     them.  The library allocates only internal scratch (per device, grown on
+ *     demand, released by fdirw_release()).
+ *   - Work is enqueued on the given hipStream_t (NULL = the default stream).
+ *     Argument checks that need the device (label range, Dmax) read a few
+ *     bytes back, so each call synchronises the stream once at its start;
+ *     passing a stats pointer synchronises again at the end.
+ *   - Every function returns an fdirw_status and never throws or aborts; on a
+ *     non-OK status nothing has been written to the outputs unless stated, and
+ *     fdirw_last_error() returns a message (per calling thread).
+ */
+#ifndef FDIRW_H_
+#define FDIRW_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDIRW_ABI_VERSION 1
+#define FDIRW_MAX_RADIUS 8   /* largest window radius r supported (W = 17) */
+#define FDIRW_MAX_PHASES 256
+
+typedef enum fdirw_status {
+    FDIRW_OK = 0,
+    FDIRW_E_ARG = -1,          /* invalid argument (null, size, label range, aliasing) */
+    FDIRW_E_UNSTABLE = -2,     /* 6 Dmax dt / h^2 > 1: explicit scheme unstable */
+    FDIRW_E_NOMEM = -3,        /* internal scratch could not be allocated */
+    FDIRW_E_DEVICE = -4,       /* a HIP call failed */
+    FDIRW_E_UNSUPPORTED = -5,  /* valid request this build does not implement */
+    FDIRW_E_NONFINITE = -6     /* non-finite input mass */
+} fdirw_status;
+
+/* Precision of the window stencil (Sec. 3.3 for the paper's FP32/FP16 split).
+ *   FP64           state, coefficients and exchange in FP64.
+ *   FP32           state, coefficients and exchange in FP32; kernels are
+ *                  renormalised by their FP64 mass before the superposition
+ *                  (FP32 rounding of 1 - sum(lambda) otherwise biases the mass
+ *                  by ~1e-6 over 200 sub-steps).
+ *   FP16X32/BF16X32  FP32 state and coefficients; neighbours exchange FP16 /
+ *                  BF16 copies (round to nearest even) and every face flux is
+ *                  formed from the two reduced copies, so the two cells of a
+ *                  face see exactly opposite fluxes; kernels are renormalised
+ *                  to unit mass before the superposition.
+ *   FP16_STATE/BF16_STATE  the state itself is rounded to FP16/BF16 after
+ *                  every sub-step (control case); renormalised.
+ *   FP16_BANK/BF16_BANK    the kernel is generated in FP32 and rounded once to
+ *                  FP16/BF16 (the paper's stored-P split); the superposition
+ *                  uses the rounded kernel, scaled by its own mass.
+ * In every mode the superposition c(s) * G_s and the mass sums are FP64. */
+typedef enum fdirw_prec {
+    FDIRW_FP64 = 0,
+    FDIRW_FP32 = 1,
+    FDIRW_FP16X32 = 2,
+    FDIRW_BF16X32 = 3,
+    FDIRW_FP16_STATE = 4,
+    FDIRW_BF16_STATE = 5,
+    FDIRW_FP16_BANK = 6,
+    FDIRW_BF16_BANK = 7
+} fdirw_prec;
+
+typedef enum fdirw_gen {
+    FDIRW_GEN_FD = 0,          /* explicit finite-difference window kernels */
+    FDIRW_GEN_NN = 1           /* learned surrogate (not in this build: E_UNSUPPORTED) */
+} fdirw_gen;
+
+/* One domain (a phase map and the parameters of one big step). */
+typedef struct fdirw_domain {
+    int32_t nx, ny, nz;        /* cells per axis, each >= 1 */
+    double h;                  /* grid spacing > 0 */
+    const uint8_t *label;      /* N phase labels, each < n_phase */
+    const double *d_phase;     /* (host) n_phase diffusivities, finite, >= 0 */
+    int32_t n_phase;           /* 1..FDIRW_MAX_PHASES */
+    int32_t r;                 /* window radius, 0..FDIRW_MAX_RADIUS (W = 2r + 1) */
+    int32_t n_sub;             /* explicit sub-steps per big step, >= 0 (0: identity) */
+    double dt;                 /* sub-step; <= 0 selects 0.9 h^2 / (6 Dmax) */
+} fdirw_domain;
+
+typedef struct fdirw_opts {
+    int32_t prec;              /* fdirw_prec */
+    int32_t gen;               /* fdirw_gen */
+    const void *nn;            /* surrogate handle (unused with GEN_FD) */
+    double audit_tol;          /* surrogate audit tolerance (unused with GEN_FD) */
+    int32_t audit_samples;     /* surrogate audit size (unused with GEN_FD) */
+    int32_t deterministic;     /* must be 0 in this build (FP64 atomics reorder sums) */
+    size_t bank_budget_bytes;  /* fdirw_run: store every kernel once if the bank fits; 0 = never */
+    void *stream;              /* hipStream_t, NULL = default stream */
+    int32_t tune;              /* launch shape: -1 = tuned/default, else a shape id */
+} fdirw_opts;
+
+typedef struct fdirw_stats {
+    double mass_in;            /* compensated FP64 sum of c_in */
+    double mass_out;           /* compensated FP64 sum of c_out */
+    double kmass_min;          /* min / max mass of the kernels generated (before any */
+    double kmass_max;          /*   renormalisation); +inf / -inf if none */
+    double audit_l1;           /* surrogate audit statistic (0 with GEN_FD) */
+    double seconds;            /* wall time of the call, synchronised */
+    int32_t fallback_used;     /* surrogate fell back to FD (0 with GEN_FD) */
+    int32_t tuned_config_id;   /* launch shape used */
+    int64_t n_sources;         /* sources processed (cells with c != 0) */
+    int32_t bank_used;         /* fdirw_run applied a stored kernel bank */
+    int32_t reserved;
+} fdirw_stats;
+
+/* Row (a1): coefficients.  Writes lam[0*N + i], lam[1*N + i], lam[2*N + i] =
+ * the FP64 coefficient of the face from cell i to its +x, +y, +z neighbour
+ * (0 on the last plane of that axis and for faces touching an impermeable
+ * cell), and *dt_out (host, may be NULL) = the sub-step used.  lam: 3N doubles.
+ * Errors: E_ARG (null, sizes, label >= n_phase, negative or non-finite D),
+ * E_UNSTABLE. */
+int fdirw_coefficients(const fdirw_domain *d, void *stream, double *lam, double *dt_out);
+
+/* Rows (a2)-(a4): the window kernels of n_src sources (Sec. 3.1: column s of P
+ * is the response to a unit point source at s).  src: n_src int64 linear
+ * indices, each in [0, N).  G: [n_src][W][W][W] ordered z, y, x relative to
+ * s - r, doubles for FDIRW_FP64 and floats otherwise; cells outside the domain
+ * are 0.  G is the kernel as generated (in the BANK modes: rounded to FP16 /
+ * BF16 and widened), before any renormalisation.  mass (may be NULL): n_src
+ * doubles, the FP64 sum of each kernel.  Every mode except FP64 superposes
+ * G / mass, so fdirw_step with c = e_s yields exactly (1 / mass) * G (FP64
+ * product) placed at s.
+ * Errors: E_ARG (also: a source index out of range), E_UNSTABLE. */
+int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src, int64_t n_src,
+                  void *G, double *mass);
+
+/* Rows (a1)-(a7): one big step of the superposition (Eq. 8, column form):
+ * c_out[i][x] = sum over s of c_in[i][s] * G_s(x) for each domain i.  d, c_in,
+ * c_out and st are (host) arrays of n_dom entries; c_in[i] and c_out[i] point
+ * to N_i doubles and must not overlap (E_ARG).  st may be NULL.  n_dom > 1
+ * runs all domains in one persistent launch. */
+int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
+               const double *const *c_in, double *const *c_out, fdirw_stats *st);
+
+/* Rows (a1)-(a7), (a11): n_steps big steps (the time marching of Eq. 8).
+ * c[i] holds the initial field and receives the final one; scratch[i] is a
+ * second buffer of N_i doubles (its content is overwritten).  If
+ * bank_budget_bytes allows, every kernel is generated once and each step
+ * applies the stored bank (P is fixed for a fixed geometry, Sec. 3.1 and 5).
+ * st (may be NULL) receives the statistics of the last step, with seconds
+ * covering the whole call. */
+int fdirw_run(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o, int32_t n_steps,
+              double *const *c, double *const *scratch, fdirw_stats *st);
+
+/* Row (a6): compensated (Neumaier per thread, two-sum tree) FP64 sum of n
+ * doubles, in a fixed order for a given n.  *sum_out is host memory. */
+int fdirw_field_sum(const double *c, int64_t n, void *stream, double *sum_out);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char *fdirw_last_error(void);
+
+/* Frees the internal scratch of every device. */
+int fdirw_release(void);
+
+int fdirw_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDIRW_H_ */

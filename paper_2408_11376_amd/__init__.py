@@ -1,0 +1,327 @@
+"""MI355X (gfx950) FDiRW fast-diffusion library: thin Python binding.
+
+Every function below marshals arguments into the C ABI of ``libfdirw.so``
+(declared in ``include/fdirw.h``) and does nothing else: all arithmetic of the
+step runs in the library's HIP kernels.  PyTorch supplies device memory and
+the current stream.  There is no CPU fallback: if the library is missing the
+import of a function raises.
+
+Names follow the ABI:
+    fdirw_coefficients, fdirw_kernels, fdirw_step, fdirw_run,
+    fdirw_field_sum, fdirw_last_error, fdirw_release, fdirw_abi_version
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdirw.so")
+
+# precision modes (fdirw_prec)
+FP64, FP32, FP16X32, BF16X32, FP16_STATE, BF16_STATE, FP16_BANK, BF16_BANK = range(8)
+PREC_NAMES = {"fp64": FP64, "fp32": FP32, "fp16x32": FP16X32, "bf16x32": BF16X32,
+              "fp16_state": FP16_STATE, "bf16_state": BF16_STATE,
+              "fp16_bank": FP16_BANK, "bf16_bank": BF16_BANK}
+GEN_FD, GEN_NN = 0, 1
+
+OK, E_ARG, E_UNSTABLE, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_UNSTABLE", -3: "E_NOMEM", -4: "E_DEVICE",
+                -5: "E_UNSUPPORTED", -6: "E_NONFINITE"}
+MAX_RADIUS = 8
+
+
+class FdirwError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class fdirw_domain(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double),
+                ("label", ctypes.c_void_p),
+                ("d_phase", ctypes.POINTER(ctypes.c_double)),
+                ("n_phase", ctypes.c_int32),
+                ("r", ctypes.c_int32),
+                ("n_sub", ctypes.c_int32),
+                ("dt", ctypes.c_double)]
+
+
+class fdirw_opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("gen", ctypes.c_int32),
+                ("nn", ctypes.c_void_p),
+                ("audit_tol", ctypes.c_double),
+                ("audit_samples", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32),
+                ("bank_budget_bytes", ctypes.c_size_t),
+                ("stream", ctypes.c_void_p),
+                ("tune", ctypes.c_int32)]
+
+
+class fdirw_stats(ctypes.Structure):
+    _fields_ = [("mass_in", ctypes.c_double), ("mass_out", ctypes.c_double),
+                ("kmass_min", ctypes.c_double), ("kmass_max", ctypes.c_double),
+                ("audit_l1", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("fallback_used", ctypes.c_int32), ("tuned_config_id", ctypes.c_int32),
+                ("n_sources", ctypes.c_int64),
+                ("bank_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run",
+                 "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfdirw.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: build it with "
+                           f"`python -m paper_2408_11376_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(fdirw_domain)
+    O = ctypes.POINTER(fdirw_opts)
+    S = ctypes.POINTER(fdirw_stats)
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.fdirw_coefficients.argtypes = [D, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.fdirw_kernels.argtypes = [D, O, P, ctypes.c_int64, P, P]
+    lib.fdirw_step.argtypes = [D, ctypes.c_int32, O, PP, PP, S]
+    lib.fdirw_run.argtypes = [D, ctypes.c_int32, O, ctypes.c_int32, PP, PP, S]
+    lib.fdirw_field_sum.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double)]
+    lib.fdirw_last_error.argtypes = []
+    lib.fdirw_last_error.restype = ctypes.c_char_p
+    lib.fdirw_release.argtypes = []
+    lib.fdirw_abi_version.argtypes = []
+    for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run", "fdirw_field_sum",
+              "fdirw_release", "fdirw_abi_version"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        msg = load_library().fdirw_last_error()
+        raise FdirwError(status, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Domain:
+    """A domain for the library: labels on the device, the D table on the host.
+
+    ``label`` is a [nz, ny, nx] uint8 tensor (or numpy array, copied to the
+    current device)."""
+
+    def __init__(self, label, d_phase, r: int, n_sub: int, h: float = 1.0, dt: float = 0.0):
+        torch = _torch()
+        if isinstance(label, np.ndarray):
+            label = torch.from_numpy(np.ascontiguousarray(label, dtype=np.uint8)).cuda()
+        self.label = _dev_tensor(label, torch.uint8, "label")
+        if self.label.dim() != 3:
+            raise ValueError("label must be [nz, ny, nx]")
+        self.d_phase = np.ascontiguousarray(d_phase, dtype=np.float64)
+        self.r, self.n_sub, self.h, self.dt = int(r), int(n_sub), float(h), float(dt)
+
+    @classmethod
+    def from_synth(cls, dom):
+        return cls(dom.label, dom.d_phase, dom.r, dom.n_sub, dom.h, dom.dt)
+
+    @property
+    def shape(self):
+        return tuple(self.label.shape)
+
+    @property
+    def n(self):
+        return int(self.label.numel())
+
+    @property
+    def W(self):
+        return 2 * self.r + 1
+
+    def c_struct(self) -> fdirw_domain:
+        nz, ny, nx = self.shape
+        s = fdirw_domain()
+        s.nx, s.ny, s.nz = nx, ny, nz
+        s.h = self.h
+        s.label = ctypes.c_void_p(self.label.data_ptr())
+        s.d_phase = self.d_phase.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.n_phase = int(self.d_phase.size)
+        s.r, s.n_sub, s.dt = self.r, self.n_sub, self.dt
+        return s
+
+
+def make_opts(prec=FP32, stream=None, bank_budget_bytes: int = 0, tune: int = -1,
+              deterministic: int = 0, gen: int = GEN_FD) -> fdirw_opts:
+    if isinstance(prec, str):
+        prec = PREC_NAMES[prec.lower()]
+    o = fdirw_opts()
+    o.prec = int(prec)
+    o.gen = int(gen)
+    o.nn = None
+    o.audit_tol = 1e-3
+    o.audit_samples = 1024
+    o.deterministic = int(deterministic)
+    o.bank_budget_bytes = int(bank_budget_bytes)
+    o.stream = _stream_ptr(stream)
+    o.tune = int(tune)
+    return o
+
+
+# ----------------------------------------------------------------- ABI calls
+
+def fdirw_abi_version() -> int:
+    return int(load_library().fdirw_abi_version())
+
+
+def fdirw_last_error() -> str:
+    m = load_library().fdirw_last_error()
+    return m.decode() if m else ""
+
+
+def fdirw_release() -> None:
+    _check(load_library().fdirw_release())
+
+
+def fdirw_coefficients(dom: Domain, lam=None, stream=None):
+    """Face coefficients [3, nz, ny, nx] float64 (device) and dt."""
+    torch = _torch()
+    if lam is None:
+        lam = torch.empty((3,) + dom.shape, dtype=torch.float64, device=dom.label.device)
+    _dev_tensor(lam, torch.float64, "lam")
+    if lam.numel() != 3 * dom.n:
+        raise ValueError("lam must hold 3 N doubles")
+    dt = ctypes.c_double(0.0)
+    ds = dom.c_struct()
+    _check(load_library().fdirw_coefficients(ctypes.byref(ds), _stream_ptr(stream),
+                                             ctypes.c_void_p(lam.data_ptr()), ctypes.byref(dt)))
+    return lam, dt.value
+
+
+def fdirw_kernels(dom: Domain, src, prec=FP32, stream=None, G=None, mass=None, tune: int = -1):
+    """Window kernels of the sources in ``src`` (int64 device tensor of linear
+    indices): G [n_src, W, W, W] (float64 for FP64, else float32) and mass."""
+    torch = _torch()
+    o = make_opts(prec, stream, tune=tune)
+    src = _dev_tensor(src, torch.int64, "src")
+    n_src = src.numel()
+    W = dom.W
+    gdt = torch.float64 if o.prec == FP64 else torch.float32
+    if G is None:
+        G = torch.empty((n_src, W, W, W), dtype=gdt, device=src.device)
+    _dev_tensor(G, gdt, "G")
+    if G.numel() != n_src * W ** 3:
+        raise ValueError("G has the wrong size")
+    if mass is None:
+        mass = torch.empty(n_src, dtype=torch.float64, device=src.device)
+    _dev_tensor(mass, torch.float64, "mass")
+    ds = dom.c_struct()
+    _check(load_library().fdirw_kernels(ctypes.byref(ds), ctypes.byref(o),
+                                        ctypes.c_void_p(src.data_ptr()), n_src,
+                                        ctypes.c_void_p(G.data_ptr()), ctypes.c_void_p(mass.data_ptr())))
+    return G, mass
+
+
+def _ptr_array(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = False, tune: int = -1):
+    """One big step for one domain or a list of domains.  Returns c_out (and
+    a list of stats dicts if ``stats``)."""
+    torch = _torch()
+    single = isinstance(doms, Domain)
+    doms = [doms] if single else list(doms)
+    c_in = [c_in] if single else list(c_in)
+    if c_out is None:
+        c_out = [torch.empty_like(c) for c in c_in]
+    elif single:
+        c_out = [c_out]
+    for i, (d, a, b) in enumerate(zip(doms, c_in, c_out)):
+        _dev_tensor(a, torch.float64, f"c_in[{i}]")
+        _dev_tensor(b, torch.float64, f"c_out[{i}]")
+        if a.numel() != d.n or b.numel() != d.n:
+            raise ValueError(f"field {i} does not match its domain")
+    o = make_opts(prec, stream, tune=tune)
+    nd = len(doms)
+    ds = (fdirw_domain * nd)(*[d.c_struct() for d in doms])
+    st = (fdirw_stats * nd)() if stats else None
+    _check(load_library().fdirw_step(ds, nd, ctypes.byref(o), _ptr_array(c_in), _ptr_array(c_out),
+                                     st if st is not None else None))
+    out = c_out[0] if single else c_out
+    if stats:
+        sd = [s.as_dict() for s in st]
+        return out, (sd[0] if single else sd)
+    return out
+
+
+def fdirw_run(doms, c, n_steps: int, scratch=None, prec=FP32, stream=None, stats: bool = False,
+              bank_budget_bytes: int = 0, tune: int = -1):
+    """``n_steps`` big steps in place on ``c`` (one tensor or a list)."""
+    torch = _torch()
+    single = isinstance(doms, Domain)
+    doms = [doms] if single else list(doms)
+    c = [c] if single else list(c)
+    if scratch is None:
+        scratch = [torch.empty_like(x) for x in c]
+    elif single:
+        scratch = [scratch]
+    for i, (d, a, b) in enumerate(zip(doms, c, scratch)):
+        _dev_tensor(a, torch.float64, f"c[{i}]")
+        _dev_tensor(b, torch.float64, f"scratch[{i}]")
+        if a.numel() != d.n or b.numel() != d.n:
+            raise ValueError(f"field {i} does not match its domain")
+    o = make_opts(prec, stream, bank_budget_bytes=bank_budget_bytes, tune=tune)
+    nd = len(doms)
+    ds = (fdirw_domain * nd)(*[d.c_struct() for d in doms])
+    st = (fdirw_stats * nd)() if stats else None
+    _check(load_library().fdirw_run(ds, nd, ctypes.byref(o), int(n_steps), _ptr_array(c),
+                                    _ptr_array(scratch), st if st is not None else None))
+    out = c[0] if single else c
+    if stats:
+        sd = [s.as_dict() for s in st]
+        return out, (sd[0] if single else sd)
+    return out
+
+
+def fdirw_field_sum(c, stream=None) -> float:
+    torch = _torch()
+    _dev_tensor(c, torch.float64, "c")
+    out = ctypes.c_double(0.0)
+    _check(load_library().fdirw_field_sum(ctypes.c_void_p(c.data_ptr()), c.numel(), _stream_ptr(stream),
+                                          ctypes.byref(out)))
+    return out.value

@@ -1,0 +1,57 @@
+// fdirw_host.h -- internal host helpers shared by the ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "../../include/fdirw.h"
+
+namespace fdirw {
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+// Scratch kept per device: coefficients (FP64 / FP32), flag words, reduction
+// partials, per-workgroup kernel masses, a few counters, and the kernel bank.
+struct DevCache {
+    int dev = -1;
+    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass;
+};
+
+struct Geometry {
+    double dt = 0.0;
+    double dmax = 0.0;
+    int64_t n = 0;
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int ensure(Buf &b, size_t bytes);
+DevCache &cache_for_current_device();
+std::mutex &cache_mutex();
+
+int check_domain(const fdirw_domain *d);
+int check_opts(const fdirw_opts *o);
+int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double *lam64, float *lam32, Geometry *g);
+int coef_buffers(const fdirw_domain *d, int prec, hipStream_t st, DevCache &dc, Geometry *g, const void **lam);
+int field_sum_dev(const double *c, int64_t n, hipStream_t st, DevCache &dc, double *out_host);
+void line_shape(const fdirw_domain *d, int tune, int *seg_len, int *n_seg);
+int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out,
+             fdirw_stats *st, DevCache &dc, hipStream_t stream, bool prepared, const void *lam, Geometry *geo);
+int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, double *scratch,
+            fdirw_stats *st, DevCache &dc, hipStream_t stream);
+
+// Bytes per stored kernel value of a precision mode in the bank.
+inline size_t bank_elem_bytes(int prec)
+{
+    if (prec == FDIRW_FP64) return 8;
+    if (prec == FDIRW_FP16_BANK || prec == FDIRW_BF16_BANK) return 2;
+    return 4;
+}
+
+}  // namespace fdirw

@@ -1,0 +1,589 @@
+// fdirw_kernels.hip -- HIP kernels of the FDiRW fast-diffusion step (gfx950).
+//
+//   coef_validate_kernel   label range check + presence mask (for Dmax)
+//   coef_kernel            row (a1): FP64 face coefficients (+ FP32 copy)
+//   window_kernel          rows (a2)-(a4): window kernels of a source list
+//   line_kernel            rows (a2)-(a5), (a7): fused generate + superpose
+//   fill / field-sum       row (a6) and output clearing
+//
+// The superposition (Eq. 8 of arXiv 2408.11376 in its column form) is
+// organised so that a workgroup walks a line of sources along z: the window of
+// source z+1 is the window of source z shifted by one plane, so each thread
+// shifts its register column of coefficients by one cell, loads one new cell,
+// and accumulates c(s) * G_s into an FP64 ring of W planes in LDS.  The plane
+// that no later source of the line can reach is flushed with one FP64 atomic
+// per window column, i.e. W^2 atomics per source instead of W^3.
+#include "fdirw_device.h"
+#include "fdirw_launch.h"
+
+namespace fdirw {
+
+// ----------------------------------------------------------------- (a1)
+
+__global__ void coef_validate_kernel(const uint8_t *__restrict__ label, int64_t n, int n_phase,
+                                     unsigned *__restrict__ out /* [8] presence bits, [8] bad flag */)
+{
+    __shared__ unsigned present[8];
+    __shared__ unsigned bad;
+    if (threadIdx.x < 8) present[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) bad = 0u;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned l = label[i];
+        if ((int)l >= n_phase) atomicOr(&bad, 1u);
+        atomicOr(&present[l >> 5], 1u << (l & 31));
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && present[threadIdx.x]) atomicOr(&out[threadIdx.x], present[threadIdx.x]);
+    if (threadIdx.x == 0 && bad) atomicOr(&out[8], 1u);
+}
+
+// Face coefficient, evaluated in exactly this order with no contraction:
+// num = (2 Da) Db, den = Da + Db, Df = num / den, lam = (Df dt) / (h h).
+__device__ __forceinline__ double face_lambda(double da, double db, double dt, double h)
+{
+#pragma clang fp contract(off)
+    if (!(da > 0.0 && db > 0.0)) return 0.0;
+    const double num = (2.0 * da) * db;
+    const double den = da + db;
+    const double df = num / den;
+    return (df * dt) / (h * h);
+}
+
+__global__ void coef_kernel(const uint8_t *__restrict__ label, int nx, int ny, int nz,
+                            CoefTable tab, double dt, double h,
+                            double *__restrict__ lam64, float *__restrict__ lam32)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        const int y = (int)((i / nx) % ny);
+        const int z = (int)(i / ((int64_t)nx * ny));
+        const double d0 = tab.d[label[i]];
+        const double vx = (x + 1 < nx) ? face_lambda(d0, tab.d[label[i + 1]], dt, h) : 0.0;
+        const double vy = (y + 1 < ny) ? face_lambda(d0, tab.d[label[i + nx]], dt, h) : 0.0;
+        const double vz = (z + 1 < nz) ? face_lambda(d0, tab.d[label[i + (int64_t)nx * ny]], dt, h) : 0.0;
+        if (lam64) { lam64[i] = vx; lam64[n + i] = vy; lam64[2 * n + i] = vz; }
+        if (lam32) { lam32[i] = (float)vx; lam32[n + i] = (float)vy; lam32[2 * n + i] = (float)vz; }
+    }
+}
+
+// ----------------------------------------------------------------- helpers
+
+__global__ void fill_kernel(double *__restrict__ p, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u32_kernel(unsigned *__restrict__ p, int64_t n, unsigned v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Two-sum of (s, c) pairs: exact sum of the leading parts plus the carries.
+__device__ __forceinline__ void two_sum_add(double &s, double &c, double s2, double c2)
+{
+#pragma clang fp contract(off)
+    const double t = s + s2;
+    const double bp = t - s;
+    const double err = (s - (t - bp)) + (s2 - bp);
+    s = t;
+    c = c + c2 + err;
+}
+
+// Row (a6), level 1: each thread a Neumaier sum over a fixed strided subset,
+// then a fixed-shape tree inside the block; out: (sum, carry) per block.
+__global__ void field_sum_partial_kernel(const double *__restrict__ v, int64_t n, double *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    __shared__ double ss[256], cc[256];
+    double s = 0.0, c = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = v[i];
+        const double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else                    c += (x - t) + s;
+        s = t;
+    }
+    ss[threadIdx.x] = s;
+    cc[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double a = ss[threadIdx.x], b = cc[threadIdx.x];
+            two_sum_add(a, b, ss[threadIdx.x + w], cc[threadIdx.x + w]);
+            ss[threadIdx.x] = a;
+            cc[threadIdx.x] = b;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[2 * blockIdx.x] = ss[0]; out[2 * blockIdx.x + 1] = cc[0]; }
+}
+
+// Level 2: one thread combines the block partials in block order.
+__global__ void field_sum_final_kernel(const double *__restrict__ part, int nblk, double *__restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (int b = 0; b < nblk; ++b) two_sum_add(s, c, part[2 * b], part[2 * b + 1]);
+    out[0] = s + c;
+}
+
+// Min / max of per-block kernel masses.
+__global__ void minmax_kernel(const double *__restrict__ v, int64_t n, double *__restrict__ out)
+{
+    __shared__ double mn[256], mx[256];
+    double a = INFINITY, b = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        a = fmin(a, v[2 * i]);
+        b = fmax(b, v[2 * i + 1]);
+    }
+    mn[threadIdx.x] = a;
+    mx[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + w]);
+            mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = mn[0]; out[1] = mx[0]; }
+}
+
+__global__ void src_check_kernel(const int64_t *__restrict__ src, int64_t n_src, int64_t n,
+                                 unsigned *__restrict__ bad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_src;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (src[i] < 0 || src[i] >= n) atomicOr(bad, 1u);
+}
+
+// ----------------------------------------------------------------- window math
+
+// After the sub-steps: kernel mass (FP64 sum of the state, or of the rounded
+// kernel in BANK modes), and the factor that turns G into its contribution.
+template <int M, int R>
+__device__ __forceinline__ double finish_kernel(typename Traits<M>::S (&G)[Win<R>::W], double *red, bool act)
+{
+    using T = Traits<M>;
+    constexpr int W = Win<R>::W;
+    if constexpr (T::bank) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) G[j] = round_to<typename T::B>(G[j]);
+    }
+    double s = 0.0;
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) s += (double)G[j];
+    }
+    return block_sum<Win<R>::NWAVE>(s, red);
+}
+
+// ----------------------------------------------------------------- (a2)-(a4)
+
+template <int M, int R>
+__global__ void __launch_bounds__(Win<R>::NT)
+window_kernel(WindowArgs a)
+{
+    using T = Traits<M>;
+    using S = typename T::S;
+    using E = typename T::E;
+    constexpr int W = Win<R>::W, W2 = Win<R>::W2, W3 = Win<R>::W3, XLEN = Win<R>::XLEN;
+    __shared__ E xb[2 * XLEN];
+    __shared__ double red[Win<R>::NWAVE];
+
+    const int t = threadIdx.x;
+    const bool act = t < W2;
+    const int cx = act ? t % W : 0, cy = act ? t / W : 0;
+    for (int i = t; i < 2 * XLEN; i += blockDim.x) xb[i] = (E)0.0f;
+    __syncthreads();
+
+    const S *lx = (const S *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
+    for (int64_t q = blockIdx.x; q < a.n_src; q += gridDim.x) {
+        const int64_t s = a.src ? a.src[q] : q;
+        const int sx = (int)(s % a.nx), sy = (int)((s / a.nx) % a.ny), sz = (int)(s / ((int64_t)a.nx * a.ny));
+        const int X = sx - R + cx, Y = sy - R + cy;
+        const bool inxy = act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
+        Column<S, W> c;
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            load_cell<S, W>(lx, ly, a.nx, a.ny, a.nz, X, Y, sz - R + j, cx, cy, inxy, c.xm[j], c.xp[j], c.ym[j], c.yp[j]);
+        c.zf[0] = S(0);
+        c.zf[W] = S(0);
+#pragma unroll
+        for (int j = 1; j < W; ++j) c.zf[j] = load_zface<S>(lz, a.nx, a.ny, a.nz, X, Y, sz - R + j, inxy);
+        compute_diag<T::x32, S, W>(c);
+
+        S G[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) G[j] = (j == R && cx == R && cy == R && act) ? S(1) : S(0);
+        run_substeps<M, R>(G, c, xb, xb + XLEN, t, act, a.n_sub);
+        const double m = finish_kernel<M, R>(G, red, act);
+        if (t == 0 && a.mass) a.mass[q] = m;
+        if (act) {
+            const bool norm = T::renorm && !T::bank && a.normalize;
+            const double inv = norm ? 1.0 / m : 1.0;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const int64_t o = q * (int64_t)W3 + (int64_t)j * W2 + t;
+                if constexpr (M == M_FP64) {
+                    ((double *)a.G)[o] = G[j];
+                } else if constexpr (T::bank) {
+                    if (a.out_lp) ((typename T::B *)a.G)[o] = (typename T::B)G[j];
+                    else ((float *)a.G)[o] = G[j];
+                } else {
+                    ((float *)a.G)[o] = norm ? (float)((double)G[j] * inv) : G[j];
+                }
+            }
+        }
+        __syncthreads();      // xb reuse by the next source of this block
+    }
+}
+
+// ----------------------------------------------------------------- (a5) fused
+
+template <int M, int R>
+__global__ void __launch_bounds__(Win<R>::NT)
+line_kernel(LineArgs a)
+{
+    using T = Traits<M>;
+    using S = typename T::S;
+    using E = typename T::E;
+    constexpr int W = Win<R>::W, W2 = Win<R>::W2, XLEN = Win<R>::XLEN;
+    __shared__ E xb[2 * XLEN];
+    __shared__ double ring[W * W2];
+    __shared__ double red[Win<R>::NWAVE];
+
+    const int t = threadIdx.x;
+    const bool act = t < W2;
+    const int cx = act ? t % W : 0, cy = act ? t / W : 0;
+    for (int i = t; i < 2 * XLEN; i += blockDim.x) xb[i] = (E)0.0f;
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) ring[j * W2 + t] = 0.0;
+    }
+    __syncthreads();
+
+    const int b = blockIdx.x;
+    const int line = b / a.n_seg, seg = b - line * a.n_seg;
+    const int sy = line / a.nx, sx = line - sy * a.nx;
+    const int z0 = seg * a.seg_len;
+    const int z1 = min(a.nz, z0 + a.seg_len);
+    if (z0 >= z1) return;                                   // uniform per block
+    const int X = sx - R + cx, Y = sy - R + cy;
+    const bool inxy = act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
+    const S *lx = (const S *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
+
+    Column<S, W> c;
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+        load_cell<S, W>(lx, ly, a.nx, a.ny, a.nz, X, Y, z0 - R + j, cx, cy, inxy, c.xm[j], c.xp[j], c.ym[j], c.yp[j]);
+    c.zf[0] = S(0);
+    c.zf[W] = S(0);
+#pragma unroll
+    for (int j = 1; j < W; ++j) c.zf[j] = load_zface<S>(lz, a.nx, a.ny, a.nz, X, Y, z0 - R + j, inxy);
+
+    double kmin = INFINITY, kmax = -INFINITY;
+    int used = 0;
+    for (int sz = z0; sz < z1; ++sz) {
+        if (sz > z0) {
+            // slide the window one plane up: shift the column, load the new top cell
+#pragma unroll
+            for (int j = 0; j < W - 1; ++j) {
+                c.xm[j] = c.xm[j + 1]; c.xp[j] = c.xp[j + 1];
+                c.ym[j] = c.ym[j + 1]; c.yp[j] = c.yp[j + 1];
+            }
+#pragma unroll
+            for (int j = 1; j < W - 1; ++j) c.zf[j] = c.zf[j + 1];
+            load_cell<S, W>(lx, ly, a.nx, a.ny, a.nz, X, Y, sz + R, cx, cy, inxy,
+                            c.xm[W - 1], c.xp[W - 1], c.ym[W - 1], c.yp[W - 1]);
+            if (W > 1) c.zf[W - 1] = load_zface<S>(lz, a.nx, a.ny, a.nz, X, Y, sz + R, inxy);
+        }
+        const double cs = a.c_in[((int64_t)sz * a.ny + sy) * a.nx + sx];
+        if (cs != 0.0) {                                    // uniform per block
+            ++used;
+            compute_diag<T::x32, S, W>(c);
+            S G[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) G[j] = (j == R && cx == R && cy == R && act) ? S(1) : S(0);
+            run_substeps<M, R>(G, c, xb, xb + XLEN, t, act, a.n_sub);
+            const double m = finish_kernel<M, R>(G, red, act);
+            kmin = fmin(kmin, m);
+            kmax = fmax(kmax, m);
+            const double scale = T::renorm ? cs / m : cs;
+            if (act) {
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    const int slot = (sz - R + j + W) % W;
+                    double &acc = ring[slot * W2 + t];
+                    acc = __builtin_fma(scale, (double)G[j], acc);
+                }
+            }
+        }
+        // plane sz - R is complete for this line segment
+        if (act) {
+            const int Z = sz - R;
+            const int slot = (Z + W) % W;
+            const double v = ring[slot * W2 + t];
+            if (v != 0.0 && inxy && Z >= 0) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+            ring[slot * W2 + t] = 0.0;
+        }
+    }
+    if (act) {
+        for (int Z = z1 - R; Z < z1 + R; ++Z) {
+            if (Z < 0) continue;
+            const int slot = (Z + W) % W;
+            const double v = ring[slot * W2 + t];
+            if (v != 0.0 && inxy && Z < a.nz) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+        }
+    }
+    if (t == 0) {
+        if (a.wg_kmass) { a.wg_kmass[2 * b] = kmin; a.wg_kmass[2 * b + 1] = kmax; }
+        if (a.n_used && used) atomicAdd(a.n_used, (unsigned long long)used);
+    }
+}
+
+// ----------------------------------------------------------------- (a11) bank
+
+// Same line walk as line_kernel; the kernel of every source is read from the
+// stored bank (coalesced: one plane of W^2 values per wave row) and the FP64
+// ring of W planes lives in registers, shifted by one plane per source.
+template <typename B, int R, bool RENORM>
+__global__ void __launch_bounds__(Win<R>::NT)
+bank_apply_kernel(BankArgs a)
+{
+    constexpr int W = Win<R>::W, W2 = Win<R>::W2, W3 = Win<R>::W3;
+    const int t = threadIdx.x;
+    const bool act = t < W2;
+    const int cx = act ? t % W : 0, cy = act ? t / W : 0;
+    const int b = blockIdx.x;
+    const int line = b / a.n_seg, seg = b - line * a.n_seg;
+    const int sy = line / a.nx, sx = line - sy * a.nx;
+    const int z0 = seg * a.seg_len;
+    const int z1 = min(a.nz, z0 + a.seg_len);
+    if (z0 >= z1 || !act) return;
+    const int X = sx - R + cx, Y = sy - R + cy;
+    const bool inxy = X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
+    const B *bank = (const B *)a.bank;
+    double acc[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) acc[j] = 0.0;
+    for (int sz = z0; sz < z1; ++sz) {
+        const int64_t s = ((int64_t)sz * a.ny + sy) * a.nx + sx;
+        const double cs = a.c_in[s];
+        if (cs != 0.0) {
+            const double scale = RENORM ? cs / a.mass[s] : cs;
+            const B *g = bank + s * (int64_t)W3 + t;
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc[j] = __builtin_fma(scale, (double)g[j * W2], acc[j]);
+        }
+        const int Z = sz - R;
+        if (acc[0] != 0.0 && inxy && Z >= 0) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], acc[0]);
+#pragma unroll
+        for (int j = 0; j < W - 1; ++j) acc[j] = acc[j + 1];
+        acc[W - 1] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < W - 1; ++j) {
+        const int Z = z1 - R + j;
+        if (acc[j] != 0.0 && inxy && Z >= 0 && Z < a.nz)
+            unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], acc[j]);
+    }
+}
+
+template <typename B, int R, bool RENORM>
+static hipError_t launch_bank_brn(const BankArgs &a, hipStream_t st)
+{
+    const int64_t nblk = (int64_t)a.nx * a.ny * a.n_seg;
+    hipLaunchKernelGGL((bank_apply_kernel<B, R, RENORM>), dim3((unsigned)nblk), dim3(Win<R>::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename B, bool RENORM>
+static hipError_t launch_bank_b(int r, const BankArgs &a, hipStream_t st)
+{
+    switch (r) {
+    case 0: return launch_bank_brn<B, 0, RENORM>(a, st);
+    case 1: return launch_bank_brn<B, 1, RENORM>(a, st);
+    case 2: return launch_bank_brn<B, 2, RENORM>(a, st);
+    case 3: return launch_bank_brn<B, 3, RENORM>(a, st);
+    case 4: return launch_bank_brn<B, 4, RENORM>(a, st);
+    case 5: return launch_bank_brn<B, 5, RENORM>(a, st);
+    case 6: return launch_bank_brn<B, 6, RENORM>(a, st);
+    case 7: return launch_bank_brn<B, 7, RENORM>(a, st);
+    case 8: return launch_bank_brn<B, 8, RENORM>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bank_apply(int prec, int r, const BankArgs &a, hipStream_t st)
+{
+    switch (prec) {
+    case M_FP64: return launch_bank_b<double, false>(r, a, st);
+    case M_FP32: case M_F16X32: case M_BF16X32: case M_F16ST: case M_BF16ST:
+        return launch_bank_b<float, true>(r, a, st);
+    case M_F16BANK: return launch_bank_b<_Float16, true>(r, a, st);
+    case M_BF16BANK: return launch_bank_b<__bf16, true>(r, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ----------------------------------------------------------------- dispatch
+
+template <int M, int R>
+static hipError_t launch_line_mr(const LineArgs &a, hipStream_t st)
+{
+    const int64_t nblk = (int64_t)a.nx * a.ny * a.n_seg;
+    hipLaunchKernelGGL((line_kernel<M, R>), dim3((unsigned)nblk), dim3(Win<R>::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int M, int R>
+static hipError_t launch_window_mr(const WindowArgs &a, hipStream_t st)
+{
+    const int64_t nblk = a.n_src < 65536 * 16 ? a.n_src : 65536 * 16;
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL((window_kernel<M, R>), dim3((unsigned)nblk), dim3(Win<R>::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_line_m(int r, const LineArgs &a, hipStream_t st)
+{
+    switch (r) {
+    case 0: return launch_line_mr<M, 0>(a, st);
+    case 1: return launch_line_mr<M, 1>(a, st);
+    case 2: return launch_line_mr<M, 2>(a, st);
+    case 3: return launch_line_mr<M, 3>(a, st);
+    case 4: return launch_line_mr<M, 4>(a, st);
+    case 5: return launch_line_mr<M, 5>(a, st);
+    case 6: return launch_line_mr<M, 6>(a, st);
+    case 7: return launch_line_mr<M, 7>(a, st);
+    case 8: return launch_line_mr<M, 8>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int M>
+static hipError_t launch_window_m(int r, const WindowArgs &a, hipStream_t st)
+{
+    switch (r) {
+    case 0: return launch_window_mr<M, 0>(a, st);
+    case 1: return launch_window_mr<M, 1>(a, st);
+    case 2: return launch_window_mr<M, 2>(a, st);
+    case 3: return launch_window_mr<M, 3>(a, st);
+    case 4: return launch_window_mr<M, 4>(a, st);
+    case 5: return launch_window_mr<M, 5>(a, st);
+    case 6: return launch_window_mr<M, 6>(a, st);
+    case 7: return launch_window_mr<M, 7>(a, st);
+    case 8: return launch_window_mr<M, 8>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_line(int mode, int r, const LineArgs &a, hipStream_t st)
+{
+    switch (mode) {
+    case M_FP64: return launch_line_m<M_FP64>(r, a, st);
+    case M_FP32: return launch_line_m<M_FP32>(r, a, st);
+    case M_F16X32: return launch_line_m<M_F16X32>(r, a, st);
+    case M_BF16X32: return launch_line_m<M_BF16X32>(r, a, st);
+    case M_F16ST: return launch_line_m<M_F16ST>(r, a, st);
+    case M_BF16ST: return launch_line_m<M_BF16ST>(r, a, st);
+    case M_F16BANK: return launch_line_m<M_F16BANK>(r, a, st);
+    case M_BF16BANK: return launch_line_m<M_BF16BANK>(r, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_window(int mode, int r, const WindowArgs &a, hipStream_t st)
+{
+    switch (mode) {
+    case M_FP64: return launch_window_m<M_FP64>(r, a, st);
+    case M_FP32: return launch_window_m<M_FP32>(r, a, st);
+    case M_F16X32: return launch_window_m<M_F16X32>(r, a, st);
+    case M_BF16X32: return launch_window_m<M_BF16X32>(r, a, st);
+    case M_F16ST: return launch_window_m<M_F16ST>(r, a, st);
+    case M_BF16ST: return launch_window_m<M_BF16ST>(r, a, st);
+    case M_F16BANK: return launch_window_m<M_F16BANK>(r, a, st);
+    case M_BF16BANK: return launch_window_m<M_BF16BANK>(r, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static inline unsigned grid_for(int64_t n, int block)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+hipError_t launch_validate(const uint8_t *label, int64_t n, int n_phase, unsigned *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, out, (int64_t)9, 0u);
+    hipLaunchKernelGGL(coef_validate_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, label, n, n_phase, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_coef(const uint8_t *label, int nx, int ny, int nz, const CoefTable &tab,
+                       double dt, double h, double *lam64, float *lam32, hipStream_t st)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL(coef_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, label, nx, ny, nz, tab, dt, h, lam64, lam32);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+int field_sum_blocks(int64_t n)
+{
+    int64_t g = (n + 256 * 8 - 1) / (256 * 8);
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    return (int)g;
+}
+
+hipError_t launch_field_sum(const double *v, int64_t n, double *part, double *out, hipStream_t st)
+{
+    const int nblk = field_sum_blocks(n);
+    hipLaunchKernelGGL(field_sum_partial_kernel, dim3(nblk), dim3(256), 0, st, v, n, part);
+    hipLaunchKernelGGL(field_sum_final_kernel, dim3(1), dim3(64), 0, st, part, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax(const double *v, int64_t n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(256), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_src_check(const int64_t *src, int64_t n_src, int64_t n, unsigned *bad, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, bad, (int64_t)1, 0u);
+    if (n_src > 0)
+        hipLaunchKernelGGL(src_check_kernel, dim3(grid_for(n_src, 256)), dim3(256), 0, st, src, n_src, n, bad);
+    return hipGetLastError();
+}
+
+}  // namespace fdirw

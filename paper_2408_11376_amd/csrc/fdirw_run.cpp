@@ -1,0 +1,126 @@
+// fdirw_run.cpp -- time marching of the superposition (Eq. 8 of arXiv
+// 2408.11376 applied once per big step) with an optional kernel bank.
+//
+// The paper computes the proportions P once for a fixed geometry and reuses
+// them every step (Sec. 3.1, "preconditioned"; Sec. 5 on the fixed domain).
+// When the caller's budget allows, fdirw_run does the same: one pass of the
+// window kernel stores every G_s (with its mass), and each big step streams the
+// bank from HBM through the same line walk as the fused step.  Otherwise every
+// step regenerates the kernels (fused path).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fdirw_host.h"
+#include "fdirw_launch.h"
+
+namespace fdirw {
+
+int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, double *scratch,
+            fdirw_stats *st, DevCache &dc, hipStream_t stream)
+{
+    int rc;
+    Geometry geo;
+    const void *lam = nullptr;
+    if ((rc = coef_buffers(d, o->prec, stream, dc, &geo, &lam))) return rc;
+    const int64_t n = geo.n;
+    const int W = 2 * d->r + 1;
+    const int64_t W3 = (int64_t)W * W * W;
+    const size_t esz = bank_elem_bytes(o->prec);
+    const double bank_bytes = (double)n * W3 * esz + (double)n * 8.0;
+    bool use_bank = n_steps >= 1 && o->bank_budget_bytes > 0 && bank_bytes <= (double)o->bank_budget_bytes;
+    if (use_bank) {
+        // a bank that does not fit in device memory silently falls back to the
+        // fused path (identical results up to FP64 summation order)
+        if (ensure(dc.bank, (size_t)(n * W3 * (int64_t)esz)) != FDIRW_OK ||
+            ensure(dc.bank_mass, (size_t)n * sizeof(double)) != FDIRW_OK)
+            use_bank = false;
+    }
+    double kmin = INFINITY, kmax = -INFINITY;
+    if (use_bank) {
+        WindowArgs a;
+        a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.n = n;
+        a.n_sub = d->n_sub;
+        a.lx = lam;
+        a.src = nullptr; a.n_src = n;
+        a.G = dc.bank.p; a.mass = (double *)dc.bank_mass.p;
+        a.normalize = 0;
+        a.out_lp = 1;
+        hipError_t e = launch_window(o->prec, d->r, a, stream);
+        if (e != hipSuccess) return hip_fail(e, "bank generation launch");
+        if (st) {
+            if ((rc = ensure(dc.small, 64))) return rc;
+            double *mm = (double *)dc.small.p + 4;
+            // bank_mass holds one value per source; minmax reads pairs, so
+            // reduce it as n/2 pairs plus a possible tail
+            double h_mm[2] = {INFINITY, -INFINITY};
+            if (n >= 2) {
+                e = launch_minmax((const double *)dc.bank_mass.p, n / 2, mm, stream);
+                if (e == hipSuccess) e = hipMemcpyAsync(h_mm, mm, sizeof h_mm, hipMemcpyDeviceToHost, stream);
+            }
+            double tail = 0.0;
+            if (e == hipSuccess && (n & 1))
+                e = hipMemcpyAsync(&tail, (const double *)dc.bank_mass.p + (n - 1), sizeof tail, hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "bank statistics");
+            kmin = std::fmin(h_mm[0], h_mm[1]);
+            kmax = std::fmax(h_mm[0], h_mm[1]);
+            if (n & 1) { kmin = std::fmin(kmin, tail); kmax = std::fmax(kmax, tail); }
+        }
+    }
+    double *cur = c, *nxt = scratch;
+    for (int step = 0; step < n_steps; ++step) {
+        const bool last = step == n_steps - 1;
+        fdirw_stats *sst = (st && last) ? st : nullptr;
+        if (use_bank) {
+            if (sst) {
+                if ((rc = field_sum_dev(cur, n, stream, dc, &sst->mass_in))) return rc;
+                if (!std::isfinite(sst->mass_in)) return fail(FDIRW_E_NONFINITE, "input mass is not finite");
+            }
+            int seg_len, n_seg;
+            line_shape(d, o->tune, &seg_len, &n_seg);
+            hipError_t e = launch_fill(nxt, n, 0.0, stream);
+            BankArgs b;
+            b.nx = d->nx; b.ny = d->ny; b.nz = d->nz;
+            b.seg_len = seg_len; b.n_seg = n_seg;
+            b.bank = dc.bank.p;
+            b.mass = (const double *)dc.bank_mass.p;
+            b.c_in = cur; b.c_out = nxt;
+            if (e == hipSuccess) e = launch_bank_apply(o->prec, d->r, b, stream);
+            if (e != hipSuccess) return hip_fail(e, "bank apply launch");
+            if (sst) {
+                if ((rc = field_sum_dev(nxt, n, stream, dc, &sst->mass_out))) return rc;
+                sst->kmass_min = kmin;
+                sst->kmass_max = kmax;
+                sst->n_sources = -1;
+                sst->audit_l1 = 0.0;
+                sst->fallback_used = 0;
+                sst->bank_used = 1;
+                sst->tuned_config_id = n_seg;
+            }
+        } else {
+            if ((rc = step_one(d, o, cur, nxt, sst, dc, stream, true, lam, &geo))) return rc;
+        }
+        double *t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != c) {
+        hipError_t e = hipMemcpyAsync(c, cur, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "result copy");
+    }
+    if (st) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "run");
+        if (n_steps == 0) {
+            double m = 0.0;
+            if ((rc = field_sum_dev(c, n, stream, dc, &m))) return rc;
+            st->mass_in = st->mass_out = m;
+            st->kmass_min = INFINITY;
+            st->kmass_max = -INFINITY;
+            st->n_sources = 0;
+            st->bank_used = 0;
+        }
+    }
+    return FDIRW_OK;
+}
+
+}  // namespace fdirw
