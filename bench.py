@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused FDiRW big step on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): a 192^3 porous
+grid from a thresholded Gaussian random field (correlation length 6 voxels,
+solid fraction 0.35), D_pore = 1, D_solid = 1e-6, window radius r = 8
+(17^3 window), 200 explicit sub-steps per big step, c0 ~ U[0, 1]; every one of
+the 7,077,888 cells is a source.  Synthetic and seeded (the paper's
+phase-field particle geometry is not available).
+
+A "step" is one fdirw_step call: coefficients, kernel generation for every
+source, FP64 scatter-add superposition and the FP64 mass balance.  Steps are
+chained (output -> next input).  ``value`` = 192^3 cells / seconds per step in
+the headline precision (FP32 state with FP16 neighbour copies, the mixed
+precision configuration); the plain FP32 and the BF16-copy steps are timed the
+same way and reported under ``modes`` with their speedup over FP32 and their
+relative L1 difference from the FP32 field.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp16x32]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X published peaks
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# Algorithmic work of one cell-sub-step of the 7-point update: 7 products and
+# 6 additions (13 flop); exchange: one write and four in-plane reads of the
+# neighbour copy (the two z neighbours stay in registers).
+FLOP_PER_CELL_SUBSTEP = 13
+LDS_ACCESSES_PER_CELL_SUBSTEP = 5
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def window_cells(shape, r):
+    """Sum over sources of the number of in-domain cells of its window
+    (separable: product over axes of sum over positions of clipped lengths)."""
+    total = 1
+    for n in shape:
+        s = sum(min(n - 1, p + r) - max(0, p - r) + 1 for p in range(n))
+        total *= s
+    return total
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2408_11376_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"source_sha:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def cpu_baseline(dom, block: int):
+    """The CPU oracle on a bounded sample: c0 kept only on a block^3 cube of
+    sources (the oracle skips zero sources), so the sample is block^3 kernels
+    of the same workload.  cells/s = sources per second (a full step is one
+    source per cell)."""
+    import oracle
+    p = oracle.Problem.from_domain(dom)
+    import synth
+    m = synth.sub_block_sources(dom.shape, block)
+    c0 = np.where(m, dom.c0, 0.0)
+    t = time.perf_counter()
+    _, used, _ = p.step(c0)
+    dt = time.perf_counter() - t
+    return {"value": used / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{block}^3 = {used} sources of the 192^3 step (c0 zeroed elsewhere), {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp16x32", help="headline precision mode")
+    ap.add_argument("--modes", default="fp32,fp16x32,bf16x32", help="modes timed for the comparison")
+    ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
+    ap.add_argument("--cpu-block", type=int, default=16, help="edge of the oracle's source sample (0: skip)")
+    ap.add_argument("--tune", type=int, default=-1)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the FDiRW step here is a single-GPU build "
+              "(multi-GPU sharding is a design note, not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2408_11376_amd as fd
+
+    torch.cuda.set_device(0)
+    log(f"generating the {args.n}^3 workload")
+    d = synth.config2(n=args.n)
+    dom = fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
+    N = d.n
+    c0 = torch.from_numpy(d.c0).cuda()
+    bufs = [torch.empty_like(c0), torch.empty_like(c0)]
+    stream = torch.cuda.current_stream()
+
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    if args.prec not in modes:
+        modes.append(args.prec)
+    results = {}
+    fields = {}
+    for mode in modes:
+        log(f"{mode}: {args.warmup} warm-up + {args.steps} timed steps")
+        cur = c0
+        for _ in range(args.warmup):
+            fd.fdirw_step(dom, cur, bufs[0], prec=mode, tune=args.tune)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        kern = []
+        cur = c0
+        t_host = time.perf_counter()
+        ev0.record(stream)
+        for k in range(args.steps):
+            out = bufs[k % 2]
+            _, st = fd.fdirw_step(dom, cur, out, prec=mode, stats=True, tune=args.tune)
+            kern.append(st["kernel_seconds"])
+            cur = out
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t_host = time.perf_counter() - t_host
+        ms = ev0.elapsed_time(ev1) / args.steps
+        # one more (untimed) step from c0 for the accuracy comparison
+        first_out, first_st = fd.fdirw_step(dom, c0, torch.empty_like(c0), prec=mode, stats=True,
+                                            tune=args.tune)
+        fields[mode] = first_out
+        results[mode] = {
+            "cells_per_s": N / (ms * 1e-3),
+            "ms_per_step": ms,
+            "kernel_ms": 1e3 * float(np.mean(kern)),
+            "host_ms_per_step": 1e3 * t_host / args.steps,
+            "mass_rel_drift": abs(first_st["mass_out"] - first_st["mass_in"]) / first_st["mass_in"],
+            "kernel_mass_range": [first_st["kmass_min"], first_st["kmass_max"]],
+            "sources": first_st["n_sources"],
+        }
+        log(f"{mode}: {ms:.1f} ms/step, kernel {results[mode]['kernel_ms']:.1f} ms, "
+            f"{results[mode]['cells_per_s'] / 1e6:.3f} Mcells/s")
+
+    if "fp32" in fields:
+        ref = fields["fp32"]
+        den = float(ref.abs().sum())
+        for mode in modes:
+            results[mode]["rel_l1_vs_fp32"] = float((fields[mode] - ref).abs().sum()) / den
+            results[mode]["speedup_vs_fp32"] = results["fp32"]["ms_per_step"] / results[mode]["ms_per_step"]
+
+    head = results[args.prec]
+    cs = window_cells(d.shape, d.r) * d.n_sub          # in-domain cell-sub-steps per step
+    flops = FLOP_PER_CELL_SUBSTEP * cs
+    achieved = flops / (head["kernel_ms"] * 1e-3) / 1e12
+    esize = {"fp32": 4, "fp64": 8}.get(args.prec, 2)
+    lds_tbs = LDS_ACCESSES_PER_CELL_SUBSTEP * esize * cs / (head["kernel_ms"] * 1e-3) / 1e12
+    kernel_tag = f"line_kernel_{args.prec}_grf{args.n}"
+    traffic = read_traffic(kernel_tag)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                "kernel": f"line_kernel<{args.prec}, r=8>",
+                "cell_substeps_per_launch": cs, "flop_per_cell_substep": FLOP_PER_CELL_SUBSTEP,
+                "lds_exchange_TBps": lds_tbs}
+
+    cpu = None
+    if args.cpu_block > 0:
+        log(f"timing the CPU oracle on a {args.cpu_block}^3 source sample")
+        cpu = cpu_baseline(d, args.cpu_block)
+        log(f"oracle: {cpu['value']:.1f} cells/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": "FDiRW big-step cells/s @192^3 (fused kernel generation + FP64 superposition)",
+        "value": head["cells_per_s"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp16x32": "f32 (f16 neighbour copies, f64 superposition)",
+                  "bf16x32": "f32 (bf16 neighbour copies, f64 superposition)",
+                  "fp32": "f32 (f64 superposition)", "fp64": "f64"}.get(args.prec, args.prec),
+        "data": "synthetic (seeded GRF porous medium standing in for the paper's particle geometry)",
+        "config": {"workload": f"grf{args.n}_r{d.r}_n{d.n_sub}", "grid": list(d.shape), "r": d.r,
+                   "n_sub": d.n_sub, "solid_fraction": 0.35, "D": [1.0, 1e-6], "prec": args.prec,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -128,6 +128,8 @@ typedef struct fdirw_stats {
     int64_t n_sources;         /* sources processed (cells with c != 0) */
     int32_t bank_used;         /* fdirw_run applied a stored kernel bank */
     int32_t reserved;
+    double kernel_seconds;     /* device time of the main kernel of the (last) step,
+                                  from HIP events recorded around its launch */
 } fdirw_stats;
 
 /* Row (a1): coefficients.  Writes lam[0*N + i], lam[1*N + i], lam[2*N + i] =

@@ -68,7 +68,8 @@ class fdirw_stats(ctypes.Structure):
                 ("audit_l1", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("fallback_used", ctypes.c_int32), ("tuned_config_id", ctypes.c_int32),
                 ("n_sources", ctypes.c_int64),
-                ("bank_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bank_used", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kernel_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

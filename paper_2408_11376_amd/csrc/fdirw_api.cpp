@@ -81,7 +81,7 @@ static void release_all()
     for (auto &kv : g_cache) {
         (void)hipSetDevice(kv.first);
         DevCache &c = kv.second;
-        for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass}) {
+        for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass, &c.ring}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
             b->cap = 0;
@@ -223,6 +223,8 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     line_shape(d, o->tune, &seg_len, &n_seg);
     const int64_t nblk = (int64_t)d->nx * d->ny * n_seg;
     if ((rc = ensure(dc.wgk, (size_t)nblk * 2 * sizeof(double)))) return rc;
+    const int64_t W = 2 * d->r + 1;
+    if ((rc = ensure(dc.ring, (size_t)nblk * W * W * W * sizeof(double)))) return rc;
     if ((rc = ensure(dc.small, 64))) return rc;
     unsigned long long *used = (unsigned long long *)dc.small.p;
     hipError_t e = launch_fill(c_out, n, 0.0, stream);
@@ -236,8 +238,13 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     a.c_in = c_in; a.c_out = c_out;
     a.wg_kmass = (double *)dc.wgk.p;
     a.n_used = used;
+    a.ring = (double *)dc.ring.p;
+    EventPair ev;
+    if (st && (e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
+    if (st) (void)hipEventRecord(ev.a, stream);
     e = launch_line(o->prec, d->r, a, stream);
     if (e != hipSuccess) return hip_fail(e, "fused step launch");
+    if (st) (void)hipEventRecord(ev.b, stream);
     if (st) {
         if ((rc = field_sum_dev(c_out, n, stream, dc, &st->mass_out))) return rc;
         double *mm = (double *)dc.small.p + 2;
@@ -251,6 +258,7 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
         st->kmass_min = h_mm[0];
         st->kmass_max = h_mm[1];
         st->n_sources = (int64_t)h_used;
+        st->kernel_seconds = ev.seconds();
         st->audit_l1 = 0.0;
         st->fallback_used = 0;
         st->bank_used = 0;

@@ -1,15 +1,24 @@
 // fdirw_device.h -- device-side building blocks of the FDiRW window stencil
 // for gfx950 (CDNA4, wave64).  Included by the kernel translation units only.
 //
-// Execution model of one window kernel (Sec. 3.1 of arXiv 2408.11376: a
-// column of P is the explicit-FD response to a unit point source):
-//   * the W x W columns of the (2r+1)^3 window are owned by W^2 threads, one
-//     z-column of W cells each, kept in registers (state and coefficients);
-//   * every sub-step each thread publishes its column to LDS (double-buffered,
-//     one barrier per sub-step) and reads its four in-plane neighbours back;
-//     the z neighbours come from its own registers;
-//   * G' = diag*G + sum_f lam_f * G_nbr, with diag = 1 - sum_f lam_f (the
-//     conservative 7-point update written with one product per term).
+// One window kernel (Sec. 3.1 of arXiv 2408.11376: a column of P is the
+// explicit-FD response to a unit point source) is computed by one workgroup:
+//   * the W x W z-columns of the (2r+1)^3 window are split into NSEG segments
+//     of at most L0 cells; one thread owns one segment in registers (state,
+//     face coefficients, and an FP64 accumulator per cell);
+//   * every sub-step each thread publishes its segment to LDS and reads the
+//     four in-plane neighbour segments back.  The LDS exchange buffer is laid
+//     out z-fastest ([column][z]) so that a neighbour segment is a contiguous,
+//     16-byte aligned run read with 128-bit LDS loads (on gfx950 these move
+//     about twice the bytes per clock of 32/64-bit LDS loads); the column
+//     stride is an odd number of 16-byte chunks so the 16 lanes served per
+//     clock hit distinct banks;
+//   * the two z neighbours come from the thread's own registers, except across
+//     a segment boundary where they come from the exchange buffer;
+//   * double-buffered exchange: one barrier per sub-step;
+//   * update G' = diag*G + sum_f lam_f * G_nbr with diag = 1 - sum_f lam_f
+//     (the conservative 7-point update, one product per term; terms added in
+//     the order own, -z, +z, -x, +x, -y, +y).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,107 +37,188 @@ enum Mode : int {
     M_COUNT = 8
 };
 
+// S: state / coefficient type; E: exchange (LDS copy) type; B: bank storage.
 template <int M> struct Traits;
 template <> struct Traits<M_FP64> {
-    using S = double; using E = double;
+    using S = double; using E = double; using B = double;
     static constexpr bool x32 = false, state = false, bank = false, renorm = false;
 };
 template <> struct Traits<M_FP32> {
-    using S = float; using E = float;
+    using S = float; using E = float; using B = float;
     static constexpr bool x32 = false, state = false, bank = false, renorm = true;
 };
 template <> struct Traits<M_F16X32> {
-    using S = float; using E = _Float16;
+    using S = float; using E = _Float16; using B = float;
     static constexpr bool x32 = true, state = false, bank = false, renorm = true;
 };
 template <> struct Traits<M_BF16X32> {
-    using S = float; using E = __bf16;
+    using S = float; using E = __bf16; using B = float;
     static constexpr bool x32 = true, state = false, bank = false, renorm = true;
 };
 template <> struct Traits<M_F16ST> {
-    using S = float; using E = _Float16;
+    using S = float; using E = _Float16; using B = float;
     static constexpr bool x32 = false, state = true, bank = false, renorm = true;
 };
 template <> struct Traits<M_BF16ST> {
-    using S = float; using E = __bf16;
+    using S = float; using E = __bf16; using B = float;
     static constexpr bool x32 = false, state = true, bank = false, renorm = true;
 };
 template <> struct Traits<M_F16BANK> {
-    using S = float; using E = float;
-    using B = _Float16;
+    using S = float; using E = float; using B = _Float16;
     static constexpr bool x32 = false, state = false, bank = true, renorm = true;
 };
 template <> struct Traits<M_BF16BANK> {
-    using S = float; using E = float;
-    using B = __bf16;
+    using S = float; using E = float; using B = __bf16;
     static constexpr bool x32 = false, state = false, bank = true, renorm = true;
 };
 
-// Round-to-nearest-even into the storage type and back (exact widening).
+// Round-to-nearest-even into a storage type and back (exact widening).
 template <typename E> __device__ __forceinline__ float round_to(float x) { return (float)(E)x; }
 template <> __device__ __forceinline__ float round_to<float>(float x) { return x; }
 
-template <int R> struct Win {
+constexpr int ru(int a, int b) { return (a + b - 1) / b * b; }
+
+#ifndef FDIRW_SEG_CELLS
+#define FDIRW_SEG_CELLS 9          // most cells of a z-column one thread owns
+#endif
+
+// Geometry of the window / thread / LDS layout for mode M and radius R.
+//
+// A z-column of W cells is cut into NSEG segments of L0 cells (the last one
+// has LAST <= L0 real cells; the rest of it is padding that stays 0).  Of each
+// segment, the first MAIN = L0 - 1 cells go to the strided array
+// main[col][z] (16-byte aligned runs, read with 128-bit loads), the top cell
+// to the dense array tail[seg][col], and the first cell is also copied to the
+// dense array head[seg][col]; the single-cell accesses of a wave are then
+// lane-contiguous and free of bank conflicts.  With one segment the whole
+// column is in main[].
+template <int M, int R> struct Geo {
+    using T = Traits<M>;
+    using S = typename T::S;
+    using E = typename T::E;
     static constexpr int W = 2 * R + 1;
     static constexpr int W2 = W * W;
     static constexpr int W3 = W2 * W;
-    static constexpr int NT = ((W2 + 63) / 64) * 64;       // threads per window
+    static constexpr int NSEG = (W + FDIRW_SEG_CELLS - 1) / FDIRW_SEG_CELLS;  // segments per column
+    static constexpr int L0 = (W + NSEG - 1) / NSEG;        // cells per thread
+    static constexpr int LAST = W - (NSEG - 1) * L0;        // real cells of the last segment
+    static constexpr int MAIN = NSEG > 1 ? L0 - 1 : W;      // cells per segment in main[]
+    static constexpr int CH = 16 / (int)sizeof(E);          // elements per 16-byte chunk
+    static constexpr int SOFF = ru(MAIN, CH);               // offset between segments in a column
+    static constexpr int ZS0 = ru((NSEG - 1) * SOFF + MAIN, CH);
+    static constexpr int ZS = ((ZS0 / CH) % 2 == 0) ? ZS0 + CH : ZS0;   // column stride
+    static constexpr int PADC = W + 1;                      // padding columns on each side
+    static constexpr int NCOL = W2 + 2 * PADC;
+    static constexpr int TAIL = NCOL * ZS;                  // tail[seg][col]
+    static constexpr int HEAD = TAIL + NSEG * NCOL;         // head[seg][col]
+    static constexpr int XLEN = ru(HEAD + NSEG * NCOL, CH); // elements of one exchange buffer
+    static constexpr int NT = ru(NSEG * W2, 64);            // threads per workgroup
     static constexpr int NWAVE = NT / 64;
-    static constexpr int PAD = W + 1;                       // LDS halo for t-1, t-W, t+1, t+W
-    static constexpr int XLEN = W3 + 2 * PAD;              // one exchange buffer
+    // register budget hint (minimum waves per SIMD): for the 10-wave r = 8
+    // workgroup a 128-VGPR budget (4 waves / SIMD, one workgroup per CU with
+    // more LDS loads in flight) measured faster than 96 VGPRs (two
+    // workgroups per CU with serialised loads)
+#ifdef FDIRW_MINW
+    static constexpr int MINW = FDIRW_MINW;
+#else
+    static constexpr int MINW = (NWAVE + 2) / 3 < 1 ? 1 : ((NWAVE + 2) / 3 > 8 ? 8 : (NWAVE + 2) / 3);
+#endif
+    static_assert(LAST >= 1 && LAST <= L0, "segment split");
 };
 
-// Per-thread column coefficients: in-plane faces of each cell and the z faces
-// between consecutive cells (zf[j] = face between cells j-1 and j; zf[0] and
-// zf[W] are the window walls and stay 0).
-template <typename S, int W> struct Column {
-    S xm[W], xp[W], ym[W], yp[W];
-    S zf[W + 1];
-    S diag[W];
+// Per-thread kernel values of one segment.
+template <int M, int R> using SegVals = typename Geo<M, R>::S[Geo<M, R>::L0];
+
+// Per-thread state of one segment.
+template <int M, int R> struct Seg {
+    using G_ = Geo<M, R>;
+    using S = typename G_::S;
+    static constexpr int L = G_::L0;
+    S xm[L], xp[L], ym[L], yp[L];
+    S zf[L + 1];          // zf[k]: face between segment cells k-1 and k (k = 0..L)
+    S diag[L];
 };
 
-// Coefficients of window cell (X, Y, Z) owned by a thread at window column
-// (cx, cy).  Faces leaving the window or the domain are 0.
-template <typename S, int W>
-__device__ __forceinline__ void load_cell(const S *__restrict__ lx, const S *__restrict__ ly,
-                                          int nx, int ny, int nz, int X, int Y, int Z,
-                                          int cx, int cy, bool inxy,
-                                          S &xm, S &xp, S &ym, S &yp)
+// Thread placement inside the workgroup.
+struct Place {
+    int t;        // thread index
+    bool act;     // owns a segment
+    int seg;      // segment index
+    int col;      // window column (cy * W + cx)
+    int cx, cy;
+    int j0;       // window-relative z of the segment's first cell
+    int len;      // real cells in the segment
+};
+
+template <int M, int R>
+__device__ __forceinline__ Place make_place(int t)
 {
-    const bool in = inxy && Z >= 0 && Z < nz;
-    xm = xp = ym = yp = S(0);
-    if (in) {
-        const int64_t i = ((int64_t)Z * ny + Y) * nx + X;
-        if (cx < W - 1) xp = lx[i];
-        if (cx > 0 && X > 0) xm = lx[i - 1];
-        if (cy < W - 1) yp = ly[i];
-        if (cy > 0 && Y > 0) ym = ly[i - nx];
+    using G_ = Geo<M, R>;
+    Place p;
+    p.t = t;
+    p.act = t < G_::NSEG * G_::W2;
+    p.seg = p.act ? t / G_::W2 : 0;
+    p.col = p.act ? t - p.seg * G_::W2 : 0;
+    p.cx = p.col % G_::W;
+    p.cy = p.col / G_::W;
+    p.j0 = p.seg * G_::L0;
+    p.len = p.seg == G_::NSEG - 1 ? G_::LAST : G_::L0;
+    return p;
+}
+
+// Loads the coefficients of a thread's segment for the window of source
+// (sx, sy, sz) from the owned-face arrays lx / ly / lz ([nz][ny][nx] each).
+// Faces leaving the window or the domain, and every face of a cell outside
+// the domain or past the segment's real cells, are 0.
+template <int M, int R>
+__device__ __forceinline__ void load_segment(Seg<M, R> &c, const typename Geo<M, R>::S *__restrict__ lx,
+                                             const typename Geo<M, R>::S *__restrict__ ly,
+                                             const typename Geo<M, R>::S *__restrict__ lz,
+                                             int nx, int ny, int nz, int sx, int sy, int sz, const Place &p)
+{
+    using G_ = Geo<M, R>;
+    using S = typename G_::S;
+    constexpr int L = G_::L0, W = G_::W;
+    const int X = sx - R + p.cx, Y = sy - R + p.cy;
+    const bool inxy = p.act && X >= 0 && X < nx && Y >= 0 && Y < ny;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const int j = p.j0 + k;                     // window-relative z
+        const int Z = sz - R + j;
+        const bool in = inxy && k < p.len && Z >= 0 && Z < nz;
+        S xm = S(0), xp = S(0), ym = S(0), yp = S(0);
+        if (in) {
+            const int64_t i = ((int64_t)Z * ny + Y) * nx + X;
+            if (p.cx < W - 1) xp = lx[i];
+            if (p.cx > 0 && X > 0) xm = lx[i - 1];
+            if (p.cy < W - 1) yp = ly[i];
+            if (p.cy > 0 && Y > 0) ym = ly[i - nx];
+        }
+        c.xm[k] = xm; c.xp[k] = xp; c.ym[k] = ym; c.yp[k] = yp;
+    }
+#pragma unroll
+    for (int k = 0; k <= L; ++k) {
+        const int j = p.j0 + k;                     // face between relative j-1 and j
+        const int Z = sz - R + j;
+        S v = S(0);
+        if (inxy && k <= p.len && j >= 1 && j <= W - 1 && Z >= 1 && Z < nz)
+            v = lz[((int64_t)(Z - 1) * ny + Y) * nx + X];
+        c.zf[k] = v;
     }
 }
 
-// z face between global planes Z-1 and Z of column (X, Y).
-template <typename S>
-__device__ __forceinline__ S load_zface(const S *__restrict__ lz, int nx, int ny, int nz,
-                                        int X, int Y, int Z, bool inxy)
+template <bool X32, int M, int R>
+__device__ __forceinline__ void compute_diag(Seg<M, R> &c)
 {
-    if (inxy && Z >= 1 && Z < nz) return lz[((int64_t)(Z - 1) * ny + Y) * nx + X];
-    return S(0);
-}
-
-// diag = 1 - sum of the six faces (plain modes), or the sum itself (X32
-// modes, where the own-cell term uses the reduced copy).  Fixed order:
-// -x, +x, -y, +y, -z, +z.
-template <bool X32, typename S, int W>
-__device__ __forceinline__ void compute_diag(Column<S, W> &c)
-{
+    using S = typename Geo<M, R>::S;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-        S s = c.xm[j] + c.xp[j];
-        s = s + c.ym[j];
-        s = s + c.yp[j];
-        s = s + c.zf[j];
-        s = s + c.zf[j + 1];
-        c.diag[j] = X32 ? s : S(1) - s;
+    for (int k = 0; k < Geo<M, R>::L0; ++k) {
+        S s = c.xm[k] + c.xp[k];
+        s = s + c.ym[k];
+        s = s + c.yp[k];
+        s = s + c.zf[k];
+        s = s + c.zf[k + 1];
+        c.diag[k] = X32 ? s : S(1) - s;
     }
 }
 
@@ -136,51 +226,98 @@ template <typename S> __device__ __forceinline__ S fmaT(S a, S b, S c);
 template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// n_sub explicit sub-steps of one window.  All threads of the block call this
-// (barriers); threads with act == false only take part in the barriers.
+// One explicit sub-step of one window, exchanging through buffer buf.
 template <int M, int R>
-__device__ __forceinline__ void run_substeps(typename Traits<M>::S (&G)[Win<R>::W],
-                                             const Column<typename Traits<M>::S, Win<R>::W> &c,
-                                             typename Traits<M>::E *xb0,
-                                             typename Traits<M>::E *xb1,
-                                             int t, bool act, int n_sub)
+__device__ __forceinline__ void one_substep(SegVals<M, R> &G, const Seg<M, R> &c,
+                                            typename Geo<M, R>::E *__restrict__ buf, const Place &p,
+                                            int own, int tail_at, int head_at, int zlo_at, int zhi_at)
 {
-    using T = Traits<M>;
-    using S = typename T::S;
-    using E = typename T::E;
-    constexpr int W = Win<R>::W, W2 = Win<R>::W2, PAD = Win<R>::PAD;
-    for (int step = 0; step < n_sub; ++step) {
-        E *xb = (step & 1) ? xb1 : xb0;
-        S gh[W];                                   // values the neighbours see
+    using G_ = Geo<M, R>;
+    using T = typename G_::T;
+    using S = typename G_::S;
+    using E = typename G_::E;
+    constexpr int L = G_::L0, W = G_::W, ZS = G_::ZS, MAIN = G_::MAIN;
+    constexpr bool MULTI = G_::NSEG > 1;
+    S gh[L];                                        // the values the neighbours see
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
-            if constexpr (T::x32) gh[j] = round_to<E>(G[j]);
-            else gh[j] = G[j];
-        }
-        if (act) {
+    for (int k = 0; k < L; ++k) {
+        if constexpr (T::x32) gh[k] = round_to<E>(G[k]);
+        else gh[k] = G[k];
+    }
+    if (p.act) {
 #pragma unroll
-            for (int j = 0; j < W; ++j) xb[PAD + j * W2 + t] = (E)gh[j];
-        }
-        __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < W; ++j) {
-                const E *p = xb + PAD + j * W2 + t;
-                const S gxm = (S)p[-1], gxp = (S)p[1], gym = (S)p[-W], gyp = (S)p[W];
-                S acc;
-                if constexpr (T::x32) acc = fmaT<S>(-c.diag[j], gh[j], G[j]);
-                else                  acc = c.diag[j] * G[j];
-                acc = fmaT<S>(c.xm[j], gxm, acc);
-                acc = fmaT<S>(c.xp[j], gxp, acc);
-                acc = fmaT<S>(c.ym[j], gym, acc);
-                acc = fmaT<S>(c.yp[j], gyp, acc);
-                if (j > 0) acc = fmaT<S>(c.zf[j], gh[j - 1], acc);
-                if (j < W - 1) acc = fmaT<S>(c.zf[j + 1], gh[j + 1], acc);
-                if constexpr (T::state) acc = round_to<E>(acc);
-                G[j] = acc;
-            }
+        for (int k = 0; k < MAIN; ++k) buf[own + k] = (E)gh[k];
+        if constexpr (MULTI) {
+            buf[tail_at] = (E)gh[L - 1];
+            buf[head_at] = (E)gh[0];
         }
     }
+    __syncthreads();
+    if (p.act) {
+        // own and z terms first (the state is dead afterwards), then the four
+        // in-plane directions one at a time so that only one neighbour
+        // segment is live; per-cell term order: own, -z, +z, -x, +x, -y, +y
+        const E *b = buf + own;
+        S zlo = S(0), zhi = S(0);
+        if constexpr (MULTI) {
+            zlo = (S)buf[zlo_at];
+            zhi = (S)buf[zhi_at];
+        }
+        S acc[L];
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            S a2;
+            if constexpr (T::x32) a2 = fmaT<S>(-c.diag[k], gh[k], G[k]);
+            else                  a2 = c.diag[k] * G[k];
+            a2 = fmaT<S>(c.zf[k], k > 0 ? gh[k - 1] : zlo, a2);
+            acc[k] = fmaT<S>(c.zf[k + 1], k < L - 1 ? gh[k + 1] : zhi, a2);
+        }
+        // neighbour cell k of column col + d: main[] for k < MAIN, else the
+        // neighbour segment's top cell in tail[]
+#define FDIRW_NB(d, k) ((k) < MAIN ? (S)b[(k) + (d) * ZS] : (S)buf[tail_at + (d)])
+#pragma unroll
+        for (int k = 0; k < L; ++k) acc[k] = fmaT<S>(c.xm[k], FDIRW_NB(-1, k), acc[k]);
+#pragma unroll
+        for (int k = 0; k < L; ++k) acc[k] = fmaT<S>(c.xp[k], FDIRW_NB(1, k), acc[k]);
+#pragma unroll
+        for (int k = 0; k < L; ++k) acc[k] = fmaT<S>(c.ym[k], FDIRW_NB(-W, k), acc[k]);
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            S a2 = fmaT<S>(c.yp[k], FDIRW_NB(W, k), acc[k]);
+            if constexpr (T::state) a2 = round_to<E>(a2);
+            G[k] = a2;
+        }
+#undef FDIRW_NB
+    }
+}
+
+// n_sub explicit sub-steps of one window.  Every thread of the block calls
+// this (barriers); threads with act == false only take part in the barriers.
+// xb: two exchange buffers of XLEN elements, 16-byte aligned, padding zeroed;
+// sub-steps alternate between them (one barrier per sub-step), unrolled by
+// two so that buffer addresses are fixed offsets.
+template <int M, int R>
+__device__ __forceinline__ void run_substeps(SegVals<M, R> &G, const Seg<M, R> &c,
+                                             typename Geo<M, R>::E *__restrict__ xb, const Place &p, int n_sub)
+{
+    using G_ = Geo<M, R>;
+    constexpr int NCOL = G_::NCOL;
+    const int col = G_::PADC + p.col;
+    const int own = col * G_::ZS + p.seg * G_::SOFF;
+    const int tail_at = G_::TAIL + p.seg * NCOL + col;                 // own top cell
+    const int head_at = G_::HEAD + p.seg * NCOL + col;                 // own first cell
+    // z neighbours across segment boundaries: the top cell of the segment
+    // below and the first cell of the segment above (first / last segments
+    // read a finite dummy that their zero wall faces cancel)
+    const int zlo_at = G_::TAIL + (p.seg > 0 ? p.seg - 1 : 0) * NCOL + col;
+    const int zhi_at = G_::HEAD + (p.seg < G_::NSEG - 1 ? p.seg + 1 : 0) * NCOL + col;
+    typename G_::E *xb1 = xb + G_::XLEN;
+    int step = 0;
+    for (; step + 1 < n_sub; step += 2) {
+        one_substep<M, R>(G, c, xb, p, own, tail_at, head_at, zlo_at, zhi_at);
+        one_substep<M, R>(G, c, xb1, p, own, tail_at, head_at, zlo_at, zhi_at);
+    }
+    if (step < n_sub) one_substep<M, R>(G, c, xb, p, own, tail_at, head_at, zlo_at, zhi_at);
 }
 
 // Block-wide FP64 sum of one value per thread (fixed order: xor butterfly in
@@ -198,6 +335,36 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 #pragma unroll
     for (int w = 1; w < NWAVE; ++w) s += red[w];
     return s;
+}
+
+// After the sub-steps: in BANK modes round the kernel to its storage type;
+// return the FP64 kernel mass (sum over the whole window).
+template <int M, int R>
+__device__ __forceinline__ double finish_kernel(SegVals<M, R> &G, double *red,
+                                                const Place &p)
+{
+    using T = typename Geo<M, R>::T;
+    constexpr int L = Geo<M, R>::L0;
+    if constexpr (T::bank) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) G[k] = round_to<typename T::B>(G[k]);
+    }
+    double s = 0.0;
+    if (p.act) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) s += (double)G[k];
+    }
+    return block_sum<Geo<M, R>::NWAVE>(s, red);
+}
+
+// Unit source at the window centre.
+template <int M, int R>
+__device__ __forceinline__ void init_delta(SegVals<M, R> &G, const Place &p)
+{
+    using S = typename Geo<M, R>::S;
+#pragma unroll
+    for (int k = 0; k < Geo<M, R>::L0; ++k)
+        G[k] = (p.act && p.cx == R && p.cy == R && p.j0 + k == R) ? S(1) : S(0);
 }
 
 }  // namespace fdirw

@@ -20,7 +20,29 @@ struct Buf {
 // partials, per-workgroup kernel masses, a few counters, and the kernel bank.
 struct DevCache {
     int dev = -1;
-    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass;
+    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass, ring;
+};
+
+// Two HIP events around one launch; destroyed with the object.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        return e;
+    }
+    double seconds() const
+    {
+        float ms = 0.0f;
+        if (a && b && hipEventElapsedTime(&ms, a, b) == hipSuccess) return 1e-3 * (double)ms;
+        return -1.0;
+    }
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
 };
 
 struct Geometry {

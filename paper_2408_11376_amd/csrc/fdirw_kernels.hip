@@ -7,12 +7,10 @@
 //   fill / field-sum       row (a6) and output clearing
 //
 // The superposition (Eq. 8 of arXiv 2408.11376 in its column form) is
-// organised so that a workgroup walks a line of sources along z: the window of
-// source z+1 is the window of source z shifted by one plane, so each thread
-// shifts its register column of coefficients by one cell, loads one new cell,
-// and accumulates c(s) * G_s into an FP64 ring of W planes in LDS.  The plane
-// that no later source of the line can reach is flushed with one FP64 atomic
-// per window column, i.e. W^2 atomics per source instead of W^3.
+// organised so that a workgroup walks a line of sources along z and
+// accumulates c(s) * G_s into an FP64 ring of W planes; the plane that no later
+// source of the line can reach is flushed with one FP64 atomic per window
+// column, i.e. W^2 atomics per source instead of W^3.
 #include "fdirw_device.h"
 #include "fdirw_launch.h"
 
@@ -166,192 +164,175 @@ __global__ void src_check_kernel(const int64_t *__restrict__ src, int64_t n_src,
         if (src[i] < 0 || src[i] >= n) atomicOr(bad, 1u);
 }
 
-// ----------------------------------------------------------------- window math
+// ----------------------------------------------------------------- launch geometry
 
-// After the sub-steps: kernel mass (FP64 sum of the state, or of the rounded
-// kernel in BANK modes), and the factor that turns G into its contribution.
-template <int M, int R>
-__device__ __forceinline__ double finish_kernel(typename Traits<M>::S (&G)[Win<R>::W], double *red, bool act)
+// Spreads consecutive logical workgroups over one XCD: the hardware hands
+// workgroup b to XCD b % 8, so logical index (b % 8) * (g / 8) + b / 8 keeps
+// neighbouring source lines (which share coefficients and output planes) in
+// the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int g)
 {
-    using T = Traits<M>;
-    constexpr int W = Win<R>::W;
-    if constexpr (T::bank) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) G[j] = round_to<typename T::B>(G[j]);
-    }
-    double s = 0.0;
-    if (act) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) s += (double)G[j];
-    }
-    return block_sum<Win<R>::NWAVE>(s, red);
+    if (g % 8 != 0) return b;
+    return (b % 8) * (g / 8) + b / 8;
+}
+
+template <int M, int R>
+__device__ __forceinline__ void zero_exchange(typename Geo<M, R>::E *xb)
+{
+    using E = typename Geo<M, R>::E;
+    for (int i = threadIdx.x; i < 2 * Geo<M, R>::XLEN; i += blockDim.x) xb[i] = (E)0.0f;
 }
 
 // ----------------------------------------------------------------- (a2)-(a4)
 
 template <int M, int R>
-__global__ void __launch_bounds__(Win<R>::NT)
+__global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
 window_kernel(WindowArgs a)
 {
-    using T = Traits<M>;
-    using S = typename T::S;
-    using E = typename T::E;
-    constexpr int W = Win<R>::W, W2 = Win<R>::W2, W3 = Win<R>::W3, XLEN = Win<R>::XLEN;
-    __shared__ E xb[2 * XLEN];
-    __shared__ double red[Win<R>::NWAVE];
+    using G_ = Geo<M, R>;
+    using T = typename G_::T;
+    using S = typename G_::S;
+    using E = typename G_::E;
+    constexpr int L = G_::L0, W2 = G_::W2, W3 = G_::W3;
+    __shared__ __align__(16) E xb[2 * G_::XLEN];
+    __shared__ double red[G_::NWAVE];
 
-    const int t = threadIdx.x;
-    const bool act = t < W2;
-    const int cx = act ? t % W : 0, cy = act ? t / W : 0;
-    for (int i = t; i < 2 * XLEN; i += blockDim.x) xb[i] = (E)0.0f;
+    const Place p = make_place<M, R>(threadIdx.x);
+    zero_exchange<M, R>(xb);
     __syncthreads();
 
     const S *lx = (const S *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
     for (int64_t q = blockIdx.x; q < a.n_src; q += gridDim.x) {
         const int64_t s = a.src ? a.src[q] : q;
         const int sx = (int)(s % a.nx), sy = (int)((s / a.nx) % a.ny), sz = (int)(s / ((int64_t)a.nx * a.ny));
-        const int X = sx - R + cx, Y = sy - R + cy;
-        const bool inxy = act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
-        Column<S, W> c;
-#pragma unroll
-        for (int j = 0; j < W; ++j)
-            load_cell<S, W>(lx, ly, a.nx, a.ny, a.nz, X, Y, sz - R + j, cx, cy, inxy, c.xm[j], c.xp[j], c.ym[j], c.yp[j]);
-        c.zf[0] = S(0);
-        c.zf[W] = S(0);
-#pragma unroll
-        for (int j = 1; j < W; ++j) c.zf[j] = load_zface<S>(lz, a.nx, a.ny, a.nz, X, Y, sz - R + j, inxy);
-        compute_diag<T::x32, S, W>(c);
-
-        S G[W];
-#pragma unroll
-        for (int j = 0; j < W; ++j) G[j] = (j == R && cx == R && cy == R && act) ? S(1) : S(0);
-        run_substeps<M, R>(G, c, xb, xb + XLEN, t, act, a.n_sub);
-        const double m = finish_kernel<M, R>(G, red, act);
-        if (t == 0 && a.mass) a.mass[q] = m;
-        if (act) {
+        Seg<M, R> c;
+        load_segment<M, R>(c, lx, ly, lz, a.nx, a.ny, a.nz, sx, sy, sz, p);
+        compute_diag<T::x32, M, R>(c);
+        S G[L];
+        init_delta<M, R>(G, p);
+        run_substeps<M, R>(G, c, xb, p, a.n_sub);
+        const double m = finish_kernel<M, R>(G, red, p);
+        if (threadIdx.x == 0 && a.mass) a.mass[q] = m;
+        if (p.act) {
             const bool norm = T::renorm && !T::bank && a.normalize;
             const double inv = norm ? 1.0 / m : 1.0;
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-                const int64_t o = q * (int64_t)W3 + (int64_t)j * W2 + t;
+            for (int k = 0; k < L; ++k) {
+                if (k >= p.len) continue;
+                const int64_t o = q * (int64_t)W3 + (int64_t)(p.j0 + k) * W2 + p.col;
                 if constexpr (M == M_FP64) {
-                    ((double *)a.G)[o] = G[j];
+                    ((double *)a.G)[o] = G[k];
                 } else if constexpr (T::bank) {
-                    if (a.out_lp) ((typename T::B *)a.G)[o] = (typename T::B)G[j];
-                    else ((float *)a.G)[o] = G[j];
+                    if (a.out_lp) ((typename T::B *)a.G)[o] = (typename T::B)G[k];
+                    else ((float *)a.G)[o] = G[k];
                 } else {
-                    ((float *)a.G)[o] = norm ? (float)((double)G[j] * inv) : G[j];
+                    ((float *)a.G)[o] = norm ? (float)((double)G[k] * inv) : G[k];
                 }
             }
         }
-        __syncthreads();      // xb reuse by the next source of this block
+        __syncthreads();      // exchange buffers are reused by the next source
     }
 }
 
 // ----------------------------------------------------------------- (a5) fused
 
+// One workgroup walks the sources (sx, sy, z0..z1-1).  c(s) * G_s is
+// accumulated in FP64 into a ring of W planes x W^2 columns that belongs to
+// the workgroup (global scratch, L2-resident, touched once per source), indexed
+// by global plane z mod W.  After source sz the plane z = sz - R can receive
+// nothing more from this line: it is added to c_out with one atomic per
+// window column and cleared.  Keeping the ring out of registers leaves the
+// register file to the sub-step loop.
 template <int M, int R>
-__global__ void __launch_bounds__(Win<R>::NT)
+__global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
 line_kernel(LineArgs a)
 {
-    using T = Traits<M>;
-    using S = typename T::S;
-    using E = typename T::E;
-    constexpr int W = Win<R>::W, W2 = Win<R>::W2, XLEN = Win<R>::XLEN;
-    __shared__ E xb[2 * XLEN];
-    __shared__ double ring[W * W2];
-    __shared__ double red[Win<R>::NWAVE];
+    using G_ = Geo<M, R>;
+    using T = typename G_::T;
+    using S = typename G_::S;
+    using E = typename G_::E;
+    constexpr int L = G_::L0, W = G_::W, W2 = G_::W2;
+    __shared__ __align__(16) E xb[2 * G_::XLEN];
+    __shared__ double red[G_::NWAVE];
 
-    const int t = threadIdx.x;
-    const bool act = t < W2;
-    const int cx = act ? t % W : 0, cy = act ? t / W : 0;
-    for (int i = t; i < 2 * XLEN; i += blockDim.x) xb[i] = (E)0.0f;
-    if (act) {
-#pragma unroll
-        for (int j = 0; j < W; ++j) ring[j * W2 + t] = 0.0;
-    }
+    const Place p = make_place<M, R>(threadIdx.x);
+    zero_exchange<M, R>(xb);
+
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    double *ring = a.ring + (int64_t)blockIdx.x * (W * W2);
+    for (int i = threadIdx.x; i < W * W2; i += blockDim.x) ring[i] = 0.0;
     __syncthreads();
 
-    const int b = blockIdx.x;
-    const int line = b / a.n_seg, seg = b - line * a.n_seg;
+    const int line = b / a.n_seg, sgi = b - line * a.n_seg;
     const int sy = line / a.nx, sx = line - sy * a.nx;
-    const int z0 = seg * a.seg_len;
+    const int z0 = sgi * a.seg_len;
     const int z1 = min(a.nz, z0 + a.seg_len);
     if (z0 >= z1) return;                                   // uniform per block
-    const int X = sx - R + cx, Y = sy - R + cy;
-    const bool inxy = act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
+    const int X = sx - R + p.cx, Y = sy - R + p.cy;
+    const bool inxy = p.act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
     const S *lx = (const S *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
-
-    Column<S, W> c;
-#pragma unroll
-    for (int j = 0; j < W; ++j)
-        load_cell<S, W>(lx, ly, a.nx, a.ny, a.nz, X, Y, z0 - R + j, cx, cy, inxy, c.xm[j], c.xp[j], c.ym[j], c.yp[j]);
-    c.zf[0] = S(0);
-    c.zf[W] = S(0);
-#pragma unroll
-    for (int j = 1; j < W; ++j) c.zf[j] = load_zface<S>(lz, a.nx, a.ny, a.nz, X, Y, z0 - R + j, inxy);
 
     double kmin = INFINITY, kmax = -INFINITY;
     int used = 0;
     for (int sz = z0; sz < z1; ++sz) {
-        if (sz > z0) {
-            // slide the window one plane up: shift the column, load the new top cell
-#pragma unroll
-            for (int j = 0; j < W - 1; ++j) {
-                c.xm[j] = c.xm[j + 1]; c.xp[j] = c.xp[j + 1];
-                c.ym[j] = c.ym[j + 1]; c.yp[j] = c.yp[j + 1];
-            }
-#pragma unroll
-            for (int j = 1; j < W - 1; ++j) c.zf[j] = c.zf[j + 1];
-            load_cell<S, W>(lx, ly, a.nx, a.ny, a.nz, X, Y, sz + R, cx, cy, inxy,
-                            c.xm[W - 1], c.xp[W - 1], c.ym[W - 1], c.yp[W - 1]);
-            if (W > 1) c.zf[W - 1] = load_zface<S>(lz, a.nx, a.ny, a.nz, X, Y, sz + R, inxy);
-        }
         const double cs = a.c_in[((int64_t)sz * a.ny + sy) * a.nx + sx];
         if (cs != 0.0) {                                    // uniform per block
             ++used;
-            compute_diag<T::x32, S, W>(c);
-            S G[W];
-#pragma unroll
-            for (int j = 0; j < W; ++j) G[j] = (j == R && cx == R && cy == R && act) ? S(1) : S(0);
-            run_substeps<M, R>(G, c, xb, xb + XLEN, t, act, a.n_sub);
-            const double m = finish_kernel<M, R>(G, red, act);
+            Seg<M, R> c;
+            load_segment<M, R>(c, lx, ly, lz, a.nx, a.ny, a.nz, sx, sy, sz, p);
+            compute_diag<T::x32, M, R>(c);
+            S G[L];
+            init_delta<M, R>(G, p);
+            run_substeps<M, R>(G, c, xb, p, a.n_sub);
+            const double m = finish_kernel<M, R>(G, red, p);
             kmin = fmin(kmin, m);
             kmax = fmax(kmax, m);
             const double scale = T::renorm ? cs / m : cs;
-            if (act) {
+            if (p.act) {
 #pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    const int slot = (sz - R + j + W) % W;
-                    double &acc = ring[slot * W2 + t];
-                    acc = __builtin_fma(scale, (double)G[j], acc);
+                for (int k = 0; k < L; ++k) {
+                    if (k < p.len) {
+                        double &r = ring[((sz - R + p.j0 + k + W) % W) * W2 + p.col];
+                        r = __builtin_fma(scale, (double)G[k], r);
+                    }
                 }
             }
         }
-        // plane sz - R is complete for this line segment
-        if (act) {
+        __syncthreads();                                    // ring updates visible to the block
+        // the lowest plane of this window (z = sz - R) is complete for the line
+        if (p.act && p.seg == 0) {
             const int Z = sz - R;
-            const int slot = (Z + W) % W;
-            const double v = ring[slot * W2 + t];
-            if (v != 0.0 && inxy && Z >= 0) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
-            ring[slot * W2 + t] = 0.0;
+            double &r = ring[((Z + W) % W) * W2 + p.col];
+            const double v = r;
+            if (v != 0.0 && inxy && Z >= 0)
+                unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+            r = 0.0;
         }
     }
-    if (act) {
+    __syncthreads();
+    if (p.act && p.seg == 0) {
         for (int Z = z1 - R; Z < z1 + R; ++Z) {
-            if (Z < 0) continue;
-            const int slot = (Z + W) % W;
-            const double v = ring[slot * W2 + t];
-            if (v != 0.0 && inxy && Z < a.nz) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+            if (Z < 0 || Z >= a.nz) continue;
+            double &r = ring[((Z + W) % W) * W2 + p.col];
+            const double v = r;
+            if (v != 0.0 && inxy) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+            r = 0.0;
         }
     }
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         if (a.wg_kmass) { a.wg_kmass[2 * b] = kmin; a.wg_kmass[2 * b + 1] = kmax; }
         if (a.n_used && used) atomicAdd(a.n_used, (unsigned long long)used);
     }
 }
 
 // ----------------------------------------------------------------- (a11) bank
+
+template <int R> struct Win {
+    static constexpr int W = 2 * R + 1;
+    static constexpr int W2 = W * W;
+    static constexpr int W3 = W2 * W;
+    static constexpr int NT = ((W2 + 63) / 64) * 64;
+};
 
 // Same line walk as line_kernel; the kernel of every source is read from the
 // stored bank (coalesced: one plane of W^2 values per wave row) and the FP64
@@ -442,7 +423,7 @@ template <int M, int R>
 static hipError_t launch_line_mr(const LineArgs &a, hipStream_t st)
 {
     const int64_t nblk = (int64_t)a.nx * a.ny * a.n_seg;
-    hipLaunchKernelGGL((line_kernel<M, R>), dim3((unsigned)nblk), dim3(Win<R>::NT), 0, st, a);
+    hipLaunchKernelGGL((line_kernel<M, R>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -451,7 +432,7 @@ static hipError_t launch_window_mr(const WindowArgs &a, hipStream_t st)
 {
     const int64_t nblk = a.n_src < 65536 * 16 ? a.n_src : 65536 * 16;
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL((window_kernel<M, R>), dim3((unsigned)nblk), dim3(Win<R>::NT), 0, st, a);
+    hipLaunchKernelGGL((window_kernel<M, R>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct LineArgs {
     double *c_out;
     double *wg_kmass;         // [n_blocks][2] min / max kernel mass, or null
     unsigned long long *n_used;
+    double *ring;             // [n_blocks][W][W*W] FP64 accumulation scratch
 };
 
 struct WindowArgs {

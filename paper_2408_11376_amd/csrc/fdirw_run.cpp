@@ -86,7 +86,11 @@ int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, 
             b.bank = dc.bank.p;
             b.mass = (const double *)dc.bank_mass.p;
             b.c_in = cur; b.c_out = nxt;
+            EventPair ev;
+            if (sst && e == hipSuccess) e = ev.create();
+            if (sst && e == hipSuccess) e = hipEventRecord(ev.a, stream);
             if (e == hipSuccess) e = launch_bank_apply(o->prec, d->r, b, stream);
+            if (sst && e == hipSuccess) e = hipEventRecord(ev.b, stream);
             if (e != hipSuccess) return hip_fail(e, "bank apply launch");
             if (sst) {
                 if ((rc = field_sum_dev(nxt, n, stream, dc, &sst->mass_out))) return rc;
@@ -97,6 +101,7 @@ int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, 
                 sst->fallback_used = 0;
                 sst->bank_used = 1;
                 sst->tuned_config_id = n_seg;
+                sst->kernel_seconds = ev.seconds();
             }
         } else {
             if ((rc = step_one(d, o, cur, nxt, sst, dc, stream, true, lam, &geo))) return rc;

@@ -1,0 +1,53 @@
+"""One fused FDiRW step on a seeded porous grid, for profiler runs.
+
+    python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024]
+
+Runs one untimed warm-up step, then ``--reps`` steps of the config-2 style
+workload (GRF porous grid, r = 8, 200 sub-steps) at edge ``--n``.  With
+``--copy-mib`` it also runs one plain device-to-device copy of that many MiB,
+the reference for scaling HBM byte counters (FETCH_SIZE / WRITE_SIZE).
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=96)
+    ap.add_argument("--prec", default="fp32")
+    ap.add_argument("--reps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--tune", type=int, default=-1)
+    args = ap.parse_args()
+    import torch
+    import synth
+    import paper_2408_11376_amd as fd
+    d = synth.config2(n=args.n)
+    dom = fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
+    c = torch.from_numpy(d.c0).cuda()
+    out = torch.empty_like(c)
+    for _ in range(args.warmup):
+        fd.fdirw_step(dom, c, out, prec=args.prec, tune=args.tune)
+    torch.cuda.synchronize()
+    for i in range(args.reps):
+        _, st = fd.fdirw_step(dom, c, out, prec=args.prec, stats=True, tune=args.tune)
+        print(f"[profile_step] n={args.n} prec={args.prec} rep {i}: kernel {st['kernel_seconds'] * 1e3:.2f} ms",
+              flush=True)
+    if args.copy_mib > 0:
+        nbytes = args.copy_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[profile_step] copied {args.copy_mib} MiB", flush=True)
+
+
+if __name__ == "__main__":
+    main()

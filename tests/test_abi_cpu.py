@@ -51,7 +51,7 @@ int main(void) {
   P(fdirw_domain, h) P(fdirw_domain, label) P(fdirw_domain, d_phase) P(fdirw_domain, n_phase)
   P(fdirw_domain, r) P(fdirw_domain, n_sub) P(fdirw_domain, dt)
   P(fdirw_opts, nn) P(fdirw_opts, audit_tol) P(fdirw_opts, bank_budget_bytes) P(fdirw_opts, stream) P(fdirw_opts, tune)
-  P(fdirw_stats, seconds) P(fdirw_stats, fallback_used) P(fdirw_stats, n_sources) P(fdirw_stats, bank_used)
+  P(fdirw_stats, seconds) P(fdirw_stats, fallback_used) P(fdirw_stats, n_sources) P(fdirw_stats, bank_used) P(fdirw_stats, kernel_seconds)
   return 0;
 }
 """
