@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--prec", default="fp16x32", help="headline precision mode")
     ap.add_argument("--modes", default="fp32,fp16x32,bf16x32", help="modes timed for the comparison")
     ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
-    ap.add_argument("--cpu-block", type=int, default=16, help="edge of the oracle's source sample (0: skip)")
+    ap.add_argument("--cpu-block", type=int, default=24, help="edge of the oracle's source sample (0: skip)")
     ap.add_argument("--tune", type=int, default=-1)
     args = ap.parse_args()
 
