@@ -113,7 +113,11 @@ typedef struct fdirw_opts {
     int32_t deterministic;     /* must be 0 in this build (FP64 atomics reorder sums) */
     size_t bank_budget_bytes;  /* fdirw_run: store every kernel once if the bank fits; 0 = never */
     void *stream;              /* hipStream_t, NULL = default stream */
-    int32_t tune;              /* launch shape: -1 = tuned/default, else a shape id */
+    int32_t tune;              /* launch shape.  n_dom == 1: > 0 = segments per source line,
+                                  else automatic.  n_dom > 1: 0..5 = batched shape id (item z
+                                  extent and queue order), -1 = autotuned (cached per precision,
+                                  radius / sub-step mix, size class and device; the cache file is
+                                  named by the environment variable FDIRW_TUNE_CACHE) */
 } fdirw_opts;
 
 typedef struct fdirw_stats {
@@ -161,11 +165,12 @@ int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src
 int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
                const double *const *c_in, double *const *c_out, fdirw_stats *st);
 
-/* Rows (a1)-(a7), (a11): n_steps big steps (the time marching of Eq. 8).
- * c[i] holds the initial field and receives the final one; scratch[i] is a
- * second buffer of N_i doubles (its content is overwritten).  If
- * bank_budget_bytes allows, every kernel is generated once and each step
- * applies the stored bank (P is fixed for a fixed geometry, Sec. 3.1 and 5).
+/* Rows (a1)-(a7), (a10), (a11): n_steps big steps (the time marching of
+ * Eq. 8).  c[i] holds the initial field and receives the final one;
+ * scratch[i] is a second buffer of N_i doubles (its content is overwritten).
+ * With n_dom == 1 and bank_budget_bytes allowing, every kernel is generated
+ * once and each step applies the stored bank (P is fixed for a fixed
+ * geometry, Sec. 3.1 and 5); n_dom > 1 runs one batched launch per step.
  * st (may be NULL) receives the statistics of the last step, with seconds
  * covering the whole call. */
 int fdirw_run(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o, int32_t n_steps,

@@ -81,7 +81,8 @@ static void release_all()
     for (auto &kv : g_cache) {
         (void)hipSetDevice(kv.first);
         DevCache &c = kv.second;
-        for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass, &c.ring}) {
+        for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass, &c.blam,
+                       &c.bsmall, &c.bdoms, &c.bitems}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
             b->cap = 0;
@@ -223,8 +224,6 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     line_shape(d, o->tune, &seg_len, &n_seg);
     const int64_t nblk = (int64_t)d->nx * d->ny * n_seg;
     if ((rc = ensure(dc.wgk, (size_t)nblk * 2 * sizeof(double)))) return rc;
-    const int64_t W = 2 * d->r + 1;
-    if ((rc = ensure(dc.ring, (size_t)nblk * W * W * W * sizeof(double)))) return rc;
     if ((rc = ensure(dc.small, 64))) return rc;
     unsigned long long *used = (unsigned long long *)dc.small.p;
     hipError_t e = launch_fill(c_out, n, 0.0, stream);
@@ -238,7 +237,6 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     a.c_in = c_in; a.c_out = c_out;
     a.wg_kmass = (double *)dc.wgk.p;
     a.n_used = used;
-    a.ring = (double *)dc.ring.p;
     EventPair ev;
     if (st && (e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
     if (st) (void)hipEventRecord(ev.a, stream);
@@ -367,9 +365,10 @@ int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
     std::lock_guard<std::mutex> lk(g_mu);
     DevCache &dc = cache_for_current_device();
     hipStream_t stream = (hipStream_t)o->stream;
-    for (int i = 0; i < n_dom; ++i) {
-        if ((rc = step_one(&d[i], o, c_in[i], c_out[i], st ? &st[i] : nullptr, dc, stream, false, nullptr, nullptr)))
-            return rc;
+    if (n_dom > 1) {
+        if ((rc = step_batched(d, n_dom, o, c_in, c_out, st, dc, stream))) return rc;
+    } else if ((rc = step_one(&d[0], o, c_in[0], c_out[0], st, dc, stream, false, nullptr, nullptr))) {
+        return rc;
     }
     if (st) {
         const double t = now_s() - t0;
@@ -393,9 +392,29 @@ int fdirw_run(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o, int32_t
     std::lock_guard<std::mutex> lk(g_mu);
     DevCache &dc = cache_for_current_device();
     hipStream_t stream = (hipStream_t)o->stream;
-    for (int i = 0; i < n_dom; ++i) {
-        rc = run_one(&d[i], o, n_steps, c[i], scratch[i], st ? &st[i] : nullptr, dc, stream);
+    if (n_dom == 1) {
+        rc = run_one(&d[0], o, n_steps, c[0], scratch[0], st, dc, stream);
         if (rc) return rc;
+    } else {
+        // batched domains: one persistent launch per big step (no kernel bank)
+        std::vector<double *> cur(c, c + n_dom), nxt(scratch, scratch + n_dom);
+        for (int step = 0; step < n_steps; ++step) {
+            fdirw_stats *sst = (st && step == n_steps - 1) ? st : nullptr;
+            rc = step_batched(d, n_dom, o, (const double *const *)cur.data(), nxt.data(), sst, dc, stream);
+            if (rc) return rc;
+            std::swap(cur, nxt);
+        }
+        for (int i = 0; i < n_dom; ++i) {
+            if (cur[i] != c[i]) {
+                const size_t bytes = (size_t)d[i].nx * d[i].ny * d[i].nz * sizeof(double);
+                hipError_t e = hipMemcpyAsync(c[i], cur[i], bytes, hipMemcpyDeviceToDevice, stream);
+                if (e != hipSuccess) return hip_fail(e, "result copy");
+            }
+        }
+        if (st) {
+            hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "run");
+        }
     }
     if (st) {
         const double t = now_s() - t0;

@@ -92,14 +92,14 @@ constexpr int ru(int a, int b) { return (a + b - 1) / b * b; }
 // dense array head[seg][col]; the single-cell accesses of a wave are then
 // lane-contiguous and free of bank conflicts.  With one segment the whole
 // column is in main[].
-template <int M, int R> struct Geo {
+template <int M, int R, int SC = FDIRW_SEG_CELLS> struct Geo {
     using T = Traits<M>;
     using S = typename T::S;
     using E = typename T::E;
     static constexpr int W = 2 * R + 1;
     static constexpr int W2 = W * W;
     static constexpr int W3 = W2 * W;
-    static constexpr int NSEG = (W + FDIRW_SEG_CELLS - 1) / FDIRW_SEG_CELLS;  // segments per column
+    static constexpr int NSEG = (W + SC - 1) / SC;          // segments per column
     static constexpr int L0 = (W + NSEG - 1) / NSEG;        // cells per thread
     static constexpr int LAST = W - (NSEG - 1) * L0;        // real cells of the last segment
     static constexpr int MAIN = NSEG > 1 ? L0 - 1 : W;      // cells per segment in main[]
@@ -114,24 +114,25 @@ template <int M, int R> struct Geo {
     static constexpr int XLEN = ru(HEAD + NSEG * NCOL, CH); // elements of one exchange buffer
     static constexpr int NT = ru(NSEG * W2, 64);            // threads per workgroup
     static constexpr int NWAVE = NT / 64;
-    // register budget hint (minimum waves per SIMD): for the 10-wave r = 8
-    // workgroup a 128-VGPR budget (4 waves / SIMD, one workgroup per CU with
-    // more LDS loads in flight) measured faster than 96 VGPRs (two
-    // workgroups per CU with serialised loads)
+    // register budget hint (minimum waves per SIMD): one workgroup per CU
+    // (the exchange buffers and the FP64 ring of an r = 8 window take ~100 KB
+    // of LDS) needs ceil(NWAVE / 4) waves per SIMD; more registers per thread
+    // keep more LDS loads in flight (measured: 128 VGPRs beat 96 VGPRs with
+    // two workgroups per CU)
 #ifdef FDIRW_MINW
     static constexpr int MINW = FDIRW_MINW;
 #else
-    static constexpr int MINW = (NWAVE + 2) / 3 < 1 ? 1 : ((NWAVE + 2) / 3 > 8 ? 8 : (NWAVE + 2) / 3);
+    static constexpr int MINW = (NWAVE + 3) / 4 < 1 ? 1 : ((NWAVE + 3) / 4 > 8 ? 8 : (NWAVE + 3) / 4);
 #endif
     static_assert(LAST >= 1 && LAST <= L0, "segment split");
 };
 
 // Per-thread kernel values of one segment.
-template <int M, int R> using SegVals = typename Geo<M, R>::S[Geo<M, R>::L0];
+template <int M, int R, int SC = FDIRW_SEG_CELLS> using SegVals = typename Geo<M, R, SC>::S[Geo<M, R, SC>::L0];
 
 // Per-thread state of one segment.
-template <int M, int R> struct Seg {
-    using G_ = Geo<M, R>;
+template <int M, int R, int SC = FDIRW_SEG_CELLS> struct Seg {
+    using G_ = Geo<M, R, SC>;
     using S = typename G_::S;
     static constexpr int L = G_::L0;
     S xm[L], xp[L], ym[L], yp[L];
@@ -150,10 +151,10 @@ struct Place {
     int len;      // real cells in the segment
 };
 
-template <int M, int R>
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
 __device__ __forceinline__ Place make_place(int t)
 {
-    using G_ = Geo<M, R>;
+    using G_ = Geo<M, R, SC>;
     Place p;
     p.t = t;
     p.act = t < G_::NSEG * G_::W2;
@@ -170,13 +171,13 @@ __device__ __forceinline__ Place make_place(int t)
 // (sx, sy, sz) from the owned-face arrays lx / ly / lz ([nz][ny][nx] each).
 // Faces leaving the window or the domain, and every face of a cell outside
 // the domain or past the segment's real cells, are 0.
-template <int M, int R>
-__device__ __forceinline__ void load_segment(Seg<M, R> &c, const typename Geo<M, R>::S *__restrict__ lx,
-                                             const typename Geo<M, R>::S *__restrict__ ly,
-                                             const typename Geo<M, R>::S *__restrict__ lz,
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ void load_segment(Seg<M, R, SC> &c, const typename Geo<M, R, SC>::S *__restrict__ lx,
+                                             const typename Geo<M, R, SC>::S *__restrict__ ly,
+                                             const typename Geo<M, R, SC>::S *__restrict__ lz,
                                              int nx, int ny, int nz, int sx, int sy, int sz, const Place &p)
 {
-    using G_ = Geo<M, R>;
+    using G_ = Geo<M, R, SC>;
     using S = typename G_::S;
     constexpr int L = G_::L0, W = G_::W;
     const int X = sx - R + p.cx, Y = sy - R + p.cy;
@@ -207,12 +208,12 @@ __device__ __forceinline__ void load_segment(Seg<M, R> &c, const typename Geo<M,
     }
 }
 
-template <bool X32, int M, int R>
-__device__ __forceinline__ void compute_diag(Seg<M, R> &c)
+template <bool X32, int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ void compute_diag(Seg<M, R, SC> &c)
 {
-    using S = typename Geo<M, R>::S;
+    using S = typename Geo<M, R, SC>::S;
 #pragma unroll
-    for (int k = 0; k < Geo<M, R>::L0; ++k) {
+    for (int k = 0; k < Geo<M, R, SC>::L0; ++k) {
         S s = c.xm[k] + c.xp[k];
         s = s + c.ym[k];
         s = s + c.yp[k];
@@ -227,12 +228,12 @@ template <> __device__ __forceinline__ float fmaT<float>(float a, float b, float
 template <> __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // One explicit sub-step of one window, exchanging through buffer buf.
-template <int M, int R>
-__device__ __forceinline__ void one_substep(SegVals<M, R> &G, const Seg<M, R> &c,
-                                            typename Geo<M, R>::E *__restrict__ buf, const Place &p,
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ void one_substep(SegVals<M, R, SC> &G, const Seg<M, R, SC> &c,
+                                            typename Geo<M, R, SC>::E *__restrict__ buf, const Place &p,
                                             int own, int tail_at, int head_at, int zlo_at, int zhi_at)
 {
-    using G_ = Geo<M, R>;
+    using G_ = Geo<M, R, SC>;
     using T = typename G_::T;
     using S = typename G_::S;
     using E = typename G_::E;
@@ -296,11 +297,11 @@ __device__ __forceinline__ void one_substep(SegVals<M, R> &G, const Seg<M, R> &c
 // xb: two exchange buffers of XLEN elements, 16-byte aligned, padding zeroed;
 // sub-steps alternate between them (one barrier per sub-step), unrolled by
 // two so that buffer addresses are fixed offsets.
-template <int M, int R>
-__device__ __forceinline__ void run_substeps(SegVals<M, R> &G, const Seg<M, R> &c,
-                                             typename Geo<M, R>::E *__restrict__ xb, const Place &p, int n_sub)
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ void run_substeps(SegVals<M, R, SC> &G, const Seg<M, R, SC> &c,
+                                             typename Geo<M, R, SC>::E *__restrict__ xb, const Place &p, int n_sub)
 {
-    using G_ = Geo<M, R>;
+    using G_ = Geo<M, R, SC>;
     constexpr int NCOL = G_::NCOL;
     const int col = G_::PADC + p.col;
     const int own = col * G_::ZS + p.seg * G_::SOFF;
@@ -314,10 +315,10 @@ __device__ __forceinline__ void run_substeps(SegVals<M, R> &G, const Seg<M, R> &
     typename G_::E *xb1 = xb + G_::XLEN;
     int step = 0;
     for (; step + 1 < n_sub; step += 2) {
-        one_substep<M, R>(G, c, xb, p, own, tail_at, head_at, zlo_at, zhi_at);
-        one_substep<M, R>(G, c, xb1, p, own, tail_at, head_at, zlo_at, zhi_at);
+        one_substep<M, R, SC>(G, c, xb, p, own, tail_at, head_at, zlo_at, zhi_at);
+        one_substep<M, R, SC>(G, c, xb1, p, own, tail_at, head_at, zlo_at, zhi_at);
     }
-    if (step < n_sub) one_substep<M, R>(G, c, xb, p, own, tail_at, head_at, zlo_at, zhi_at);
+    if (step < n_sub) one_substep<M, R, SC>(G, c, xb, p, own, tail_at, head_at, zlo_at, zhi_at);
 }
 
 // Block-wide FP64 sum of one value per thread (fixed order: xor butterfly in
@@ -338,13 +339,12 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 }
 
 // After the sub-steps: in BANK modes round the kernel to its storage type;
-// return the FP64 kernel mass (sum over the whole window).
-template <int M, int R>
-__device__ __forceinline__ double finish_kernel(SegVals<M, R> &G, double *red,
-                                                const Place &p)
+// return this thread's FP64 share of the kernel mass.
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ double kernel_partial_mass(SegVals<M, R, SC> &G, const Place &p)
 {
-    using T = typename Geo<M, R>::T;
-    constexpr int L = Geo<M, R>::L0;
+    using T = typename Geo<M, R, SC>::T;
+    constexpr int L = Geo<M, R, SC>::L0;
     if constexpr (T::bank) {
 #pragma unroll
         for (int k = 0; k < L; ++k) G[k] = round_to<typename T::B>(G[k]);
@@ -354,16 +354,23 @@ __device__ __forceinline__ double finish_kernel(SegVals<M, R> &G, double *red,
 #pragma unroll
         for (int k = 0; k < L; ++k) s += (double)G[k];
     }
-    return block_sum<Geo<M, R>::NWAVE>(s, red);
+    return s;
+}
+
+// Kernel mass over a workgroup that holds one window.
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ double finish_kernel(SegVals<M, R, SC> &G, double *red, const Place &p)
+{
+    return block_sum<Geo<M, R, SC>::NWAVE>(kernel_partial_mass<M, R, SC>(G, p), red);
 }
 
 // Unit source at the window centre.
-template <int M, int R>
-__device__ __forceinline__ void init_delta(SegVals<M, R> &G, const Place &p)
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ void init_delta(SegVals<M, R, SC> &G, const Place &p)
 {
-    using S = typename Geo<M, R>::S;
+    using S = typename Geo<M, R, SC>::S;
 #pragma unroll
-    for (int k = 0; k < Geo<M, R>::L0; ++k)
+    for (int k = 0; k < Geo<M, R, SC>::L0; ++k)
         G[k] = (p.act && p.cx == R && p.cy == R && p.j0 + k == R) ? S(1) : S(0);
 }
 

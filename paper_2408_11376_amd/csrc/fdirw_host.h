@@ -20,7 +20,8 @@ struct Buf {
 // partials, per-workgroup kernel masses, a few counters, and the kernel bank.
 struct DevCache {
     int dev = -1;
-    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass, ring;
+    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass;
+    Buf blam, bsmall, bdoms, bitems;      // batched launch
 };
 
 // Two HIP events around one launch; destroyed with the object.
@@ -67,6 +68,9 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
              fdirw_stats *st, DevCache &dc, hipStream_t stream, bool prepared, const void *lam, Geometry *geo);
 int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, double *scratch,
             fdirw_stats *st, DevCache &dc, hipStream_t stream);
+int step_batched(const fdirw_domain *d, int n_dom, const fdirw_opts *o, const double *const *c_in,
+                 double *const *c_out, fdirw_stats *st, DevCache &dc, hipStream_t stream);
+int batch_config_count();
 
 // Bytes per stored kernel value of a precision mode in the bank.
 inline size_t bank_elem_bytes(int prec)

@@ -237,12 +237,11 @@ window_kernel(WindowArgs a)
 // ----------------------------------------------------------------- (a5) fused
 
 // One workgroup walks the sources (sx, sy, z0..z1-1).  c(s) * G_s is
-// accumulated in FP64 into a ring of W planes x W^2 columns that belongs to
-// the workgroup (global scratch, L2-resident, touched once per source), indexed
-// by global plane z mod W.  After source sz the plane z = sz - R can receive
-// nothing more from this line: it is added to c_out with one atomic per
-// window column and cleared.  Keeping the ring out of registers leaves the
-// register file to the sub-step loop.
+// accumulated in FP64 into an LDS ring of W planes x W^2 columns indexed by
+// global plane z mod W (touched once per source, so it costs no sub-step
+// bandwidth and keeps the register file for the sub-step loop).  After source
+// sz the plane z = sz - R can receive nothing more from this line: it is added
+// to c_out with one atomic per window column and cleared.
 template <int M, int R>
 __global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
 line_kernel(LineArgs a)
@@ -254,12 +253,12 @@ line_kernel(LineArgs a)
     constexpr int L = G_::L0, W = G_::W, W2 = G_::W2;
     __shared__ __align__(16) E xb[2 * G_::XLEN];
     __shared__ double red[G_::NWAVE];
+    __shared__ double ring[W * W2];
 
     const Place p = make_place<M, R>(threadIdx.x);
     zero_exchange<M, R>(xb);
 
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    double *ring = a.ring + (int64_t)blockIdx.x * (W * W2);
     for (int i = threadIdx.x; i < W * W2; i += blockDim.x) ring[i] = 0.0;
     __syncthreads();
 

@@ -21,7 +21,6 @@ struct LineArgs {
     double *c_out;
     double *wg_kmass;         // [n_blocks][2] min / max kernel mass, or null
     unsigned long long *n_used;
-    double *ring;             // [n_blocks][W][W*W] FP64 accumulation scratch
 };
 
 struct WindowArgs {
@@ -47,6 +46,34 @@ struct BankArgs {
     const double *c_in;
     double *c_out;
 };
+
+// Batched persistent launch (fdirw_batched.hip).
+struct BatchDom {
+    int nx, ny, nz, r, n_sub;
+    int64_t n;
+    const void *lam;          // [3][n] coefficients of the stencil precision
+    const double *c_in;
+    double *c_out;
+    unsigned long long *n_used;
+};
+
+struct BatchItem {
+    int dom;                  // domain index
+    int line0, nlines;        // source lines (y * nx + x) line0 .. line0 + nlines - 1
+    int z0, z1;               // source planes z0 .. z1 - 1
+};
+
+struct BatchArgs {
+    const BatchDom *doms;
+    const BatchItem *items;
+    int n_items;
+    unsigned *head;           // work counter, 0 at launch
+    double *item_kmass;       // [n_items][2] kernel-mass range, or null
+};
+
+hipError_t launch_batched(int mode, const BatchArgs &a, int grid, hipStream_t st);
+hipError_t batched_occupancy(int mode, int *blocks);
+int batch_windows_per_group(int r);
 
 hipError_t launch_validate(const uint8_t *label, int64_t n, int n_phase, unsigned *out, hipStream_t st);
 hipError_t launch_coef(const uint8_t *label, int nx, int ny, int nz, const CoefTable &tab,

@@ -1,0 +1,105 @@
+"""GPU parity of the batched persistent launch (many uneven domains, one
+launch) against the CPU oracle and against single-domain launches."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import rel_l1, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2408_11376_amd as fd  # noqa: E402
+
+
+def _dev(d):
+    return fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
+
+
+def _mixed_domains(seed=0):
+    specs = [((7, 9, 11), 1, 7), ((12, 10, 9), 2, 15), ((9, 13, 8), 3, 30), ((11, 12, 14), 4, 25),
+             ((6, 15, 13), 5, 20), ((14, 11, 12), 6, 40), ((16, 9, 10), 7, 12), ((18, 17, 19), 8, 30),
+             ((5, 4, 3), 0, 9), ((1, 20, 6), 4, 11)]
+    return [synth.random_small(s, 3, r=r, n_sub=n, seed=seed + i) for i, (s, r, n) in enumerate(specs)]
+
+
+@pytest.mark.parametrize("prec,tol", [(fd.FP64, 1e-12), (fd.FP32, 1e-5)])
+def test_batched_matches_oracle_every_radius(prec, tol):
+    ds = _mixed_domains(100)
+    outs, sts = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=prec, stats=True, tune=3)
+    for d, o, st in zip(ds, outs, sts):
+        ref, used, _ = oracle.Problem.from_domain(d).step(d.c0)
+        assert np.max(np.abs(to_host(o) - ref)) <= tol, (d.shape, d.r)
+        assert st["n_sources"] == used
+        assert abs(st["mass_out"] - st["mass_in"]) <= 1e-9 * st["mass_in"]
+
+
+@pytest.mark.parametrize("tune", list(range(6)))
+def test_batched_shapes_agree(tune):
+    ds = _mixed_domains(200)[3:8]
+    base = [to_host(fd.fdirw_step(_dev(d), to_dev(d.c0), prec=fd.FP32)) for d in ds]
+    outs = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=fd.FP32, tune=tune)
+    for b, o in zip(base, outs):
+        assert np.max(np.abs(to_host(o) - b)) <= 1e-12 * np.abs(b).max()
+
+
+def test_batched_reduced_precision_and_zero_sources():
+    ds = _mixed_domains(300)[4:9]
+    c0 = []
+    for i, d in enumerate(ds):
+        c = d.c0.copy()
+        if i % 2 == 0:
+            c.reshape(-1)[::3] = 0.0          # skipped sources inside a batch
+        c0.append(c)
+    outs, sts = fd.fdirw_step([_dev(d) for d in ds], [to_dev(c) for c in c0], prec=fd.FP16X32, stats=True)
+    for d, c, o, st in zip(ds, c0, outs, sts):
+        ref, used, _ = oracle.Problem.from_domain(d).step(c)
+        assert rel_l1(to_host(o), ref) <= 1e-3
+        assert st["n_sources"] == used
+        assert 0 <= st["tuned_config_id"] < 6
+        assert abs(st["mass_out"] - st["mass_in"]) <= 1e-6 * st["mass_in"]
+
+
+def test_autotuner_choice_gives_the_same_field():
+    # the cache file is read once per process; the call must succeed and the
+    # chosen shape must give the same field as a fixed shape
+    ds = _mixed_domains(400)[5:8]
+    outs, sts = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=fd.FP32, stats=True, tune=-1)
+    fixed = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=fd.FP32, tune=0)
+    for o, f in zip(outs, fixed):
+        assert np.max(np.abs(to_host(o) - to_host(f))) <= 1e-12 * to_host(f).max()
+    assert all(0 < s["tuned_config_id"] < 6 for s in sts)
+
+
+def test_batched_run_multiple_steps():
+    ds = _mixed_domains(500)[2:6]
+    cs = [to_dev(d.c0) for d in ds]
+    fd.fdirw_run([_dev(d) for d in ds], cs, 3, prec=fd.FP64)
+    for d, c in zip(ds, cs):
+        p = oracle.Problem.from_domain(d)
+        ref = d.c0
+        for _ in range(3):
+            ref, _, _ = p.step(ref)
+        assert np.max(np.abs(to_host(c) - ref)) <= 1e-12
+
+
+@pytest.mark.slow
+def test_config3_batched_equals_single_launches():
+    """The 64-domain workload (edges 32..128, r in {4, 6, 8}, contrast
+    1e2..1e6) in one launch against per-domain launches, FP32."""
+    ds = synth.config3()
+    doms = [_dev(d) for d in ds]
+    cins = [to_dev(d.c0) for d in ds]
+    outs, sts = fd.fdirw_step(doms, cins, prec=fd.FP32, stats=True)
+    for i in (0, 17, 40, 63):
+        single = fd.fdirw_step(doms[i], cins[i], prec=fd.FP32)
+        a, b = to_host(outs[i]), to_host(single)
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.abs(b).max()
+    for st in sts:
+        assert abs(st["mass_out"] - st["mass_in"]) <= 1e-9 * st["mass_in"]
