@@ -56,11 +56,11 @@ def window_cells(shape, r):
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the fused line kernel."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_11376_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("fdirw_device.h", "fdirw_kernels.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

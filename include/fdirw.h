@@ -89,7 +89,7 @@ typedef enum fdirw_prec {
 
 typedef enum fdirw_gen {
     FDIRW_GEN_FD = 0,          /* explicit finite-difference window kernels */
-    FDIRW_GEN_NN = 1           /* learned surrogate (not in this build: E_UNSUPPORTED) */
+    FDIRW_GEN_NN = 1           /* learned surrogate (fdirw_nn_*), audited against FD */
 } fdirw_gen;
 
 /* One domain (a phase map and the parameters of one big step). */
@@ -107,9 +107,9 @@ typedef struct fdirw_domain {
 typedef struct fdirw_opts {
     int32_t prec;              /* fdirw_prec */
     int32_t gen;               /* fdirw_gen */
-    const void *nn;            /* surrogate handle (unused with GEN_FD) */
-    double audit_tol;          /* surrogate audit tolerance (unused with GEN_FD) */
-    int32_t audit_samples;     /* surrogate audit size (unused with GEN_FD) */
+    const void *nn;            /* surrogate handle from fdirw_nn_create (GEN_NN) */
+    double audit_tol;          /* GEN_NN: largest mean per-kernel L1 error accepted; <= 0: 1e-3 */
+    int32_t audit_samples;     /* GEN_NN: sources audited per step; <= 0: 1024 */
     int32_t deterministic;     /* must be 0 in this build (FP64 atomics reorder sums) */
     size_t bank_budget_bytes;  /* fdirw_run: store every kernel once if the bank fits; 0 = never */
     void *stream;              /* hipStream_t, NULL = default stream */
@@ -136,7 +136,7 @@ typedef struct fdirw_stats {
                                   from HIP events recorded around its launch */
 } fdirw_stats;
 
-/* Row (a1): coefficients.  Writes lam[0*N + i], lam[1*N + i], lam[2*N + i] =
+/* Coefficients.  Writes lam[0*N + i], lam[1*N + i], lam[2*N + i] =
  * the FP64 coefficient of the face from cell i to its +x, +y, +z neighbour
  * (0 on the last plane of that axis and for faces touching an impermeable
  * cell), and *dt_out (host, may be NULL) = the sub-step used.  lam: 3N doubles.
@@ -144,7 +144,7 @@ typedef struct fdirw_stats {
  * E_UNSTABLE. */
 int fdirw_coefficients(const fdirw_domain *d, void *stream, double *lam, double *dt_out);
 
-/* Rows (a2)-(a4): the window kernels of n_src sources (Sec. 3.1: column s of P
+/* The window kernels of n_src sources (Sec. 3.1: column s of P
  * is the response to a unit point source at s).  src: n_src int64 linear
  * indices, each in [0, N).  G: [n_src][W][W][W] ordered z, y, x relative to
  * s - r, doubles for FDIRW_FP64 and floats otherwise; cells outside the domain
@@ -157,15 +157,22 @@ int fdirw_coefficients(const fdirw_domain *d, void *stream, double *lam, double 
 int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src, int64_t n_src,
                   void *G, double *mass);
 
-/* Rows (a1)-(a7): one big step of the superposition (Eq. 8, column form):
+/* One big step of the superposition (Eq. 8, column form):
  * c_out[i][x] = sum over s of c_in[i][s] * G_s(x) for each domain i.  d, c_in,
  * c_out and st are (host) arrays of n_dom entries; c_in[i] and c_out[i] point
  * to N_i doubles and must not overlap (E_ARG).  st may be NULL.  n_dom > 1
- * runs all domains in one persistent launch. */
+ * runs all domains in one persistent launch.
+ * With gen = GEN_NN (n_dom must be 1, else E_UNSUPPORTED; r and n_sub must
+ * match the surrogate, else E_ARG) the kernels come from the surrogate o->nn:
+ * first audit_samples seeded sources are generated both ways (surrogate and
+ * FP32 FD) and the mean of sum |G_nn - G_fd| over them is compared with
+ * audit_tol; above it the step falls back to the FD step in precision o->prec
+ * (st->fallback_used = 1); else every kernel is the surrogate's, superposed
+ * as G / sum(G) in FP64.  st->audit_l1 holds the audit mean in both cases. */
 int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
                const double *const *c_in, double *const *c_out, fdirw_stats *st);
 
-/* Rows (a1)-(a7), (a10), (a11): n_steps big steps (the time marching of
+/* n_steps big steps (the time marching of
  * Eq. 8).  c[i] holds the initial field and receives the final one;
  * scratch[i] is a second buffer of N_i doubles (its content is overwritten).
  * With n_dom == 1 and bank_budget_bytes allowing, every kernel is generated
@@ -176,9 +183,75 @@ int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
 int fdirw_run(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o, int32_t n_steps,
               double *const *c, double *const *scratch, fdirw_stats *st);
 
-/* Row (a6): compensated (Neumaier per thread, two-sum tree) FP64 sum of n
+/* Compensated (Neumaier per thread, two-sum tree) FP64 sum of n
  * doubles, in a fixed order for a given n.  *sum_out is host memory. */
 int fdirw_field_sum(const double *c, int64_t n, void *stream, double *sum_out);
+
+/* ------------------------------------------------------------------ surrogate
+ * A learned generator of window kernels (an extension: the
+ * paper obtains every column of P by FD from a point source, Sec. 3.1).  For a
+ * source s with window radius FDIRW_NN_RADIUS (W = 17) the network reads three
+ * features per window cell (permeable-and-in-domain flag; (max(log10 D, -12)
+ * + 6) / 6 inside the domain, -1 outside; the prior log U / 20, U the FD kernel
+ * of an all-permeable window with lambda = 0.15 on every face), applies five
+ * 3x3x3 convolutions with zero padding (3 -> 16 -> 16 -> 16 -> 16 -> 1
+ * channels, SiLU after the first four; BF16 operands on MFMA, FP32
+ * accumulation) and returns G = softmax over the structural support (cells
+ * reached from s in at most n_sub crossings of faces whose two cells are in
+ * the domain with D > 0) of log U + network output; G is 0 elsewhere.
+ * Parameters: one flat FP32 vector of fdirw_nn_num_params() values, per layer
+ * w[co][ci][3][3][3] (taps z, y, x) then b[co].
+ * A handle belongs to the device current at creation; every call must be made
+ * with that device current (E_ARG otherwise).  Handles are not thread-safe
+ * against each other's use of the same handle. */
+#define FDIRW_NN_RADIUS 8
+
+/* Number of parameters (22,529). */
+int64_t fdirw_nn_num_params(void);
+
+/* Creates a surrogate for windows of FDIRW_NN_RADIUS and n_sub sub-steps
+ * (the prior and the support depth depend on n_sub).  Parameters start from
+ * a deterministic He-normal draw of `seed` (last layer scaled by 0.1, zero
+ * biases); Adam moments start at 0.  *nn receives the handle.
+ * Errors: E_ARG, E_NOMEM, E_DEVICE. */
+int fdirw_nn_create(int32_t n_sub, uint64_t seed, void **nn);
+
+/* Frees the handle and its device memory (NULL is accepted). */
+int fdirw_nn_destroy(void *nn);
+
+/* Copies the parameters in / out; theta is (host) memory of
+ * fdirw_nn_num_params() floats.  Setting resets nothing else. */
+int fdirw_nn_set_params(void *nn, const float *theta);
+int fdirw_nn_get_params(const void *nn, float *theta);
+
+/* Surrogate kernels of n_src sources of domain d (d->r must be
+ * FDIRW_NN_RADIUS and d->n_sub the handle's).  src: n_src int64 linear
+ * indices in [0, N).  Outputs (each may be NULL), [n_src][W][W][W] in z, y, x
+ * order relative to s - r: G (float, unit mass up to FP32 rounding),
+ * support (uint8 0 / 1), logits (float, log U + network output, every cell).
+ * Errors: E_ARG (also: a source or label out of range), E_UNSTABLE. */
+int fdirw_nn_forward(void *nn, const fdirw_domain *d, const int64_t *src, int64_t n_src, float *G,
+                     uint8_t *support, float *logits, void *stream);
+
+/* Loss and gradient over n_src >= 1 windows: loss = mean over windows of
+ * KL(q || G) + sum |q - G| over the support, q = target / sum(target).
+ * target: [n_src][W][W][W] floats, or NULL to use the FP32 FD kernels of the
+ * sources (generated here).  grad (may be NULL): fdirw_nn_num_params() floats
+ * receiving d loss / d parameters; the gradient is also kept in the handle for
+ * fdirw_nn_adam.  loss (host, may be NULL): 2 doubles, the mean KL and the
+ * mean L1 term.  Synchronises the stream.  Errors as fdirw_nn_forward. */
+int fdirw_nn_backward(void *nn, const fdirw_domain *d, const int64_t *src, int64_t n_src, const float *target,
+                      float *grad, double *loss, void *stream);
+
+/* One Adam step (Kingma and Ba 2015, bias-corrected) on the FP32 parameters
+ * with the gradient of the last fdirw_nn_backward.  Errors: E_ARG. */
+int fdirw_nn_adam(void *nn, double lr, double beta1, double beta2, double eps, void *stream);
+
+/* Writes / reads the parameters, Adam moments and step count to / from a
+ * little-endian binary file.  load checks the file's n_sub against the
+ * handle's.  Errors: E_ARG (I/O, format), E_DEVICE. */
+int fdirw_nn_save(const void *nn, const char *path);
+int fdirw_nn_load(void *nn, const char *path);
 
 /* Message describing the last non-OK status returned on this thread. */
 const char *fdirw_last_error(void);

@@ -86,7 +86,7 @@ static double face_lambda(double da, double db, double dt, double h)
     return (df * dt) / (h * h);
 }
 
-/* Row (a1): the three owned face coefficients of every cell. */
+/* Coefficients: the three owned face coefficients of every cell. */
 void fo_coefficients(int nx, int ny, int nz, const uint8_t *label,
                      const double *d_phase, double h, double dt,
                      double *lam_x, double *lam_y, double *lam_z)
@@ -142,7 +142,7 @@ static void window_box(int nx, int ny, int nz, int r, int sx, int sy, int sz, in
     }
 }
 
-/* Row (a2)-(a4) for one source: the W^3 window kernel G_s (placed relative to
+/* Window kernel of one source: the W^3 window kernel G_s (placed relative to
  * s - r, zeros outside the domain) and its mass.  work: 2 * W^3 doubles. */
 static void kernel_one(int nx, int ny, int nz,
                        const double *lam_x, const double *lam_y, const double *lam_z,
@@ -186,7 +186,7 @@ void fo_kernels(int nx, int ny, int nz,
     }
 }
 
-/* Row (a5): c_new(x) = sum over sources s (ascending, c_old(s) != 0) of
+/* Superposition: c_new(x) = sum over sources s (ascending, c_old(s) != 0) of
  * c_old(s) * G_s(x), added in window z, y, x order.  Kernels are generated in
  * parallel in batches and added strictly in ascending source order, so the
  * result does not depend on the thread count.  Optional: kmass_minmax[2] =

@@ -8,7 +8,10 @@ import of a function raises.
 
 Names follow the ABI:
     fdirw_coefficients, fdirw_kernels, fdirw_step, fdirw_run,
-    fdirw_field_sum, fdirw_last_error, fdirw_release, fdirw_abi_version
+    fdirw_field_sum, fdirw_last_error, fdirw_release, fdirw_abi_version,
+    fdirw_nn_create, fdirw_nn_destroy, fdirw_nn_num_params,
+    fdirw_nn_set_params, fdirw_nn_get_params, fdirw_nn_forward,
+    fdirw_nn_backward, fdirw_nn_adam, fdirw_nn_save, fdirw_nn_load
 """
 from __future__ import annotations
 
@@ -76,7 +79,11 @@ class fdirw_stats(ctypes.Structure):
 
 
 ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run",
-                 "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version")
+                 "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version",
+                 "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
+                 "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
+                 "fdirw_nn_save", "fdirw_nn_load")
+NN_RADIUS = 8
 
 _lib = None
 
@@ -104,8 +111,21 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_last_error.restype = ctypes.c_char_p
     lib.fdirw_release.argtypes = []
     lib.fdirw_abi_version.argtypes = []
+    lib.fdirw_nn_num_params.argtypes = []
+    lib.fdirw_nn_num_params.restype = ctypes.c_int64
+    lib.fdirw_nn_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, PP]
+    lib.fdirw_nn_destroy.argtypes = [P]
+    lib.fdirw_nn_set_params.argtypes = [P, P]
+    lib.fdirw_nn_get_params.argtypes = [P, P]
+    lib.fdirw_nn_forward.argtypes = [P, D, P, ctypes.c_int64, P, P, P, P]
+    lib.fdirw_nn_backward.argtypes = [P, D, P, ctypes.c_int64, P, P, ctypes.POINTER(ctypes.c_double), P]
+    lib.fdirw_nn_adam.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+    lib.fdirw_nn_save.argtypes = [P, ctypes.c_char_p]
+    lib.fdirw_nn_load.argtypes = [P, ctypes.c_char_p]
     for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run", "fdirw_field_sum",
-              "fdirw_release", "fdirw_abi_version"):
+              "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
+              "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
+              "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -184,15 +204,16 @@ class Domain:
 
 
 def make_opts(prec=FP32, stream=None, bank_budget_bytes: int = 0, tune: int = -1,
-              deterministic: int = 0, gen: int = GEN_FD) -> fdirw_opts:
+              deterministic: int = 0, gen: int = GEN_FD, nn=None, audit_tol: float = 1e-3,
+              audit_samples: int = 1024) -> fdirw_opts:
     if isinstance(prec, str):
         prec = PREC_NAMES[prec.lower()]
     o = fdirw_opts()
     o.prec = int(prec)
     o.gen = int(gen)
-    o.nn = None
-    o.audit_tol = 1e-3
-    o.audit_samples = 1024
+    o.nn = nn.handle if isinstance(nn, Surrogate) else nn
+    o.audit_tol = float(audit_tol)
+    o.audit_samples = int(audit_samples)
     o.deterministic = int(deterministic)
     o.bank_budget_bytes = int(bank_budget_bytes)
     o.stream = _stream_ptr(stream)
@@ -261,9 +282,11 @@ def _ptr_array(ts):
     return arr
 
 
-def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = False, tune: int = -1):
+def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = False, tune: int = -1,
+               nn=None, audit_tol: float = 1e-3, audit_samples: int = 1024):
     """One big step for one domain or a list of domains.  Returns c_out (and
-    a list of stats dicts if ``stats``)."""
+    a list of stats dicts if ``stats``).  ``nn``: a Surrogate to generate the
+    kernels with (GEN_NN, audited against FD)."""
     torch = _torch()
     single = isinstance(doms, Domain)
     doms = [doms] if single else list(doms)
@@ -277,7 +300,8 @@ def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = Fal
         _dev_tensor(b, torch.float64, f"c_out[{i}]")
         if a.numel() != d.n or b.numel() != d.n:
             raise ValueError(f"field {i} does not match its domain")
-    o = make_opts(prec, stream, tune=tune)
+    o = make_opts(prec, stream, tune=tune, gen=GEN_NN if nn is not None else GEN_FD, nn=nn,
+                  audit_tol=audit_tol, audit_samples=audit_samples)
     nd = len(doms)
     ds = (fdirw_domain * nd)(*[d.c_struct() for d in doms])
     st = (fdirw_stats * nd)() if stats else None
@@ -326,3 +350,137 @@ def fdirw_field_sum(c, stream=None) -> float:
     _check(load_library().fdirw_field_sum(ctypes.c_void_p(c.data_ptr()), c.numel(), _stream_ptr(stream),
                                           ctypes.byref(out)))
     return out.value
+
+
+# ----------------------------------------------------------------- surrogate
+
+def fdirw_nn_num_params() -> int:
+    return int(load_library().fdirw_nn_num_params())
+
+
+class Surrogate:
+    """Handle of the learned window-kernel generator (r = NN_RADIUS) on the
+    current device.  Thin wrapper of the fdirw_nn_* calls."""
+
+    def __init__(self, n_sub: int, seed: int = 0):
+        self.handle = fdirw_nn_create(n_sub, seed)
+        self.n_sub = int(n_sub)
+
+    def close(self):
+        if self.handle is not None:
+            fdirw_nn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        fdirw_nn_set_params(self.handle, theta)
+
+    def get_params(self):
+        return fdirw_nn_get_params(self.handle)
+
+    def forward(self, dom, src, stream=None, G=True, support=False, logits=False):
+        return fdirw_nn_forward(self.handle, dom, src, stream=stream, G=G, support=support, logits=logits)
+
+    def backward(self, dom, src, target=None, stream=None, grad=False):
+        return fdirw_nn_backward(self.handle, dom, src, target=target, stream=stream, grad=grad)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        fdirw_nn_adam(self.handle, lr, beta1, beta2, eps, stream=stream)
+
+    def save(self, path):
+        fdirw_nn_save(self.handle, path)
+
+    def load(self, path):
+        fdirw_nn_load(self.handle, path)
+
+
+def fdirw_nn_create(n_sub: int, seed: int = 0):
+    h = ctypes.c_void_p()
+    _check(load_library().fdirw_nn_create(int(n_sub), ctypes.c_uint64(int(seed)), ctypes.byref(h)))
+    return h.value
+
+
+def fdirw_nn_destroy(handle) -> None:
+    _check(load_library().fdirw_nn_destroy(handle))
+
+
+def fdirw_nn_set_params(handle, theta) -> None:
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    if th.size != fdirw_nn_num_params():
+        raise ValueError("theta has the wrong size")
+    _check(load_library().fdirw_nn_set_params(handle, th.ctypes.data_as(ctypes.c_void_p)))
+
+
+def fdirw_nn_get_params(handle) -> np.ndarray:
+    th = np.empty(fdirw_nn_num_params(), dtype=np.float32)
+    _check(load_library().fdirw_nn_get_params(handle, th.ctypes.data_as(ctypes.c_void_p)))
+    return th
+
+
+def _nn_src(dom, src):
+    torch = _torch()
+    if dom.r != NN_RADIUS:
+        raise ValueError(f"the surrogate needs r = {NN_RADIUS}")
+    return _dev_tensor(src, torch.int64, "src")
+
+
+def fdirw_nn_forward(handle, dom: Domain, src, stream=None, G=True, support=False, logits=False):
+    """Surrogate kernels of the sources ``src``.  Returns a dict with the
+    requested [n_src, W, W, W] tensors ``G`` (float32), ``support`` (uint8) and
+    ``logits`` (float32)."""
+    torch = _torch()
+    src = _nn_src(dom, src)
+    n_src = src.numel()
+    W = dom.W
+    out = {}
+    if G:
+        out["G"] = torch.empty((n_src, W, W, W), dtype=torch.float32, device=src.device)
+    if support:
+        out["support"] = torch.empty((n_src, W, W, W), dtype=torch.uint8, device=src.device)
+    if logits:
+        out["logits"] = torch.empty((n_src, W, W, W), dtype=torch.float32, device=src.device)
+    ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None
+    ds = dom.c_struct()
+    _check(load_library().fdirw_nn_forward(handle, ctypes.byref(ds), ctypes.c_void_p(src.data_ptr()), n_src,
+                                           ptr("G"), ptr("support"), ptr("logits"), _stream_ptr(stream)))
+    return out
+
+
+def fdirw_nn_backward(handle, dom: Domain, src, target=None, stream=None, grad=False):
+    """Mean loss (KL, L1) over the windows of ``src`` against ``target``
+    (float32 [n_src, W, W, W] device tensor, or None for FD kernels) and,
+    if ``grad``, the gradient as a float32 device tensor."""
+    torch = _torch()
+    src = _nn_src(dom, src)
+    n_src = src.numel()
+    tp = None
+    if target is not None:
+        _dev_tensor(target, torch.float32, "target")
+        if target.numel() != n_src * dom.W ** 3:
+            raise ValueError("target has the wrong size")
+        tp = ctypes.c_void_p(target.data_ptr())
+    g = torch.empty(fdirw_nn_num_params(), dtype=torch.float32, device=src.device) if grad else None
+    loss = (ctypes.c_double * 2)()
+    ds = dom.c_struct()
+    _check(load_library().fdirw_nn_backward(handle, ctypes.byref(ds), ctypes.c_void_p(src.data_ptr()), n_src, tp,
+                                            ctypes.c_void_p(g.data_ptr()) if g is not None else None, loss,
+                                            _stream_ptr(stream)))
+    return (loss[0], loss[1]), g
+
+
+def fdirw_nn_adam(handle, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> None:
+    _check(load_library().fdirw_nn_adam(handle, float(lr), float(beta1), float(beta2), float(eps),
+                                        _stream_ptr(stream)))
+
+
+def fdirw_nn_save(handle, path: str) -> None:
+    _check(load_library().fdirw_nn_save(handle, os.fsencode(path)))
+
+
+def fdirw_nn_load(handle, path: str) -> None:
+    _check(load_library().fdirw_nn_load(handle, os.fsencode(path)))

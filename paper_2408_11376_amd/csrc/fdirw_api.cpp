@@ -120,7 +120,7 @@ int check_opts(const fdirw_opts *o)
     if (!o) return fail(FDIRW_E_ARG, "opts is null");
     if (o->prec < FDIRW_FP64 || o->prec > FDIRW_BF16_BANK) return fail(FDIRW_E_ARG, "unknown precision %d", o->prec);
     if (o->gen != FDIRW_GEN_FD && o->gen != FDIRW_GEN_NN) return fail(FDIRW_E_ARG, "unknown generator %d", o->gen);
-    if (o->gen == FDIRW_GEN_NN) return fail(FDIRW_E_UNSUPPORTED, "the learned generator is not available in this entry point");
+    if (o->gen == FDIRW_GEN_NN && !o->nn) return fail(FDIRW_E_ARG, "GEN_NN needs a surrogate handle (opts.nn)");
     if (o->deterministic) return fail(FDIRW_E_UNSUPPORTED, "deterministic mode is not implemented");
     return FDIRW_OK;
 }
@@ -307,6 +307,8 @@ int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src
     if (rc) return rc;
     if ((rc = check_opts(o))) return rc;
     if (n_src < 0) return fail(FDIRW_E_ARG, "n_src < 0");
+    if (o->gen == FDIRW_GEN_NN)
+        return fail(FDIRW_E_UNSUPPORTED, "fdirw_kernels generates FD kernels; use fdirw_nn_forward for the surrogate");
     if (n_src == 0) return FDIRW_OK;
     if (!src || !G) return fail(FDIRW_E_ARG, "src and G must not be null");
     std::lock_guard<std::mutex> lk(g_mu);
@@ -365,7 +367,10 @@ int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
     std::lock_guard<std::mutex> lk(g_mu);
     DevCache &dc = cache_for_current_device();
     hipStream_t stream = (hipStream_t)o->stream;
-    if (n_dom > 1) {
+    if (o->gen == FDIRW_GEN_NN) {
+        if (n_dom > 1) return fail(FDIRW_E_UNSUPPORTED, "the surrogate step takes one domain per call");
+        if ((rc = step_nn(&d[0], o, c_in[0], c_out[0], st, dc, stream))) return rc;
+    } else if (n_dom > 1) {
         if ((rc = step_batched(d, n_dom, o, c_in, c_out, st, dc, stream))) return rc;
     } else if ((rc = step_one(&d[0], o, c_in[0], c_out[0], st, dc, stream, false, nullptr, nullptr))) {
         return rc;
@@ -392,7 +397,24 @@ int fdirw_run(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o, int32_t
     std::lock_guard<std::mutex> lk(g_mu);
     DevCache &dc = cache_for_current_device();
     hipStream_t stream = (hipStream_t)o->stream;
-    if (n_dom == 1) {
+    if (o->gen == FDIRW_GEN_NN) {
+        if (n_dom > 1) return fail(FDIRW_E_UNSUPPORTED, "the surrogate step takes one domain per call");
+        const int64_t n = (int64_t)d[0].nx * d[0].ny * d[0].nz;
+        double *cur = c[0], *nxt = scratch[0];
+        for (int step = 0; step < n_steps; ++step) {
+            fdirw_stats *sst = (st && step == n_steps - 1) ? st : nullptr;
+            if ((rc = step_nn(&d[0], o, cur, nxt, sst, dc, stream))) return rc;
+            std::swap(cur, nxt);
+        }
+        if (cur != c[0]) {
+            hipError_t e = hipMemcpyAsync(c[0], cur, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_fail(e, "result copy");
+        }
+        if (st) {
+            hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "run");
+        }
+    } else if (n_dom == 1) {
         rc = run_one(&d[0], o, n_steps, c[0], scratch[0], st, dc, stream);
         if (rc) return rc;
     } else {

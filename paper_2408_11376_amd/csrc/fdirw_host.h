@@ -71,6 +71,8 @@ int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, 
 int step_batched(const fdirw_domain *d, int n_dom, const fdirw_opts *o, const double *const *c_in,
                  double *const *c_out, fdirw_stats *st, DevCache &dc, hipStream_t stream);
 int batch_config_count();
+int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out, fdirw_stats *st,
+            DevCache &dc, hipStream_t stream);
 
 // Bytes per stored kernel value of a precision mode in the bank.
 inline size_t bank_elem_bytes(int prec)

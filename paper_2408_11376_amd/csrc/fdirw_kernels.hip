@@ -1,10 +1,10 @@
 // fdirw_kernels.hip -- HIP kernels of the FDiRW fast-diffusion step (gfx950).
 //
 //   coef_validate_kernel   label range check + presence mask (for Dmax)
-//   coef_kernel            row (a1): FP64 face coefficients (+ FP32 copy)
-//   window_kernel          rows (a2)-(a4): window kernels of a source list
-//   line_kernel            rows (a2)-(a5), (a7): fused generate + superpose
-//   fill / field-sum       row (a6) and output clearing
+//   coef_kernel            FP64 face coefficients (+ FP32 copy)
+//   window_kernel          window kernels of a source list
+//   line_kernel            fused generate + superpose
+//   fill / field-sum       global mass balance and output clearing
 //
 // The superposition (Eq. 8 of arXiv 2408.11376 in its column form) is
 // organised so that a workgroup walks a line of sources along z and
@@ -16,7 +16,7 @@
 
 namespace fdirw {
 
-// ----------------------------------------------------------------- (a1)
+// ----------------------------------------------------------------- coefficients
 
 __global__ void coef_validate_kernel(const uint8_t *__restrict__ label, int64_t n, int n_phase,
                                      unsigned *__restrict__ out /* [8] presence bits, [8] bad flag */)
@@ -95,7 +95,7 @@ __device__ __forceinline__ void two_sum_add(double &s, double &c, double s2, dou
     c = c + c2 + err;
 }
 
-// Row (a6), level 1: each thread a Neumaier sum over a fixed strided subset,
+// Field sum, level 1: each thread a Neumaier sum over a fixed strided subset,
 // then a fixed-shape tree inside the block; out: (sum, carry) per block.
 __global__ void field_sum_partial_kernel(const double *__restrict__ v, int64_t n, double *__restrict__ out)
 {
@@ -134,14 +134,16 @@ __global__ void field_sum_final_kernel(const double *__restrict__ part, int nblk
     out[0] = s + c;
 }
 
-// Min / max of per-block kernel masses.
+// Min / max of kernel masses.  PAIRS: v holds n (min, max) pairs (one per
+// workgroup); otherwise v holds n scalars.
+template <bool PAIRS>
 __global__ void minmax_kernel(const double *__restrict__ v, int64_t n, double *__restrict__ out)
 {
     __shared__ double mn[256], mx[256];
     double a = INFINITY, b = -INFINITY;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        a = fmin(a, v[2 * i]);
-        b = fmax(b, v[2 * i + 1]);
+        a = fmin(a, PAIRS ? v[2 * i] : v[i]);
+        b = fmax(b, PAIRS ? v[2 * i + 1] : v[i]);
     }
     mn[threadIdx.x] = a;
     mx[threadIdx.x] = b;
@@ -183,7 +185,7 @@ __device__ __forceinline__ void zero_exchange(typename Geo<M, R>::E *xb)
     for (int i = threadIdx.x; i < 2 * Geo<M, R>::XLEN; i += blockDim.x) xb[i] = (E)0.0f;
 }
 
-// ----------------------------------------------------------------- (a2)-(a4)
+// ----------------------------------------------------------------- window kernels
 
 template <int M, int R>
 __global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
@@ -234,7 +236,7 @@ window_kernel(WindowArgs a)
     }
 }
 
-// ----------------------------------------------------------------- (a5) fused
+// ----------------------------------------------------------------- fused step
 
 // One workgroup walks the sources (sx, sy, z0..z1-1).  c(s) * G_s is
 // accumulated in FP64 into an LDS ring of W planes x W^2 columns indexed by
@@ -324,7 +326,7 @@ line_kernel(LineArgs a)
     }
 }
 
-// ----------------------------------------------------------------- (a11) bank
+// ----------------------------------------------------------------- kernel bank
 
 template <int R> struct Win {
     static constexpr int W = 2 * R + 1;
@@ -554,7 +556,13 @@ hipError_t launch_field_sum(const double *v, int64_t n, double *part, double *ou
 
 hipError_t launch_minmax(const double *v, int64_t n, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(256), 0, st, v, n, out);
+    hipLaunchKernelGGL(minmax_kernel<true>, dim3(1), dim3(256), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_minmax_scalar(const double *v, int64_t n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(minmax_kernel<false>, dim3(1), dim3(256), 0, st, v, n, out);
     return hipGetLastError();
 }
 

@@ -86,6 +86,79 @@ hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);
 int field_sum_blocks(int64_t n);
 hipError_t launch_field_sum(const double *v, int64_t n, double *part, double *out, hipStream_t st);
 hipError_t launch_minmax(const double *v, int64_t n, double *out, hipStream_t st);
+hipError_t launch_minmax_scalar(const double *v, int64_t n, double *out, hipStream_t st);
 hipError_t launch_src_check(const int64_t *src, int64_t n_src, int64_t n, unsigned *bad, hipStream_t st);
+
+// ----------------------------------------------------------------- surrogate
+// (fdirw_nn.hip).  The network runs on windows of radius NN_R; 16-bit values
+// are BF16 bit patterns held as uint16_t.
+
+#define NN_R 8
+constexpr int NN_W = 2 * NN_R + 1;
+constexpr int NN_V = NN_W * NN_W * NN_W;
+
+struct NnFeatArgs {
+    int nx, ny, nz;
+    int n_sub;
+    const int64_t *src;       // [B] source indices
+    const uint8_t *label;
+    float f1[256];            // log-D feature per phase (-1 for D = 0)
+    uint8_t open[256];        // 1 where the phase has D > 0
+    const float *prior;       // [V] log of the uniform-D window kernel
+    uint16_t *X;              // [B][V][8] features (BF16)
+    uint8_t *support;         // [B][V]
+};
+
+struct NnConvArgs {
+    const uint16_t *in;       // [B][V][CI] BF16 channel-last
+    const uint16_t *wpack;    // packed B operands
+    const float *bias;        // [16] (modes 0, 1)
+    int mode;                 // 0 hidden layer, 1 last layer, 2 input gradient
+    float *zpre;              // mode 0: [B][V][16] pre-activation, or null
+    uint16_t *hout;           // mode 0: [B][V][16] SiLU output (BF16)
+    float *z5;                // mode 1: [B][V]
+    float *dh;                // mode 2: [B][V][16]
+};
+
+struct NnLossArgs {
+    const float *z5;          // [B][V] last-layer output
+    const float *prior;       // [V]
+    const uint8_t *support;   // [B][V]
+    const float *target;      // [B][V] FD kernels (any positive mass), or null
+    float *G;                 // [B][V] softmax kernel, or null
+    double *mass;             // [B] FP64 sum of G as stored, or null
+    float *logits;            // [B][V] prior + z5, or null
+    double *loss;             // [B][2] KL and L1 (with target)
+    uint16_t *dlog8;          // [B][V][8] d loss / d logits in channel 0 (with target)
+    float grad_scale;         // factor on d loss / d logits (1 / batch)
+};
+
+struct NnWgradArgs {
+    const uint16_t *dz;       // [B][V][COP] gradient at the layer output
+    const uint16_t *h;        // [B][V][CI] layer input
+    int co_n, ci_n;           // real channel counts
+    int n_slab;               // B * slabs per window
+    float *part;              // [grid][27][16][16] weight partials
+    float *bpart;             // [grid][16] bias partials
+};
+
+int nn_slabs_per_window();
+hipError_t nn_launch_features(const NnFeatArgs &a, int batch, hipStream_t st);
+hipError_t nn_launch_pack(const float *w, int co_n, int ci_n, int CI, int flip, uint16_t *out, hipStream_t st);
+int nn_pack_chunks(int CI);
+hipError_t nn_launch_conv(int CI, const NnConvArgs &a, int batch, hipStream_t st);
+hipError_t nn_launch_loss(const NnLossArgs &a, int batch, hipStream_t st);
+hipError_t nn_launch_silu_bwd(const float *dh, const float *zpre, uint16_t *dz, int64_t n, hipStream_t st);
+hipError_t nn_launch_wgrad(int CI, int COP, const NnWgradArgs &a, int grid, hipStream_t st);
+hipError_t nn_launch_wgrad_reduce(const float *part, const float *bpart, int grid, int co_n, int ci_n,
+                                  float *gw, float *gb, hipStream_t st);
+hipError_t nn_launch_adam(float *w, float *m, float *v, const float *g, int n, float lr, float b1, float b2,
+                          float eps, float c1, float c2, hipStream_t st);
+hipError_t nn_launch_lines_src(int64_t line0, int nlines, int nx, int ny, int nz, int64_t *src, hipStream_t st);
+hipError_t nn_launch_apply(int nx, int ny, int nz, int64_t line0, int nlines, int seg_len, int n_seg,
+                           const float *G, const double *mass, const double *c_in, double *c_out,
+                           unsigned long long *n_used, hipStream_t st);
+hipError_t nn_launch_l1(const float *a, const float *b, int batch, double *out, hipStream_t st);
+hipError_t nn_launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 
 }  // namespace fdirw

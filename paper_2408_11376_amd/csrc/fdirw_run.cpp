@@ -51,21 +51,13 @@ int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, 
         if (st) {
             if ((rc = ensure(dc.small, 64))) return rc;
             double *mm = (double *)dc.small.p + 4;
-            // bank_mass holds one value per source; minmax reads pairs, so
-            // reduce it as n/2 pairs plus a possible tail
             double h_mm[2] = {INFINITY, -INFINITY};
-            if (n >= 2) {
-                e = launch_minmax((const double *)dc.bank_mass.p, n / 2, mm, stream);
-                if (e == hipSuccess) e = hipMemcpyAsync(h_mm, mm, sizeof h_mm, hipMemcpyDeviceToHost, stream);
-            }
-            double tail = 0.0;
-            if (e == hipSuccess && (n & 1))
-                e = hipMemcpyAsync(&tail, (const double *)dc.bank_mass.p + (n - 1), sizeof tail, hipMemcpyDeviceToHost, stream);
+            e = launch_minmax_scalar((const double *)dc.bank_mass.p, n, mm, stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(h_mm, mm, sizeof h_mm, hipMemcpyDeviceToHost, stream);
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_fail(e, "bank statistics");
-            kmin = std::fmin(h_mm[0], h_mm[1]);
-            kmax = std::fmax(h_mm[0], h_mm[1]);
-            if (n & 1) { kmin = std::fmin(kmin, tail); kmax = std::fmax(kmax, tail); }
+            kmin = h_mm[0];
+            kmax = h_mm[1];
         }
     }
     double *cur = c, *nxt = scratch;

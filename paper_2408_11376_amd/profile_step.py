@@ -1,11 +1,13 @@
 """One fused FDiRW step on a seeded porous grid, for profiler runs.
 
-    python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024]
+    python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024] [--gen nn]
 
 Runs one untimed warm-up step, then ``--reps`` steps of the config-2 style
 workload (GRF porous grid, r = 8, 200 sub-steps) at edge ``--n``.  With
 ``--copy-mib`` it also runs one plain device-to-device copy of that many MiB,
 the reference for scaling HBM byte counters (FETCH_SIZE / WRITE_SIZE).
+With ``--gen nn`` the steps use a surrogate (default initialisation, audit
+disabled, so every kernel is the network's) instead of the FD kernels.
 """
 import argparse
 import os
@@ -24,6 +26,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--tune", type=int, default=-1)
+    ap.add_argument("--gen", default="fd", choices=["fd", "nn"])
     args = ap.parse_args()
     import torch
     import synth
@@ -32,13 +35,16 @@ def main():
     dom = fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
     c = torch.from_numpy(d.c0).cuda()
     out = torch.empty_like(c)
+    kw = {}
+    if args.gen == "nn":
+        kw = {"nn": fd.Surrogate(d.n_sub, seed=0), "audit_tol": 1e30, "audit_samples": 1}
     for _ in range(args.warmup):
-        fd.fdirw_step(dom, c, out, prec=args.prec, tune=args.tune)
+        fd.fdirw_step(dom, c, out, prec=args.prec, tune=args.tune, **kw)
     torch.cuda.synchronize()
     for i in range(args.reps):
-        _, st = fd.fdirw_step(dom, c, out, prec=args.prec, stats=True, tune=args.tune)
-        print(f"[profile_step] n={args.n} prec={args.prec} rep {i}: kernel {st['kernel_seconds'] * 1e3:.2f} ms",
-              flush=True)
+        _, st = fd.fdirw_step(dom, c, out, prec=args.prec, stats=True, tune=args.tune, **kw)
+        print(f"[profile_step] n={args.n} prec={args.prec} gen={args.gen} rep {i}: "
+              f"kernel {st['kernel_seconds'] * 1e3:.2f} ms, wall {st['seconds'] * 1e3:.2f} ms", flush=True)
     if args.copy_mib > 0:
         nbytes = args.copy_mib << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)

@@ -25,7 +25,7 @@ def _dev_domain(d):
     return fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
 
 
-# ------------------------------------------------------------------ (a1)
+# ------------------------------------------------------------------ coefficients
 
 @pytest.mark.parametrize("seed,shape,nph", [(1, (9, 7, 11), 4), (2, (1, 1, 5), 2), (3, (16, 16, 16), 3)])
 def test_coefficients_bitexact(seed, shape, nph):
@@ -49,7 +49,7 @@ def test_coefficients_config0_and_given_dt():
     assert dt == 0.02 and np.array_equal(to_host(lam), np.stack([lx, ly, lz]))
 
 
-# ------------------------------------------------------------------ (a2)-(a4)
+# ------------------------------------------------------------------ window kernels
 
 @pytest.mark.parametrize("r,n_sub,shape,seed", [(0, 7, (4, 5, 6), 1), (1, 9, (5, 5, 5), 2), (2, 20, (7, 9, 8), 3),
                                                  (3, 40, (12, 10, 14), 4), (4, 33, (6, 13, 11), 5),
@@ -88,7 +88,7 @@ def test_kernels_fp32_match_oracle(prec):
     assert np.max(np.abs(to_host(m) - 1.0)) <= 1e-5
 
 
-# ------------------------------------------------------------------ (a5), (a6)
+# ------------------------------------------------------------------ superposition, mass balance
 
 def test_step_fp64_config0_full():
     d = synth.config0()
@@ -170,7 +170,7 @@ def test_multi_domain_call_equals_single_calls():
         assert np.max(np.abs(to_host(o) - ref)) <= 1e-13
 
 
-# ------------------------------------------------------------------ (a11) bank
+# ------------------------------------------------------------------ kernel bank
 
 @pytest.mark.parametrize("prec", [fd.FP64, fd.FP32, fd.FP16X32, fd.BF16_BANK])
 def test_run_bank_equals_fused(prec):
@@ -207,7 +207,7 @@ def test_run_zero_and_odd_steps_keep_result_in_place():
     assert np.max(np.abs(to_host(c) - ref)) <= 1e-13
 
 
-# ------------------------------------------------------------------ (a7) precision modes
+# ------------------------------------------------------------------ precision modes
 
 @pytest.mark.parametrize("prec,kern_tol", [(fd.FP16X32, 1e-3), (fd.BF16X32, 3e-3), (fd.FP16_BANK, 1e-3),
                                            (fd.BF16_BANK, 4e-3), (fd.FP16_STATE, 2e-2), (fd.BF16_STATE, 1e-1)])

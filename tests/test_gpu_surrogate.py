@@ -1,0 +1,350 @@
+"""GPU parity of the learned kernel generator (features, support, MFMA
+forward, loss, gradients, Adam, the audited surrogate step) against the FP64
+CPU oracle in oracle/surrogate.py.
+
+Tolerances.  The GPU keeps weights, activations and back-propagated
+gradients in BF16 (unit roundoff u = 2^-9) with FP32 accumulation.  Replaying
+those roundings in an FP64 emulation of the same network and windows gives a
+relative L2 error of 0.6-0.7 % for the last-layer output and 0.5-0.6 % per
+layer for the gradients; the bounds below are four times that (2.5e-2).  The
+loss terms are sums over thousands of cells and agree to ~1e-4 relative in
+that emulation (bound 2e-3).  Support and placement are integer: bit-exact."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import surrogate as su
+from helpers import rel_l1, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2408_11376_amd as fd  # noqa: E402
+
+R = 8
+N_SUB = 60
+Z_TOL = 2.5e-2
+GRAD_TOL = 2.5e-2
+LOSS_TOL = 2e-3
+
+
+def _dev(d):
+    return fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
+
+
+def _params(seed, last_scale=10.0):
+    """Seeded parameters rounded to FP32 (what the GPU holds); the last layer
+    is scaled up so its output is O(1) and a layout error would show."""
+    p = su.init_params(seed)
+    p[4] = (p[4][0] * last_scale, p[4][1])
+    p = [(w.astype(np.float32).astype(np.float64), (b + 0.01 * (l + 1)).astype(np.float32).astype(np.float64))
+         for l, (w, b) in enumerate(p)]
+    return p
+
+
+@pytest.fixture(scope="module")
+def prior():
+    return su.prior_log_uniform(R, N_SUB)
+
+
+@pytest.fixture(scope="module")
+def dom():
+    return synth.random_small((20, 18, 22), 3, r=R, n_sub=N_SUB, seed=5)
+
+
+def _net(params, n_sub=N_SUB):
+    nn = fd.Surrogate(n_sub, seed=0)
+    nn.set_params(su.flatten(params).astype(np.float32))
+    return nn
+
+
+SOURCES = [0, 1234, 4000, 20 * 18 * 22 - 1, 3 * 22 + 5, 10 * 18 * 22 + 9 * 22 + 11]
+
+
+def test_parameter_round_trip_and_count():
+    assert fd.fdirw_nn_num_params() == su.num_params()
+    nn = fd.Surrogate(N_SUB, seed=3)
+    th = su.flatten(_params(1)).astype(np.float32)
+    nn.set_params(th)
+    assert np.array_equal(nn.get_params(), th)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "nn.bin")
+        nn.save(path)
+        other = fd.Surrogate(N_SUB, seed=9)
+        assert not np.array_equal(other.get_params(), th)
+        other.load(path)
+        assert np.array_equal(other.get_params(), th)
+        wrong = fd.Surrogate(N_SUB + 1)
+        with pytest.raises(fd.FdirwError):
+            wrong.load(path)
+
+
+def test_default_init_statistics():
+    th = fd.Surrogate(N_SUB, seed=7).get_params()
+    p = su.unflatten(th)
+    for l, (w, b) in enumerate(p):
+        ci = su.CHANNELS[l]
+        want = np.sqrt(2.0 / (ci * 27)) * (0.1 if l == 4 else 1.0)
+        assert np.all(b == 0)
+        if w.size > 1000:
+            assert abs(w.std() / want - 1) < 0.1 and abs(w.mean()) < 0.1 * want
+
+
+def test_support_is_bit_exact(dom, prior):
+    nn = _net(_params(1))
+    P = oracle.Problem.from_domain(dom)
+    src = torch.tensor(SOURCES, dtype=torch.int64, device="cuda")
+    out = nn.forward(_dev(dom), src, support=True, G=False)
+    S = to_host(out["support"])
+    for i, s in enumerate(SOURCES):
+        assert np.array_equal(S[i], P.support(s).astype(np.uint8)), s
+
+
+def test_support_fast_path_all_permeable():
+    # every cell permeable, n_sub >= 3r: the support is the in-domain window
+    d = synth.random_small((19, 21, 20), 2, r=R, n_sub=30, seed=8, d_zero_phase=False)
+    nn = _net(_params(1), n_sub=30)
+    P = oracle.Problem.from_domain(d)
+    srcs = [0, 5000, 19 * 21 * 20 - 1]
+    out = nn.forward(_dev(d), torch.tensor(srcs, dtype=torch.int64, device="cuda"), support=True, G=False)
+    for i, s in enumerate(srcs):
+        assert np.array_equal(to_host(out["support"])[i], P.support(s).astype(np.uint8))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_forward_matches_oracle(dom, prior, seed):
+    params = _params(seed)
+    nn = _net(params)
+    src = torch.tensor(SOURCES, dtype=torch.int64, device="cuda")
+    out = nn.forward(_dev(dom), src, G=True, support=True, logits=True)
+    L, G, S = to_host(out["logits"]), to_host(out["G"]), to_host(out["support"]).astype(bool)
+    for i, s in enumerate(SOURCES):
+        f = su.window_features(dom.label, dom.d_phase, s, R, prior)
+        lo, _ = su.forward(params, f)
+        z5o, z5g = lo - prior, L[i].astype(np.float64) - prior
+        err = np.linalg.norm(z5g - z5o) / np.linalg.norm(z5o)
+        assert err <= Z_TOL, (s, err)
+        go = su.masked_softmax(lo, S[i])
+        assert np.all(G[i][~S[i]] == 0)
+        assert abs(G[i].astype(np.float64).sum() - 1.0) <= 1e-5
+        assert rel_l1(G[i].astype(np.float64), go) <= 2 * Z_TOL
+
+
+def test_forward_many_sources_is_consistent(dom):
+    # more windows than one launch chunk holds is not needed for parity; check
+    # that batching does not change a window's result
+    nn = _net(_params(3))
+    dd = _dev(dom)
+    allsrc = torch.arange(0, dom.label.size, 37, dtype=torch.int64, device="cuda")
+    big = to_host(nn.forward(dd, allsrc)["G"])
+    for j in (0, 5, len(allsrc) - 1):
+        one = to_host(nn.forward(dd, allsrc[j:j + 1])["G"])[0]
+        assert np.array_equal(one, big[j])
+
+
+def _oracle_grads(params, dom, prior, srcs, targets):
+    """Mean gradient, mean (KL, L1) and mean sum |d loss / d logits|."""
+    P = oracle.Problem.from_domain(dom)
+    acc, kl_l1, dl_abs = None, np.zeros(2), 0.0
+    for i, s in enumerate(srcs):
+        f = su.window_features(dom.label, dom.d_phase, s, R, prior)
+        sup = P.support(s).astype(bool)
+        q = targets[i].astype(np.float64)
+        q = q / q.sum()
+        lo, cache = su.forward(params, f)
+        g = su.masked_softmax(lo, sup)
+        loss, dl = su.loss_and_dlogits(g, q, sup)
+        qs, gs = q[sup], g[sup]
+        kl_l1 += [np.where(qs > 0, qs * (np.log(np.where(qs > 0, qs, 1)) - np.log(gs)), 0).sum(),
+                  np.abs(qs - gs).sum()]
+        dl_abs += np.abs(dl).sum()
+        v = su.flatten(su.backward(params, cache, dl))
+        acc = v if acc is None else acc + v
+    return acc / len(srcs), kl_l1 / len(srcs), dl_abs / len(srcs)
+
+
+def test_gradients_match_oracle(dom, prior):
+    params = _params(4)
+    nn = _net(params)
+    srcs = [0, 4000, 7919, 2500, 6001]
+    P = oracle.Problem.from_domain(dom)
+    Gfd, _ = P.kernels(srcs)
+    target = Gfd.astype(np.float32)
+    (kl, l1), g = nn.backward(_dev(dom), torch.tensor(srcs, dtype=torch.int64, device="cuda"),
+                              target=to_dev(target), grad=True)
+    go, (klo, l1o), dl_abs = _oracle_grads(params, dom, prior, srcs, target)
+    assert kl == pytest.approx(klo, rel=LOSS_TOL)
+    assert l1 == pytest.approx(l1o, rel=LOSS_TOL)
+    gg = to_host(g).astype(np.float64)
+    off = 0
+    for l, (ws, bs) in enumerate(su.param_shapes()):
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        a, b = gg[off:off + nw], go[off:off + nw]
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= GRAD_TOL, ("w", l)
+        a, b = gg[off + nw:off + nw + nb], go[off + nw:off + nw + nb]
+        if l < 4:
+            assert np.linalg.norm(a - b) <= GRAD_TOL * np.linalg.norm(b), ("b", l)
+        else:
+            # the last bias shifts every logit: its exact gradient is 0 (softmax
+            # shift invariance); the GPU sums BF16-rounded d loss / d logits, so
+            # the bound is the rounding of that sum, u * sum |d loss / d logits|
+            assert abs(b[0]) <= 1e-12 and abs(a[0]) <= 2.0 ** -8 * dl_abs, (a, dl_abs)
+        off += nw + nb
+
+
+def test_gradient_is_a_mean_over_micro_batches(dom):
+    # 256 windows span two training micro-batches of 128.  With power-of-two
+    # batch sizes the BF16 roundings scale exactly, so the mean gradient of
+    # the 256 equals the mean of the two halves' gradients up to FP32 sums.
+    params = _params(5)
+    nn = _net(params)
+    dd = _dev(dom)
+    src = (torch.arange(0, 256 * 29, 29, dtype=torch.int64, device="cuda") % dom.label.size).contiguous()
+    (kl, l1), g = nn.backward(dd, src, grad=True)
+    (kla, l1a), ga = nn.backward(dd, src[:128].contiguous(), grad=True)
+    (klb, l1b), gb = nn.backward(dd, src[128:].contiguous(), grad=True)
+    mix = (to_host(ga).astype(np.float64) + to_host(gb).astype(np.float64)) / 2
+    assert np.linalg.norm(to_host(g) - mix) <= 1e-5 * np.linalg.norm(mix)
+    assert kl == pytest.approx((kla + klb) / 2, rel=1e-12)
+    assert l1 == pytest.approx((l1a + l1b) / 2, rel=1e-12)
+
+
+def test_adam_step_matches_formula():
+    nn = fd.Surrogate(N_SUB, seed=1)
+    d = synth.random_small((18, 18, 18), 2, r=R, n_sub=N_SUB, seed=12)
+    th0 = nn.get_params().astype(np.float64)
+    src = torch.tensor([100, 2000, 4000], dtype=torch.int64, device="cuda")
+    _, g = nn.backward(_dev(d), src, grad=True)
+    g = to_host(g).astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    nn.adam(lr, b1, b2, eps)
+    m = (1 - b1) * g
+    v = (1 - b2) * g * g
+    want = th0 - lr * (m / (1 - b1)) / (np.sqrt(v / (1 - b2)) + eps)
+    assert np.max(np.abs(nn.get_params() - want)) <= 1e-6 * max(1.0, np.abs(want).max())
+
+
+def test_surrogate_step_audit_fallback_equals_fd(dom):
+    # an untrained network fails the 1e-3 audit: the step is the FD step
+    nn = _net(_params(1))
+    dd = _dev(dom)
+    c = to_dev(dom.c0)
+    out, st = fd.fdirw_step(dd, c, prec=fd.FP32, stats=True, nn=nn, audit_samples=64)
+    ref = fd.fdirw_step(dd, c, prec=fd.FP32)
+    assert st["fallback_used"] == 1 and st["audit_l1"] > 1e-3
+    assert np.max(np.abs(to_host(out) - to_host(ref))) <= 1e-12 * to_host(ref).max()
+
+
+def test_surrogate_step_matches_oracle_superposition(dom, prior):
+    # audit disabled (tolerance above any L1): every kernel is the network's.
+    # c0 is zero outside a few sources so the oracle can evaluate each kernel.
+    params = _params(2)
+    nn = _net(params)
+    dd = _dev(dom)
+    srcs = [0, 4000, 7919, 3 * 22 + 5, 6001]
+    c0 = np.zeros(dom.label.shape)
+    rng = np.random.default_rng(3)
+    for s in srcs:
+        c0.reshape(-1)[s] = rng.uniform(0.5, 1.5)
+    out, st = fd.fdirw_step(dd, to_dev(c0), prec=fd.FP32, stats=True, nn=nn, audit_tol=1e9, audit_samples=16)
+    assert st["fallback_used"] == 0
+    assert st["n_sources"] == len(srcs)
+    assert abs(st["mass_out"] - st["mass_in"]) <= 1e-12 * st["mass_in"]
+    P = oracle.Problem.from_domain(dom)
+    ref = np.zeros_like(c0)
+    nz, ny, nx = dom.label.shape
+    for s in srcs:
+        f = su.window_features(dom.label, dom.d_phase, s, R, prior)
+        lo, _ = su.forward(params, f)
+        g = su.masked_softmax(lo, P.support(s).astype(bool))
+        z, rem = divmod(s, nx * ny)
+        y, x = divmod(rem, nx)
+        for wz in range(2 * R + 1):
+            for wy in range(2 * R + 1):
+                for wx in range(2 * R + 1):
+                    Z, Y, X = z - R + wz, y - R + wy, x - R + wx
+                    if 0 <= Z < nz and 0 <= Y < ny and 0 <= X < nx:
+                        ref[Z, Y, X] += c0.reshape(-1)[s] * g[wz, wy, wx]
+    assert rel_l1(to_host(out), ref) <= 2 * Z_TOL
+    # placement and superposition exactly as the forward kernels say
+    G = to_host(nn.forward(dd, torch.tensor(srcs, dtype=torch.int64, device="cuda"))["G"]).astype(np.float64)
+    mine = np.zeros_like(c0)
+    for i, s in enumerate(srcs):
+        z, rem = divmod(s, nx * ny)
+        y, x = divmod(rem, nx)
+        gi = G[i] / G[i].sum()
+        for wz in range(2 * R + 1):
+            Z = z - R + wz
+            if not 0 <= Z < nz:
+                continue
+            for wy in range(2 * R + 1):
+                Y = y - R + wy
+                if not 0 <= Y < ny:
+                    continue
+                x0, x1 = max(0, x - R), min(nx, x + R + 1)
+                mine[Z, Y, x0:x1] += c0.reshape(-1)[s] * gi[wz, wy, x0 - (x - R):x1 - (x - R)]
+    assert np.max(np.abs(to_host(out) - mine)) <= 1e-12 * mine.max()
+
+
+def test_surrogate_errors(dom):
+    nn = _net(_params(1))
+    d8 = _dev(dom)
+    bad_r = fd.Domain(dom.label, dom.d_phase, 6, N_SUB)
+    bad_n = fd.Domain(dom.label, dom.d_phase, R, N_SUB + 1)
+    src = torch.tensor([1, 2], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        nn.forward(bad_r, src)
+    with pytest.raises(fd.FdirwError) as e:
+        nn.forward(bad_n, src)
+    assert e.value.status == fd.E_ARG
+    with pytest.raises(fd.FdirwError) as e:
+        nn.forward(d8, torch.tensor([dom.label.size], dtype=torch.int64, device="cuda"))
+    assert e.value.status == fd.E_ARG
+    c = to_dev(dom.c0)
+    with pytest.raises(fd.FdirwError) as e:
+        fd.fdirw_step([d8, d8], [c, c.clone()], nn=nn)
+    assert e.value.status == fd.E_UNSUPPORTED
+
+
+def test_training_gains_over_the_prior():
+    """Train on two GRF geometries (the 192^3 workload's generator at 40^3,
+    D 1 / 1e-6, r = 8, n_sub = 200) and evaluate on a third: the mean
+    per-kernel L1 error against the oracle's FD kernels must fall below both
+    the untrained network's and the prior's (the kernel without the network:
+    softmax of log U over the support)."""
+    from paper_2408_11376_amd.surrogate_train import train
+    n = 40
+    train_doms = [synth.config2(seed=100 + i, n=n) for i in range(2)]
+    ev = synth.config2(seed=200, n=n)
+    P = oracle.Problem.from_domain(ev)
+    srcs = [int(x) for x in (synth.uniform(201, 24) * n ** 3).astype(np.int64)]
+    Gfd, _ = P.kernels(srcs)
+    prior = su.prior_log_uniform(R, ev.n_sub)
+    sup = [P.support(s).astype(bool) for s in srcs]
+    q = [Gfd[i] / Gfd[i].sum() for i in range(len(srcs))]
+    l1_prior = np.mean([np.abs(su.masked_softmax(prior, sup[i]) - q[i]).sum() for i in range(len(srcs))])
+
+    nn = fd.Surrogate(ev.n_sub, seed=0)
+    evd = _dev(ev)
+    st = torch.tensor(srcs, dtype=torch.int64, device="cuda")
+
+    def l1_nn():
+        G = to_host(nn.forward(evd, st)["G"]).astype(np.float64)
+        return np.mean([np.abs(G[i] - q[i]).sum() for i in range(len(srcs))])
+
+    l1_0 = l1_nn()
+    hist = train(nn, [_dev(d) for d in train_doms], steps=300, batch=32, lr=3e-3, seed=1)
+    l1_1 = l1_nn()
+    print(f"mean per-kernel L1: prior {l1_prior:.4f}  untrained {l1_0:.4f}  trained {l1_1:.4f}; "
+          f"train loss {hist[0]} -> {hist[-1]}")
+    assert sum(hist[-20:][i][0] + hist[-20:][i][1] for i in range(20)) < \
+        sum(hist[:20][i][0] + hist[:20][i][1] for i in range(20))
+    assert l1_1 < l1_0
+    assert l1_1 < l1_prior

@@ -25,7 +25,7 @@ def _lin(shape, z, y, x):
     return (z * shape[1] + y) * shape[2] + x
 
 
-# ------------------------------------------------------------------ (a1)
+# ------------------------------------------------------------------ coefficients
 
 def test_dt_from_stability_limit():
     label = np.zeros((3, 3, 3), dtype=np.uint8)
@@ -64,7 +64,7 @@ def test_two_cell_closed_form_pins_harmonic_mean():
         assert abs(m[0] - 1.0) < 1e-15
 
 
-# ------------------------------------------------------------------ (a2)-(a4)
+# ------------------------------------------------------------------ window kernels
 
 def test_zero_substeps_is_identity():
     d = synth.random_small((5, 6, 7), 3, r=2, n_sub=0, seed=3)
@@ -183,7 +183,7 @@ def test_support_matches_l1_ball_and_nonzero_pattern():
         assert np.array_equal(G[0] > 0, q.support(s).astype(bool))
 
 
-# ------------------------------------------------------------------ (a5), (a6)
+# ------------------------------------------------------------------ superposition, mass balance
 
 def _tiny_covered(seed, shape, n_phase, n_sub):
     d = synth.random_small(shape, n_phase, r=max(shape) - 1, n_sub=n_sub, seed=seed)
