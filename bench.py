@@ -16,7 +16,12 @@ precision configuration); the plain FP32 and the BF16-copy steps are timed the
 same way and reported under ``modes`` with their speedup over FP32 and their
 relative L1 difference from the FP32 field.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp16x32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp16x32] [--nn-train-steps S]
+
+The learned generator (surrogate) is trained for S Adam steps on two other
+seeded 64^3 geometries of the same kind and its step is timed under ``modes``
+as "nn": the audited step as the library runs it (audit L1 and fallback
+flag) and the surrogate-only step with its speedup and field error.
 """
 import argparse
 import hashlib
@@ -95,6 +100,58 @@ def cpu_baseline(dom, block: int):
             "sample": f"{block}^3 = {used} sources of the 192^3 step (c0 zeroed elsewhere), {dt:.2f} s"}
 
 
+def surrogate_mode(fd, d, dom, c0, bufs, stream, args):
+    """Train the learned generator on two other seeded GRF geometries of the
+    same kind (64^3), then time its step on the workload: the audited step as
+    the library runs it (falls back to FD when the mean per-kernel L1 of 1024
+    audited sources exceeds 1e-3) and the surrogate-only step (audit off)."""
+    import torch
+    import synth
+    from paper_2408_11376_amd.surrogate_train import train
+    log(f"nn: training {args.nn_train_steps} Adam steps on two 64^3 GRF geometries")
+    nn = fd.Surrogate(d.n_sub, seed=0)
+    tdoms = [fd.Domain.from_synth(synth.config2(seed=100 + i, n=64)) for i in range(2)]
+    t = time.perf_counter()
+    hist = train(nn, tdoms, args.nn_train_steps, batch=32, lr=3e-3, seed=1)
+    train_s = time.perf_counter() - t
+    out = {"train_steps": args.nn_train_steps, "train_seconds": train_s,
+           "train_loss_first_last": [list(hist[0]), list(hist[-1])]}
+    # the audited step (what fdirw_step with GEN_NN does)
+    _, st = fd.fdirw_step(dom, c0, bufs[0], nn=nn, stats=True)
+    out["audit_l1"] = st["audit_l1"]
+    out["fallback_used"] = st["fallback_used"]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        fd.fdirw_step(dom, c0, bufs[0], nn=nn)
+    torch.cuda.synchronize()
+    out["audited_ms_per_step"] = 1e3 * (time.perf_counter() - t) / args.steps
+    # surrogate-only step
+    kw = {"nn": nn, "audit_tol": 1e30, "audit_samples": 1}
+    for _ in range(args.warmup):
+        fd.fdirw_step(dom, c0, bufs[0], **kw)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kern = []
+    cur = c0
+    ev0.record(stream)
+    for k in range(args.steps):
+        o = bufs[k % 2]
+        _, st = fd.fdirw_step(dom, cur, o, stats=True, **kw)
+        kern.append(st["kernel_seconds"])
+        cur = o
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    first, st = fd.fdirw_step(dom, c0, torch.empty_like(c0), stats=True, **kw)
+    out.update({"cells_per_s": d.n / (ms * 1e-3), "ms_per_step": ms, "kernel_ms": 1e3 * float(np.mean(kern)),
+                "mass_rel_drift": abs(st["mass_out"] - st["mass_in"]) / st["mass_in"],
+                "kernel_mass_range": [st["kmass_min"], st["kmass_max"]], "sources": st["n_sources"]})
+    log(f"nn: audit L1 {out['audit_l1']:.4f} (fallback {out['fallback_used']}), surrogate-only {ms:.1f} ms/step")
+    return out, first
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +162,8 @@ def main():
     ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
     ap.add_argument("--cpu-block", type=int, default=24, help="edge of the oracle's source sample (0: skip)")
     ap.add_argument("--tune", type=int, default=-1)
+    ap.add_argument("--nn-train-steps", type=int, default=300,
+                    help="Adam steps of the surrogate before its step is timed (0: skip the surrogate)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -167,10 +226,13 @@ def main():
         log(f"{mode}: {ms:.1f} ms/step, kernel {results[mode]['kernel_ms']:.1f} ms, "
             f"{results[mode]['cells_per_s'] / 1e6:.3f} Mcells/s")
 
+    if args.nn_train_steps > 0:
+        results["nn"], fields["nn"] = surrogate_mode(fd, d, dom, c0, bufs, stream, args)
+
     if "fp32" in fields:
         ref = fields["fp32"]
         den = float(ref.abs().sum())
-        for mode in modes:
+        for mode in results:
             results[mode]["rel_l1_vs_fp32"] = float((fields[mode] - ref).abs().sum()) / den
             results[mode]["speedup_vs_fp32"] = results["fp32"]["ms_per_step"] / results[mode]["ms_per_step"]
 

@@ -142,7 +142,28 @@ struct NnWgradArgs {
     float *bpart;             // [grid][16] bias partials
 };
 
+// Fused inference: one workgroup runs features, support, the five layers
+// (activations resident in LDS) and the softmax of one window.
+struct NnFusedArgs {
+    int nx, ny, nz;
+    int n_sub;
+    const int64_t *src;       // [B] source indices
+    const uint8_t *label;
+    float f1[256];
+    uint8_t open[256];
+    const float *prior;       // [V]
+    const uint16_t *wf[5];    // weights in the fused operand layout (nn_launch_fpack)
+    const float *bias[5];
+    float *G;                 // [B][V] softmax kernel, or null
+    double *mass;             // [B] FP64 sum of G as stored, or null
+    float *logits;            // [B][V], or null
+    uint8_t *support;         // [B][V], or null
+};
+
 int nn_slabs_per_window();
+int nn_fpack_elems(int layer);
+hipError_t nn_launch_fpack(const float *w, int layer, int co_n, int ci_n, uint16_t *out, hipStream_t st);
+hipError_t nn_launch_fused(const NnFusedArgs &a, int batch, hipStream_t st);
 hipError_t nn_launch_features(const NnFeatArgs &a, int batch, hipStream_t st);
 hipError_t nn_launch_pack(const float *w, int co_n, int ci_n, int CI, int flip, uint16_t *out, hipStream_t st);
 int nn_pack_chunks(int CI);

@@ -40,10 +40,12 @@ constexpr int TZ = 3;                 // output planes per slab
 constexpr int NSLAB = (W + TZ - 1) / TZ;
 constexpr int NTHR = 256;
 
-__device__ __forceinline__ float silu_f(float x) { return x / (1.0f + expf(-x)); }
+// SiLU with the hardware exp and reciprocal (about 1 ulp each; the result is
+// rounded to BF16, 2^-9 relative, right after)
+__device__ __forceinline__ float silu_f(float x) { return x * __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 __device__ __forceinline__ float silu_grad_f(float x)
 {
-    const float s = 1.0f / (1.0f + expf(-x));
+    const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-x));
     return s * (1.0f + x * (1.0f - s));
 }
 
@@ -56,6 +58,42 @@ __device__ __forceinline__ bf16x8 zero8()
 }
 
 // ----------------------------------------------------------------- features
+
+// Breadth-first growth of the support from the window centre: sa holds the
+// seed (the centre), one face crossing per sweep, at most n_sub sweeps,
+// stopping early when a sweep adds nothing.  open[v]: cell v is in the domain
+// and permeable.  Returns the array (sa or sb) holding the result.
+__device__ const uint8_t *grow_support(const uint8_t *open, uint8_t *sa, uint8_t *sb, int n_sub, int *changed)
+{
+    uint8_t *cur = sa, *nxt = sb;
+    for (int it = 0; it < n_sub; ++it) {
+        if (threadIdx.x == 0) *changed = 0;
+        __syncthreads();
+        int any = 0;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            uint8_t r = cur[v];
+            if (!r && open[v]) {
+                const int wx = v % W, wy = (v / W) % W, wz = v / W2;
+                if ((wx > 0 && cur[v - 1] && open[v - 1]) || (wx < W - 1 && cur[v + 1] && open[v + 1]) ||
+                    (wy > 0 && cur[v - W] && open[v - W]) || (wy < W - 1 && cur[v + W] && open[v + W]) ||
+                    (wz > 0 && cur[v - W2] && open[v - W2]) || (wz < W - 1 && cur[v + W2] && open[v + W2])) {
+                    r = 1;
+                    any = 1;
+                }
+            }
+            nxt[v] = r;
+        }
+        if (any) atomicOr(changed, 1);
+        __syncthreads();
+        const int ch = *changed;
+        uint8_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        __syncthreads();                                     // every thread has read changed
+        if (!ch) break;
+    }
+    return cur;
+}
 
 // Window q of source src[q]: features X[q][v][0..7] (BF16: channel 0 = the
 // cell is in the domain and permeable, 1 = log-D feature or -1 outside the
@@ -111,34 +149,7 @@ features_kernel(NnFeatArgs a)
         }
         return;
     }
-    // breadth-first growth, one face crossing per sweep, stops when nothing changes
-    uint8_t *cur = sa, *nxt = sb;
-    for (int it = 0; it < a.n_sub; ++it) {
-        if (threadIdx.x == 0) changed = 0;
-        __syncthreads();
-        int any = 0;
-        for (int v = threadIdx.x; v < V; v += NTHR) {
-            uint8_t r = cur[v];
-            if (!r && open[v]) {
-                const int wx = v % W, wy = (v / W) % W, wz = v / W2;
-                if ((wx > 0 && cur[v - 1] && open[v - 1]) || (wx < W - 1 && cur[v + 1] && open[v + 1]) ||
-                    (wy > 0 && cur[v - W] && open[v - W]) || (wy < W - 1 && cur[v + W] && open[v + W]) ||
-                    (wz > 0 && cur[v - W2] && open[v - W2]) || (wz < W - 1 && cur[v + W2] && open[v + W2])) {
-                    r = 1;
-                    any = 1;
-                }
-            }
-            nxt[v] = r;
-        }
-        if (any) atomicOr(&changed, 1);
-        __syncthreads();
-        const int ch = changed;
-        uint8_t *t = cur;
-        cur = nxt;
-        nxt = t;
-        __syncthreads();                                     // every thread has read changed
-        if (!ch) break;
-    }
+    const uint8_t *cur = grow_support(open, sa, sb, a.n_sub, &changed);
     for (int v = threadIdx.x; v < V; v += NTHR) S[v] = cur[v];
 }
 
@@ -252,7 +263,7 @@ conv_kernel(NnConvArgs a)
 
 // ----------------------------------------------------------------- softmax / loss
 
-template <typename T>
+template <typename T, int NW = NTHR / 64>
 __device__ __forceinline__ T block_reduce_sum(T x, T *red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -261,7 +272,7 @@ __device__ __forceinline__ T block_reduce_sum(T x, T *red)
     if (lane == 0) red[wave] = x;
     __syncthreads();
     T s = 0;
-    for (int w = 0; w < NTHR / 64; ++w) s += red[w];
+    for (int w = 0; w < NW; ++w) s += red[w];
     return s;
 }
 
@@ -618,6 +629,379 @@ __global__ void fill_f32_kernel(float *__restrict__ p, int64_t n, float v)
         p[i] = v;
 }
 
+// ----------------------------------------------------------------- fused inference
+
+// One workgroup (8 waves, two per SIMD) per window.  The activations of the
+// window live in LDS for all five layers: 17 planes x 289 voxels x 16
+// channels of BF16 (157 KB), each plane stored as two halves of 8 channels so
+// that the 16 voxels of an MFMA operand are 16 consecutive 16-byte vectors.
+// Each layer walks the input planes p = 0 .. 16 once; the operand loaded for
+// input plane p feeds the three output planes p + 1, p, p - 1 (taps dz = 0,
+// 1, 2) from registers, so LDS is read once per input plane instead of once
+// per tap.  A plane's input is dead after its step, so output plane p - 1
+// overwrites input plane p - 1 during step p (one barrier per step).  MFMA
+// roles: A = weights (rows = output channels), B = activations (columns = 16
+// voxels of a plane), so each lane writes 4 consecutive channels of one
+// voxel.  Layer 0 reads its 3 (stored as 8) feature channels from a two-plane
+// ring built from the labels one step ahead; the last layer (one output
+// channel) puts the three dz taps in the A rows instead.
+constexpr int FNT = 512;                                    // threads per workgroup
+constexpr int FWAVES = FNT / 64;                            // 8
+constexpr int FTILES = (W2 + 15) / 16;                      // 19 voxel tiles per plane
+constexpr int FHALF = W2 * 8;                               // BF16 elements of one 8-channel half plane
+constexpr int FSLOT = 2 * FHALF;                            // BF16 elements of one activation plane
+constexpr int FTPW = (FTILES + FWAVES - 1) / FWAVES;        // tiles per wave (3)
+constexpr int FZ5 = FSLOT / 2;                              // float stride of the z5 planes
+constexpr int fchunks(int layer) { return layer == 0 ? 3 : 5; }
+constexpr int fpack_count(int layer) { return (layer == 4 ? 1 : 3) * fchunks(layer); }
+
+// Weights in the fused A layout: for each (dz, chunk) a bf16x8 per lane; lane
+// l holds row l % 16 (output channel; dz for the last layer) and reduction
+// indices 8 (l / 16) + i of the chunk.  Layer 0: chunk c covers plane
+// positions 4c .. 4c + 3 (8 channels each); other layers: positions 2c, 2c + 1
+// (16 channels each); position = dy * 3 + dx, 9 = padding.
+__global__ void fpack_kernel(const float *__restrict__ w, int layer, int co_n, int ci_n, uint16_t *__restrict__ out)
+{
+    const int nc = fchunks(layer);
+    const int total = fpack_count(layer) * 512;
+    __bf16 *o = reinterpret_cast<__bf16 *>(out);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int i = e % 8, l = (e / 8) % 64, idx = e / 512;
+        const int row = l % 16, kb = l / 16;
+        int dz, c;
+        if (layer == 4) { c = idx; dz = row; }
+        else            { dz = idx / nc; c = idx % nc; }
+        int pos, ch;
+        if (layer == 0) { pos = 4 * c + kb;        ch = i; }
+        else            { pos = 2 * c + (kb >> 1); ch = 8 * (kb & 1) + i; }
+        const int co = layer == 4 ? 0 : row;
+        float v = 0.0f;
+        if (pos < 9 && dz < 3 && co < co_n && ch < ci_n) v = w[((size_t)co * ci_n + ch) * 27 + dz * 9 + pos];
+        o[e] = (__bf16)v;
+    }
+}
+
+struct FusedCtx {
+    int lane, wave, n, kb;
+    int sx, sy, sz;
+    bool vok[FTPW];
+    int vp[FTPW];
+};
+
+__device__ __forceinline__ bool fused_tile(const FusedCtx &f, int i) { return f.wave + FWAVES * i < FTILES; }
+
+// SiLU(acc + bias) of output plane z of one tile into LDS (channels 4 kb .. 4 kb + 3)
+__device__ __forceinline__ void fused_store(__bf16 *act, const FusedCtx &f, int i, int z, const floatx4 &acc,
+                                            const float *bias4)
+{
+    if (!f.vok[i]) return;
+    typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
+    bf16x4 h;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j] = (__bf16)silu_f(acc[j] + bias4[j]);
+    *reinterpret_cast<bf16x4 *>(act + (size_t)z * FSLOT + (f.kb >> 1) * FHALF + f.vp[i] * 8 + 4 * (f.kb & 1)) = h;
+}
+
+// Global inputs of the layer-0 features of one voxel of window plane pz
+struct FeatIn {
+    int lab;                  // -1 outside the domain
+    float prior;
+};
+
+__device__ __forceinline__ FeatIn fused_fetch_x(const NnFusedArgs &a, const FusedCtx &f, int pz)
+{
+    FeatIn r{-1, 0.0f};
+    const int vp = threadIdx.x;
+    if (vp < W2) {
+        const int y = vp / W, x = vp - (vp / W) * W;
+        const int gx = f.sx - R + x, gy = f.sy - R + y, gz = f.sz - R + pz;
+        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
+            r.lab = a.label[((int64_t)gz * a.ny + gy) * a.nx + gx];
+        r.prior = a.prior[pz * W2 + vp];
+    }
+    return r;
+}
+
+__device__ __forceinline__ void fused_put_x(const FeatIn &in, const float *f1t, const uint8_t *opt, __bf16 *ring)
+{
+    const int vp = threadIdx.x;
+    if (vp >= W2) return;
+    bf16x8 v = zero8();
+    v[0] = (__bf16)(in.lab >= 0 && opt[in.lab] ? 1.0f : 0.0f);
+    v[1] = (__bf16)(in.lab >= 0 ? f1t[in.lab] : -1.0f);
+    v[2] = (__bf16)(in.prior * (1.0f / 20.0f));
+    *reinterpret_cast<bf16x8 *>(ring + vp * 8) = v;
+}
+
+__device__ __forceinline__ bf16x8 fused_load(const __bf16 *base, int off)
+{
+    bf16x8 b = *reinterpret_cast<const bf16x8 *>(base + (off >= 0 ? off : 0));
+    return off >= 0 ? b : zero8();
+}
+
+// One step (input plane p) of a 16-channel layer with NC chunks per dz; xin
+// points at the plane.  acc[i][0..2] = outputs p - 1, p, p + 1.
+template <int NC>
+__device__ __forceinline__ void fused_step(const __bf16 *xin, const int (&off)[FTPW][5], const bf16x8 (&wr)[3][5],
+                                           floatx4 (&acc)[FTPW][3], const FusedCtx &f, int p)
+{
+    bf16x8 b[FTPW][NC];
+#pragma unroll
+    for (int i = 0; i < FTPW; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) b[i][c] = fused_tile(f, i) ? fused_load(xin, off[i][c]) : zero8();
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i) {
+            if (!fused_tile(f, i)) continue;
+            acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[1][c], b[i][c], acc[i][1], 0, 0, 0);
+            if (p > 0) acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[2][c], b[i][c], acc[i][0], 0, 0, 0);
+            if (p + 1 < W) acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][c], b[i][c], acc[i][2], 0, 0, 0);
+        }
+}
+
+__device__ __forceinline__ void fused_retire(__bf16 *act, floatx4 (&acc)[FTPW][3], const FusedCtx &f, int p,
+                                             const float *b4)
+{
+#pragma unroll
+    for (int i = 0; i < FTPW; ++i) {
+        if (!fused_tile(f, i)) continue;
+        if (p > 0) fused_store(act, f, i, p - 1, acc[i][0], b4);
+        acc[i][0] = acc[i][1];
+        acc[i][1] = acc[i][2];
+        acc[i][2] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+}
+
+__global__ void __launch_bounds__(FNT)
+fused_kernel(NnFusedArgs a)
+{
+    __shared__ __align__(16) __bf16 act[W * FSLOT];
+    __shared__ float f1t[256];
+    __shared__ uint8_t opt[256];
+    __shared__ unsigned smask[(V + 31) / 32];
+    __shared__ float redf[FWAVES];
+    __shared__ double redd[FWAVES];
+    __shared__ int flag;
+
+    FusedCtx f;
+    const int t = threadIdx.x;
+    f.lane = t & 63; f.wave = t >> 6; f.n = f.lane & 15; f.kb = f.lane >> 4;
+    const int q = blockIdx.x;
+    {
+        const int64_t s = a.src[q];
+        const int64_t plane = (int64_t)a.nx * a.ny;
+        f.sz = (int)(s / plane);
+        const int64_t rem = s - (int64_t)f.sz * plane;
+        f.sy = (int)(rem / a.nx);
+        f.sx = (int)(rem - (int64_t)f.sy * a.nx);
+    }
+    for (int i = t; i < 256; i += FNT) { f1t[i] = a.f1[i]; opt[i] = a.open[i]; }
+
+    // ---- structural support (scratch in the activation area), kept as a bit mask
+    uint8_t *openw = reinterpret_cast<uint8_t *>(act), *sa = openw + V, *sb = sa + V;
+    if (t == 0) flag = 1;
+    __syncthreads();
+    int notopen = 0;
+    for (int v = t; v < V; v += FNT) {
+        const int wx = v % W, wy = (v / W) % W, wz = v / W2;
+        const int gx = f.sx - R + wx, gy = f.sy - R + wy, gz = f.sz - R + wz;
+        uint8_t op = 0;
+        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz) {
+            op = opt[a.label[((int64_t)gz * a.ny + gy) * a.nx + gx]];
+            if (!op) notopen = 1;
+        }
+        openw[v] = op;
+        sa[v] = (wx == R && wy == R && wz == R) ? 1 : 0;
+    }
+    if (notopen) atomicAnd(&flag, 0);
+    __syncthreads();
+    const bool fast = flag && a.n_sub >= 3 * R;
+    __syncthreads();
+    const uint8_t *sup = fast ? nullptr : grow_support(openw, sa, sb, a.n_sub, &flag);
+    for (int wd = t; wd < (V + 31) / 32; wd += FNT) {
+        unsigned m = 0;
+        for (int b = 0; b < 32; ++b) {
+            const int v = wd * 32 + b;
+            if (v >= V) break;
+            bool in;
+            if (fast) {
+                const int wx = v % W, wy = (v / W) % W, wz = v / W2;
+                const int gx = f.sx - R + wx, gy = f.sy - R + wy, gz = f.sz - R + wz;
+                in = gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz;
+            } else {
+                in = sup[v] != 0;
+            }
+            m |= (unsigned)in << b;
+        }
+        smask[wd] = m;
+    }
+    __syncthreads();                                         // mask complete; support scratch free
+    if (a.support)
+        for (int v = t; v < V; v += FNT) a.support[(int64_t)q * V + v] = (smask[v >> 5] >> (v & 31)) & 1u;
+
+    // ---- this lane's voxels and operand offsets (element offsets within a plane)
+#pragma unroll
+    for (int i = 0; i < FTPW; ++i) {
+        const int tile = f.wave + FWAVES * i;
+        f.vp[i] = tile * 16 + f.n;
+        f.vok[i] = tile < FTILES && f.vp[i] < W2;
+    }
+    int off8[FTPW][5], off16[FTPW][5];
+#pragma unroll
+    for (int i = 0; i < FTPW; ++i) {
+        const int y = f.vok[i] ? f.vp[i] / W : 0, x = f.vok[i] ? f.vp[i] % W : 0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            int pos = 4 * c + f.kb;
+            int yy = y + pos / 3 - 1, xx = x + pos % 3 - 1;
+            bool ok = c < 3 && f.vok[i] && pos < 9 && yy >= 0 && yy < W && xx >= 0 && xx < W;
+            off8[i][c] = ok ? (yy * W + xx) * 8 : -1;
+            pos = 2 * c + (f.kb >> 1);
+            yy = y + pos / 3 - 1;
+            xx = x + pos % 3 - 1;
+            ok = f.vok[i] && pos < 9 && yy >= 0 && yy < W && xx >= 0 && xx < W;
+            off16[i][c] = ok ? (f.kb & 1) * FHALF + (yy * W + xx) * 8 : -1;
+        }
+    }
+
+    // ---- layer 0: features (two-plane ring in activation slot 16) -> act
+    {
+        __bf16 *ring = act + (size_t)(W - 1) * FSLOT;
+        const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wf[0]);
+        bf16x8 wr[3][5];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) wr[dz][c] = c < 3 ? wp[(dz * 3 + c) * 64 + f.lane] : zero8();
+        float b4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b4[j] = a.bias[0][4 * f.kb + j];
+        floatx4 acc[FTPW][3];
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        fused_put_x(fused_fetch_x(a, f, 0), f1t, opt, ring);
+        for (int p = 0; p < W; ++p) {
+            __syncthreads();
+            // the next plane's labels are fetched now and written after the MFMAs,
+            // into the ring half that held plane p - 1 (read during step p - 1)
+            FeatIn nx{-1, 0.0f};
+            if (p + 1 < W) nx = fused_fetch_x(a, f, p + 1);
+            fused_step<3>(ring + (p & 1) * FHALF, off8, wr, acc, f, p);
+            if (p + 1 < W) fused_put_x(nx, f1t, opt, ring + ((p + 1) & 1) * FHALF);
+            fused_retire(act, acc, f, p, b4);
+        }
+        __syncthreads();                                     // the ring (slot 16) is consumed
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i)
+            if (fused_tile(f, i)) fused_store(act, f, i, W - 1, acc[i][0], b4);
+    }
+
+    // ---- layers 1 .. 3: in place in LDS
+    for (int l = 1; l <= 3; ++l) {
+        const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wf[l]);
+        bf16x8 wr[3][5];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) wr[dz][c] = wp[(dz * 5 + c) * 64 + f.lane];
+        float b4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b4[j] = a.bias[l][4 * f.kb + j];
+        floatx4 acc[FTPW][3];
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int p = 0; p < W; ++p) {
+            __syncthreads();
+            fused_step<5>(act + (size_t)p * FSLOT, off16, wr, acc, f, p);
+            fused_retire(act, acc, f, p, b4);
+        }
+        __syncthreads();                                     // plane 16 read by every wave
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i)
+            if (fused_tile(f, i)) fused_store(act, f, i, W - 1, acc[i][0], b4);
+    }
+
+    // ---- layer 4 (16 -> 1): rows of A = dz; z5 (FP32) into the dead planes
+    float *z5 = reinterpret_cast<float *>(act);
+    {
+        const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wf[4]);
+        bf16x8 w4[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) w4[c] = wp[c * 64 + f.lane];
+        const float b5 = a.bias[4][0];
+        float sacc[FTPW][3];
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i) sacc[i][0] = sacc[i][1] = sacc[i][2] = 0.0f;
+        for (int p = 0; p < W; ++p) {
+            __syncthreads();
+            const __bf16 *xin = act + (size_t)p * FSLOT;
+            bf16x8 b[FTPW][5];
+#pragma unroll
+            for (int i = 0; i < FTPW; ++i)
+#pragma unroll
+                for (int c = 0; c < 5; ++c) b[i][c] = fused_tile(f, i) ? fused_load(xin, off16[i][c]) : zero8();
+            floatx4 c4[FTPW];
+#pragma unroll
+            for (int i = 0; i < FTPW; ++i) c4[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+#pragma unroll
+                for (int i = 0; i < FTPW; ++i)
+                    if (fused_tile(f, i)) c4[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[c], b[i][c], c4[i], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < FTPW; ++i) {
+                if (!fused_tile(f, i)) continue;
+                // lanes with kb = 0 hold rows 0..3: dz = 0 -> plane p + 1, 1 -> p, 2 -> p - 1
+                if (p + 1 < W) sacc[i][2] += c4[i][0];
+                sacc[i][1] += c4[i][1];
+                if (p > 0) {
+                    sacc[i][0] += c4[i][2];
+                    if (f.kb == 0 && f.vok[i]) z5[(size_t)(p - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
+                }
+                sacc[i][0] = sacc[i][1];
+                sacc[i][1] = sacc[i][2];
+                sacc[i][2] = 0.0f;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < FTPW; ++i)
+            if (fused_tile(f, i) && f.kb == 0 && f.vok[i]) z5[(size_t)(W - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
+        __syncthreads();
+    }
+
+    // ---- softmax over the support
+    float mx = -INFINITY;
+    for (int v = t; v < V; v += FNT)
+        if ((smask[v >> 5] >> (v & 31)) & 1u) mx = fmaxf(mx, a.prior[v] + z5[(v / W2) * FZ5 + v % W2]);
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if (f.lane == 0) redf[f.wave] = mx;
+    __syncthreads();
+    mx = redf[0];
+    for (int w = 1; w < FWAVES; ++w) mx = fmaxf(mx, redf[w]);
+    double se = 0.0;
+    for (int v = t; v < V; v += FNT)
+        if ((smask[v >> 5] >> (v & 31)) & 1u) se += (double)__expf(a.prior[v] + z5[(v / W2) * FZ5 + v % W2] - mx);
+    se = block_reduce_sum<double, FWAVES>(se, redd);
+    const float inv = (float)(1.0 / se);
+    double ms = 0.0;
+    for (int v = t; v < V; v += FNT) {
+        const float lg = a.prior[v] + z5[(v / W2) * FZ5 + v % W2];
+        const float g = ((smask[v >> 5] >> (v & 31)) & 1u) ? __expf(lg - mx) * inv : 0.0f;
+        if (a.G) a.G[(int64_t)q * V + v] = g;
+        if (a.logits) a.logits[(int64_t)q * V + v] = lg;
+        ms += (double)g;
+    }
+    ms = block_reduce_sum<double, FWAVES>(ms, redd);
+    if (t == 0 && a.mass) a.mass[q] = ms;
+}
+
 }  // namespace nn
 
 // ----------------------------------------------------------------- launchers
@@ -632,6 +1016,22 @@ static unsigned grid_1d(int64_t n, int nt)
 
 int nn_slabs_per_window() { return nn::NSLAB; }
 int nn_pack_chunks(int CI) { return nn::nchunks(CI); }
+
+int nn_fpack_elems(int layer) { return nn::fpack_count(layer) * 512; }
+
+hipError_t nn_launch_fpack(const float *w, int layer, int co_n, int ci_n, uint16_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(nn::fpack_kernel, dim3(grid_1d(nn::fpack_count(layer) * 512, 256)), dim3(256), 0, st, w,
+                       layer, co_n, ci_n, out);
+    return hipGetLastError();
+}
+
+hipError_t nn_launch_fused(const NnFusedArgs &a, int batch, hipStream_t st)
+{
+    if (batch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nn::fused_kernel, dim3(batch), dim3(nn::FNT), 0, st, a);
+    return hipGetLastError();
+}
 
 hipError_t nn_launch_features(const NnFeatArgs &a, int batch, hipStream_t st)
 {

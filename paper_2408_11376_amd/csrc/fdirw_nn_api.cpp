@@ -43,7 +43,7 @@ struct NnModel {
     int n_sub = 0;
     int64_t t = 0;            // Adam steps taken
     bool dirty = true;        // packed weights out of date
-    Buf theta, grad, m, v, prior, wp[5], wpf[5];
+    Buf theta, grad, m, v, prior, wp[5], wpf[5], wfu[5];
     NnWork ws;
     double last_loss[2] = {0.0, 0.0};
 };
@@ -58,7 +58,7 @@ static void free_buf(Buf &b)
 static void free_model(NnModel *m)
 {
     for (Buf *b : {&m->theta, &m->grad, &m->m, &m->v, &m->prior}) free_buf(*b);
-    for (int l = 0; l < 5; ++l) { free_buf(m->wp[l]); free_buf(m->wpf[l]); }
+    for (int l = 0; l < 5; ++l) { free_buf(m->wp[l]); free_buf(m->wpf[l]); free_buf(m->wfu[l]); }
     NnWork &w = m->ws;
     for (Buf *b : {&w.src, &w.X, &w.S, &w.z5, &w.G, &w.mass, &w.targ, &w.tmass, &w.loss, &w.dlog8, &w.dh, &w.dz,
                    &w.part, &w.bpart, &w.l1, &w.kmm})
@@ -102,25 +102,27 @@ static int nn_domain_check(const NnModel *m, const fdirw_domain *d)
     return FDIRW_OK;
 }
 
+// Work buffers for cap windows.  Inference (fused kernel) needs the source
+// list, G, masses and the audit's FD targets; training adds every activation.
 static int ensure_work(NnModel *m, int cap, bool train)
 {
     NnWork &w = m->ws;
     const size_t V = NN_V;
     int rc;
     if ((rc = ensure(w.src, (size_t)cap * 8))) return rc;
-    if ((rc = ensure(w.X, (size_t)cap * V * 8 * 2))) return rc;
-    if ((rc = ensure(w.S, (size_t)cap * V))) return rc;
-    for (int l = 0; l < (train ? 4 : 2); ++l)
-        if ((rc = ensure(w.h[l], (size_t)cap * V * 16 * 2))) return rc;
-    if ((rc = ensure(w.z5, (size_t)cap * V * 4))) return rc;
     if ((rc = ensure(w.G, (size_t)cap * V * 4))) return rc;
     if ((rc = ensure(w.mass, (size_t)cap * 8))) return rc;
     if ((rc = ensure(w.targ, (size_t)cap * V * 4))) return rc;
     if ((rc = ensure(w.tmass, (size_t)cap * 8))) return rc;
     if ((rc = ensure(w.l1, (size_t)cap * 8))) return rc;
     if (train) {
-        for (int l = 0; l < 4; ++l)
+        if ((rc = ensure(w.X, (size_t)cap * V * 8 * 2))) return rc;
+        if ((rc = ensure(w.S, (size_t)cap * V))) return rc;
+        if ((rc = ensure(w.z5, (size_t)cap * V * 4))) return rc;
+        for (int l = 0; l < 4; ++l) {
+            if ((rc = ensure(w.h[l], (size_t)cap * V * 16 * 2))) return rc;
             if ((rc = ensure(w.zpre[l], (size_t)cap * V * 16 * 4))) return rc;
+        }
         if ((rc = ensure(w.loss, (size_t)cap * 16))) return rc;
         if ((rc = ensure(w.dlog8, (size_t)cap * V * 8 * 2))) return rc;
         if ((rc = ensure(w.dh, (size_t)cap * V * 16 * 4))) return rc;
@@ -143,6 +145,7 @@ static int pack_weights(NnModel *m, hipStream_t st)
         if (e == hipSuccess && l >= 1)
             e = nn_launch_pack(th + layer_w_off(l), kChan[l + 1], kChan[l], l == 4 ? 8 : 16, 1,
                                (uint16_t *)m->wpf[l].p, st);
+        if (e == hipSuccess) e = nn_launch_fpack(th + layer_w_off(l), l, kChan[l + 1], kChan[l], (uint16_t *)m->wfu[l].p, st);
         if (e != hipSuccess) return hip_fail(e, "weight packing");
     }
     m->dirty = false;
@@ -174,8 +177,8 @@ static int run_features(NnModel *m, const fdirw_domain *d, int n, hipStream_t st
     return e == hipSuccess ? FDIRW_OK : hip_fail(e, "feature launch");
 }
 
-// Forward pass of n windows.  train: keep every activation and
-// pre-activation for the backward pass; else ping-pong two buffers.
+// Layer-by-layer forward pass of n windows for training: keeps every
+// activation and pre-activation for the backward pass.
 static int run_forward(NnModel *m, int n, bool train, hipStream_t st)
 {
     NnWork &w = m->ws;
@@ -280,21 +283,28 @@ static int fd_targets(NnModel *m, const fdirw_domain *d, const void *lam32, int 
     return e == hipSuccess ? FDIRW_OK : hip_fail(e, "FD target launch");
 }
 
-static int softmax_only(NnModel *m, int n, float *G, float *logits, hipStream_t st)
+// Fused inference of n windows whose sources are in ws.src: G, mass and the
+// optional logits / support outputs.
+static int run_fused(NnModel *m, const fdirw_domain *d, int n, float *G, double *mass, float *logits,
+                     uint8_t *support, hipStream_t st)
 {
-    NnLossArgs la;
-    la.z5 = (const float *)m->ws.z5.p;
-    la.prior = (const float *)m->prior.p;
-    la.support = (const uint8_t *)m->ws.S.p;
-    la.target = nullptr;
-    la.G = G;
-    la.mass = (double *)m->ws.mass.p;
-    la.logits = logits;
-    la.loss = nullptr;
-    la.dlog8 = nullptr;
-    la.grad_scale = 0.0f;
-    hipError_t e = nn_launch_loss(la, n, st);
-    return e == hipSuccess ? FDIRW_OK : hip_fail(e, "softmax launch");
+    NnFusedArgs a;
+    a.nx = d->nx; a.ny = d->ny; a.nz = d->nz;
+    a.n_sub = d->n_sub;
+    a.src = (const int64_t *)m->ws.src.p;
+    a.label = d->label;
+    NnFeatArgs t;
+    feature_tables(d, t);
+    for (int i = 0; i < 256; ++i) { a.f1[i] = t.f1[i]; a.open[i] = t.open[i]; }
+    a.prior = (const float *)m->prior.p;
+    const float *th = (const float *)m->theta.p;
+    for (int l = 0; l < 5; ++l) {
+        a.wf[l] = (const uint16_t *)m->wfu[l].p;
+        a.bias[l] = th + layer_b_off(l);
+    }
+    a.G = G; a.mass = mass; a.logits = logits; a.support = support;
+    hipError_t e = nn_launch_fused(a, n, st);
+    return e == hipSuccess ? FDIRW_OK : hip_fail(e, "fused surrogate launch");
 }
 
 // ----------------------------------------------------------------- surrogate step
@@ -330,9 +340,7 @@ int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, doub
         for (int i = 0; i < nb; ++i) hsrc[i] = (int64_t)audit_index((uint64_t)(k0 + i), (uint64_t)n);
         hipError_t e = hipMemcpyAsync(w.src.p, hsrc.data(), (size_t)nb * 8, hipMemcpyHostToDevice, stream);
         if (e != hipSuccess) return hip_fail(e, "audit sources");
-        if ((rc = run_features(m, d, nb, stream))) return rc;
-        if ((rc = run_forward(m, nb, false, stream))) return rc;
-        if ((rc = softmax_only(m, nb, (float *)w.G.p, nullptr, stream))) return rc;
+        if ((rc = run_fused(m, d, nb, (float *)w.G.p, (double *)w.mass.p, nullptr, nullptr, stream))) return rc;
         if ((rc = fd_targets(m, d, lam32, nb, stream))) return rc;
         e = nn_launch_l1((const float *)w.G.p, (const float *)w.targ.p, nb, (double *)w.l1.p, stream);
         if (e == hipSuccess) e = hipMemcpyAsync(hl1.data(), w.l1.p, (size_t)nb * 8, hipMemcpyDeviceToHost, stream);
@@ -376,9 +384,7 @@ int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, doub
         const int nb = nl * nz;
         e = nn_launch_lines_src(l0, nl, d->nx, d->ny, nz, (int64_t *)w.src.p, stream);
         if (e != hipSuccess) return hip_fail(e, "source list");
-        if ((rc = run_features(m, d, nb, stream))) return rc;
-        if ((rc = run_forward(m, nb, false, stream))) return rc;
-        if ((rc = softmax_only(m, nb, (float *)w.G.p, nullptr, stream))) return rc;
+        if ((rc = run_fused(m, d, nb, (float *)w.G.p, (double *)w.mass.p, nullptr, nullptr, stream))) return rc;
         int n_seg = (int)((1024 + nl - 1) / nl);
         if (n_seg > nz) n_seg = nz;
         const int seg_len = (nz + n_seg - 1) / n_seg;
@@ -438,6 +444,7 @@ int fdirw_nn_create(int32_t n_sub, uint64_t seed, void **nn)
     for (int l = 0; l < 5 && !rc; ++l) {
         rc = ensure(m->wp[l], (size_t)nn_pack_chunks(kStoreCI[l]) * 512 * 2);
         if (!rc) rc = ensure(m->wpf[l], (size_t)nn_pack_chunks(16) * 512 * 2);
+        if (!rc) rc = ensure(m->wfu[l], (size_t)nn_fpack_elems(l) * 2);
     }
     // default parameters: He-normal for the SiLU layers, a tenth of that for
     // the last layer (so an untrained model starts at the prior), zero biases
@@ -585,14 +592,9 @@ int fdirw_nn_forward(void *nn, const fdirw_domain *d, const int64_t *src, int64_
         const int nb = (int)((n_src - k0) < w.cap ? (n_src - k0) : w.cap);
         hipError_t e = hipMemcpyAsync(w.src.p, src + k0, (size_t)nb * 8, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "source copy");
-        if ((rc = run_features(m, d, nb, st))) return rc;
-        if ((rc = run_forward(m, nb, false, st))) return rc;
-        if ((rc = softmax_only(m, nb, G ? G + k0 * NN_V : nullptr, logits ? logits + k0 * NN_V : nullptr, st)))
+        if ((rc = run_fused(m, d, nb, G ? G + k0 * NN_V : nullptr, (double *)w.mass.p,
+                            logits ? logits + k0 * NN_V : nullptr, support ? support + k0 * NN_V : nullptr, st)))
             return rc;
-        if (support) {
-            e = hipMemcpyAsync(support + k0 * NN_V, w.S.p, (size_t)nb * NN_V, hipMemcpyDeviceToDevice, st);
-            if (e != hipSuccess) return hip_fail(e, "support copy");
-        }
     }
     return FDIRW_OK;
 }
