@@ -642,9 +642,9 @@ __global__ void fill_f32_kernel(float *__restrict__ p, int64_t n, float v)
 // overwrites input plane p - 1 during step p (one barrier per step).  MFMA
 // roles: A = weights (rows = output channels), B = activations (columns = 16
 // voxels of a plane), so each lane writes 4 consecutive channels of one
-// voxel.  Layer 0 reads its 3 (stored as 8) feature channels from a two-plane
-// ring built from the labels one step ahead; the last layer (one output
-// channel) puts the three dz taps in the A rows instead.
+// voxel.  Layer 0 reads its 3 (stored as 8) feature channels from the second
+// half of each plane's slot, filled from the labels before the first layer;
+// the last layer (one output channel) puts the three dz taps in the A rows.
 constexpr int FNT = 512;                                    // threads per workgroup
 constexpr int FWAVES = FNT / 64;                            // 8
 constexpr int FTILES = (W2 + 15) / 16;                      // 19 voxel tiles per plane
@@ -702,54 +702,26 @@ __device__ __forceinline__ void fused_store(__bf16 *act, const FusedCtx &f, int 
     *reinterpret_cast<bf16x4 *>(act + (size_t)z * FSLOT + (f.kb >> 1) * FHALF + f.vp[i] * 8 + 4 * (f.kb & 1)) = h;
 }
 
-// Global inputs of the layer-0 features of one voxel of window plane pz
-struct FeatIn {
-    int lab;                  // -1 outside the domain
-    float prior;
-};
-
-__device__ __forceinline__ FeatIn fused_fetch_x(const NnFusedArgs &a, const FusedCtx &f, int pz)
+// Operand of one lane: 8 channels at element offset off of the plane that
+// starts at element pb, or the zero vector kept at element FZERO.
+constexpr int FZERO = W * FSLOT;
+__device__ __forceinline__ bf16x8 fused_load(const __bf16 *act, int pb, int off)
 {
-    FeatIn r{-1, 0.0f};
-    const int vp = threadIdx.x;
-    if (vp < W2) {
-        const int y = vp / W, x = vp - (vp / W) * W;
-        const int gx = f.sx - R + x, gy = f.sy - R + y, gz = f.sz - R + pz;
-        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz)
-            r.lab = a.label[((int64_t)gz * a.ny + gy) * a.nx + gx];
-        r.prior = a.prior[pz * W2 + vp];
-    }
-    return r;
-}
-
-__device__ __forceinline__ void fused_put_x(const FeatIn &in, const float *f1t, const uint8_t *opt, __bf16 *ring)
-{
-    const int vp = threadIdx.x;
-    if (vp >= W2) return;
-    bf16x8 v = zero8();
-    v[0] = (__bf16)(in.lab >= 0 && opt[in.lab] ? 1.0f : 0.0f);
-    v[1] = (__bf16)(in.lab >= 0 ? f1t[in.lab] : -1.0f);
-    v[2] = (__bf16)(in.prior * (1.0f / 20.0f));
-    *reinterpret_cast<bf16x8 *>(ring + vp * 8) = v;
-}
-
-__device__ __forceinline__ bf16x8 fused_load(const __bf16 *base, int off)
-{
-    bf16x8 b = *reinterpret_cast<const bf16x8 *>(base + (off >= 0 ? off : 0));
-    return off >= 0 ? b : zero8();
+    return *reinterpret_cast<const bf16x8 *>(act + (off >= 0 ? pb + off : FZERO));
 }
 
 // One step (input plane p) of a 16-channel layer with NC chunks per dz; xin
 // points at the plane.  acc[i][0..2] = outputs p - 1, p, p + 1.
 template <int NC>
-__device__ __forceinline__ void fused_step(const __bf16 *xin, const int (&off)[FTPW][5], const bf16x8 (&wr)[3][5],
-                                           floatx4 (&acc)[FTPW][3], const FusedCtx &f, int p)
+__device__ __forceinline__ void fused_step(const __bf16 *act, int pb, const int (&off)[FTPW][5],
+                                           const bf16x8 (&wr)[3][5], floatx4 (&acc)[FTPW][3], const FusedCtx &f,
+                                           int p)
 {
     bf16x8 b[FTPW][NC];
 #pragma unroll
     for (int i = 0; i < FTPW; ++i)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) b[i][c] = fused_tile(f, i) ? fused_load(xin, off[i][c]) : zero8();
+        for (int c = 0; c < NC; ++c) b[i][c] = fused_load(act, pb, fused_tile(f, i) ? off[i][c] : -1);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -777,13 +749,14 @@ __device__ __forceinline__ void fused_retire(__bf16 *act, floatx4 (&acc)[FTPW][3
 __global__ void __launch_bounds__(FNT)
 fused_kernel(NnFusedArgs a)
 {
-    __shared__ __align__(16) __bf16 act[W * FSLOT];
+    __shared__ __align__(16) __bf16 act[W * FSLOT + 8];     // + the zero operand
     __shared__ float f1t[256];
     __shared__ uint8_t opt[256];
     __shared__ unsigned smask[(V + 31) / 32];
     __shared__ float redf[FWAVES];
     __shared__ double redd[FWAVES];
     __shared__ int flag;
+    constexpr int PER = (V + FNT - 1) / FNT;                 // window cells per thread (10)
 
     FusedCtx f;
     const int t = threadIdx.x;
@@ -802,18 +775,31 @@ fused_kernel(NnFusedArgs a)
     // ---- structural support (scratch in the activation area), kept as a bit mask
     uint8_t *openw = reinterpret_cast<uint8_t *>(act), *sa = openw + V, *sb = sa + V;
     if (t == 0) flag = 1;
-    __syncthreads();
-    int notopen = 0;
-    for (int v = t; v < V; v += FNT) {
+    if (t < 8) act[FZERO + t] = (__bf16)0.0f;
+    // the labels of this thread's cells (v = t + k FNT), all loads in flight at once
+    unsigned labp[(PER + 3) / 4] = {};                       // labels packed 4 per register
+    unsigned inmask = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int v = t + k * FNT;
         const int wx = v % W, wy = (v / W) % W, wz = v / W2;
         const int gx = f.sx - R + wx, gy = f.sy - R + wy, gz = f.sz - R + wz;
-        uint8_t op = 0;
-        if (gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz) {
-            op = opt[a.label[((int64_t)gz * a.ny + gy) * a.nx + gx]];
-            if (!op) notopen = 1;
-        }
+        const bool in = v < V && gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz;
+        inmask |= (unsigned)in << k;
+        const unsigned lb = in ? a.label[((int64_t)gz * a.ny + gy) * a.nx + gx] : 0u;
+        labp[k >> 2] |= lb << (8 * (k & 3));
+    }
+    __syncthreads();
+    int notopen = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int v = t + k * FNT;
+        if (v >= V) break;
+        const bool in = (inmask >> k) & 1u;
+        const uint8_t op = in ? opt[(labp[k >> 2] >> (8 * (k & 3))) & 255u] : 0;
+        if (in && !op) notopen = 1;
         openw[v] = op;
-        sa[v] = (wx == R && wy == R && wz == R) ? 1 : 0;
+        sa[v] = v == (R * W + R) * W + R ? 1 : 0;
     }
     if (notopen) atomicAnd(&flag, 0);
     __syncthreads();
@@ -866,9 +852,30 @@ fused_kernel(NnFusedArgs a)
         }
     }
 
-    // ---- layer 0: features (two-plane ring in activation slot 16) -> act
+    // ---- layer-0 input: the features of every plane (8 BF16 channels) in the
+    // second half of that plane's activation slot; layer 0's output plane z
+    // overwrites slot z only after feature plane z has been consumed
     {
-        __bf16 *ring = act + (size_t)(W - 1) * FSLOT;
+        float pr[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) pr[k] = t + k * FNT < V ? a.prior[t + k * FNT] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int v = t + k * FNT;
+            if (v >= V) break;
+            const int pz = v / W2, vp = v - pz * W2;
+            const bool in = (inmask >> k) & 1u;
+            bf16x8 x8 = zero8();
+            const unsigned lb = (labp[k >> 2] >> (8 * (k & 3))) & 255u;
+            x8[0] = (__bf16)(in && opt[lb] ? 1.0f : 0.0f);
+            x8[1] = (__bf16)(in ? f1t[lb] : -1.0f);
+            x8[2] = (__bf16)(pr[k] * (1.0f / 20.0f));
+            *reinterpret_cast<bf16x8 *>(act + (size_t)pz * FSLOT + FHALF + vp * 8) = x8;
+        }
+    }
+
+    // ---- layer 0 (3 -> 16 channels)
+    {
         const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wf[0]);
         bf16x8 wr[3][5];
 #pragma unroll
@@ -883,18 +890,12 @@ fused_kernel(NnFusedArgs a)
         for (int i = 0; i < FTPW; ++i)
 #pragma unroll
             for (int k = 0; k < 3; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        fused_put_x(fused_fetch_x(a, f, 0), f1t, opt, ring);
         for (int p = 0; p < W; ++p) {
             __syncthreads();
-            // the next plane's labels are fetched now and written after the MFMAs,
-            // into the ring half that held plane p - 1 (read during step p - 1)
-            FeatIn nx{-1, 0.0f};
-            if (p + 1 < W) nx = fused_fetch_x(a, f, p + 1);
-            fused_step<3>(ring + (p & 1) * FHALF, off8, wr, acc, f, p);
-            if (p + 1 < W) fused_put_x(nx, f1t, opt, ring + ((p + 1) & 1) * FHALF);
+            fused_step<3>(act, p * FSLOT + FHALF, off8, wr, acc, f, p);
             fused_retire(act, acc, f, p, b4);
         }
-        __syncthreads();                                     // the ring (slot 16) is consumed
+        __syncthreads();                                     // feature plane 16 read by every wave
 #pragma unroll
         for (int i = 0; i < FTPW; ++i)
             if (fused_tile(f, i)) fused_store(act, f, i, W - 1, acc[i][0], b4);
@@ -918,7 +919,7 @@ fused_kernel(NnFusedArgs a)
             for (int k = 0; k < 3; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         for (int p = 0; p < W; ++p) {
             __syncthreads();
-            fused_step<5>(act + (size_t)p * FSLOT, off16, wr, acc, f, p);
+            fused_step<5>(act, p * FSLOT, off16, wr, acc, f, p);
             fused_retire(act, acc, f, p, b4);
         }
         __syncthreads();                                     // plane 16 read by every wave
@@ -940,12 +941,11 @@ fused_kernel(NnFusedArgs a)
         for (int i = 0; i < FTPW; ++i) sacc[i][0] = sacc[i][1] = sacc[i][2] = 0.0f;
         for (int p = 0; p < W; ++p) {
             __syncthreads();
-            const __bf16 *xin = act + (size_t)p * FSLOT;
             bf16x8 b[FTPW][5];
 #pragma unroll
             for (int i = 0; i < FTPW; ++i)
 #pragma unroll
-                for (int c = 0; c < 5; ++c) b[i][c] = fused_tile(f, i) ? fused_load(xin, off16[i][c]) : zero8();
+                for (int c = 0; c < 5; ++c) b[i][c] = fused_load(act, p * FSLOT, fused_tile(f, i) ? off16[i][c] : -1);
             floatx4 c4[FTPW];
 #pragma unroll
             for (int i = 0; i < FTPW; ++i) c4[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -976,26 +976,43 @@ fused_kernel(NnFusedArgs a)
         __syncthreads();
     }
 
-    // ---- softmax over the support
+    // ---- softmax over the support (this thread's cells in registers)
+    float lg[PER];
+    unsigned smine = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) lg[k] = t + k * FNT < V ? a.prior[t + k * FNT] : 0.0f;
     float mx = -INFINITY;
-    for (int v = t; v < V; v += FNT)
-        if ((smask[v >> 5] >> (v & 31)) & 1u) mx = fmaxf(mx, a.prior[v] + z5[(v / W2) * FZ5 + v % W2]);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int v = t + k * FNT;
+        if (v >= V) break;
+        lg[k] += z5[(v / W2) * FZ5 + v % W2];
+        if (a.logits) a.logits[(int64_t)q * V + v] = lg[k];
+        const bool in = (smask[v >> 5] >> (v & 31)) & 1u;
+        smine |= (unsigned)in << k;
+        if (in) mx = fmaxf(mx, lg[k]);
+    }
     for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     if (f.lane == 0) redf[f.wave] = mx;
     __syncthreads();
     mx = redf[0];
     for (int w = 1; w < FWAVES; ++w) mx = fmaxf(mx, redf[w]);
     double se = 0.0;
-    for (int v = t; v < V; v += FNT)
-        if ((smask[v >> 5] >> (v & 31)) & 1u) se += (double)__expf(a.prior[v] + z5[(v / W2) * FZ5 + v % W2] - mx);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        lg[k] = ((smine >> k) & 1u) ? __expf(lg[k] - mx) : 0.0f;
+        if ((smine >> k) & 1u) se += (double)lg[k];
+    }
     se = block_reduce_sum<double, FWAVES>(se, redd);
     const float inv = (float)(1.0 / se);
     double ms = 0.0;
-    for (int v = t; v < V; v += FNT) {
-        const float lg = a.prior[v] + z5[(v / W2) * FZ5 + v % W2];
-        const float g = ((smask[v >> 5] >> (v & 31)) & 1u) ? __expf(lg - mx) * inv : 0.0f;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int v = t + k * FNT;
+        if (v >= V) break;
+        const bool in = (smine >> k) & 1u;
+        const float g = in ? lg[k] * inv : 0.0f;
         if (a.G) a.G[(int64_t)q * V + v] = g;
-        if (a.logits) a.logits[(int64_t)q * V + v] = lg;
         ms += (double)g;
     }
     ms = block_reduce_sum<double, FWAVES>(ms, redd);
