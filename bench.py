@@ -152,6 +152,68 @@ def surrogate_mode(fd, d, dom, c0, bufs, stream, args):
     return out, first
 
 
+def batched_leg(fd, args):
+    """The batched workload: 64 GRF domains (edges 32..128, r in {4, 6, 8},
+    contrast 1e2..1e6) in one persistent launch per step, FP32, autotuned
+    (the first call tunes; the timed calls reuse the cached choice)."""
+    import torch
+    import synth
+    log("batched: generating 64 domains")
+    ds = synth.config3()
+    doms = [fd.Domain.from_synth(x) for x in ds]
+    cin = [torch.from_numpy(x.c0).cuda() for x in ds]
+    cout = [torch.empty_like(c) for c in cin]
+    cells = sum(x.n for x in ds)
+    cs = sum(window_cells(x.shape, x.r) * x.n_sub for x in ds)
+    _, st = fd.fdirw_step(doms, cin, cout, prec="fp32", stats=True, tune=-1)     # tunes
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    kern = []
+    for _ in range(args.steps):
+        _, st = fd.fdirw_step(doms, cin, cout, prec="fp32", stats=True, tune=-1)
+        kern.append(st[0]["kernel_seconds"])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / args.steps
+    drift = max(abs(x["mass_out"] - x["mass_in"]) / x["mass_in"] for x in st)
+    out = {"domains": len(ds), "cells": cells, "cell_substeps": cs, "ms_per_step": ms,
+           "kernel_ms": 1e3 * float(np.mean(kern)), "cells_per_s": cells / (ms * 1e-3),
+           "cell_substeps_per_s": cs / (ms * 1e-3), "tuned_config_id": st[0]["tuned_config_id"],
+           "mass_rel_drift_max": drift}
+    log(f"batched: {ms:.1f} ms/step, {out['cells_per_s'] / 1e6:.3f} Mcells/s, "
+        f"{out['cell_substeps_per_s'] / 1e12:.3f} T cell-substeps/s, shape {out['tuned_config_id']}")
+    return out
+
+
+def bank_leg(fd, d, dom, c0, ref, args):
+    """fdirw_run with every kernel stored once as FP16 (69.5 GB at 192^3) and
+    streamed each step: the paper's stored-P use (P fixed for a fixed
+    geometry).  Reports the whole run and the per-step apply time."""
+    import torch
+    n_steps = 3
+    W3 = (2 * d.r + 1) ** 3
+    budget = d.n * W3 * 2 + d.n * 8 + (1 << 30)
+    free, _ = torch.cuda.mem_get_info()
+    if budget > free:
+        log(f"bank: needs {budget / 1e9:.1f} GB, {free / 1e9:.1f} GB free: skipped")
+        return {"skipped": f"needs {budget / 1e9:.1f} GB"}
+    log(f"bank: fdirw_run, {n_steps} steps, FP16 bank of {d.n * W3 * 2 / 1e9:.1f} GB")
+    c = c0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, st = fd.fdirw_run(dom, c, n_steps, prec="fp16_bank", stats=True, bank_budget_bytes=budget)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t
+    out = {"steps": n_steps, "seconds": total, "bank_used": st["bank_used"],
+           "apply_ms_last_step": 1e3 * st["kernel_seconds"],
+           "bank_bytes": d.n * W3 * 2,
+           "apply_GBps": d.n * W3 * 2 / st["kernel_seconds"] / 1e9 if st["kernel_seconds"] > 0 else None,
+           "mass_rel_drift": abs(st["mass_out"] - st["mass_in"]) / st["mass_in"]}
+    fd.fdirw_release()
+    log(f"bank: {total:.2f} s for {n_steps} steps, apply {out['apply_ms_last_step']:.1f} ms "
+        f"({out['apply_GBps']:.0f} GB/s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,8 +224,10 @@ def main():
     ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
     ap.add_argument("--cpu-block", type=int, default=24, help="edge of the oracle's source sample (0: skip)")
     ap.add_argument("--tune", type=int, default=-1)
-    ap.add_argument("--nn-train-steps", type=int, default=300,
+    ap.add_argument("--nn-train-steps", type=int, default=2000,
                     help="Adam steps of the surrogate before its step is timed (0: skip the surrogate)")
+    ap.add_argument("--batched", type=int, default=1, help="also time the 64-domain batched step (0: skip)")
+    ap.add_argument("--bank", type=int, default=1, help="also time fdirw_run with the FP16 kernel bank (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -229,6 +293,12 @@ def main():
     if args.nn_train_steps > 0:
         results["nn"], fields["nn"] = surrogate_mode(fd, d, dom, c0, bufs, stream, args)
 
+    extra = {}
+    if args.batched:
+        extra["batched"] = batched_leg(fd, args)
+    if args.bank:
+        extra["bank"] = bank_leg(fd, d, dom, c0, fields.get("fp32"), args)
+
     if "fp32" in fields:
         ref = fields["fp32"]
         den = float(ref.abs().sum())
@@ -278,6 +348,7 @@ def main():
         "cpu_baseline": cpu,
         "modes": results,
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

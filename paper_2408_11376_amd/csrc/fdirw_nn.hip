@@ -648,7 +648,8 @@ __global__ void fill_f32_kernel(float *__restrict__ p, int64_t n, float v)
 constexpr int FNT = 512;                                    // threads per workgroup
 constexpr int FWAVES = FNT / 64;                            // 8
 constexpr int FTILES = (W2 + 15) / 16;                      // 19 voxel tiles per plane
-constexpr int FHALF = W2 * 8;                               // BF16 elements of one 8-channel half plane
+constexpr int FPAD = W2 * 8;                                // zero 16-byte vector after each half plane
+constexpr int FHALF = W2 * 8 + 8;                           // BF16 elements of one 8-channel half plane + pad
 constexpr int FSLOT = 2 * FHALF;                            // BF16 elements of one activation plane
 constexpr int FTPW = (FTILES + FWAVES - 1) / FWAVES;        // tiles per wave (3)
 constexpr int FZ5 = FSLOT / 2;                              // float stride of the z5 planes
@@ -702,54 +703,132 @@ __device__ __forceinline__ void fused_store(__bf16 *act, const FusedCtx &f, int 
     *reinterpret_cast<bf16x4 *>(act + (size_t)z * FSLOT + (f.kb >> 1) * FHALF + f.vp[i] * 8 + 4 * (f.kb & 1)) = h;
 }
 
-// Operand of one lane: 8 channels at element offset off of the plane that
-// starts at element pb, or the zero vector kept at element FZERO.
-constexpr int FZERO = W * FSLOT;
+// Operand of one lane: 8 channels at element offset off of the half plane
+// that starts at element pb; off = FPAD reads the half plane's zero pad.
 __device__ __forceinline__ bf16x8 fused_load(const __bf16 *act, int pb, int off)
 {
-    return *reinterpret_cast<const bf16x8 *>(act + (off >= 0 ? pb + off : FZERO));
+    return *reinterpret_cast<const bf16x8 *>(act + pb + off);
 }
 
 // One step (input plane p) of a 16-channel layer with NC chunks per dz; xin
 // points at the plane.  acc[i][0..2] = outputs p - 1, p, p + 1.
-template <int NC>
-__device__ __forceinline__ void fused_step(const __bf16 *act, int pb, const int (&off)[FTPW][5],
-                                           const bf16x8 (&wr)[3][5], floatx4 (&acc)[FTPW][3], const FusedCtx &f,
-                                           int p)
-{
-    bf16x8 b[FTPW][NC];
-#pragma unroll
-    for (int i = 0; i < FTPW; ++i)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) b[i][c] = fused_load(act, pb, fused_tile(f, i) ? off[i][c] : -1);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i) {
-            if (!fused_tile(f, i)) continue;
-            acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[1][c], b[i][c], acc[i][1], 0, 0, 0);
-            if (p > 0) acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[2][c], b[i][c], acc[i][0], 0, 0, 0);
-            if (p + 1 < W) acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][c], b[i][c], acc[i][2], 0, 0, 0);
-        }
-}
+// Step kinds of a layer walk: the first plane (no output p - 1), the second
+// (nothing held back yet), the middle planes, and the last (no output p + 1).
+enum { FK_FIRST = 0, FK_SECOND = 1, FK_MID = 2, FK_LAST = 3 };
 
-__device__ __forceinline__ void fused_retire(__bf16 *act, floatx4 (&acc)[FTPW][3], const FusedCtx &f, int p,
-                                             const float *b4)
+// One step (input plane p) of a 16-output-channel layer for a wave with NT
+// tiles: the operand of chunk c feeds output planes p - 1, p, p + 1 (acc[0],
+// acc[1], acc[2]); then output plane p - 2, completed in the previous step and
+// held back so that its SiLU overlaps this step's MFMAs, is stored (its slot
+// was last read in step p - 2), and the accumulators shift: acc[3] <- p - 1,
+// acc[0] <- p, acc[1] <- p + 1, acc[2] <- 0.  pb: element offset of the half
+// plane the offsets refer to.
+template <int NT, int NC, int KIND>
+__device__ __forceinline__ void fused_kstep(__bf16 *act, int pb, int p, const int (&off)[FTPW][5],
+                                            const bf16x8 (&wr)[3][5], floatx4 (&acc)[FTPW][4], const FusedCtx &f,
+                                            const float *b4)
 {
 #pragma unroll
-    for (int i = 0; i < FTPW; ++i) {
-        if (!fused_tile(f, i)) continue;
-        if (p > 0) fused_store(act, f, i, p - 1, acc[i][0], b4);
+    for (int c = 0; c < NC; ++c) {
+        bf16x8 b[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) b[i] = fused_load(act, pb, off[i][c]);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[1][c], b[i], acc[i][1], 0, 0, 0);
+            if (KIND != FK_FIRST) acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[2][c], b[i], acc[i][0], 0, 0, 0);
+            if (KIND != FK_LAST) acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][c], b[i], acc[i][2], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        if (KIND >= FK_MID) fused_store(act, f, i, p - 2, acc[i][3], b4);
+        acc[i][3] = acc[i][0];
         acc[i][0] = acc[i][1];
         acc[i][1] = acc[i][2];
         acc[i][2] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
     }
 }
 
+// A whole 16-output-channel layer for a wave with NT tiles.  base: element
+// offset of the input half plane of plane 0 (planes are FSLOT apart).  After
+// the last step: outputs 15 (acc[3]) and 16 (acc[0]); plane 16 was read by
+// every wave in the last step, hence the barrier before storing it.
+template <int NT, int NC>
+__device__ __forceinline__ void fused_layer(__bf16 *act, int base, const int (&off)[FTPW][5],
+                                            const bf16x8 (&wr)[3][5], const FusedCtx &f, const float *b4)
+{
+    floatx4 acc[FTPW][4];
+#pragma unroll
+    for (int i = 0; i < FTPW; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    __syncthreads();
+    fused_kstep<NT, NC, FK_FIRST>(act, base, 0, off, wr, acc, f, b4);
+    __syncthreads();
+    fused_kstep<NT, NC, FK_SECOND>(act, base + FSLOT, 1, off, wr, acc, f, b4);
+    for (int p = 2; p < W - 1; ++p) {
+        __syncthreads();
+        fused_kstep<NT, NC, FK_MID>(act, base + p * FSLOT, p, off, wr, acc, f, b4);
+    }
+    __syncthreads();
+    fused_kstep<NT, NC, FK_LAST>(act, base + (W - 1) * FSLOT, W - 1, off, wr, acc, f, b4);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) fused_store(act, f, i, W - 2, acc[i][3], b4);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NT; ++i) fused_store(act, f, i, W - 1, acc[i][0], b4);
+}
+
+// The last layer (16 -> 1) for a wave with NT tiles: A rows = dz, so one MFMA
+// chain per tile gives the contributions of input plane p to output planes
+// p + 1, p, p - 1 (rows 0, 1, 2 in the lanes with kb = 0); the sums are kept
+// per lane and output plane p - 1 (FP32, + bias) goes into the dead plane p - 1.
+template <int NT>
+__device__ __forceinline__ void fused_last_layer(__bf16 *act, const int (&off)[FTPW][5], const bf16x8 (&w4)[5],
+                                                 const FusedCtx &f, float b5)
+{
+    float *z5 = reinterpret_cast<float *>(act);
+    float sacc[FTPW][3];
+#pragma unroll
+    for (int i = 0; i < FTPW; ++i) sacc[i][0] = sacc[i][1] = sacc[i][2] = 0.0f;
+    for (int p = 0; p < W; ++p) {
+        __syncthreads();
+        floatx4 c4[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) c4[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            bf16x8 b[NT];
+#pragma unroll
+            for (int i = 0; i < NT; ++i) b[i] = fused_load(act, p * FSLOT, off[i][c]);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) c4[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[c], b[i], c4[i], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            if (p + 1 < W) sacc[i][2] += c4[i][0];
+            sacc[i][1] += c4[i][1];
+            if (p > 0) {
+                sacc[i][0] += c4[i][2];
+                if (f.kb == 0 && f.vok[i]) z5[(size_t)(p - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
+            }
+            sacc[i][0] = sacc[i][1];
+            sacc[i][1] = sacc[i][2];
+            sacc[i][2] = 0.0f;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+        if (f.kb == 0 && f.vok[i]) z5[(size_t)(W - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(FNT)
 fused_kernel(NnFusedArgs a)
 {
-    __shared__ __align__(16) __bf16 act[W * FSLOT + 8];     // + the zero operand
+    __shared__ __align__(16) __bf16 act[W * FSLOT];
     __shared__ float f1t[256];
     __shared__ uint8_t opt[256];
     __shared__ unsigned smask[(V + 31) / 32];
@@ -775,7 +854,6 @@ fused_kernel(NnFusedArgs a)
     // ---- structural support (scratch in the activation area), kept as a bit mask
     uint8_t *openw = reinterpret_cast<uint8_t *>(act), *sa = openw + V, *sb = sa + V;
     if (t == 0) flag = 1;
-    if (t < 8) act[FZERO + t] = (__bf16)0.0f;
     // the labels of this thread's cells (v = t + k FNT), all loads in flight at once
     unsigned labp[(PER + 3) / 4] = {};                       // labels packed 4 per register
     unsigned inmask = 0;
@@ -824,6 +902,8 @@ fused_kernel(NnFusedArgs a)
         smask[wd] = m;
     }
     __syncthreads();                                         // mask complete; support scratch free
+    for (int k = t; k < 2 * W; k += FNT)                     // the zero pad of every half plane
+        *reinterpret_cast<bf16x8 *>(act + (size_t)k * FHALF + FPAD) = zero8();
     if (a.support)
         for (int v = t; v < V; v += FNT) a.support[(int64_t)q * V + v] = (smask[v >> 5] >> (v & 31)) & 1u;
 
@@ -843,12 +923,12 @@ fused_kernel(NnFusedArgs a)
             int pos = 4 * c + f.kb;
             int yy = y + pos / 3 - 1, xx = x + pos % 3 - 1;
             bool ok = c < 3 && f.vok[i] && pos < 9 && yy >= 0 && yy < W && xx >= 0 && xx < W;
-            off8[i][c] = ok ? (yy * W + xx) * 8 : -1;
+            off8[i][c] = ok ? (yy * W + xx) * 8 : FPAD;
             pos = 2 * c + (f.kb >> 1);
             yy = y + pos / 3 - 1;
             xx = x + pos % 3 - 1;
             ok = f.vok[i] && pos < 9 && yy >= 0 && yy < W && xx >= 0 && xx < W;
-            off16[i][c] = ok ? (f.kb & 1) * FHALF + (yy * W + xx) * 8 : -1;
+            off16[i][c] = ok ? (f.kb & 1) * FHALF + (yy * W + xx) * 8 : FPAD;
         }
     }
 
@@ -885,20 +965,8 @@ fused_kernel(NnFusedArgs a)
         float b4[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) b4[j] = a.bias[0][4 * f.kb + j];
-        floatx4 acc[FTPW][3];
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int p = 0; p < W; ++p) {
-            __syncthreads();
-            fused_step<3>(act, p * FSLOT + FHALF, off8, wr, acc, f, p);
-            fused_retire(act, acc, f, p, b4);
-        }
-        __syncthreads();                                     // feature plane 16 read by every wave
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i)
-            if (fused_tile(f, i)) fused_store(act, f, i, W - 1, acc[i][0], b4);
+        if (f.wave < FTILES - (FTPW - 1) * FWAVES) fused_layer<FTPW, 3>(act, FHALF, off8, wr, f, b4);
+        else                                      fused_layer<FTPW - 1, 3>(act, FHALF, off8, wr, f, b4);
     }
 
     // ---- layers 1 .. 3: in place in LDS
@@ -912,23 +980,11 @@ fused_kernel(NnFusedArgs a)
         float b4[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) b4[j] = a.bias[l][4 * f.kb + j];
-        floatx4 acc[FTPW][3];
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int p = 0; p < W; ++p) {
-            __syncthreads();
-            fused_step<5>(act, p * FSLOT, off16, wr, acc, f, p);
-            fused_retire(act, acc, f, p, b4);
-        }
-        __syncthreads();                                     // plane 16 read by every wave
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i)
-            if (fused_tile(f, i)) fused_store(act, f, i, W - 1, acc[i][0], b4);
+        if (f.wave < FTILES - (FTPW - 1) * FWAVES) fused_layer<FTPW, 5>(act, 0, off16, wr, f, b4);
+        else                                      fused_layer<FTPW - 1, 5>(act, 0, off16, wr, f, b4);
     }
 
-    // ---- layer 4 (16 -> 1): rows of A = dz; z5 (FP32) into the dead planes
+    // ---- layer 4 (16 -> 1): z5 (FP32) into the dead planes
     float *z5 = reinterpret_cast<float *>(act);
     {
         const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wf[4]);
@@ -936,44 +992,8 @@ fused_kernel(NnFusedArgs a)
 #pragma unroll
         for (int c = 0; c < 5; ++c) w4[c] = wp[c * 64 + f.lane];
         const float b5 = a.bias[4][0];
-        float sacc[FTPW][3];
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i) sacc[i][0] = sacc[i][1] = sacc[i][2] = 0.0f;
-        for (int p = 0; p < W; ++p) {
-            __syncthreads();
-            bf16x8 b[FTPW][5];
-#pragma unroll
-            for (int i = 0; i < FTPW; ++i)
-#pragma unroll
-                for (int c = 0; c < 5; ++c) b[i][c] = fused_load(act, p * FSLOT, fused_tile(f, i) ? off16[i][c] : -1);
-            floatx4 c4[FTPW];
-#pragma unroll
-            for (int i = 0; i < FTPW; ++i) c4[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-#pragma unroll
-                for (int i = 0; i < FTPW; ++i)
-                    if (fused_tile(f, i)) c4[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[c], b[i][c], c4[i], 0, 0, 0);
-#pragma unroll
-            for (int i = 0; i < FTPW; ++i) {
-                if (!fused_tile(f, i)) continue;
-                // lanes with kb = 0 hold rows 0..3: dz = 0 -> plane p + 1, 1 -> p, 2 -> p - 1
-                if (p + 1 < W) sacc[i][2] += c4[i][0];
-                sacc[i][1] += c4[i][1];
-                if (p > 0) {
-                    sacc[i][0] += c4[i][2];
-                    if (f.kb == 0 && f.vok[i]) z5[(size_t)(p - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
-                }
-                sacc[i][0] = sacc[i][1];
-                sacc[i][1] = sacc[i][2];
-                sacc[i][2] = 0.0f;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < FTPW; ++i)
-            if (fused_tile(f, i) && f.kb == 0 && f.vok[i]) z5[(size_t)(W - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
-        __syncthreads();
+        if (f.wave < FTILES - (FTPW - 1) * FWAVES) fused_last_layer<FTPW>(act, off16, w4, f, b5);
+        else                                      fused_last_layer<FTPW - 1>(act, off16, w4, f, b5);
     }
 
     // ---- softmax over the support (this thread's cells in registers)
