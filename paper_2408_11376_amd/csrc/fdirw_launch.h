@@ -158,6 +158,7 @@ struct NnFusedArgs {
     double *mass;             // [B] FP64 sum of G as stored, or null
     float *logits;            // [B][V], or null
     uint8_t *support;         // [B][V], or null
+    float *z5g;               // [B][V] scratch for the last layer's output (may be G)
 };
 
 int nn_slabs_per_window();

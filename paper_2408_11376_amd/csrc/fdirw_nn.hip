@@ -652,7 +652,6 @@ constexpr int FPAD = W2 * 8;                                // zero 16-byte vect
 constexpr int FHALF = W2 * 8 + 8;                           // BF16 elements of one 8-channel half plane + pad
 constexpr int FSLOT = 2 * FHALF;                            // BF16 elements of one activation plane
 constexpr int FTPW = (FTILES + FWAVES - 1) / FWAVES;        // tiles per wave (3)
-constexpr int FZ5 = FSLOT / 2;                              // float stride of the z5 planes
 constexpr int fchunks(int layer) { return layer == 0 ? 3 : 5; }
 constexpr int fpack_count(int layer) { return (layer == 4 ? 1 : 3) * fchunks(layer); }
 
@@ -687,6 +686,8 @@ struct FusedCtx {
     int sx, sy, sz;
     bool vok[FTPW];
     int vp[FTPW];
+    int sto[FTPW];            // element offset of this lane's 4 output channels within a plane
+    __bf16 *dummy;            // store target of the lanes past the last voxel
 };
 
 __device__ __forceinline__ bool fused_tile(const FusedCtx &f, int i) { return f.wave + FWAVES * i < FTILES; }
@@ -695,12 +696,13 @@ __device__ __forceinline__ bool fused_tile(const FusedCtx &f, int i) { return f.
 __device__ __forceinline__ void fused_store(__bf16 *act, const FusedCtx &f, int i, int z, const floatx4 &acc,
                                             const float *bias4)
 {
-    if (!f.vok[i]) return;
     typedef __attribute__((ext_vector_type(4))) __bf16 bf16x4;
     bf16x4 h;
 #pragma unroll
     for (int j = 0; j < 4; ++j) h[j] = (__bf16)silu_f(acc[j] + bias4[j]);
-    *reinterpret_cast<bf16x4 *>(act + (size_t)z * FSLOT + (f.kb >> 1) * FHALF + f.vp[i] * 8 + 4 * (f.kb & 1)) = h;
+    // no branch: lanes past the last voxel write a dummy vector
+    __bf16 *dst = f.vok[i] ? act + z * FSLOT + f.sto[i] : f.dummy;
+    *reinterpret_cast<bf16x4 *>(dst) = h;
 }
 
 // Operand of one lane: 8 channels at element offset off of the half plane
@@ -715,114 +717,151 @@ __device__ __forceinline__ bf16x8 fused_load(const __bf16 *act, int pb, int off)
 // Step kinds of a layer walk: the first plane (no output p - 1), the second
 // (nothing held back yet), the middle planes, and the last (no output p + 1).
 enum { FK_FIRST = 0, FK_SECOND = 1, FK_MID = 2, FK_LAST = 3 };
+#ifndef FDIRW_NN_PREFETCH
+#define FDIRW_NN_PREFETCH 1
+#endif
+constexpr bool FPREF = FDIRW_NN_PREFETCH != 0;              // carry chunk 0 of the next plane across the barrier
+#ifndef FDIRW_NN_SCHED
+#define FDIRW_NN_SCHED 1
+#endif
+constexpr bool FSCHED = FDIRW_NN_SCHED != 0;                // interleave MFMA and VALU in the middle steps
 
-// One step (input plane p) of a 16-output-channel layer for a wave with NT
-// tiles: the operand of chunk c feeds output planes p - 1, p, p + 1 (acc[0],
-// acc[1], acc[2]); then output plane p - 2, completed in the previous step and
-// held back so that its SiLU overlaps this step's MFMAs, is stored (its slot
-// was last read in step p - 2), and the accumulators shift: acc[3] <- p - 1,
-// acc[0] <- p, acc[1] <- p + 1, acc[2] <- 0.  pb: element offset of the half
-// plane the offsets refer to.
-template <int NT, int NC, int KIND>
+// One step (input plane p, P4 = p mod 4) of a 16-output-channel layer for a
+// wave with NT tiles.  acc[i][z mod 4] accumulates output plane z: the
+// operand of chunk c feeds output planes p + 1, p, p - 1 (taps dz = 0, 1, 2);
+// plane p + 1 starts from a zero accumulator.  Output plane p - 2, complete
+// since the previous step, is stored afterwards (its slot was last read in
+// step p - 2) so that its SiLU overlaps this step's MFMAs.  b0 holds the
+// chunk-0 operands of plane p (loaded before the step's barrier) and receives
+// those of plane p + 1: input planes are final until the step that stores
+// the same plane's output, two steps later.
+template <int NT, int NC, int KIND, int P4>
 __device__ __forceinline__ void fused_kstep(__bf16 *act, int pb, int p, const int (&off)[FTPW][5],
-                                            const bf16x8 (&wr)[3][5], floatx4 (&acc)[FTPW][4], const FusedCtx &f,
-                                            const float *b4)
+                                            const bf16x8 (&wr)[3][5], floatx4 (&acc)[FTPW][4], bf16x8 (&b0)[FTPW],
+                                            const FusedCtx &f, const float *b4)
 {
+    constexpr int SN = (P4 + 1) & 3, SC = P4, SP = (P4 + 3) & 3, SD = (P4 + 2) & 3;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         bf16x8 b[NT];
 #pragma unroll
-        for (int i = 0; i < NT; ++i) b[i] = fused_load(act, pb, off[i][c]);
+        for (int i = 0; i < NT; ++i) b[i] = (c == 0 && FPREF) ? b0[i] : fused_load(act, pb, off[i][c]);
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-            acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[1][c], b[i], acc[i][1], 0, 0, 0);
-            if (KIND != FK_FIRST) acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[2][c], b[i], acc[i][0], 0, 0, 0);
-            if (KIND != FK_LAST) acc[i][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][c], b[i], acc[i][2], 0, 0, 0);
+            acc[i][SC] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[1][c], b[i], acc[i][SC], 0, 0, 0);
+            if (KIND != FK_FIRST) acc[i][SP] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[2][c], b[i], acc[i][SP], 0, 0, 0);
+            if (KIND != FK_LAST) {
+                if (c == 0) acc[i][SN] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][c], b[i], floatx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+                else        acc[i][SN] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[0][c], b[i], acc[i][SN], 0, 0, 0);
+            }
         }
     }
+    if (FPREF && KIND != FK_LAST) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) {
-        if (KIND >= FK_MID) fused_store(act, f, i, p - 2, acc[i][3], b4);
-        acc[i][3] = acc[i][0];
-        acc[i][0] = acc[i][1];
-        acc[i][1] = acc[i][2];
-        acc[i][2] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < NT; ++i) b0[i] = fused_load(act, pb + FSLOT, off[i][0]);
+    }
+    if (KIND >= FK_MID) {
+#pragma unroll
+        for (int i = 0; i < NT; ++i) fused_store(act, f, i, p - 2, acc[i][SD], b4);
+    }
+    if (KIND == FK_MID && FSCHED) {
+        // interleave: each MFMA followed by up to three VALU instructions (the
+        // SiLU of the held-back plane), so both pipes stay busy
+#pragma unroll
+        for (int k = 0; k < NT * NC * 3; ++k) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        }
     }
 }
 
 // A whole 16-output-channel layer for a wave with NT tiles.  base: element
 // offset of the input half plane of plane 0 (planes are FSLOT apart).  After
-// the last step: outputs 15 (acc[3]) and 16 (acc[0]); plane 16 was read by
-// every wave in the last step, hence the barrier before storing it.
+// the last step: outputs 15 and 16; plane 16 was read by every wave in the
+// last step, hence the barrier before storing it.
 template <int NT, int NC>
 __device__ __forceinline__ void fused_layer(__bf16 *act, int base, const int (&off)[FTPW][5],
                                             const bf16x8 (&wr)[3][5], const FusedCtx &f, const float *b4)
 {
+    static_assert(W == 17, "the unrolled walk assumes 17 planes");
     floatx4 acc[FTPW][4];
 #pragma unroll
-    for (int i = 0; i < FTPW; ++i)
+    for (int i = 0; i < FTPW; ++i) acc[i][0] = acc[i][1] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 b0[FTPW];
+    __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[i][k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int i = 0; i < NT; ++i) b0[i] = FPREF ? fused_load(act, base, off[i][0]) : zero8();
+    fused_kstep<NT, NC, FK_FIRST, 0>(act, base, 0, off, wr, acc, b0, f, b4);
     __syncthreads();
-    fused_kstep<NT, NC, FK_FIRST>(act, base, 0, off, wr, acc, f, b4);
-    __syncthreads();
-    fused_kstep<NT, NC, FK_SECOND>(act, base + FSLOT, 1, off, wr, acc, f, b4);
-    for (int p = 2; p < W - 1; ++p) {
+    fused_kstep<NT, NC, FK_SECOND, 1>(act, base + FSLOT, 1, off, wr, acc, b0, f, b4);
+    for (int p = 2; p < 14; p += 4) {
         __syncthreads();
-        fused_kstep<NT, NC, FK_MID>(act, base + p * FSLOT, p, off, wr, acc, f, b4);
+        fused_kstep<NT, NC, FK_MID, 2>(act, base + p * FSLOT, p, off, wr, acc, b0, f, b4);
+        __syncthreads();
+        fused_kstep<NT, NC, FK_MID, 3>(act, base + (p + 1) * FSLOT, p + 1, off, wr, acc, b0, f, b4);
+        __syncthreads();
+        fused_kstep<NT, NC, FK_MID, 0>(act, base + (p + 2) * FSLOT, p + 2, off, wr, acc, b0, f, b4);
+        __syncthreads();
+        fused_kstep<NT, NC, FK_MID, 1>(act, base + (p + 3) * FSLOT, p + 3, off, wr, acc, b0, f, b4);
     }
     __syncthreads();
-    fused_kstep<NT, NC, FK_LAST>(act, base + (W - 1) * FSLOT, W - 1, off, wr, acc, f, b4);
+    fused_kstep<NT, NC, FK_MID, 2>(act, base + 14 * FSLOT, 14, off, wr, acc, b0, f, b4);
+    __syncthreads();
+    fused_kstep<NT, NC, FK_MID, 3>(act, base + 15 * FSLOT, 15, off, wr, acc, b0, f, b4);
+    __syncthreads();
+    fused_kstep<NT, NC, FK_LAST, 0>(act, base + 16 * FSLOT, 16, off, wr, acc, b0, f, b4);
 #pragma unroll
-    for (int i = 0; i < NT; ++i) fused_store(act, f, i, W - 2, acc[i][3], b4);
+    for (int i = 0; i < NT; ++i) fused_store(act, f, i, 15, acc[i][3], b4);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NT; ++i) fused_store(act, f, i, W - 1, acc[i][0], b4);
+    for (int i = 0; i < NT; ++i) fused_store(act, f, i, 16, acc[i][0], b4);
 }
 
-// The last layer (16 -> 1) for a wave with NT tiles: A rows = dz, so one MFMA
-// chain per tile gives the contributions of input plane p to output planes
-// p + 1, p, p - 1 (rows 0, 1, 2 in the lanes with kb = 0); the sums are kept
-// per lane and output plane p - 1 (FP32, + bias) goes into the dead plane p - 1.
+// The last layer (16 -> 1) for a wave with NT tiles: A rows = dz, so the
+// MFMAs of a tile give the contributions of input plane p to output planes
+// p + 1, p, p - 1 (rows 0, 1, 2 in the lanes with kb = 0); the lanes keep the
+// three running sums and write output plane p - 1 (FP32, + bias) to z5g, the
+// window's slice of global scratch.  The layer writes no LDS, so the waves
+// walk the planes without barriers.
 template <int NT>
-__device__ __forceinline__ void fused_last_layer(__bf16 *act, const int (&off)[FTPW][5], const bf16x8 (&w4)[5],
-                                                 const FusedCtx &f, float b5)
+__device__ __forceinline__ void fused_last_layer(const __bf16 *act, const int (&off)[FTPW][5], const bf16x8 (&w4)[5],
+                                                 const FusedCtx &f, float b5, float *z5g)
 {
-    float *z5 = reinterpret_cast<float *>(act);
     float sacc[FTPW][3];
 #pragma unroll
     for (int i = 0; i < FTPW; ++i) sacc[i][0] = sacc[i][1] = sacc[i][2] = 0.0f;
-    for (int p = 0; p < W; ++p) {
-        __syncthreads();
-        floatx4 c4[NT];
 #pragma unroll
-        for (int i = 0; i < NT; ++i) c4[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < W; ++p) {
+        floatx4 ca[NT], cb[NT];                              // even / odd chunks: two independent chains
+#pragma unroll
+        for (int i = 0; i < NT; ++i) ca[i] = cb[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             bf16x8 b[NT];
 #pragma unroll
             for (int i = 0; i < NT; ++i) b[i] = fused_load(act, p * FSLOT, off[i][c]);
 #pragma unroll
-            for (int i = 0; i < NT; ++i) c4[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[c], b[i], c4[i], 0, 0, 0);
+            for (int i = 0; i < NT; ++i) {
+                if (c & 1) cb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[c], b[i], cb[i], 0, 0, 0);
+                else       ca[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[c], b[i], ca[i], 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-            if (p + 1 < W) sacc[i][2] += c4[i][0];
-            sacc[i][1] += c4[i][1];
+            if (p + 1 < W) sacc[i][2] += ca[i][0] + cb[i][0];
+            sacc[i][1] += ca[i][1] + cb[i][1];
             if (p > 0) {
-                sacc[i][0] += c4[i][2];
-                if (f.kb == 0 && f.vok[i]) z5[(size_t)(p - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
+                sacc[i][0] += ca[i][2] + cb[i][2];
+                if (f.kb == 0 && f.vok[i]) z5g[(p - 1) * W2 + f.vp[i]] = sacc[i][0] + b5;
             }
             sacc[i][0] = sacc[i][1];
             sacc[i][1] = sacc[i][2];
             sacc[i][2] = 0.0f;
         }
     }
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < NT; ++i)
-        if (f.kb == 0 && f.vok[i]) z5[(size_t)(W - 1) * FZ5 + f.vp[i]] = sacc[i][0] + b5;
-    __syncthreads();
+        if (f.kb == 0 && f.vok[i]) z5g[(W - 1) * W2 + f.vp[i]] = sacc[i][0] + b5;
 }
 
 __global__ void __launch_bounds__(FNT)
@@ -835,6 +874,7 @@ fused_kernel(NnFusedArgs a)
     __shared__ float redf[FWAVES];
     __shared__ double redd[FWAVES];
     __shared__ int flag;
+    __shared__ __align__(16) __bf16 dummy[8];
     constexpr int PER = (V + FNT - 1) / FNT;                 // window cells per thread (10)
 
     FusedCtx f;
@@ -857,6 +897,7 @@ fused_kernel(NnFusedArgs a)
     // the labels of this thread's cells (v = t + k FNT), all loads in flight at once
     unsigned labp[(PER + 3) / 4] = {};                       // labels packed 4 per register
     unsigned inmask = 0;
+    float pr[PER];                                           // prior of the same cells
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int v = t + k * FNT;
@@ -866,6 +907,7 @@ fused_kernel(NnFusedArgs a)
         inmask |= (unsigned)in << k;
         const unsigned lb = in ? a.label[((int64_t)gz * a.ny + gy) * a.nx + gx] : 0u;
         labp[k >> 2] |= lb << (8 * (k & 3));
+        pr[k] = v < V ? a.prior[v] : 0.0f;
     }
     __syncthreads();
     int notopen = 0;
@@ -884,22 +926,15 @@ fused_kernel(NnFusedArgs a)
     const bool fast = flag && a.n_sub >= 3 * R;
     __syncthreads();
     const uint8_t *sup = fast ? nullptr : grow_support(openw, sa, sb, a.n_sub, &flag);
-    for (int wd = t; wd < (V + 31) / 32; wd += FNT) {
-        unsigned m = 0;
-        for (int b = 0; b < 32; ++b) {
-            const int v = wd * 32 + b;
-            if (v >= V) break;
-            bool in;
-            if (fast) {
-                const int wx = v % W, wy = (v / W) % W, wz = v / W2;
-                const int gx = f.sx - R + wx, gy = f.sy - R + wy, gz = f.sz - R + wz;
-                in = gx >= 0 && gx < a.nx && gy >= 0 && gy < a.ny && gz >= 0 && gz < a.nz;
-            } else {
-                in = sup[v] != 0;
-            }
-            m |= (unsigned)in << b;
-        }
-        smask[wd] = m;
+    // bit mask: cells v = t + k FNT of a wave are 64 consecutive bits
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int v = t + k * FNT;
+        const bool in = fast ? ((inmask >> k) & 1u) != 0 : (v < V && sup[v] != 0);
+        const unsigned long long bits = __ballot(in);
+        const int wd = (v - f.lane) >> 5;
+        if (f.lane == 0 && wd < (V + 31) / 32) smask[wd] = (unsigned)bits;
+        if (f.lane == 0 && wd + 1 < (V + 31) / 32) smask[wd + 1] = (unsigned)(bits >> 32);
     }
     __syncthreads();                                         // mask complete; support scratch free
     for (int k = t; k < 2 * W; k += FNT)                     // the zero pad of every half plane
@@ -913,7 +948,9 @@ fused_kernel(NnFusedArgs a)
         const int tile = f.wave + FWAVES * i;
         f.vp[i] = tile * 16 + f.n;
         f.vok[i] = tile < FTILES && f.vp[i] < W2;
+        f.sto[i] = (f.kb >> 1) * FHALF + f.vp[i] * 8 + 4 * (f.kb & 1);
     }
+    f.dummy = dummy;
     int off8[FTPW][5], off16[FTPW][5];
 #pragma unroll
     for (int i = 0; i < FTPW; ++i) {
@@ -936,9 +973,6 @@ fused_kernel(NnFusedArgs a)
     // second half of that plane's activation slot; layer 0's output plane z
     // overwrites slot z only after feature plane z has been consumed
     {
-        float pr[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) pr[k] = t + k * FNT < V ? a.prior[t + k * FNT] : 0.0f;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int v = t + k * FNT;
@@ -984,29 +1018,34 @@ fused_kernel(NnFusedArgs a)
         else                                      fused_layer<FTPW - 1, 5>(act, 0, off16, wr, f, b4);
     }
 
-    // ---- layer 4 (16 -> 1): z5 (FP32) into the dead planes
-    float *z5 = reinterpret_cast<float *>(act);
+    // ---- layer 4 (16 -> 1): z5 (FP32) into the window's global scratch slice
+    float *z5g = a.z5g + (int64_t)q * V;
+    float prs[PER];                                          // prior again, for the softmax
     {
         const bf16x8 *wp = reinterpret_cast<const bf16x8 *>(a.wf[4]);
         bf16x8 w4[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) w4[c] = wp[c * 64 + f.lane];
         const float b5 = a.bias[4][0];
-        if (f.wave < FTILES - (FTPW - 1) * FWAVES) fused_last_layer<FTPW>(act, off16, w4, f, b5);
-        else                                      fused_last_layer<FTPW - 1>(act, off16, w4, f, b5);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) prs[k] = t + k * FNT < V ? a.prior[t + k * FNT] : 0.0f;
+        __syncthreads();                                     // layer 3's last plane is stored
+        if (f.wave < FTILES - (FTPW - 1) * FWAVES) fused_last_layer<FTPW>(act, off16, w4, f, b5, z5g);
+        else                                      fused_last_layer<FTPW - 1>(act, off16, w4, f, b5, z5g);
+        __syncthreads();                                     // z5 complete and visible in the workgroup
     }
 
     // ---- softmax over the support (this thread's cells in registers)
     float lg[PER];
     unsigned smine = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) lg[k] = t + k * FNT < V ? a.prior[t + k * FNT] : 0.0f;
+    for (int k = 0; k < PER; ++k) lg[k] = prs[k];
     float mx = -INFINITY;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int v = t + k * FNT;
         if (v >= V) break;
-        lg[k] += z5[(v / W2) * FZ5 + v % W2];
+        lg[k] += z5g[v];
         if (a.logits) a.logits[(int64_t)q * V + v] = lg[k];
         const bool in = (smask[v >> 5] >> (v & 31)) & 1u;
         smine |= (unsigned)in << k;

@@ -303,6 +303,7 @@ static int run_fused(NnModel *m, const fdirw_domain *d, int n, float *G, double 
         a.bias[l] = th + layer_b_off(l);
     }
     a.G = G; a.mass = mass; a.logits = logits; a.support = support;
+    a.z5g = G ? G : (float *)m->ws.G.p;
     hipError_t e = nn_launch_fused(a, n, st);
     return e == hipSuccess ? FDIRW_OK : hip_fail(e, "fused surrogate launch");
 }
