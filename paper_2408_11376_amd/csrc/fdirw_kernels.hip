@@ -141,7 +141,7 @@ __global__ void minmax_kernel(const double *__restrict__ v, int64_t n, double *_
 {
     __shared__ double mn[256], mx[256];
     double a = INFINITY, b = -INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         a = fmin(a, PAIRS ? v[2 * i] : v[i]);
         b = fmax(b, PAIRS ? v[2 * i + 1] : v[i]);
     }
@@ -155,7 +155,7 @@ __global__ void minmax_kernel(const double *__restrict__ v, int64_t n, double *_
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) { out[0] = mn[0]; out[1] = mx[0]; }
+    if (threadIdx.x == 0) { out[2 * blockIdx.x] = mn[0]; out[2 * blockIdx.x + 1] = mx[0]; }
 }
 
 __global__ void src_check_kernel(const int64_t *__restrict__ src, int64_t n_src, int64_t n,
@@ -560,9 +560,16 @@ hipError_t launch_minmax(const double *v, int64_t n, double *out, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_minmax_scalar(const double *v, int64_t n, double *out, hipStream_t st)
+// Scalars: with part (room for 2 x 256 doubles) and many values, 256 blocks
+// write (min, max) pairs that one block then reduces.
+hipError_t launch_minmax_scalar(const double *v, int64_t n, double *part, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(minmax_kernel<false>, dim3(1), dim3(256), 0, st, v, n, out);
+    if (part && n > 65536) {
+        hipLaunchKernelGGL(minmax_kernel<false>, dim3(256), dim3(256), 0, st, v, n, part);
+        hipLaunchKernelGGL(minmax_kernel<true>, dim3(1), dim3(256), 0, st, (const double *)part, (int64_t)256, out);
+    } else {
+        hipLaunchKernelGGL(minmax_kernel<false>, dim3(1), dim3(256), 0, st, v, n, out);
+    }
     return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);
 int field_sum_blocks(int64_t n);
 hipError_t launch_field_sum(const double *v, int64_t n, double *part, double *out, hipStream_t st);
 hipError_t launch_minmax(const double *v, int64_t n, double *out, hipStream_t st);
-hipError_t launch_minmax_scalar(const double *v, int64_t n, double *out, hipStream_t st);
+hipError_t launch_minmax_scalar(const double *v, int64_t n, double *part, double *out, hipStream_t st);
 hipError_t launch_src_check(const int64_t *src, int64_t n_src, int64_t n, unsigned *bad, hipStream_t st);
 
 // ----------------------------------------------------------------- surrogate

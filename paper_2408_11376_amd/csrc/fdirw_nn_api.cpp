@@ -42,7 +42,8 @@ struct NnModel {
     int dev = -1;
     int n_sub = 0;
     int64_t t = 0;            // Adam steps taken
-    bool dirty = true;        // packed weights out of date
+    bool dirty = true;        // training operand layouts out of date
+    bool dirty_fused = true;  // fused inference layout out of date
     Buf theta, grad, m, v, prior, wp[5], wpf[5], wfu[5];
     NnWork ws;
     double last_loss[2] = {0.0, 0.0};
@@ -134,22 +135,29 @@ static int ensure_work(NnModel *m, int cap, bool train)
     return FDIRW_OK;
 }
 
-static int pack_weights(NnModel *m, hipStream_t st)
+// Packs the BF16 MFMA operands from the FP32 parameters when they changed:
+// the training layouts (forward and input-gradient) or the fused inference
+// layout, whichever the caller is about to use.
+static int pack_weights(NnModel *m, hipStream_t st, bool fused)
 {
-    if (!m->dirty) return FDIRW_OK;
     const float *th = (const float *)m->theta.p;
-    for (int l = 0; l < 5; ++l) {
-        hipError_t e = nn_launch_pack(th + layer_w_off(l), kChan[l + 1], kChan[l], kStoreCI[l], 0,
-                                      (uint16_t *)m->wp[l].p, st);
-        // input-gradient weights: input channels = this layer's outputs (8 slots for the last layer)
-        if (e == hipSuccess && l >= 1)
-            e = nn_launch_pack(th + layer_w_off(l), kChan[l + 1], kChan[l], l == 4 ? 8 : 16, 1,
-                               (uint16_t *)m->wpf[l].p, st);
-        if (e == hipSuccess) e = nn_launch_fpack(th + layer_w_off(l), l, kChan[l + 1], kChan[l], (uint16_t *)m->wfu[l].p, st);
-        if (e != hipSuccess) return hip_fail(e, "weight packing");
+    hipError_t e = hipSuccess;
+    if (fused && m->dirty_fused) {
+        for (int l = 0; l < 5 && e == hipSuccess; ++l)
+            e = nn_launch_fpack(th + layer_w_off(l), l, kChan[l + 1], kChan[l], (uint16_t *)m->wfu[l].p, st);
+        if (e == hipSuccess) m->dirty_fused = false;
     }
-    m->dirty = false;
-    return FDIRW_OK;
+    if (!fused && m->dirty) {
+        for (int l = 0; l < 5 && e == hipSuccess; ++l) {
+            e = nn_launch_pack(th + layer_w_off(l), kChan[l + 1], kChan[l], kStoreCI[l], 0, (uint16_t *)m->wp[l].p, st);
+            // input-gradient weights: input channels = this layer's outputs (8 slots for the last layer)
+            if (e == hipSuccess && l >= 1)
+                e = nn_launch_pack(th + layer_w_off(l), kChan[l + 1], kChan[l], l == 4 ? 8 : 16, 1,
+                                   (uint16_t *)m->wpf[l].p, st);
+        }
+        if (e == hipSuccess) m->dirty = false;
+    }
+    return e == hipSuccess ? FDIRW_OK : hip_fail(e, "weight packing");
 }
 
 static void feature_tables(const fdirw_domain *d, NnFeatArgs &a)
@@ -324,7 +332,7 @@ int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, doub
     if ((rc = coef_buffers(d, FDIRW_FP32, stream, dc, &geo, &lam32))) return rc;
     const int64_t n = geo.n;
     if ((rc = ensure_work(m, kMbInfer > d->nz ? kMbInfer : d->nz, false))) return rc;
-    if ((rc = pack_weights(m, stream))) return rc;
+    if ((rc = pack_weights(m, stream, true))) return rc;
     NnWork &w = m->ws;
 
     // audit: K seeded sources, mean per-kernel L1 of the surrogate against FD
@@ -393,7 +401,7 @@ int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, doub
         e = nn_launch_apply(d->nx, d->ny, nz, l0, nl, seg_len, n_seg, (const float *)w.G.p,
                             (const double *)w.mass.p, c_in, c_out, used, stream);
         if (e == hipSuccess && st)
-            e = launch_minmax_scalar((const double *)w.mass.p, nb, (double *)w.kmm.p + 2 * ci, stream);
+            e = launch_minmax_scalar((const double *)w.mass.p, nb, nullptr, (double *)w.kmm.p + 2 * ci, stream);
         if (e != hipSuccess) return hip_fail(e, "surrogate superposition");
     }
     if (st) (void)hipEventRecord(ev.b, stream);
@@ -552,7 +560,7 @@ int fdirw_nn_set_params(void *nn, const float *theta)
     std::lock_guard<std::mutex> lk(cache_mutex());
     hipError_t e = hipMemcpy(m->theta.p, theta, (size_t)num_params() * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "parameter upload");
-    m->dirty = true;
+    m->dirty = m->dirty_fused = true;
     return FDIRW_OK;
 }
 
@@ -587,7 +595,7 @@ int fdirw_nn_forward(void *nn, const fdirw_domain *d, const int64_t *src, int64_
     const void *lam32 = nullptr;
     if ((rc = coef_buffers(d, FDIRW_FP32, st, dc, &geo, &lam32))) return rc;   // validates labels
     if ((rc = ensure_work(m, kMbInfer, false))) return rc;
-    if ((rc = pack_weights(m, st))) return rc;
+    if ((rc = pack_weights(m, st, true))) return rc;
     NnWork &w = m->ws;
     for (int64_t k0 = 0; k0 < n_src; k0 += w.cap) {
         const int nb = (int)((n_src - k0) < w.cap ? (n_src - k0) : w.cap);
@@ -618,7 +626,7 @@ int fdirw_nn_backward(void *nn, const fdirw_domain *d, const int64_t *src, int64
     const void *lam32 = nullptr;
     if ((rc = coef_buffers(d, FDIRW_FP32, st, dc, &geo, &lam32))) return rc;
     if ((rc = ensure_work(m, kMbTrain, true))) return rc;
-    if ((rc = pack_weights(m, st))) return rc;
+    if ((rc = pack_weights(m, st, false))) return rc;
     NnWork &w = m->ws;
     const int64_t np = num_params();
     hipError_t e = nn_launch_fill_f32((float *)m->grad.p, np, 0.0f, st);
@@ -677,7 +685,7 @@ int fdirw_nn_adam(void *nn, double lr, double beta1, double beta2, double eps, v
                                   (int)num_params(), (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
                                   (float)c2, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "Adam launch");
-    m->dirty = true;
+    m->dirty = m->dirty_fused = true;
     return FDIRW_OK;
 }
 
@@ -730,7 +738,7 @@ int fdirw_nn_load(void *nn, const char *path)
     if (e == hipSuccess) e = hipMemcpy(m->v.p, buf.data() + 2 * np, (size_t)np * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "parameter upload");
     m->t = nums[1];
-    m->dirty = true;
+    m->dirty = m->dirty_fused = true;
     return FDIRW_OK;
 }
 

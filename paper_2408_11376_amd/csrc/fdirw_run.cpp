@@ -50,9 +50,10 @@ int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, 
         if (e != hipSuccess) return hip_fail(e, "bank generation launch");
         if (st) {
             if ((rc = ensure(dc.small, 64))) return rc;
+            if ((rc = ensure(dc.wgk, 512 * sizeof(double)))) return rc;
             double *mm = (double *)dc.small.p + 4;
             double h_mm[2] = {INFINITY, -INFINITY};
-            e = launch_minmax_scalar((const double *)dc.bank_mass.p, n, mm, stream);
+            e = launch_minmax_scalar((const double *)dc.bank_mass.p, n, (double *)dc.wgk.p, mm, stream);
             if (e == hipSuccess) e = hipMemcpyAsync(h_mm, mm, sizeof h_mm, hipMemcpyDeviceToHost, stream);
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
             if (e != hipSuccess) return hip_fail(e, "bank statistics");

@@ -196,6 +196,21 @@ def test_run_bank_equals_fused(prec):
     assert abs(sb["mass_out"] - sb["mass_in"]) <= 1e-9 * sb["mass_in"]
 
 
+@pytest.mark.parametrize("shape,r,n_sub", [((12, 11, 10), 3, 20), ((48, 40, 40), 2, 4)])
+def test_bank_kernel_mass_range_equals_fused(shape, r, n_sub):
+    # the bank's statistics reduce one mass per source (the larger domain
+    # takes the multi-block reduction); the fused step reduces per-workgroup
+    # ranges of the same kernels
+    d = synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=62)
+    dom = _dev_domain(d)
+    _, sa = fd.fdirw_run(dom, to_dev(d.c0), 1, prec=fd.FP32, stats=True)
+    _, sb = fd.fdirw_run(dom, to_dev(d.c0), 1, prec=fd.FP32, stats=True, bank_budget_bytes=1 << 34)
+    assert sb["bank_used"] == 1
+    assert sb["kmass_min"] == pytest.approx(sa["kmass_min"], rel=1e-12)
+    assert sb["kmass_max"] == pytest.approx(sa["kmass_max"], rel=1e-12)
+    assert sb["kmass_min"] <= sb["kmass_max"]
+
+
 def test_run_zero_and_odd_steps_keep_result_in_place():
     d = synth.random_small((6, 7, 8), 2, r=2, n_sub=4, seed=71)
     dom = _dev_domain(d)
