@@ -348,3 +348,24 @@ def test_training_gains_over_the_prior():
         sum(hist[:20][i][0] + hist[:20][i][1] for i in range(20))
     assert l1_1 < l1_0
     assert l1_1 < l1_prior
+
+
+@pytest.mark.slow
+def test_full_size_sampled_windows():
+    """The 192^3 workload geometry (GRF, D 1 / 1e-6, r = 8, n = 200) in the
+    launch configuration of the benchmark's surrogate step: sampled windows
+    of the fused kernel against the oracle's network."""
+    d = synth.config2()
+    params = _params(6)
+    nn = _net(params, n_sub=d.n_sub)
+    prior = su.prior_log_uniform(R, d.n_sub)
+    n = d.label.size
+    srcs = [0, n - 1, 192 * 192 * 96 + 192 * 7 + 100] + [int(x) for x in (synth.uniform(77, 3) * n).astype(np.int64)]
+    out = nn.forward(_dev(d), torch.tensor(srcs, dtype=torch.int64, device="cuda"), logits=True, support=True)
+    L, S = to_host(out["logits"]), to_host(out["support"])
+    P = oracle.Problem.from_domain(d)
+    for i, s in enumerate(srcs):
+        lo, _ = su.forward(params, su.window_features(d.label, d.d_phase, s, R, prior))
+        z5o, z5g = lo - prior, L[i].astype(np.float64) - prior
+        assert np.linalg.norm(z5g - z5o) / np.linalg.norm(z5o) <= Z_TOL, s
+        assert np.array_equal(S[i], P.support(s).astype(np.uint8)), s
