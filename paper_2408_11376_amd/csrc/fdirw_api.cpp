@@ -81,7 +81,7 @@ static void release_all()
     for (auto &kv : g_cache) {
         (void)hipSetDevice(kv.first);
         DevCache &c = kv.second;
-        for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass, &c.blam,
+        for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass, &c.bank_chat, &c.blam,
                        &c.bsmall, &c.bdoms, &c.bitems}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
@@ -334,6 +334,7 @@ int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src
     a.G = G; a.mass = mass;
     a.normalize = 0;
     a.out_lp = 0;
+    a.offset_major = 0;
     e = launch_window(o->prec, d->r, a, st);
     if (e != hipSuccess) return hip_fail(e, "window kernel launch");
     return FDIRW_OK;

@@ -20,7 +20,7 @@ struct Buf {
 // partials, per-workgroup kernel masses, a few counters, and the kernel bank.
 struct DevCache {
     int dev = -1;
-    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass;
+    Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass, bank_chat;
     Buf blam, bsmall, bdoms, bitems;      // batched launch
 };
 

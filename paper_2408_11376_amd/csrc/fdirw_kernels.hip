@@ -4,6 +4,7 @@
 //   coef_kernel            FP64 face coefficients (+ FP32 copy)
 //   window_kernel          window kernels of a source list
 //   line_kernel            fused generate + superpose
+//   bank_gather_kernel     superposition from a stored kernel bank (row form)
 //   fill / field-sum       global mass balance and output clearing
 //
 // The superposition (Eq. 8 of arXiv 2408.11376 in its column form) is
@@ -15,6 +16,13 @@
 #include "fdirw_launch.h"
 
 namespace fdirw {
+
+// Elements of one offset plane of the kernel bank, whose cells are ordered
+// [z / zb][y][x][z % zb] (zb z-consecutive values form one 16-byte group).
+__host__ __device__ inline int64_t bank_plane_elems(int nx, int ny, int nz, int zb)
+{
+    return (int64_t)((nz + zb - 1) / zb) * ny * nx * zb;
+}
 
 // ----------------------------------------------------------------- coefficients
 
@@ -218,10 +226,25 @@ window_kernel(WindowArgs a)
         if (p.act) {
             const bool norm = T::renorm && !T::bank && a.normalize;
             const double inv = norm ? 1.0 / m : 1.0;
+            const int X = sx - R + p.cx, Y = sy - R + p.cy;
+            const bool inxy = X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
+            // z cells per 16-byte group of the stored element type
+            const int zb = M == M_FP64 ? 2 : (T::bank && a.out_lp ? 8 : 4);
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k >= p.len) continue;
-                const int64_t o = q * (int64_t)W3 + (int64_t)(p.j0 + k) * W2 + p.col;
+                int64_t o;
+                if (a.offset_major) {
+                    // bank layout [offset][z / zb][y][x][z % zb]: the value at
+                    // cell x = s + o is P[o][x]; cells outside the domain are
+                    // walls (0) and are not stored
+                    const int Z = sz - R + p.j0 + k;
+                    if (!inxy || Z < 0 || Z >= a.nz) continue;
+                    o = (int64_t)((p.j0 + k) * W2 + p.col) * bank_plane_elems(a.nx, a.ny, a.nz, zb) +
+                        (((int64_t)(Z / zb) * a.ny + Y) * a.nx + X) * zb + Z % zb;
+                } else {
+                    o = q * (int64_t)W3 + (int64_t)(p.j0 + k) * W2 + p.col;
+                }
                 if constexpr (M == M_FP64) {
                     ((double *)a.G)[o] = G[k];
                 } else if constexpr (T::bank) {
@@ -328,95 +351,186 @@ line_kernel(LineArgs a)
 
 // ----------------------------------------------------------------- kernel bank
 
-template <int R> struct Win {
-    static constexpr int W = 2 * R + 1;
-    static constexpr int W2 = W * W;
-    static constexpr int W3 = W2 * W;
-    static constexpr int NT = ((W2 + 63) / 64) * 64;
+// Bank apply in the row (gather) form of Eq. 8: c'(x) = sum_o P[o][x] c^(x - o)
+// with the bank stored offset-major, P[o][x] = G_{x-o}(o) for the W^3 window
+// offsets o, and c^(s) = c(s) / m_s (renormalising modes) or c(s) (FP64).
+// Within one offset plane the cells are ordered [z / ZB][y][x][z % ZB] with
+// ZB = 16 bytes / element size, so that the ZB z-consecutive values a thread
+// needs are one 16-byte load and a wave reads 1 KB contiguously.
+// A workgroup owns a tile of 64 (x) x 1 (y) x TZ (z) output cells; every bank
+// value is read once and every output written once: no atomics, a fixed
+// summation order per cell.  c^ is read from a zero-padded copy (halo R on
+// each side); per source row y - oy the block stages the (TZ + 2R) x (64 + 2R)
+// slab of it in LDS, and each thread keeps the ZB + 2R values its z-run needs
+// in registers across the W z-offsets.
+template <typename B> struct BankZ {
+    static constexpr int ZB = 16 / (int)sizeof(B);   // z cells per 16-byte group
 };
 
-// Same line walk as line_kernel; the kernel of every source is read from the
-// stored bank (coalesced: one plane of W^2 values per wave row) and the FP64
-// ring of W planes lives in registers, shifted by one plane per source.
-template <typename B, int R, bool RENORM>
-__global__ void __launch_bounds__(Win<R>::NT)
-bank_apply_kernel(BankArgs a)
+template <typename B, int R> struct Gath {
+    static constexpr int W = 2 * R + 1;
+    static constexpr int W2 = W * W;
+    static constexpr int TX = 64;             // x cells per tile (one wave row)
+    static constexpr int TZW = 4;             // wave rows (z runs) per tile
+    static constexpr int ZB = BankZ<B>::ZB;   // z cells per thread
+    static constexpr int TZ = TZW * ZB;       // z cells per tile
+    static constexpr int SX = TX + 2 * R;     // slab extents
+    static constexpr int SZ = TZ + 2 * R;
+    static constexpr int NT = TX * TZW;
+};
+
+// c^ on the padded grid [nz + 2R][ny + 2R][nx + 2R]; the halo is 0.
+__global__ void bank_scale_kernel(const double *__restrict__ c, const double *__restrict__ mass, int nx,
+                                  int ny, int nz, int r, double *__restrict__ chat)
 {
-    constexpr int W = Win<R>::W, W2 = Win<R>::W2, W3 = Win<R>::W3;
-    const int t = threadIdx.x;
-    const bool act = t < W2;
-    const int cx = act ? t % W : 0, cy = act ? t / W : 0;
-    const int b = blockIdx.x;
-    const int line = b / a.n_seg, seg = b - line * a.n_seg;
-    const int sy = line / a.nx, sx = line - sy * a.nx;
-    const int z0 = seg * a.seg_len;
-    const int z1 = min(a.nz, z0 + a.seg_len);
-    if (z0 >= z1 || !act) return;
-    const int X = sx - R + cx, Y = sy - R + cy;
-    const bool inxy = X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
-    const B *bank = (const B *)a.bank;
-    double acc[W];
-#pragma unroll
-    for (int j = 0; j < W; ++j) acc[j] = 0.0;
-    for (int sz = z0; sz < z1; ++sz) {
-        const int64_t s = ((int64_t)sz * a.ny + sy) * a.nx + sx;
-        const double cs = a.c_in[s];
-        if (cs != 0.0) {
-            const double scale = RENORM ? cs / a.mass[s] : cs;
-            const B *g = bank + s * (int64_t)W3 + t;
-#pragma unroll
-            for (int j = 0; j < W; ++j) acc[j] = __builtin_fma(scale, (double)g[j * W2], acc[j]);
+    const int px = nx + 2 * r, py = ny + 2 * r, pz = nz + 2 * r;
+    const int64_t np = (int64_t)px * py * pz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int X = (int)(i % px) - r;
+        const int Y = (int)((i / px) % py) - r;
+        const int Z = (int)(i / ((int64_t)px * py)) - r;
+        double v = 0.0;
+        if (X >= 0 && X < nx && Y >= 0 && Y < ny && Z >= 0 && Z < nz) {
+            const int64_t s = ((int64_t)Z * ny + Y) * nx + X;
+            v = mass ? c[s] / mass[s] : c[s];
         }
-        const int Z = sz - R;
-        if (acc[0] != 0.0 && inxy && Z >= 0) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], acc[0]);
-#pragma unroll
-        for (int j = 0; j < W - 1; ++j) acc[j] = acc[j + 1];
-        acc[W - 1] = 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < W - 1; ++j) {
-        const int Z = z1 - R + j;
-        if (acc[j] != 0.0 && inxy && Z >= 0 && Z < a.nz)
-            unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], acc[j]);
+        chat[i] = v;
     }
 }
 
-template <typename B, int R, bool RENORM>
-static hipError_t launch_bank_brn(const BankArgs &a, hipStream_t st)
+// The ZB stored values of one 16-byte group, widened exactly to FP64.
+template <typename B> __device__ __forceinline__ void widen_group(const uint4 &u, double (&v)[BankZ<B>::ZB])
 {
-    const int64_t nblk = (int64_t)a.nx * a.ny * a.n_seg;
-    hipLaunchKernelGGL((bank_apply_kernel<B, R, RENORM>), dim3((unsigned)nblk), dim3(Win<R>::NT), 0, st, a);
+    constexpr int ZB = BankZ<B>::ZB;
+    B e[ZB];
+    __builtin_memcpy(e, &u, 16);
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) v[k] = (double)(float)e[k];
+}
+template <> __device__ __forceinline__ void widen_group<double>(const uint4 &u, double (&v)[2])
+{
+    __builtin_memcpy(v, &u, 16);
+}
+
+template <typename B, int R>
+__global__ void __launch_bounds__((Gath<B, R>::NT)) bank_gather_kernel(BankArgs a)
+{
+    using G_ = Gath<B, R>;
+    constexpr int W = G_::W, W2 = G_::W2, ZB = G_::ZB, SX = G_::SX, SZ = G_::SZ, NT = G_::NT;
+    __shared__ double slab[SZ * SX];
+    const int tx = threadIdx.x % G_::TX, tz = threadIdx.x / G_::TX;
+    const int x0 = blockIdx.x * G_::TX, y = blockIdx.y, z0 = blockIdx.z * G_::TZ;
+    const int x = x0 + tx;
+    const int zt = z0 + tz * ZB;                      // first output z of the thread (uniform per wave)
+    const int px = a.nx + 2 * R, py = a.ny + 2 * R, pz = a.nz + 2 * R;
+    const bool act = x < a.nx && zt < a.nz;
+    // the thread's group in every offset plane, and the plane stride
+    const int64_t grp = (((int64_t)(zt / ZB) * a.ny + y) * a.nx + x) * ZB;
+    const int64_t plane = bank_plane_elems(a.nx, a.ny, a.nz, ZB);
+    const B *P = (const B *)a.bank + grp;
+    double acc[ZB];
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) acc[k] = 0.0;
+
+    for (int oy = -R; oy <= R; ++oy) {
+        const int64_t row = (int64_t)(y - oy + R) * px;   // padded source row
+        __syncthreads();                                  // the previous slab is consumed
+        for (int i = threadIdx.x; i < SZ * SX; i += NT) {
+            const int iz = i / SX, ix = i - iz * SX;
+            const int zz = z0 + iz, xx = x0 + ix;         // padded source coordinates
+            slab[i] = (zz < pz && xx < px) ? a.chat[(int64_t)zz * py * px + row + xx] : 0.0;
+        }
+        __syncthreads();
+        if (!act) continue;
+        for (int ox = -R; ox <= R; ++ox) {
+            // source (z - oz, y - oy, x - ox): slab column tx - ox + R, slab row
+            // tz*ZB + k - oz + R = tz*ZB + m with m = k - j + 2R, j = oz + R
+            const int ix = tx - ox + R;
+            double cc[ZB + 2 * R];
+#pragma unroll
+            for (int m = 0; m < ZB + 2 * R; ++m) cc[m] = slab[(tz * ZB + m) * SX + ix];
+            const int64_t obase = (int64_t)(oy + R) * W + (ox + R);
+            // all W groups of this (oy, ox) are requested before the first is
+            // used, so that each wave keeps W x 1 KB of bank reads in flight
+            uint4 raw[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) raw[j] = *(const uint4 *)(P + ((int64_t)j * W2 + obase) * plane);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                double g[ZB];
+                widen_group<B>(raw[j], g);
+#pragma unroll
+                for (int k = 0; k < ZB; ++k) acc[k] = __builtin_fma(g[k], cc[k - j + 2 * R], acc[k]);
+            }
+        }
+    }
+    if (act) {
+        const int64_t o0 = ((int64_t)zt * a.ny + y) * a.nx + x;
+        const int64_t nxy = (int64_t)a.nx * a.ny;
+#pragma unroll
+        for (int k = 0; k < ZB; ++k)
+            if (zt + k < a.nz) a.c_out[o0 + k * nxy] = acc[k];
+    }
+}
+
+template <typename B, int R>
+static hipError_t launch_gather_r(const BankArgs &a, hipStream_t st)
+{
+    using G_ = Gath<B, R>;
+    const dim3 grid((unsigned)((a.nx + G_::TX - 1) / G_::TX), (unsigned)a.ny, (unsigned)((a.nz + G_::TZ - 1) / G_::TZ));
+    hipLaunchKernelGGL((bank_gather_kernel<B, R>), grid, dim3(G_::NT), 0, st, a);
     return hipGetLastError();
 }
 
-template <typename B, bool RENORM>
-static hipError_t launch_bank_b(int r, const BankArgs &a, hipStream_t st)
+template <typename B>
+static hipError_t launch_gather_b(int r, const BankArgs &a, hipStream_t st)
 {
     switch (r) {
-    case 0: return launch_bank_brn<B, 0, RENORM>(a, st);
-    case 1: return launch_bank_brn<B, 1, RENORM>(a, st);
-    case 2: return launch_bank_brn<B, 2, RENORM>(a, st);
-    case 3: return launch_bank_brn<B, 3, RENORM>(a, st);
-    case 4: return launch_bank_brn<B, 4, RENORM>(a, st);
-    case 5: return launch_bank_brn<B, 5, RENORM>(a, st);
-    case 6: return launch_bank_brn<B, 6, RENORM>(a, st);
-    case 7: return launch_bank_brn<B, 7, RENORM>(a, st);
-    case 8: return launch_bank_brn<B, 8, RENORM>(a, st);
+    case 0: return launch_gather_r<B, 0>(a, st);
+    case 1: return launch_gather_r<B, 1>(a, st);
+    case 2: return launch_gather_r<B, 2>(a, st);
+    case 3: return launch_gather_r<B, 3>(a, st);
+    case 4: return launch_gather_r<B, 4>(a, st);
+    case 5: return launch_gather_r<B, 5>(a, st);
+    case 6: return launch_gather_r<B, 6>(a, st);
+    case 7: return launch_gather_r<B, 7>(a, st);
+    case 8: return launch_gather_r<B, 8>(a, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+int64_t bank_chat_elems(int nx, int ny, int nz, int r)
+{
+    return (int64_t)(nx + 2 * r) * (ny + 2 * r) * (nz + 2 * r);
+}
+
+int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes)
+{
+    const int64_t w = 2 * r + 1;
+    return w * w * w * bank_plane_elems(nx, ny, nz, 16 / elem_bytes);
 }
 
 hipError_t launch_bank_apply(int prec, int r, const BankArgs &a, hipStream_t st)
 {
+    if (r < 0 || r > 8) return hipErrorInvalidValue;
+    const int64_t np = bank_chat_elems(a.nx, a.ny, a.nz, r);
+    const int64_t blocks = (np + 255) / 256 < 8192 ? (np + 255) / 256 : 8192;
+    hipLaunchKernelGGL(bank_scale_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a.c_in,
+                       prec == M_FP64 ? nullptr : a.mass, a.nx, a.ny, a.nz, r, a.chat);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     switch (prec) {
-    case M_FP64: return launch_bank_b<double, false>(r, a, st);
+    case M_FP64: return launch_gather_b<double>(r, a, st);
     case M_FP32: case M_F16X32: case M_BF16X32: case M_F16ST: case M_BF16ST:
-        return launch_bank_b<float, true>(r, a, st);
-    case M_F16BANK: return launch_bank_b<_Float16, true>(r, a, st);
-    case M_BF16BANK: return launch_bank_b<__bf16, true>(r, a, st);
+        return launch_gather_b<float>(r, a, st);
+    case M_F16BANK: return launch_gather_b<_Float16>(r, a, st);
+    case M_BF16BANK: return launch_gather_b<__bf16>(r, a, st);
     default: return hipErrorInvalidValue;
     }
 }
+
 
 // ----------------------------------------------------------------- dispatch
 

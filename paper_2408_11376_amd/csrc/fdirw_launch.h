@@ -34,17 +34,19 @@ struct WindowArgs {
     double *mass;
     int normalize;            // renormalising modes: write G / mass instead of G
     int out_lp;               // BANK modes: write the 16-bit rounded values
+    int offset_major;         // store as the bank [W^3][z/zb][y][x][z%zb] (zb = 16 B / element):
+                              // P[o][s + o] = G_s(o); cells outside the domain are skipped
 };
 
-// Apply a stored kernel bank: same line walk as the fused step, kernels read
-// from HBM instead of generated.
+// Apply a stored kernel bank in the row form c'(x) = sum_o P[o][x] c^(x - o).
 struct BankArgs {
     int nx, ny, nz;
-    int seg_len, n_seg;
-    const void *bank;         // [N][W][W][W] of the bank element type
-    const double *mass;       // [N] kernel mass (renormalising modes), or null
+    int64_t n;
+    const void *bank;         // offset-major bank (bank_elems() elements of the bank type)
+    const double *mass;       // [N] kernel mass (renormalising modes)
     const double *c_in;
-    double *c_out;
+    double *c_out;            // every cell written
+    double *chat;             // scratch of bank_chat_elems() doubles
 };
 
 // Batched persistent launch (fdirw_batched.hip).
@@ -81,6 +83,8 @@ hipError_t launch_coef(const uint8_t *label, int nx, int ny, int nz, const CoefT
 hipError_t launch_line(int mode, int r, const LineArgs &a, hipStream_t st);
 hipError_t launch_window(int mode, int r, const WindowArgs &a, hipStream_t st);
 hipError_t launch_bank_apply(int prec, int r, const BankArgs &a, hipStream_t st);
+int64_t bank_chat_elems(int nx, int ny, int nz, int r);
+int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes);   // offset-major bank, padded
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);
 int field_sum_blocks(int64_t n);

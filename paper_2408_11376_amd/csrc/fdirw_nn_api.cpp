@@ -287,6 +287,7 @@ static int fd_targets(NnModel *m, const fdirw_domain *d, const void *lam32, int 
     a.mass = (double *)m->ws.tmass.p;
     a.normalize = 1;
     a.out_lp = 0;
+    a.offset_major = 0;
     hipError_t e = launch_window(FDIRW_FP32, NN_R, a, st);
     return e == hipSuccess ? FDIRW_OK : hip_fail(e, "FD target launch");
 }
@@ -509,6 +510,7 @@ int fdirw_nn_create(int32_t n_sub, uint64_t seed, void **nn)
             a.G = G; a.mass = mass;
             a.normalize = 0;
             a.out_lp = 0;
+            a.offset_major = 0;
             hipError_t e = launch_window(FDIRW_FP64, NN_R, a, st);
             if (e == hipSuccess) e = hipMemcpy(hG.data(), G, (size_t)NN_V * 8, hipMemcpyDeviceToHost);
             if (e != hipSuccess) rc = hip_fail(e, "prior kernel");
