@@ -11,12 +11,14 @@ phase-field particle geometry is not available).
 A "step" is one fdirw_step call: coefficients, kernel generation for every
 source, FP64 scatter-add superposition and the FP64 mass balance.  Steps are
 chained (output -> next input).  ``value`` = 192^3 cells / seconds per step in
-the headline precision (FP32 state with FP16 neighbour copies, the mixed
-precision configuration); the plain FP32 and the BF16-copy steps are timed the
-same way and reported under ``modes`` with their speedup over FP32 and their
-relative L1 difference from the FP32 field.
+the headline precision (default FP32, the fastest fused mode on gfx950); the
+mixed precision steps (FP32 state with FP16 or BF16 neighbour copies) are timed
+the same way and reported under ``modes`` with their speedup over FP32 and
+their relative L1 difference from the FP32 field.  The ``bank`` leg stores
+every kernel once (in FP32 and in FP16, the paper's stored-P use) and times
+the HBM-streaming apply of one big step.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp16x32] [--nn-train-steps S]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32] [--nn-train-steps S]
 
 The learned generator (surrogate) is trained for S Adam steps on two other
 seeded 64^3 geometries of the same kind and its step is timed under ``modes``
@@ -231,7 +233,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="fp16x32", help="headline precision mode")
+    ap.add_argument("--prec", default="fp32", help="headline precision mode")
     ap.add_argument("--modes", default="fp32,fp16x32,bf16x32", help="modes timed for the comparison")
     ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
     ap.add_argument("--cpu-block", type=int, default=24, help="edge of the oracle's source sample (0: skip)")

@@ -1,13 +1,16 @@
 """One fused FDiRW step on a seeded porous grid, for profiler runs.
 
-    python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024] [--gen nn]
+    python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024] [--gen nn] [--bank 1]
 
 Runs one untimed warm-up step, then ``--reps`` steps of the config-2 style
 workload (GRF porous grid, r = 8, 200 sub-steps) at edge ``--n``.  With
 ``--copy-mib`` it also runs one plain device-to-device copy of that many MiB,
 the reference for scaling HBM byte counters (FETCH_SIZE / WRITE_SIZE).
 With ``--gen nn`` the steps use a surrogate (default initialisation, audit
-disabled, so every kernel is the network's) instead of the FD kernels.
+disabled, so every kernel is the network's) instead of the FD kernels.  With
+``--bank 1`` each repetition is instead one fdirw_run call that stores every
+kernel once in a bank of the precision ``--prec`` (fp32, fp16_bank, ...) and
+applies it for one big step.
 """
 import argparse
 import os
@@ -27,6 +30,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--tune", type=int, default=-1)
     ap.add_argument("--gen", default="fd", choices=["fd", "nn"])
+    ap.add_argument("--bank", type=int, default=0)
     args = ap.parse_args()
     import torch
     import synth
@@ -38,6 +42,15 @@ def main():
     kw = {}
     if args.gen == "nn":
         kw = {"nn": fd.Surrogate(d.n_sub, seed=0), "audit_tol": 1e30, "audit_samples": 1}
+    if args.bank:
+        for i in range(args.reps):
+            cb = c.clone()
+            _, st = fd.fdirw_run(dom, cb, 1, prec=args.prec, stats=True, bank_budget_bytes=1 << 40)
+            print(f"[profile_step] n={args.n} bank prec={args.prec} rep {i}: bank used {st['bank_used']}, "
+                  f"apply {st['kernel_seconds'] * 1e3:.2f} ms", flush=True)
+            fd.fdirw_release()
+        args.reps = 0
+        args.warmup = 0
     for _ in range(args.warmup):
         fd.fdirw_step(dom, c, out, prec=args.prec, tune=args.tune, **kw)
     torch.cuda.synchronize()

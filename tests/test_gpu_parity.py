@@ -196,6 +196,23 @@ def test_run_bank_equals_fused(prec):
     assert abs(sb["mass_out"] - sb["mass_in"]) <= 1e-9 * sb["mass_in"]
 
 
+@pytest.mark.parametrize("prec", [fd.FP32, fd.FP16_BANK, fd.FP64])
+def test_run_bank_equals_fused_several_tiles(prec):
+    # r = 8 on a grid that spans two x tiles of the apply (the second ragged),
+    # a ragged last z tile and z groups, against the fused step (whose kernels
+    # are the same values, superposed in another order)
+    d = synth.random_small((37, 21, 70), 3, r=8, n_sub=12, seed=63)
+    dom = _dev_domain(d)
+    a = to_dev(d.c0)
+    b = to_dev(d.c0)
+    fd.fdirw_run(dom, a, 2, prec=prec)
+    _, sb = fd.fdirw_run(dom, b, 2, prec=prec, stats=True, bank_budget_bytes=1 << 34)
+    assert sb["bank_used"] == 1
+    A, B = to_host(a), to_host(b)
+    assert np.max(np.abs(A - B)) <= 1e-12 * np.abs(A).max()
+    assert abs(sb["mass_out"] - sb["mass_in"]) <= 1e-12 * sb["mass_in"]
+
+
 @pytest.mark.parametrize("shape,r,n_sub", [((12, 11, 10), 3, 20), ((48, 40, 40), 2, 4)])
 def test_bank_kernel_mass_range_equals_fused(shape, r, n_sub):
     # the bank's statistics reduce one mass per source (the larger domain
