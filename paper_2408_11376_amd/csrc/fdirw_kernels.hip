@@ -367,11 +367,15 @@ template <typename B> struct BankZ {
     static constexpr int ZB = 16 / (int)sizeof(B);   // z cells per 16-byte group
 };
 
+#ifndef FDIRW_GATHER_TZW
+#define FDIRW_GATHER_TZW 4                    // wave rows (z runs) per bank-apply tile
+#endif
+
 template <typename B, int R> struct Gath {
     static constexpr int W = 2 * R + 1;
     static constexpr int W2 = W * W;
     static constexpr int TX = 64;             // x cells per tile (one wave row)
-    static constexpr int TZW = 4;             // wave rows (z runs) per tile
+    static constexpr int TZW = FDIRW_GATHER_TZW;
     static constexpr int ZB = BankZ<B>::ZB;   // z cells per thread
     static constexpr int TZ = TZW * ZB;       // z cells per tile
     static constexpr int SX = TX + 2 * R;     // slab extents

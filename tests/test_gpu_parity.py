@@ -213,6 +213,25 @@ def test_run_bank_equals_fused_several_tiles(prec):
     assert abs(sb["mass_out"] - sb["mass_in"]) <= 1e-12 * sb["mass_in"]
 
 
+@pytest.mark.parametrize("prec", [fd.FP32, fd.FP16_BANK, fd.FP64])
+@pytest.mark.parametrize("shape,r,n_sub", [((1, 1, 1), 0, 3), ((1, 1, 1), 2, 3), ((9, 2, 1), 1, 5),
+                                           ((3, 1, 70), 2, 4), ((17, 5, 65), 4, 0)])
+def test_run_bank_degenerate_shapes(prec, shape, r, n_sub):
+    # single cells, windows larger than the domain, z shorter than one 16-byte
+    # group, lines of one cell, n_sub = 0 (identity kernels): bank == fused
+    d = synth.random_small(shape, 2, r=r, n_sub=n_sub, seed=64)
+    dom = _dev_domain(d)
+    a = to_dev(d.c0)
+    b = to_dev(d.c0)
+    fd.fdirw_run(dom, a, 2, prec=prec)
+    _, sb = fd.fdirw_run(dom, b, 2, prec=prec, stats=True, bank_budget_bytes=1 << 34)
+    assert sb["bank_used"] == 1
+    A, B = to_host(a), to_host(b)
+    assert np.max(np.abs(A - B)) <= 1e-12 * max(np.abs(A).max(), 1e-300)
+    if n_sub == 0:
+        assert np.array_equal(B, d.c0)
+
+
 @pytest.mark.parametrize("shape,r,n_sub", [((12, 11, 10), 3, 20), ((48, 40, 40), 2, 4)])
 def test_bank_kernel_mass_range_equals_fused(shape, r, n_sub):
     # the bank's statistics reduce one mass per source (the larger domain
