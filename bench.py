@@ -46,6 +46,14 @@ PEAK_HBM_GBS = 8000.0
 # neighbour copy (the two z neighbours stay in registers).
 FLOP_PER_CELL_SUBSTEP = 13
 LDS_ACCESSES_PER_CELL_SUBSTEP = 5
+FMA_PER_CELL_SUBSTEP = 7
+# Chip rates for the secondary ceilings of the fused kernel: 256 CUs at
+# 2.4 GHz; one FP32 FMA per lane per clock on 4 x 16 lanes per CU (packed FP32
+# is not used); LDS rates measured on the MI355X with a microbenchmark:
+# 128-bit reads ~198 B/clk/CU, writes ~75 B/clk/CU.
+CU_HZ = 256 * 2.4e9
+LDS_READ_B_PER_CLK = 198.0
+LDS_WRITE_B_PER_CLK = 75.0
 
 
 def log(msg):
@@ -98,8 +106,22 @@ def cpu_baseline(dom, block: int):
     t = time.perf_counter()
     _, used, _ = p.step(c0)
     dt = time.perf_counter() - t
-    return {"value": used / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{block}^3 = {used} sources of the 192^3 step (c0 zeroed elsewhere), {dt:.2f} s"}
+    out = {"value": used / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{block}^3 = {used} sources of the {dom.shape[0]}^3 step (c0 zeroed elsewhere), {dt:.2f} s"}
+    # one core (the paper's CPU reference is one core): a smaller cube of sources
+    b1 = max(2, block // 3)
+    m1 = synth.sub_block_sources(dom.shape, b1)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        _, used1, _ = p.step(np.where(m1, dom.c0, 0.0))
+        dt1 = time.perf_counter() - t
+    finally:
+        oracle.set_num_threads(threads)
+    out["value_1core"] = used1 / dt1
+    out["sample_1core"] = f"{b1}^3 = {used1} sources on 1 thread, {dt1:.2f} s"
+    return out
 
 
 def surrogate_mode(fd, d, dom, c0, bufs, stream, args):
@@ -218,6 +240,8 @@ def bank_leg(fd, d, dom, c0, ref, args):
                "mass_rel_drift": abs(st["mass_out"] - st["mass_in"]) / st["mass_in"]}
         if rec["apply_GBps"]:
             rec["hbm_frac"] = rec["apply_GBps"] / PEAK_HBM_GBS
+        # P computed once and reused (the paper's use): cost per step over 10 steps
+        rec["amortised_ms_per_step_10"] = (1e3 * total + 9 * rec["apply_ms"]) / 10
         if ref is not None:
             rec["rel_l1_vs_fp32"] = float((c - ref).abs().sum()) / float(ref.abs().sum())
         out[prec] = rec
@@ -300,6 +324,7 @@ def main():
             "mass_rel_drift": abs(first_st["mass_out"] - first_st["mass_in"]) / first_st["mass_in"],
             "kernel_mass_range": [first_st["kmass_min"], first_st["kmass_max"]],
             "sources": first_st["n_sources"],
+            "cell_substeps_per_s": window_cells(d.shape, d.r) * d.n_sub / (ms * 1e-3),
         }
         log(f"{mode}: {ms:.1f} ms/step, kernel {results[mode]['kernel_ms']:.1f} ms, "
             f"{results[mode]['cells_per_s'] / 1e6:.3f} Mcells/s")
@@ -325,14 +350,21 @@ def main():
     flops = FLOP_PER_CELL_SUBSTEP * cs
     achieved = flops / (head["kernel_ms"] * 1e-3) / 1e12
     esize = {"fp32": 4, "fp64": 8}.get(args.prec, 2)
-    lds_tbs = LDS_ACCESSES_PER_CELL_SUBSTEP * esize * cs / (head["kernel_ms"] * 1e-3) / 1e12
+    t_kern = head["kernel_ms"] * 1e-3
+    lds_tbs = LDS_ACCESSES_PER_CELL_SUBSTEP * esize * cs / t_kern / 1e12
+    # exchange time at the LDS rates (four neighbour reads, one write per
+    # cell-sub-step) and FMA issue time at one FMA per lane per clock
+    t_lds = cs * (4 * esize / LDS_READ_B_PER_CLK + esize / LDS_WRITE_B_PER_CLK) / CU_HZ
+    t_valu = cs * FMA_PER_CELL_SUBSTEP / (64 * CU_HZ)
     kernel_tag = f"line_kernel_{args.prec}_grf{args.n}"
     traffic = read_traffic(kernel_tag)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                 "kernel": f"line_kernel<{args.prec}, r=8>",
                 "cell_substeps_per_launch": cs, "flop_per_cell_substep": FLOP_PER_CELL_SUBSTEP,
-                "lds_exchange_TBps": lds_tbs}
+                "lds_exchange_TBps": lds_tbs,
+                "lds_bound_s": t_lds, "lds_frac": t_lds / t_kern,
+                "fma_issue_bound_s": t_valu, "fma_issue_frac": t_valu / t_kern}
 
     cpu = None
     if args.cpu_block > 0:

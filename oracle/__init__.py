@@ -68,6 +68,8 @@ def _load():
         lib.fo_sum.restype = f64
         lib.fo_num_threads.argtypes = []
         lib.fo_num_threads.restype = i32
+        lib.fo_set_num_threads.argtypes = [i32]
+        lib.fo_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -84,6 +86,11 @@ def _grid(label: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().fo_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    _load().fo_set_num_threads(int(n))
 
 
 def resolve_dt(label, d_phase, h: float = 1.0, dt: float = 0.0) -> float:

@@ -310,3 +310,13 @@ int fo_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads used by the OpenMP loops from now on (timing on one core). */
+void fo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
