@@ -1,0 +1,73 @@
+"""Pins of the coarse-mesh oracle (Sec. 3.1, Eqs. 10-15) against results that
+it does not compute itself: the fine oracle step (B = 1), the whole-domain
+average (one block), dense powers of the whole-domain operator aggregated by
+blocks, and mass conservation.  CPU only."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from closed_forms import dense_operator
+from oracle import coarse
+
+
+def _problem(d):
+    return oracle.Problem(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
+
+
+@pytest.mark.parametrize("shape,r,n_sub,seed", [((6, 7, 5), 2, 6, 1), ((4, 5, 9), 1, 3, 2)])
+def test_block_one_is_the_fine_step(shape, r, n_sub, seed):
+    d = synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=seed)
+    p = _problem(d)
+    P = coarse.coarse_matrix(p, 1)
+    got = coarse.step(p, P, d.c0, 1)
+    ref, _, _ = p.step(d.c0)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+def test_one_block_is_the_domain_average():
+    d = synth.random_small((5, 4, 6), 2, r=2, n_sub=5, seed=3, d_zero_phase=False)
+    p = _problem(d)
+    P = coarse.coarse_matrix(p, 8)
+    assert P.shape == (1, 1)
+    assert abs(P[0, 0] - 1.0) <= 1e-13
+    got = coarse.step(p, P, d.c0, 8)
+    assert np.max(np.abs(got - d.c0.mean())) <= 1e-13
+
+
+@pytest.mark.parametrize("B", [2, 3])
+def test_matrix_equals_aggregated_whole_domain_operator(B):
+    # windows larger than the domain: every fine kernel is a column of the
+    # n-th power of the whole-domain one-sub-step operator, so
+    # S = A M^n A^T with A the block membership of the mobile cells
+    d = synth.random_small((3, 4, 5), 3, r=5, n_sub=4, seed=4)
+    p = _problem(d)
+    M = np.linalg.matrix_power(dense_operator(d.label, d.d_phase, p.dt, p.h), d.n_sub)
+    block, mobile, count = coarse.groups(d.label, d.d_phase, B)
+    A = np.zeros((count.size, d.label.size))
+    A[block.ravel()[mobile.ravel()], np.flatnonzero(mobile.ravel())] = 1.0
+    S = A @ M @ A.T
+    ref = np.zeros_like(S)
+    ref[count > 0] = S[count > 0] / count[count > 0, None]
+    got = coarse.coarse_matrix(p, B)
+    assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("B", [2, 3, 5])
+def test_mass_conserved_and_immobile_cells_kept(B):
+    d = synth.random_small((7, 6, 8), 3, r=2, n_sub=8, seed=5)
+    p = _problem(d)
+    P = coarse.coarse_matrix(p, B)
+    _, mobile, count = coarse.groups(d.label, d.d_phase, B)
+    # column sums of the mass form N_I P[I, J] / N_J are one
+    has = count > 0
+    colsum = (count[:, None] * P)[:, has].sum(axis=0) / count[has]
+    assert np.max(np.abs(colsum - 1.0)) <= 1e-13
+    got = coarse.step(p, P, d.c0, B)
+    assert abs(got.sum() - d.c0.sum()) <= 1e-12 * d.c0.sum()
+    assert np.array_equal(got[~mobile], d.c0[~mobile])
+    # remapping makes every group uniform
+    block, _, _ = coarse.groups(d.label, d.d_phase, B)
+    for I in np.flatnonzero(has)[:10]:
+        vals = got[mobile & (block == I)]
+        assert np.all(vals == vals[0])
