@@ -11,7 +11,9 @@ Names follow the ABI:
     fdirw_field_sum, fdirw_last_error, fdirw_release, fdirw_abi_version,
     fdirw_nn_create, fdirw_nn_destroy, fdirw_nn_num_params,
     fdirw_nn_set_params, fdirw_nn_get_params, fdirw_nn_forward,
-    fdirw_nn_backward, fdirw_nn_adam, fdirw_nn_save, fdirw_nn_load
+    fdirw_nn_backward, fdirw_nn_adam, fdirw_nn_save, fdirw_nn_load,
+    fdirw_coarse_create, fdirw_coarse_step, fdirw_coarse_shape,
+    fdirw_coarse_matrix, fdirw_coarse_destroy (wrapped by ``Coarse``)
 """
 from __future__ import annotations
 
@@ -82,7 +84,8 @@ ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run
                  "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version",
                  "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
-                 "fdirw_nn_save", "fdirw_nn_load")
+                 "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create", "fdirw_coarse_step",
+                 "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_destroy")
 NN_RADIUS = 8
 
 _lib = None
@@ -122,10 +125,16 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_nn_adam.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
     lib.fdirw_nn_save.argtypes = [P, ctypes.c_char_p]
     lib.fdirw_nn_load.argtypes = [P, ctypes.c_char_p]
+    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, PP, ctypes.POINTER(ctypes.c_double)]
+    lib.fdirw_coarse_step.argtypes = [P, P, P, P, S]
+    lib.fdirw_coarse_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.fdirw_coarse_matrix.argtypes = [P, P]
+    lib.fdirw_coarse_destroy.argtypes = [P]
     for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run", "fdirw_field_sum",
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
-              "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load"):
+              "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create",
+              "fdirw_coarse_step", "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -201,6 +210,10 @@ class Domain:
         s.n_phase = int(self.d_phase.size)
         s.r, s.n_sub, s.dt = self.r, self.n_sub, self.dt
         return s
+
+
+def _prec(prec) -> int:
+    return PREC_NAMES[prec.lower()] if isinstance(prec, str) else int(prec)
 
 
 def make_opts(prec=FP32, stream=None, bank_budget_bytes: int = 0, tune: int = -1,
@@ -350,6 +363,82 @@ def fdirw_field_sum(c, stream=None) -> float:
     _check(load_library().fdirw_field_sum(ctypes.c_void_p(c.data_ptr()), c.numel(), _stream_ptr(stream),
                                           ctypes.byref(out)))
     return out.value
+
+
+# ----------------------------------------------------------------- coarse mesh
+
+def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, stream=None):
+    """Handle and build seconds of the coarse operator of ``dom``."""
+    h = ctypes.c_void_p()
+    sec = ctypes.c_double(0.0)
+    ds = dom.c_struct()
+    _check(load_library().fdirw_coarse_create(ctypes.byref(ds), int(block), _prec(prec), _stream_ptr(stream),
+                                              ctypes.byref(h), ctypes.byref(sec)))
+    return h, sec.value
+
+
+def fdirw_coarse_step(handle, c_in, c_out, stream=None, stats: bool = False):
+    st = fdirw_stats() if stats else None
+    _check(load_library().fdirw_coarse_step(handle, ctypes.c_void_p(c_in.data_ptr()),
+                                            ctypes.c_void_p(c_out.data_ptr()), _stream_ptr(stream),
+                                            ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+def fdirw_coarse_shape(handle):
+    shp = (ctypes.c_int32 * 5)()
+    nn = ctypes.c_int64(0)
+    _check(load_library().fdirw_coarse_shape(handle, shp, ctypes.byref(nn)))
+    return tuple(shp), nn.value
+
+
+def fdirw_coarse_matrix(handle, out: np.ndarray):
+    _check(load_library().fdirw_coarse_matrix(handle, ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+def fdirw_coarse_destroy(handle) -> None:
+    _check(load_library().fdirw_coarse_destroy(handle))
+
+
+class Coarse:
+    """Coarse-mesh FDiRW operator of one geometry (Sec. 3.1, Eqs. 10-15):
+    ``block``^3 groups of mobile cells, P stored in ``prec`` (fp64, fp32,
+    fp16_bank or bf16_bank)."""
+
+    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, stream=None):
+        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, stream)
+        shp, self.n_nodes = fdirw_coarse_shape(self.handle)
+        self.coarse_shape = tuple(shp[:3])
+        self.K, self.block = shp[3], shp[4]
+        self.n = dom.n
+
+    def step(self, c_in, c_out=None, stream=None, stats: bool = False):
+        torch = _torch()
+        _dev_tensor(c_in, torch.float64, "c_in")
+        if c_out is None:
+            c_out = torch.empty_like(c_in)
+        _dev_tensor(c_out, torch.float64, "c_out")
+        if c_in.numel() != self.n or c_out.numel() != self.n:
+            raise ValueError("field does not match the domain")
+        st = fdirw_coarse_step(self.handle, c_in, c_out, stream, stats)
+        return (c_out, st) if stats else c_out
+
+    def matrix(self) -> np.ndarray:
+        """P as [(2K+1)^3, n_nodes] float64: entry [o, I] = P[I][I - (o - K)]."""
+        kw = 2 * self.K + 1
+        return fdirw_coarse_matrix(self.handle, np.empty((kw ** 3, self.n_nodes)))
+
+    def close(self):
+        if self.handle:
+            fdirw_coarse_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- surrogate

@@ -1,0 +1,243 @@
+// fdirw_coarse.hip -- coarse-mesh FDiRW (Sec. 3.1 of arXiv 2408.11376,
+// Eqs. 10-15) on gfx950.
+//
+// Nodes are the mobile cells (phase D > 0) of B x B x B blocks.  The coarse
+// matrix is built once per geometry from the fine window kernels: every mobile
+// source j of block J adds G_j(i) / m_j to S[I - J][I] for the block I of each
+// window cell i (one workgroup per source: LDS bins per block offset, then one
+// FP64 atomic per nonzero bin), and P = S / N_I is stored in the offset-major,
+// 16-byte-grouped layout of the kernel bank.  A coarse step is then
+//   mapping    C = mean of c over each group, on the coarse grid padded by K
+//   FDiRW      C' = P C (the bank's row-form gather with window radius K)
+//   remapping  c'(i) = C'(node of i); immobile cells keep c(i)
+#include "fdirw_device.h"
+#include "fdirw_launch.h"
+
+namespace fdirw {
+
+// node[i] = block index of cell i if its phase is mobile, else -1; count[I]
+// += 1 for every mobile cell of block I (exact in FP64).
+__global__ void coarse_nodes_kernel(const uint8_t *__restrict__ label, CoarseTable tab, int nx, int ny, int nz,
+                                    int B, int ncx, int ncy, int *__restrict__ node, double *__restrict__ count)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+        int v = -1;
+        if (tab.mobile[label[i]]) {
+            v = ((z / B) * ncy + y / B) * ncx + x / B;
+            atomicAdd(&count[v], 1.0);
+        }
+        node[i] = v;
+    }
+}
+
+// One workgroup per mobile source: its fine window kernel, renormalised to
+// unit mass, summed per destination block into S[offset][I] (offset = I - J
+// + K per axis, J the source's block).
+template <int M, int R>
+__global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
+coarse_window_kernel(CoarseGenArgs a)
+{
+    using G_ = Geo<M, R>;
+    using T = typename G_::T;
+    using S = typename G_::S;
+    using E = typename G_::E;
+    constexpr int L = G_::L0, W3 = G_::W3;
+    __shared__ __align__(16) E xb[2 * G_::XLEN];
+    __shared__ double red[G_::NWAVE];
+    __shared__ double bins[W3];                    // (2K + 1)^3 <= W^3 block offsets
+
+    const Place p = make_place<M, R>(threadIdx.x);
+    for (int i = threadIdx.x; i < 2 * G_::XLEN; i += blockDim.x) xb[i] = (E)0.0f;   // padding stays 0
+    for (int i = threadIdx.x; i < W3; i += blockDim.x) bins[i] = 0.0;
+    __syncthreads();
+
+    const S *lx = (const S *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
+    const int B = a.block, K = a.K, KW = 2 * a.K + 1, nb = KW * KW * KW;
+    for (int64_t s = blockIdx.x; s < a.n; s += gridDim.x) {
+        if (a.node[s] < 0) continue;                // immobile source: uniform per block
+        const int sx = (int)(s % a.nx), sy = (int)((s / a.nx) % a.ny), sz = (int)(s / ((int64_t)a.nx * a.ny));
+        Seg<M, R> c;
+        load_segment<M, R>(c, lx, ly, lz, a.nx, a.ny, a.nz, sx, sy, sz, p);
+        compute_diag<T::x32, M, R>(c);
+        S G[L];
+        init_delta<M, R>(G, p);
+        run_substeps<M, R>(G, c, xb, p, a.n_sub);
+        const double m = finish_kernel<M, R>(G, red, p);
+        const double inv = 1.0 / m;
+        const int jx = sx / B, jy = sy / B, jz = sz / B;
+        if (p.act) {
+            const int X = sx - R + p.cx, Y = sy - R + p.cy;
+            if (X >= 0 && X < a.nx && Y >= 0 && Y < a.ny) {
+                const int oxy = (Y / B - jy + K) * KW + (X / B - jx + K);
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    const int Z = sz - R + p.j0 + k;
+                    if (k < p.len && Z >= 0 && Z < a.nz && G[k] != S(0))
+                        atomicAdd(&bins[(Z / B - jz + K) * KW * KW + oxy], (double)G[k] * inv);
+                }
+            }
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < nb; o += blockDim.x) {
+            const double v = bins[o];
+            if (v != 0.0) {
+                const int oz = o / (KW * KW), oy = (o / KW) % KW, ox = o % KW;
+                const int64_t I = ((int64_t)(jz + oz - K) * a.ncy + (jy + oy - K)) * a.ncx + (jx + ox - K);
+                atomicAdd(&a.S[(int64_t)o * a.n_nodes + I], v);
+                bins[o] = 0.0;
+            }
+        }
+        __syncthreads();                            // bins and exchange buffers are reused
+    }
+}
+
+// P[o][I] = S[o][I] / N_I in the bank layout of element type B: per offset
+// plane the coarse cells are ordered [z / zb][y][x][z % zb].
+template <typename B>
+__global__ void coarse_finalize_kernel(const double *__restrict__ S, const double *__restrict__ count,
+                                       int64_t n_nodes, int nb, int ncx, int ncy, int ncz, B *__restrict__ P)
+{
+    constexpr int zb = 16 / (int)sizeof(B);
+    const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
+    const int64_t total = (int64_t)nb * n_nodes;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = i / n_nodes, I = i - o * n_nodes;
+        const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
+        const double nI = count[I];
+        const double v = nI > 0.0 ? S[i] / nI : 0.0;
+        P[o * plane + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb] = (B)v;
+    }
+}
+
+// Eq. 13 on the coarse grid padded by K (halo and empty blocks 0).
+__global__ void coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
+                                  const double *__restrict__ count, int nx, int ny, int nz, int B, int ncx,
+                                  int ncy, int ncz, int K, double *__restrict__ cpad)
+{
+    const int px = ncx + 2 * K, py = ncy + 2 * K, pz = ncz + 2 * K;
+    const int64_t np = (int64_t)px * py * pz;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int bx = (int)(i % px) - K, by = (int)((i / px) % py) - K, bz = (int)(i / ((int64_t)px * py)) - K;
+        double v = 0.0;
+        if (bx >= 0 && bx < ncx && by >= 0 && by < ncy && bz >= 0 && bz < ncz) {
+            const int64_t I = ((int64_t)bz * ncy + by) * ncx + bx;
+            const double nI = count[I];
+            if (nI > 0.0) {
+                double sum = 0.0;
+                for (int z = bz * B; z < nz && z < (bz + 1) * B; ++z)
+                    for (int y = by * B; y < ny && y < (by + 1) * B; ++y)
+                        for (int x = bx * B; x < nx && x < (bx + 1) * B; ++x) {
+                            const int64_t j = ((int64_t)z * ny + y) * nx + x;
+                            if (node[j] >= 0) sum += c[j];
+                        }
+                v = sum / nI;
+            }
+        }
+        cpad[i] = v;
+    }
+}
+
+// Eq. 15: every mobile cell takes its node's value, immobile cells keep theirs.
+__global__ void coarse_remap_kernel(const double *__restrict__ c_in, const int *__restrict__ node,
+                                    const double *__restrict__ cnew, int64_t n, double *__restrict__ c_out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int I = node[i];
+        c_out[i] = I >= 0 ? cnew[I] : c_in[i];
+    }
+}
+
+static unsigned grid_for(int64_t n)
+{
+    const int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+hipError_t launch_coarse_nodes(const uint8_t *label, const CoarseTable &tab, int nx, int ny, int nz, int B,
+                               int ncx, int ncy, int *node, double *count, hipStream_t st)
+{
+    hipLaunchKernelGGL(coarse_nodes_kernel, dim3(grid_for((int64_t)nx * ny * nz)), dim3(256), 0, st, label, tab,
+                       nx, ny, nz, B, ncx, ncy, node, count);
+    return hipGetLastError();
+}
+
+template <int M, int R>
+static hipError_t launch_cw_mr(const CoarseGenArgs &a, hipStream_t st)
+{
+    const int64_t nblk = a.n < 65536 * 16 ? a.n : 65536 * 16;
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL((coarse_window_kernel<M, R>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_cw_m(int r, const CoarseGenArgs &a, hipStream_t st)
+{
+    switch (r) {
+    case 0: return launch_cw_mr<M, 0>(a, st);
+    case 1: return launch_cw_mr<M, 1>(a, st);
+    case 2: return launch_cw_mr<M, 2>(a, st);
+    case 3: return launch_cw_mr<M, 3>(a, st);
+    case 4: return launch_cw_mr<M, 4>(a, st);
+    case 5: return launch_cw_mr<M, 5>(a, st);
+    case 6: return launch_cw_mr<M, 6>(a, st);
+    case 7: return launch_cw_mr<M, 7>(a, st);
+    case 8: return launch_cw_mr<M, 8>(a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_coarse_window(int fp64, int r, const CoarseGenArgs &a, hipStream_t st)
+{
+    return fp64 ? launch_cw_m<M_FP64>(r, a, st) : launch_cw_m<M_FP32>(r, a, st);
+}
+
+hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
+                                  int ncy, int ncz, void *P, hipStream_t st)
+{
+    const unsigned g = grid_for((int64_t)nb * n_nodes);
+    switch (prec) {
+    case M_FP64:
+        hipLaunchKernelGGL(coarse_finalize_kernel<double>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
+                           ncy, ncz, (double *)P);
+        break;
+    case M_FP32:
+        hipLaunchKernelGGL(coarse_finalize_kernel<float>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
+                           ncy, ncz, (float *)P);
+        break;
+    case M_F16BANK:
+        hipLaunchKernelGGL(coarse_finalize_kernel<_Float16>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
+                           ncy, ncz, (_Float16 *)P);
+        break;
+    case M_BF16BANK:
+        hipLaunchKernelGGL(coarse_finalize_kernel<__bf16>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
+                           ncy, ncz, (__bf16 *)P);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st)
+{
+    const int64_t np = (int64_t)(ncx + 2 * K) * (ncy + 2 * K) * (ncz + 2 * K);
+    hipLaunchKernelGGL(coarse_map_kernel, dim3(grid_for(np)), dim3(256), 0, st, c, node, count, nx, ny, nz, B, ncx,
+                       ncy, ncz, K, cpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(coarse_remap_kernel, dim3(grid_for(n)), dim3(256), 0, st, c_in, node, cnew, n, c_out);
+    return hipGetLastError();
+}
+
+}  // namespace fdirw

@@ -1,0 +1,290 @@
+// fdirw_coarse_api.cpp -- host side of the coarse-mesh FDiRW entry points
+// (include/fdirw.h; Sec. 3.1 of arXiv 2408.11376, Eqs. 10-15).
+//
+// A handle owns the coarse operator of one geometry: the node index of every
+// cell, the cell count of every node and P in the bank layout of its storage
+// precision.  fdirw_coarse_create builds P from the fine window kernels of
+// every mobile source (the same FD as fdirw_kernels); fdirw_coarse_step maps,
+// applies P with the bank's gather kernel and remaps.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/fdirw.h"
+#include "fdirw_host.h"
+#include "fdirw_launch.h"
+
+namespace fdirw {
+
+namespace {
+
+struct Coarse {
+    int dev = -1;
+    int nx = 0, ny = 0, nz = 0;
+    int64_t n = 0;
+    int B = 1, K = 0, ncx = 0, ncy = 0, ncz = 0;
+    int64_t n_nodes = 0;
+    int prec = FDIRW_FP64;          // storage of P: FP64, FP32, FP16_BANK or BF16_BANK
+    size_t esz = 8;
+    int64_t plane = 0;              // elements of one offset plane of P (grouped layout)
+    void *node = nullptr;           // int [N]
+    void *count = nullptr;          // double [n_nodes]
+    void *P = nullptr;              // esz * (2K+1)^3 * plane bytes
+    void *cpad = nullptr;           // double [(ncz+2K)(ncy+2K)(ncx+2K)]
+    void *cnew = nullptr;           // double [n_nodes]
+    void *part = nullptr;           // field-sum partials
+
+    ~Coarse()
+    {
+        for (void *p : {node, count, P, cpad, cnew, part})
+            if (p) (void)hipFree(p);
+    }
+    int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
+};
+
+int coarse_alloc(void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(FDIRW_E_NOMEM, "coarse FDiRW: could not allocate %zu bytes", bytes);
+    }
+    return FDIRW_OK;
+}
+
+int check_handle(const Coarse *h)
+{
+    if (!h) return fail(FDIRW_E_ARG, "coarse handle is null");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->dev)
+        return fail(FDIRW_E_ARG, "coarse handle belongs to device %d, current device is %d", h->dev, dev);
+    return FDIRW_OK;
+}
+
+int field_sum_h(Coarse *h, const double *c, hipStream_t st, double *out)
+{
+    double *part = (double *)h->part;
+    double *res = part + 2 * field_sum_blocks(h->n);
+    hipError_t e = launch_field_sum(c, h->n, part, res, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, res, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "coarse field sum");
+    return FDIRW_OK;
+}
+
+}  // namespace
+
+}  // namespace fdirw
+
+using namespace fdirw;
+
+extern "C" {
+
+int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, void *stream, void **handle,
+                        double *seconds)
+{
+    if (!handle) return fail(FDIRW_E_ARG, "handle is null");
+    *handle = nullptr;
+    int rc = check_domain(d);
+    if (rc) return rc;
+    if (block < 1) return fail(FDIRW_E_ARG, "block = %d must be >= 1", block);
+    if (prec != FDIRW_FP64 && prec != FDIRW_FP32 && prec != FDIRW_FP16_BANK && prec != FDIRW_BF16_BANK)
+        return fail(FDIRW_E_ARG, "coarse P precision must be FP64, FP32, FP16_BANK or BF16_BANK (got %d)", prec);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    auto *h = new (std::nothrow) Coarse;
+    if (!h) return fail(FDIRW_E_NOMEM, "coarse handle");
+    if (hipGetDevice(&h->dev) != hipSuccess) {
+        delete h;
+        return fail(FDIRW_E_DEVICE, "hipGetDevice failed");
+    }
+    h->nx = d->nx; h->ny = d->ny; h->nz = d->nz;
+    h->n = (int64_t)d->nx * d->ny * d->nz;
+    h->B = block;
+    h->K = (d->r + block - 1) / block;
+    h->ncx = (d->nx + block - 1) / block;
+    h->ncy = (d->ny + block - 1) / block;
+    h->ncz = (d->nz + block - 1) / block;
+    h->n_nodes = (int64_t)h->ncx * h->ncy * h->ncz;
+    h->prec = prec;
+    h->esz = bank_elem_bytes(prec);
+    const int zb = 16 / (int)h->esz;
+    h->plane = (int64_t)((h->ncz + zb - 1) / zb) * h->ncy * h->ncx * zb;
+    const int nb = h->nb();
+    const int64_t n_pad = (int64_t)(h->ncx + 2 * h->K) * (h->ncy + 2 * h->K) * (h->ncz + 2 * h->K);
+    double *S = nullptr;
+    hipError_t e = hipSuccess;
+    {
+        std::lock_guard<std::mutex> lk(cache_mutex());
+        DevCache &dc = cache_for_current_device();
+        Geometry g;
+        const void *lam = nullptr;
+        rc = coef_buffers(d, prec == FDIRW_FP64 ? FDIRW_FP64 : FDIRW_FP32, st, dc, &g, &lam);
+        if (!rc) rc = coarse_alloc(&h->node, (size_t)h->n * sizeof(int));
+        if (!rc) rc = coarse_alloc(&h->count, (size_t)h->n_nodes * sizeof(double));
+        if (!rc) rc = coarse_alloc(&h->P, (size_t)nb * h->plane * h->esz);
+        if (!rc) rc = coarse_alloc(&h->cpad, (size_t)n_pad * sizeof(double));
+        if (!rc) rc = coarse_alloc(&h->cnew, (size_t)h->n_nodes * sizeof(double));
+        if (!rc) rc = coarse_alloc(&h->part, (size_t)(2 * field_sum_blocks(h->n) + 2) * sizeof(double));
+        if (!rc) rc = coarse_alloc((void **)&S, (size_t)nb * h->n_nodes * sizeof(double));
+        if (rc) {
+            if (S) (void)hipFree(S);
+            delete h;
+            return rc;
+        }
+        CoarseTable tab;
+        std::memset(&tab, 0, sizeof tab);
+        for (int i = 0; i < d->n_phase; ++i) tab.mobile[i] = d->d_phase[i] > 0.0 ? 1 : 0;
+        // P entries of empty nodes and of the padding groups stay 0
+        e = launch_fill((double *)h->count, h->n_nodes, 0.0, st);
+        if (e == hipSuccess) e = launch_fill(S, (int64_t)nb * h->n_nodes, 0.0, st);
+        if (e == hipSuccess)
+            e = launch_fill_u32((unsigned *)h->P, (int64_t)((size_t)nb * h->plane * h->esz / 4), 0u, st);
+        if (e == hipSuccess)
+            e = launch_coarse_nodes(d->label, tab, d->nx, d->ny, d->nz, block, h->ncx, h->ncy, (int *)h->node,
+                                    (double *)h->count, st);
+        if (e == hipSuccess) {
+            CoarseGenArgs a;
+            a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.n = h->n;
+            a.n_sub = d->n_sub;
+            a.lx = lam;
+            a.node = (const int *)h->node;
+            a.block = block; a.K = h->K;
+            a.ncx = h->ncx; a.ncy = h->ncy;
+            a.n_nodes = h->n_nodes;
+            a.S = S;
+            e = launch_coarse_window(prec == FDIRW_FP64, d->r, a, st);
+        }
+        if (e == hipSuccess)
+            e = launch_coarse_finalize(prec, S, (const double *)h->count, h->n_nodes, nb, h->ncx, h->ncy, h->ncz,
+                                       h->P, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(S);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "coarse operator build");
+    }
+    if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *handle = h;
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *stream, fdirw_stats *stats)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!c_in || !c_out) return fail(FDIRW_E_ARG, "c_in and c_out must not be null");
+    if (c_in == c_out) return fail(FDIRW_E_ARG, "c_in and c_out must not overlap");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    fdirw_stats loc;
+    std::memset(&loc, 0, sizeof loc);
+    if (stats && (rc = field_sum_h(h, c_in, st, &loc.mass_in))) return rc;
+    EventPair ev;
+    hipError_t e = stats ? ev.create() : hipSuccess;
+    if (stats && e == hipSuccess) e = hipEventRecord(ev.a, st);
+    if (e == hipSuccess)
+        e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
+                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st);
+    if (e == hipSuccess) {
+        BankArgs b;
+        b.nx = h->ncx; b.ny = h->ncy; b.nz = h->ncz;
+        b.n = h->n_nodes;
+        b.bank = h->P;
+        b.mass = nullptr;
+        b.c_in = nullptr;
+        b.c_out = (double *)h->cnew;
+        b.chat = (double *)h->cpad;
+        e = launch_bank_gather(h->prec, h->K, b, st);
+    }
+    if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
+    if (stats && e == hipSuccess) e = hipEventRecord(ev.b, st);
+    if (e != hipSuccess) return hip_fail(e, "coarse step launch");
+    if (stats) {
+        if ((rc = field_sum_h(h, c_out, st, &loc.mass_out))) return rc;
+        loc.kmass_min = INFINITY;
+        loc.kmass_max = -INFINITY;
+        loc.n_sources = h->n_nodes;
+        loc.tuned_config_id = h->B;
+        loc.kernel_seconds = ev.seconds();
+        loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *stats = loc;
+    }
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_shape(const void *handle, int32_t *shape5, int64_t *n_nodes)
+{
+    const Coarse *h = (const Coarse *)handle;
+    if (!h) return fail(FDIRW_E_ARG, "coarse handle is null");
+    if (shape5) {
+        shape5[0] = h->ncz; shape5[1] = h->ncy; shape5[2] = h->ncx;
+        shape5[3] = h->K; shape5[4] = h->B;
+    }
+    if (n_nodes) *n_nodes = h->n_nodes;
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_matrix(void *handle, double *P_host)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!P_host) return fail(FDIRW_E_ARG, "P is null");
+    const int nb = h->nb();
+    std::vector<unsigned char> raw((size_t)nb * h->plane * h->esz);
+    hipError_t e = hipMemcpy(raw.data(), h->P, raw.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "coarse matrix copy");
+    const int zb = 16 / (int)h->esz;
+    for (int o = 0; o < nb; ++o)
+        for (int64_t I = 0; I < h->n_nodes; ++I) {
+            const int x = (int)(I % h->ncx), y = (int)((I / h->ncx) % h->ncy);
+            const int z = (int)(I / ((int64_t)h->ncx * h->ncy));
+            const size_t k = (size_t)o * h->plane + (((size_t)(z / zb) * h->ncy + y) * h->ncx + x) * zb + z % zb;
+            double v;
+            if (h->prec == FDIRW_FP64) {
+                std::memcpy(&v, raw.data() + k * 8, 8);
+            } else if (h->prec == FDIRW_FP32) {
+                float f;
+                std::memcpy(&f, raw.data() + k * 4, 4);
+                v = f;
+            } else {
+                uint16_t u;
+                std::memcpy(&u, raw.data() + k * 2, 2);
+                if (h->prec == FDIRW_BF16_BANK) {
+                    const uint32_t w = (uint32_t)u << 16;
+                    float f;
+                    std::memcpy(&f, &w, 4);
+                    v = f;
+                } else {
+                    _Float16 hv;
+                    std::memcpy(&hv, &u, 2);
+                    v = (double)(float)hv;
+                }
+            }
+            P_host[(size_t)o * h->n_nodes + I] = v;
+        }
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_destroy(void *handle)
+{
+    Coarse *h = (Coarse *)handle;
+    if (!h) return FDIRW_OK;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    const int own = h->dev;
+    if (dev != own) (void)hipSetDevice(own);
+    delete h;
+    if (dev != own && dev >= 0) (void)hipSetDevice(dev);
+    return FDIRW_OK;
+}
+
+}  // extern "C"

@@ -525,6 +525,12 @@ hipError_t launch_bank_apply(int prec, int r, const BankArgs &a, hipStream_t st)
                        prec == M_FP64 ? nullptr : a.mass, a.nx, a.ny, a.nz, r, a.chat);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_bank_gather(prec, r, a, st);
+}
+
+hipError_t launch_bank_gather(int prec, int r, const BankArgs &a, hipStream_t st)
+{
+    if (r < 0 || r > 8) return hipErrorInvalidValue;
     switch (prec) {
     case M_FP64: return launch_gather_b<double>(r, a, st);
     case M_FP32: case M_F16X32: case M_BF16X32: case M_F16ST: case M_BF16ST:

@@ -49,6 +49,23 @@ struct BankArgs {
     double *chat;             // scratch of bank_chat_elems() doubles
 };
 
+// Coarse-mesh FDiRW (fdirw_coarse.hip).
+struct CoarseTable {
+    uint8_t mobile[256];      // 1 if the phase's D > 0
+};
+
+struct CoarseGenArgs {
+    int nx, ny, nz;
+    int64_t n;
+    int n_sub;
+    const void *lx;           // coefficients as in LineArgs
+    const int *node;          // [N] node (block) index of a mobile cell, -1 if immobile
+    int block, K;             // block edge B, offset reach K = ceil(r / B)
+    int ncx, ncy;             // coarse grid (x, y extents)
+    int64_t n_nodes;
+    double *S;                // [(2K+1)^3][n_nodes] sums of renormalised kernels, 0 at launch
+};
+
 // Batched persistent launch (fdirw_batched.hip).
 struct BatchDom {
     int nx, ny, nz, r, n_sub;
@@ -84,6 +101,16 @@ hipError_t launch_line(int mode, int r, const LineArgs &a, hipStream_t st);
 hipError_t launch_window(int mode, int r, const WindowArgs &a, hipStream_t st);
 hipError_t launch_bank_apply(int prec, int r, const BankArgs &a, hipStream_t st);
 int64_t bank_chat_elems(int nx, int ny, int nz, int r);
+hipError_t launch_bank_gather(int prec, int r, const BankArgs &a, hipStream_t st);   // a.chat given
+hipError_t launch_coarse_nodes(const uint8_t *label, const CoarseTable &tab, int nx, int ny, int nz, int B,
+                               int ncx, int ncy, int *node, double *count, hipStream_t st);
+hipError_t launch_coarse_window(int fp64, int r, const CoarseGenArgs &a, hipStream_t st);
+hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
+                                  int ncy, int ncz, void *P, hipStream_t st);
+hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st);
+hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
+                               hipStream_t st);
 int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes);   // offset-major bank, padded
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);

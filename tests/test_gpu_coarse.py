@@ -1,0 +1,152 @@
+"""GPU parity of the coarse-mesh FDiRW (Sec. 3.1, Eqs. 10-15) through the C ABI
+against the coarse oracle (oracle/coarse.py, pinned in test_oracle_coarse.py).
+
+Bars: P and the step in FP64 to 1e-13 / 1e-12 (atomic summation order only);
+FP32 P to 1e-6 of the field maximum (1e-5 per entry at 192^3); FP16 / BF16 P:
+relative L1 of the step <= 1e-3 / 5e-3; immobile cells bit-exact; mass to
+1e-12 with FP64 P."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import rel_l1, to_dev, to_host
+from oracle import coarse
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2408_11376_amd as fd  # noqa: E402
+
+
+def _dev_domain(d):
+    return fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
+
+
+def _offset_form(P, cshape, K):
+    """Dense oracle P[I, J] -> [o, I] with o = (oz, oy, ox) = I - J + K."""
+    ncz, ncy, ncx = cshape
+    kw = 2 * K + 1
+    out = np.zeros((kw ** 3, P.shape[0]))
+    for I in range(P.shape[0]):
+        bz, rem = divmod(I, ncy * ncx)
+        by, bx = divmod(rem, ncx)
+        for o in range(kw ** 3):
+            oz, rem2 = divmod(o, kw * kw)
+            oy, ox = divmod(rem2, kw)
+            jz, jy, jx = bz - (oz - K), by - (oy - K), bx - (ox - K)
+            if 0 <= jz < ncz and 0 <= jy < ncy and 0 <= jx < ncx:
+                out[o, I] = P[I, (jz * ncy + jy) * ncx + jx]
+    return out
+
+
+CASES = [((6, 7, 5), 2, 6, 2, 11), ((9, 8, 10), 3, 10, 3, 12), ((5, 4, 6), 2, 5, 8, 13), ((7, 6, 8), 2, 8, 1, 14),
+         ((3, 1, 70), 2, 4, 5, 15)]
+
+
+@pytest.mark.parametrize("shape,r,n_sub,B,seed", CASES)
+def test_matrix_and_step_fp64_match_oracle(shape, r, n_sub, B, seed):
+    d = synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=seed)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, B)
+    cg = fd.Coarse(_dev_domain(d), B, fd.FP64)
+    assert cg.coarse_shape == coarse.coarse_dims(shape, B)
+    assert cg.K == -(-r // B)
+    got = cg.matrix()
+    ref = _offset_form(P, cg.coarse_shape, cg.K)
+    assert np.max(np.abs(got - ref)) <= 1e-13
+    out, st = cg.step(to_dev(d.c0), stats=True)
+    want = coarse.step(p, P, d.c0, B)
+    assert np.max(np.abs(to_host(out) - want)) <= 1e-12 * max(np.abs(want).max(), 1e-300)
+    assert abs(st["mass_out"] - st["mass_in"]) <= 1e-12 * st["mass_in"]
+    _, mobile, _ = coarse.groups(d.label, d.d_phase, B)
+    assert np.array_equal(to_host(out)[~mobile], d.c0[~mobile])
+    cg.close()
+
+
+@pytest.mark.parametrize("prec,kind,tol", [(fd.FP32, "max", 1e-6), (fd.FP16_BANK, "l1", 1e-3),
+                                           (fd.BF16_BANK, "l1", 5e-3)])
+def test_reduced_precision_p(prec, kind, tol):
+    d = synth.random_small((12, 11, 13), 3, r=3, n_sub=12, seed=16)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, 3)
+    want = coarse.step(p, P, d.c0, 3)
+    cg = fd.Coarse(_dev_domain(d), 3, prec)
+    out, st = cg.step(to_dev(d.c0), stats=True)
+    got = to_host(out)
+    if kind == "max":
+        assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
+    else:
+        assert rel_l1(got, want) <= tol
+    assert abs(st["mass_out"] - st["mass_in"]) <= 1e-2 * st["mass_in"]
+    cg.close()
+
+
+def test_block_one_equals_the_fine_step():
+    d = synth.random_small((10, 9, 11), 3, r=3, n_sub=15, seed=17)
+    dom = _dev_domain(d)
+    fine = to_host(fd.fdirw_step(dom, to_dev(d.c0), prec=fd.FP64))
+    cg = fd.Coarse(dom, 1, fd.FP64)
+    got = to_host(cg.step(to_dev(d.c0)))
+    assert np.max(np.abs(got - fine)) <= 1e-12 * np.abs(fine).max()
+    cg.close()
+
+
+def test_two_steps_and_errors():
+    d = synth.random_small((8, 9, 7), 2, r=2, n_sub=6, seed=18)
+    dom = _dev_domain(d)
+    cg = fd.Coarse(dom, 2, fd.FP64)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, 2)
+    a = cg.step(to_dev(d.c0))
+    b = cg.step(a)
+    want = coarse.step(p, P, coarse.step(p, P, d.c0, 2), 2)
+    assert np.max(np.abs(to_host(b) - want)) <= 1e-12 * np.abs(want).max()
+    with pytest.raises(fd.FdirwError):
+        cg.step(a, a)
+    with pytest.raises(fd.FdirwError):
+        fd.Coarse(dom, 0, fd.FP64)
+    with pytest.raises(fd.FdirwError):
+        fd.Coarse(dom, 2, fd.FP16X32)
+    cg.close()
+
+
+@pytest.mark.slow
+def test_full_size_sampled_columns():
+    """The 192^3 workload (GRF, D 1 / 1e-6, r = 8, n = 200) with 5^3 blocks and
+    FP32 P: sampled columns J of P against the oracle's kernels of the
+    sources of group J."""
+    d = synth.config2()
+    B = 5
+    cg = fd.Coarse(_dev_domain(d), B, fd.FP32)
+    K = cg.K
+    kw = 2 * K + 1
+    got = cg.matrix()
+    ncz, ncy, ncx = cg.coarse_shape
+    p = oracle.Problem.from_domain(d)
+    block, mobile, count = coarse.groups(d.label, d.d_phase, B)
+    for (jz, jy, jx) in [(0, 0, 0), (19, 20, 7), (38, 38, 38)]:
+        J = (jz * ncy + jy) * ncx + jx
+        src = np.flatnonzero(mobile.ravel() & (block.ravel() == J))
+        S = np.zeros(count.size)
+        G, mass = p.kernels(src)
+        W, r = p.W, p.r
+        rel = np.arange(W) - r
+        for q, s in enumerate(src):
+            sz, sy, sx = np.unravel_index(s, d.label.shape)
+            Z, Y, X = sz + rel, sy + rel, sx + rel
+            kz, ky, kx = (Z >= 0) & (Z < 192), (Y >= 0) & (Y < 192), (X >= 0) & (X < 192)
+            np.add.at(S, block[np.ix_(Z[kz], Y[ky], X[kx])].ravel(), (G[q][np.ix_(kz, ky, kx)] / mass[q]).ravel())
+        for o in range(kw ** 3):
+            oz, rem = divmod(o, kw * kw)
+            oy, ox = divmod(rem, kw)
+            iz, iy, ix = jz + oz - K, jy + oy - K, jx + ox - K
+            if not (0 <= iz < ncz and 0 <= iy < ncy and 0 <= ix < ncx):
+                continue
+            I = (iz * ncy + iy) * ncx + ix
+            want = S[I] / count[I] if count[I] > 0 else 0.0
+            assert abs(got[o, I] - want) <= 1e-5 * max(abs(want), 1e-3), (J, o)
+    cg.close()
