@@ -16,7 +16,8 @@ mixed precision steps (FP32 state with FP16 or BF16 neighbour copies) are timed
 the same way and reported under ``modes`` with their speedup over FP32 and
 their relative L1 difference from the FP32 field.  The ``bank`` leg stores
 every kernel once (in FP32 and in FP16, the paper's stored-P use) and times
-the HBM-streaming apply of one big step.
+the HBM-streaming apply of one big step; the ``coarse`` leg runs the paper's
+coarse-mesh method (5^3 blocks, mapping / P C / remapping).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32] [--nn-train-steps S]
 
@@ -252,6 +253,54 @@ def bank_leg(fd, d, dom, c0, ref, args):
     return out
 
 
+def coarse_leg(fd, d, dom, c0, c1, args):
+    """Coarse-mesh FDiRW, the paper's GPU method (Sec. 3.1-3.3, Eqs. 13-15):
+    blocks of B^3 cells, P built once from the fine window kernels, then per
+    step mapping, P C and remapping.  Per storage precision of P (FP32, FP16):
+    the build time, the step time (20 chained steps between events), the mass
+    drift, and the field error against the fused FP32 step, from c0 (noise) and
+    from c1 = one fused FP32 step of c0 (a diffused field).  Only the fast
+    phase is grouped (D_pore = 1); solid cells keep their values."""
+    import torch
+    B = args.coarse_block
+    # the liquid (pore, D = 1) is the grouped phase; the solid (D = 1e-6)
+    # keeps its value, as the paper maps the liquid nodes only
+    grouped = [1 if D >= 1e-3 * max(d.d_phase) else 0 for D in d.d_phase]
+    fine2 = fd.fdirw_step(dom, c1, prec="fp32") if c1 is not None else None
+    torch.cuda.synchronize()
+    out = {"block": B, "grouped_phases": grouped}
+    stream = torch.cuda.current_stream()
+    for prec in ("fp32", "fp16_bank"):
+        log(f"coarse {prec}: building P over {B}^3 blocks")
+        cg = fd.Coarse(dom, B, prec, grouped=grouped)
+        bufs = [torch.empty_like(c0), torch.empty_like(c0)]
+        cg.step(c0, bufs[0])
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        n = 20
+        cur = c0
+        ev0.record(stream)
+        for k in range(n):
+            cg.step(cur, bufs[k % 2])
+            cur = bufs[k % 2]
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / n
+        o0, st = cg.step(c0, stats=True)
+        rec = {"nodes": cg.n_nodes, "K": cg.K, "build_seconds": cg.build_seconds, "ms_per_step": ms,
+               "cells_per_s": d.n / (ms * 1e-3), "kernel_ms": 1e3 * st["kernel_seconds"],
+               "mass_rel_drift": abs(st["mass_out"] - st["mass_in"]) / st["mass_in"]}
+        if c1 is not None:
+            rec["rel_l1_vs_fp32_from_c0"] = float((o0 - c1).abs().sum()) / float(c1.abs().sum())
+            o1 = cg.step(c1)
+            rec["rel_l1_vs_fp32_from_c1"] = float((o1 - fine2).abs().sum()) / float(fine2.abs().sum())
+        out[prec] = rec
+        cg.close()
+        log(f"coarse {prec}: {cg.n_nodes} nodes, build {rec['build_seconds']:.2f} s, {ms:.4f} ms / step")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +315,8 @@ def main():
                     help="Adam steps of the surrogate before its step is timed (0: skip the surrogate)")
     ap.add_argument("--batched", type=int, default=1, help="also time the 64-domain batched step (0: skip)")
     ap.add_argument("--bank", type=int, default=1, help="also time fdirw_run with FP32 and FP16 kernel banks (0: skip)")
+    ap.add_argument("--coarse-block", type=int, default=5,
+                    help="block edge of the coarse-mesh leg (the paper's 1/125 nodes); 0: skip the leg")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -337,6 +388,8 @@ def main():
         extra["batched"] = batched_leg(fd, args)
     if args.bank:
         extra["bank"] = bank_leg(fd, d, dom, c0, fields.get("fp32"), args)
+    if args.coarse_block > 0:
+        extra["coarse"] = coarse_leg(fd, d, dom, c0, fields.get("fp32"), args)
 
     if "fp32" in fields:
         ref = fields["fp32"]

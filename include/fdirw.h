@@ -255,32 +255,37 @@ int fdirw_nn_load(void *nn, const char *path);
 
 /* ------------------------------------------------------------------ coarse mesh
  * Coarse-mesh FDiRW (Sec. 3.1, Eqs. 10-15): the fine grid is cut into blocks
- * of `block`^3 cells (ragged at the far edges); the mobile cells (phase D > 0)
- * of block I form group I with N_I cells, whose representative node carries
- * the mean concentration C_I.  Impermeable cells (D = 0) keep their value.
+ * of `block`^3 cells (ragged at the far edges); the grouped cells (those of the
+ * fast, liquid phases) of block I form group I with N_I cells, whose
+ * representative node carries the mean concentration C_I.  Cells of the other
+ * phases keep their value (the paper maps the liquid nodes only).
  * One coarse big step is
  *   mapping (Eq. 13)    C_J = mean of c_in over group J
  *   FDiRW (Eq. 14)      C'_I = sum_J P[I][J] C_J
  *   remapping (Eq. 15)  c_out(i) = C'_I for every cell i of group I
- * with P[I][J] = (1 / N_I) sum over mobile sources j of group J and cells i
+ * with P[I][J] = (1 / N_I) sum over grouped sources j of group J and cells i
  * of group I of G_j(i) / m_j, G_j the fine window kernel of fdirw_kernels
- * (radius d->r, d->n_sub sub-steps) and m_j its mass: the share of group J's
- * mass that the big step moves into group I, as a concentration ratio.  P is
+ * (radius d->r, d->n_sub sub-steps) and m_j its mass over the grouped cells:
+ * the share of group J's mass that the big step moves into group I, as a
+ * concentration ratio (columns conserve mass exactly).  P is
  * nonzero only for |I - J| <= K = ceil(r / block) per axis and is stored
  * offset-major in the precision `prec`; the product and its sum are FP64.
- * With block = 1 the step is the fine step with renormalised kernels.  The
- * far-field term of Eq. 14 is zero (no-flux domain walls). */
+ * With block = 1 and the default grouping the step is the fine step with
+ * renormalised kernels.  The far-field term of Eq. 14 is zero (no-flux
+ * domain walls). */
 
 /* Builds the coarse operator of domain d (generating every fine kernel once,
  * FP64 for prec = FDIRW_FP64, FP32 otherwise; P stored as FP64, FP32,
- * FP16 (FDIRW_FP16_BANK) or BF16 (FDIRW_BF16_BANK)).  d->label is read only
- * here.  *handle receives a handle owning device memory of about
- * 4 N + (2K+1)^3 x N_nodes x element bytes; seconds (host, may be NULL)
- * receives the build time.  Synchronises the stream.  The handle belongs to
- * the current device.  Errors: E_ARG (also block < 1 or another precision),
+ * FP16 (FDIRW_FP16_BANK) or BF16 (FDIRW_BF16_BANK)).  grouped (host, may be
+ * NULL): d->n_phase flags, nonzero for the grouped phases; NULL groups every
+ * phase with D > 0.  block: 1..256.  d->label is read only here.  *handle
+ * receives a handle owning device memory of about 4 N + (2K+1)^3 x N_nodes x
+ * element bytes; seconds (host, may be NULL) receives the build time.
+ * Synchronises the stream.  The handle belongs to the current device.
+ * Errors: E_ARG (also a block outside 1..256 or another precision),
  * E_UNSTABLE, E_NOMEM, E_DEVICE. */
-int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, void *stream, void **handle,
-                        double *seconds);
+int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped, void *stream,
+                        void **handle, double *seconds);
 
 /* One coarse big step from c_in to c_out (N doubles each, not overlapping).
  * st (may be NULL) receives mass_in / mass_out (compensated FP64 sums, one

@@ -5,26 +5,28 @@ may use it, the product library never does.
 Definition (built on the fine oracle's window kernels, ``Problem.kernels``):
 
 Nodes.  The grid is cut into blocks of B x B x B cells (ragged at the far
-edges).  A cell is mobile if its phase has D > 0; the mobile cells of block I
-form group I with N_I cells and the representative node I (blocks without a
-mobile cell have no node).  Immobile cells (D = 0) take no part: the fine
-step leaves them unchanged (their kernel is the unit point), and so does this
-one.
+edges).  A cell is grouped if its phase is one of the fast (liquid) phases:
+by default every phase with D > 0, or the phases the caller flags.  The
+grouped cells of block I form group I with N_I cells and the representative
+node I (blocks without a grouped cell have no node).  Other cells take no part
+and keep their value (the paper maps only the liquid nodes; the solid phase
+and the liquid-solid exchange belong to other parts of its solver).
 
 P (Eq. 10, coarse counterpart of p, Eq. 9).  The mass of group J, spread
 uniformly over its cells, moves in one big step as the sum of the fine kernels
 of its cells; the share that lands in group I, as a concentration ratio, is
-    S[I, J] = sum over mobile j in J, cells i in I of G_j(i) / m_j
+    S[I, J] = sum over grouped j in J, cells i in I of G_j(i) / m_j
     P[I, J] = S[I, J] / N_I
-(G_j the fine kernel of source j, m_j its mass; normalising every kernel to
-unit mass makes the columns of N_I P[I, J] / N_J sum to one, so the coarse
-step conserves mass exactly).
+(G_j the fine kernel of source j, m_j its mass over the grouped cells;
+normalising every kernel that way makes the columns of N_I P[I, J] / N_J sum
+to one, so the coarse step conserves mass exactly.  With the default grouping
+m_j is the whole kernel mass, since cells with D = 0 never receive any).
 
 Step (Eqs. 13-15):
     mapping     C_J = mean of c over the cells of group J               (Eq. 13)
     FDiRW       C'_I = sum_J P[I, J] C_J                                 (Eq. 14)
     remapping   c'(i) = C'_I for every cell i of group I; c'(i) = c(i)  (Eq. 15)
-                for immobile cells
+                for the cells outside every group
 
 The far-field term of Eq. 14 (P_BC c_far-field) is zero here: the domain walls
 are no-flux, as in the fine step.  With B = 1 every group is one cell and the
@@ -40,24 +42,26 @@ def coarse_dims(shape, B: int):
     return ((nz + B - 1) // B, (ny + B - 1) // B, (nx + B - 1) // B)
 
 
-def groups(label, d_phase, B: int):
-    """(block index of every cell [nz, ny, nx] int64, mobile mask, N per node
-    [n_nodes]) with nodes numbered (bz * ncy + by) * ncx + bx."""
+def groups(label, d_phase, B: int, grouped=None):
+    """(block index of every cell [nz, ny, nx] int64, grouped-cell mask, N per
+    node [n_nodes]) with nodes numbered (bz * ncy + by) * ncx + bx.
+    grouped: per-phase flags of the fast phases, or None for D > 0."""
     label = np.asarray(label)
     d_phase = np.asarray(d_phase, dtype=np.float64)
     nz, ny, nx = label.shape
     ncz, ncy, ncx = coarse_dims(label.shape, B)
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     block = ((z // B) * ncy + (y // B)) * ncx + (x // B)
-    mobile = d_phase[label] > 0
+    flags = d_phase > 0 if grouped is None else np.asarray(grouped, dtype=bool)
+    mobile = flags[label]
     count = np.bincount(block[mobile].ravel(), minlength=ncz * ncy * ncx).astype(np.float64)
     return block, mobile, count
 
 
-def coarse_matrix(problem, B: int) -> np.ndarray:
+def coarse_matrix(problem, B: int, grouped=None) -> np.ndarray:
     """Dense P [n_nodes, n_nodes] (rows = destination I, columns = source J)."""
     label = problem.label
-    block, mobile, count = groups(label, problem.d_phase, B)
+    block, mobile, count = groups(label, problem.d_phase, B, grouped)
     n_nodes = count.size
     shape = label.shape
     nz, ny, nx = shape
@@ -70,33 +74,34 @@ def coarse_matrix(problem, B: int) -> np.ndarray:
         sz, sy, sx = np.unravel_index(s, shape)
         Z, Y, X = sz + rel, sy + rel, sx + rel
         kz, ky, kx = (Z >= 0) & (Z < nz), (Y >= 0) & (Y < ny), (X >= 0) & (X < nx)
-        g = G[q][np.ix_(kz, ky, kx)] / mass[q]
-        dest = block[np.ix_(Z[kz], Y[ky], X[kx])]
-        np.add.at(S[:, block.flat[s]], dest.ravel(), g.ravel())
+        inside = np.ix_(Z[kz], Y[ky], X[kx])
+        keep = mobile[inside]
+        g = G[q][np.ix_(kz, ky, kx)][keep]
+        np.add.at(S[:, block.flat[s]], block[inside][keep], g / g.sum())
     P = np.zeros_like(S)
     has = count > 0
     P[has] = S[has] / count[has, None]
     return P
 
 
-def mapping(c, label, d_phase, B: int) -> np.ndarray:
+def mapping(c, label, d_phase, B: int, grouped=None) -> np.ndarray:
     """Eq. 13: the mean of c over each group (0 for blocks without a node)."""
-    block, mobile, count = groups(label, d_phase, B)
+    block, mobile, count = groups(label, d_phase, B, grouped)
     tot = np.bincount(block[mobile].ravel(), weights=np.asarray(c)[mobile].ravel(), minlength=count.size)
     C = np.zeros_like(tot)
     C[count > 0] = tot[count > 0] / count[count > 0]
     return C
 
 
-def remapping(C, c_old, label, d_phase, B: int) -> np.ndarray:
-    """Eq. 15: every mobile cell takes its node's value; immobile cells keep c_old."""
-    block, mobile, _ = groups(label, d_phase, B)
+def remapping(C, c_old, label, d_phase, B: int, grouped=None) -> np.ndarray:
+    """Eq. 15: every grouped cell takes its node's value; other cells keep c_old."""
+    block, mobile, _ = groups(label, d_phase, B, grouped)
     out = np.array(c_old, dtype=np.float64, copy=True)
     out[mobile] = np.asarray(C)[block[mobile]]
     return out
 
 
-def step(problem, P, c, B: int) -> np.ndarray:
+def step(problem, P, c, B: int, grouped=None) -> np.ndarray:
     """One coarse big step (Eqs. 13-15) with the matrix from coarse_matrix."""
-    C = mapping(c, problem.label, problem.d_phase, B)
-    return remapping(P @ C, c, problem.label, problem.d_phase, B)
+    C = mapping(c, problem.label, problem.d_phase, B, grouped)
+    return remapping(P @ C, c, problem.label, problem.d_phase, B, grouped)

@@ -125,7 +125,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_nn_adam.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
     lib.fdirw_nn_save.argtypes = [P, ctypes.c_char_p]
     lib.fdirw_nn_load.argtypes = [P, ctypes.c_char_p]
-    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, PP, ctypes.POINTER(ctypes.c_double)]
+    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, P, PP, ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_coarse_step.argtypes = [P, P, P, P, S]
     lib.fdirw_coarse_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.fdirw_coarse_matrix.argtypes = [P, P]
@@ -367,13 +367,20 @@ def fdirw_field_sum(c, stream=None) -> float:
 
 # ----------------------------------------------------------------- coarse mesh
 
-def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, stream=None):
-    """Handle and build seconds of the coarse operator of ``dom``."""
+def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, grouped=None, stream=None):
+    """Handle and build seconds of the coarse operator of ``dom``; ``grouped``:
+    per-phase flags of the grouped (fast) phases, None for every D > 0."""
     h = ctypes.c_void_p()
     sec = ctypes.c_double(0.0)
     ds = dom.c_struct()
-    _check(load_library().fdirw_coarse_create(ctypes.byref(ds), int(block), _prec(prec), _stream_ptr(stream),
-                                              ctypes.byref(h), ctypes.byref(sec)))
+    flags = None
+    if grouped is not None:
+        g = np.ascontiguousarray(grouped, dtype=np.uint8)
+        if g.size != len(dom.d_phase):
+            raise ValueError("grouped needs one flag per phase")
+        flags = (ctypes.c_uint8 * g.size)(*g.tolist())
+    _check(load_library().fdirw_coarse_create(ctypes.byref(ds), int(block), _prec(prec), flags,
+                                              _stream_ptr(stream), ctypes.byref(h), ctypes.byref(sec)))
     return h, sec.value
 
 
@@ -403,11 +410,11 @@ def fdirw_coarse_destroy(handle) -> None:
 
 class Coarse:
     """Coarse-mesh FDiRW operator of one geometry (Sec. 3.1, Eqs. 10-15):
-    ``block``^3 groups of mobile cells, P stored in ``prec`` (fp64, fp32,
-    fp16_bank or bf16_bank)."""
+    ``block``^3 groups of the grouped phases' cells (default: every D > 0),
+    P stored in ``prec`` (fp64, fp32, fp16_bank or bf16_bank)."""
 
-    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, stream=None):
-        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, stream)
+    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, grouped=None, stream=None):
+        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, grouped, stream)
         shp, self.n_nodes = fdirw_coarse_shape(self.handle)
         self.coarse_shape = tuple(shp[:3])
         self.K, self.block = shp[3], shp[4]

@@ -1,22 +1,22 @@
 // fdirw_coarse.hip -- coarse-mesh FDiRW (Sec. 3.1 of arXiv 2408.11376,
 // Eqs. 10-15) on gfx950.
 //
-// Nodes are the mobile cells (phase D > 0) of B x B x B blocks.  The coarse
-// matrix is built once per geometry from the fine window kernels: every mobile
-// source j of block J adds G_j(i) / m_j to S[I - J][I] for the block I of each
-// window cell i (one workgroup per source: LDS bins per block offset, then one
+// Nodes are the grouped cells (the fast phases) of B x B x B blocks.  The
+// coarse matrix is built once per geometry from the fine window kernels: every
+// grouped source j of block J adds G_j(i) / m_j (m_j = its mass over grouped
+// cells) to S[I - J][I] for the block I of each grouped window cell i (one workgroup per source: LDS bins per block offset, then one
 // FP64 atomic per nonzero bin), and P = S / N_I is stored in the offset-major,
 // 16-byte-grouped layout of the kernel bank.  A coarse step is then
 //   mapping    C = mean of c over each group, on the coarse grid padded by K
-//   FDiRW      C' = P C (the bank's row-form gather with window radius K)
-//   remapping  c'(i) = C'(node of i); immobile cells keep c(i)
+//   FDiRW      C' = P C (row form: one thread per node over the offsets)
+//   remapping  c'(i) = C'(node of i); cells outside every group keep c(i)
 #include "fdirw_device.h"
 #include "fdirw_launch.h"
 
 namespace fdirw {
 
-// node[i] = block index of cell i if its phase is mobile, else -1; count[I]
-// += 1 for every mobile cell of block I (exact in FP64).
+// node[i] = block index of cell i if its phase is grouped, else -1; count[I]
+// += 1 for every grouped cell of block I (exact in FP64).
 __global__ void coarse_nodes_kernel(const uint8_t *__restrict__ label, CoarseTable tab, int nx, int ny, int nz,
                                     int B, int ncx, int ncy, int *__restrict__ node, double *__restrict__ count)
 {
@@ -33,9 +33,9 @@ __global__ void coarse_nodes_kernel(const uint8_t *__restrict__ label, CoarseTab
     }
 }
 
-// One workgroup per mobile source: its fine window kernel, renormalised to
-// unit mass, summed per destination block into S[offset][I] (offset = I - J
-// + K per axis, J the source's block).
+// One workgroup per grouped source: its fine window kernel over the grouped
+// cells, renormalised to unit mass there, summed per destination block into
+// S[offset][I] (offset = I - J + K per axis, J the source's block).
 template <int M, int R>
 __global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
 coarse_window_kernel(CoarseGenArgs a)
@@ -57,7 +57,7 @@ coarse_window_kernel(CoarseGenArgs a)
     const S *lx = (const S *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
     const int B = a.block, K = a.K, KW = 2 * a.K + 1, nb = KW * KW * KW;
     for (int64_t s = blockIdx.x; s < a.n; s += gridDim.x) {
-        if (a.node[s] < 0) continue;                // immobile source: uniform per block
+        if (a.node[s] < 0) continue;                // source outside every group: uniform per block
         const int sx = (int)(s % a.nx), sy = (int)((s / a.nx) % a.ny), sz = (int)(s / ((int64_t)a.nx * a.ny));
         Seg<M, R> c;
         load_segment<M, R>(c, lx, ly, lz, a.nx, a.ny, a.nz, sx, sy, sz, p);
@@ -65,19 +65,26 @@ coarse_window_kernel(CoarseGenArgs a)
         S G[L];
         init_delta<M, R>(G, p);
         run_substeps<M, R>(G, c, xb, p, a.n_sub);
-        const double m = finish_kernel<M, R>(G, red, p);
-        const double inv = 1.0 / m;
-        const int jx = sx / B, jy = sy / B, jz = sz / B;
-        if (p.act) {
-            const int X = sx - R + p.cx, Y = sy - R + p.cy;
-            if (X >= 0 && X < a.nx && Y >= 0 && Y < a.ny) {
-                const int oxy = (Y / B - jy + K) * KW + (X / B - jx + K);
+        // the kernel's mass over the grouped cells (FP64, fixed order)
+        const int X = sx - R + p.cx, Y = sy - R + p.cy;
+        const bool inxy = p.act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
+        bool grp[L];
+        double part = 0.0;
 #pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    const int Z = sz - R + p.j0 + k;
-                    if (k < p.len && Z >= 0 && Z < a.nz && G[k] != S(0))
-                        atomicAdd(&bins[(Z / B - jz + K) * KW * KW + oxy], (double)G[k] * inv);
-                }
+        for (int k = 0; k < L; ++k) {
+            const int Z = sz - R + p.j0 + k;
+            grp[k] = inxy && k < p.len && Z >= 0 && Z < a.nz && a.node[((int64_t)Z * a.ny + Y) * a.nx + X] >= 0;
+            if (grp[k]) part += (double)G[k];
+        }
+        const double inv = 1.0 / block_sum<G_::NWAVE>(part, red);
+        const int jx = sx / B, jy = sy / B, jz = sz / B;
+        if (inxy) {
+            const int oxy = (Y / B - jy + K) * KW + (X / B - jx + K);
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const int Z = sz - R + p.j0 + k;
+                if (grp[k] && G[k] != S(0))
+                    atomicAdd(&bins[(Z / B - jz + K) * KW * KW + oxy], (double)G[k] * inv);
             }
         }
         __syncthreads();
@@ -113,36 +120,108 @@ __global__ void coarse_finalize_kernel(const double *__restrict__ S, const doubl
     }
 }
 
-// Eq. 13 on the coarse grid padded by K (halo and empty blocks 0).
-__global__ void coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
-                                  const double *__restrict__ count, int nx, int ny, int nz, int B, int ncx,
-                                  int ncy, int ncz, int K, double *__restrict__ cpad)
+// Eq. 13 on the coarse grid padded by K (halo and empty blocks 0).  One
+// workgroup per coarse (by, bz) row of blocks: each thread sums one fine x
+// column over the block's B x B (y, z) rows (coalesced across the threads),
+// then one thread per block adds its B columns in x order: a fixed order, so
+// the mapping is deterministic.  Workgroups with bz or by in the halo write
+// that halo row of zeros.
+constexpr int MAP_NT = 256;
+
+__global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
+                                                            const double *__restrict__ count, int nx, int ny, int nz,
+                                                            int B, int ncx, int ncy, int ncz, int K,
+                                                            double *__restrict__ cpad)
 {
-    const int px = ncx + 2 * K, py = ncy + 2 * K, pz = ncz + 2 * K;
-    const int64_t np = (int64_t)px * py * pz;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int bx = (int)(i % px) - K, by = (int)((i / px) % py) - K, bz = (int)(i / ((int64_t)px * py)) - K;
-        double v = 0.0;
-        if (bx >= 0 && bx < ncx && by >= 0 && by < ncy && bz >= 0 && bz < ncz) {
-            const int64_t I = ((int64_t)bz * ncy + by) * ncx + bx;
-            const double nI = count[I];
-            if (nI > 0.0) {
-                double sum = 0.0;
-                for (int z = bz * B; z < nz && z < (bz + 1) * B; ++z)
-                    for (int y = by * B; y < ny && y < (by + 1) * B; ++y)
-                        for (int x = bx * B; x < nx && x < (bx + 1) * B; ++x) {
-                            const int64_t j = ((int64_t)z * ny + y) * nx + x;
-                            if (node[j] >= 0) sum += c[j];
-                        }
-                v = sum / nI;
-            }
+    __shared__ double col[MAP_NT];
+    const int px = ncx + 2 * K, py = ncy + 2 * K;
+    const int byp = blockIdx.x, bzp = blockIdx.y;                 // padded coarse (y, z)
+    const int by = byp - K, bz = bzp - K;
+    double *row = cpad + ((int64_t)bzp * py + byp) * px;
+    const bool inside = by >= 0 && by < ncy && bz >= 0 && bz < ncz;
+    for (int x0 = 0; x0 < px; x0 += MAP_NT) {                     // halo rows, and the x halo
+        const int x = x0 + threadIdx.x;
+        if (x < px && (!inside || x < K || x >= K + ncx)) row[x] = 0.0;
+    }
+    if (!inside) return;                                          // uniform per block
+    const int y0 = by * B, z0 = bz * B;
+    const int y1 = min(ny, y0 + B), z1 = min(nz, z0 + B);
+    for (int xb0 = 0; xb0 < ncx; xb0 += MAP_NT / B) {             // blocks of this pass
+        const int nbk = min(MAP_NT / B, ncx - xb0);
+        const int x = xb0 * B + threadIdx.x;
+        double s = 0.0;
+        if (threadIdx.x < nbk * B && x < nx) {
+            for (int z = z0; z < z1; ++z)
+                for (int y = y0; y < y1; ++y) {
+                    const int64_t j = ((int64_t)z * ny + y) * nx + x;
+                    if (node[j] >= 0) s += c[j];
+                }
         }
-        cpad[i] = v;
+        __syncthreads();                                          // col of the previous pass is read
+        col[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < nbk) {
+            const int bx = xb0 + threadIdx.x;
+            const double nI = count[((int64_t)bz * ncy + by) * ncx + bx];
+            double t = 0.0;
+            for (int k = 0; k < B; ++k) t += col[threadIdx.x * B + k];
+            row[K + bx] = nI > 0.0 ? t / nI : 0.0;
+        }
     }
 }
 
-// Eq. 15: every mobile cell takes its node's value, immobile cells keep theirs.
+// Eq. 14 on the coarse grid: one thread per node, C'_I = sum over the
+// (2K+1)^3 offsets o of P[o][I] C[I - o] (fixed order, FP64), with P in the
+// bank layout of element type T and C read from the padded grid.
+template <typename T>
+__global__ void coarse_apply_kernel(const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy,
+                                    int ncz, int K, double *__restrict__ cnew)
+{
+    constexpr int zb = 16 / (int)sizeof(T);
+    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
+    const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
+    const int kw = 2 * K + 1, px = ncx + 2 * K, py = ncy + 2 * K;
+    for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < n_nodes;
+         I += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
+        const T *p = P + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb;
+        double acc = 0.0;
+        int o = 0;
+        for (int oz = 0; oz < kw; ++oz)
+            for (int oy = 0; oy < kw; ++oy) {
+                // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
+                const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
+                for (int ox = 0; ox < kw; ++ox, ++o)
+                    acc = __builtin_fma((double)(float)p[o * plane], crow[-ox], acc);
+            }
+        cnew[I] = acc;
+    }
+}
+
+template <>
+__global__ void coarse_apply_kernel<double>(const double *__restrict__ P, const double *__restrict__ cpad, int ncx,
+                                            int ncy, int ncz, int K, double *__restrict__ cnew)
+{
+    constexpr int zb = 2;
+    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
+    const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
+    const int kw = 2 * K + 1, px = ncx + 2 * K, py = ncy + 2 * K;
+    for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < n_nodes;
+         I += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
+        const double *p = P + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb;
+        double acc = 0.0;
+        int o = 0;
+        for (int oz = 0; oz < kw; ++oz)
+            for (int oy = 0; oy < kw; ++oy) {
+                const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
+                for (int ox = 0; ox < kw; ++ox, ++o) acc = __builtin_fma(p[o * plane], crow[-ox], acc);
+            }
+        cnew[I] = acc;
+    }
+}
+
+// Eq. 15: every grouped cell takes its node's value, the others keep theirs.
 __global__ void coarse_remap_kernel(const double *__restrict__ c_in, const int *__restrict__ node,
                                     const double *__restrict__ cnew, int64_t n, double *__restrict__ c_out)
 {
@@ -227,9 +306,35 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
                              int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st)
 {
-    const int64_t np = (int64_t)(ncx + 2 * K) * (ncy + 2 * K) * (ncz + 2 * K);
-    hipLaunchKernelGGL(coarse_map_kernel, dim3(grid_for(np)), dim3(256), 0, st, c, node, count, nx, ny, nz, B, ncx,
-                       ncy, ncz, K, cpad);
+    if (B > MAP_NT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(coarse_map_kernel, dim3((unsigned)(ncy + 2 * K), (unsigned)(ncz + 2 * K)), dim3(MAP_NT), 0,
+                       st, c, node, count, nx, ny, nz, B, ncx, ncy, ncz, K, cpad);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
+                               double *cnew, hipStream_t st)
+{
+    const unsigned g = grid_for((int64_t)ncx * ncy * ncz);
+    switch (prec) {
+    case M_FP64:
+        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(256), 0, st, (const double *)P, cpad, ncx, ncy,
+                           ncz, K, cnew);
+        break;
+    case M_FP32:
+        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(256), 0, st, (const float *)P, cpad, ncx, ncy,
+                           ncz, K, cnew);
+        break;
+    case M_F16BANK:
+        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(256), 0, st, (const _Float16 *)P, cpad, ncx,
+                           ncy, ncz, K, cnew);
+        break;
+    case M_BF16BANK:
+        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(256), 0, st, (const __bf16 *)P, cpad, ncx,
+                           ncy, ncz, K, cnew);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

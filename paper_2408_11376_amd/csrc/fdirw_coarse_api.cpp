@@ -4,8 +4,8 @@
 // A handle owns the coarse operator of one geometry: the node index of every
 // cell, the cell count of every node and P in the bank layout of its storage
 // precision.  fdirw_coarse_create builds P from the fine window kernels of
-// every mobile source (the same FD as fdirw_kernels); fdirw_coarse_step maps,
-// applies P with the bank's gather kernel and remaps.
+// every grouped source (the same FD as fdirw_kernels); fdirw_coarse_step maps,
+// applies P (one thread per node) and remaps.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -85,14 +85,14 @@ using namespace fdirw;
 
 extern "C" {
 
-int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, void *stream, void **handle,
-                        double *seconds)
+int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped, void *stream,
+                        void **handle, double *seconds)
 {
     if (!handle) return fail(FDIRW_E_ARG, "handle is null");
     *handle = nullptr;
     int rc = check_domain(d);
     if (rc) return rc;
-    if (block < 1) return fail(FDIRW_E_ARG, "block = %d must be >= 1", block);
+    if (block < 1 || block > 256) return fail(FDIRW_E_ARG, "block = %d outside 1..256", block);
     if (prec != FDIRW_FP64 && prec != FDIRW_FP32 && prec != FDIRW_FP16_BANK && prec != FDIRW_BF16_BANK)
         return fail(FDIRW_E_ARG, "coarse P precision must be FP64, FP32, FP16_BANK or BF16_BANK (got %d)", prec);
     const auto t0 = std::chrono::steady_clock::now();
@@ -139,7 +139,8 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, void
         }
         CoarseTable tab;
         std::memset(&tab, 0, sizeof tab);
-        for (int i = 0; i < d->n_phase; ++i) tab.mobile[i] = d->d_phase[i] > 0.0 ? 1 : 0;
+        for (int i = 0; i < d->n_phase; ++i)
+            tab.mobile[i] = (grouped ? grouped[i] != 0 : d->d_phase[i] > 0.0) ? 1 : 0;
         // P entries of empty nodes and of the padding groups stay 0
         e = launch_fill((double *)h->count, h->n_nodes, 0.0, st);
         if (e == hipSuccess) e = launch_fill(S, (int64_t)nb * h->n_nodes, 0.0, st);
@@ -193,17 +194,9 @@ int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *str
     if (e == hipSuccess)
         e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
                               h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st);
-    if (e == hipSuccess) {
-        BankArgs b;
-        b.nx = h->ncx; b.ny = h->ncy; b.nz = h->ncz;
-        b.n = h->n_nodes;
-        b.bank = h->P;
-        b.mass = nullptr;
-        b.c_in = nullptr;
-        b.c_out = (double *)h->cnew;
-        b.chat = (double *)h->cpad;
-        e = launch_bank_gather(h->prec, h->K, b, st);
-    }
+    if (e == hipSuccess)
+        e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
+                                (double *)h->cnew, st);
     if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
     if (stats && e == hipSuccess) e = hipEventRecord(ev.b, st);
     if (e != hipSuccess) return hip_fail(e, "coarse step launch");

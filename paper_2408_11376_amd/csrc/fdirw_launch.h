@@ -51,7 +51,7 @@ struct BankArgs {
 
 // Coarse-mesh FDiRW (fdirw_coarse.hip).
 struct CoarseTable {
-    uint8_t mobile[256];      // 1 if the phase's D > 0
+    uint8_t mobile[256];      // 1 if the phase is grouped (a fast phase)
 };
 
 struct CoarseGenArgs {
@@ -59,7 +59,7 @@ struct CoarseGenArgs {
     int64_t n;
     int n_sub;
     const void *lx;           // coefficients as in LineArgs
-    const int *node;          // [N] node (block) index of a mobile cell, -1 if immobile
+    const int *node;          // [N] node (block) index of a grouped cell, -1 otherwise
     int block, K;             // block edge B, offset reach K = ceil(r / B)
     int ncx, ncy;             // coarse grid (x, y extents)
     int64_t n_nodes;
@@ -109,6 +109,8 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
                                   int ncy, int ncz, void *P, hipStream_t st);
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
                              int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st);
+hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
+                               double *cnew, hipStream_t st);
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
                                hipStream_t st);
 int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes);   // offset-major bank, padded

@@ -1,6 +1,7 @@
 """One fused FDiRW step on a seeded porous grid, for profiler runs.
 
     python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024] [--gen nn] [--bank 1]
+        [--coarse B]
 
 Runs one untimed warm-up step, then ``--reps`` steps of the config-2 style
 workload (GRF porous grid, r = 8, 200 sub-steps) at edge ``--n``.  With
@@ -10,7 +11,9 @@ With ``--gen nn`` the steps use a surrogate (default initialisation, audit
 disabled, so every kernel is the network's) instead of the FD kernels.  With
 ``--bank 1`` each repetition is instead one fdirw_run call that stores every
 kernel once in a bank of the precision ``--prec`` (fp32, fp16_bank, ...) and
-applies it for one big step.
+applies it for one big step.  With ``--coarse B`` the coarse-mesh operator
+over B^3 blocks is built once (P stored in ``--prec``) and each repetition is
+one coarse step.
 """
 import argparse
 import os
@@ -31,6 +34,7 @@ def main():
     ap.add_argument("--tune", type=int, default=-1)
     ap.add_argument("--gen", default="fd", choices=["fd", "nn"])
     ap.add_argument("--bank", type=int, default=0)
+    ap.add_argument("--coarse", type=int, default=0)
     args = ap.parse_args()
     import torch
     import synth
@@ -42,6 +46,16 @@ def main():
     kw = {}
     if args.gen == "nn":
         kw = {"nn": fd.Surrogate(d.n_sub, seed=0), "audit_tol": 1e30, "audit_samples": 1}
+    if args.coarse:
+        cg = fd.Coarse(dom, args.coarse, args.prec)
+        print(f"[profile_step] n={args.n} coarse block {args.coarse} prec={args.prec}: {cg.n_nodes} nodes, "
+              f"build {cg.build_seconds:.2f} s", flush=True)
+        for i in range(args.reps):
+            _, st = cg.step(c, out, stats=True)
+            print(f"[profile_step] coarse step {i}: kernels {st['kernel_seconds'] * 1e3:.3f} ms", flush=True)
+        cg.close()
+        args.reps = 0
+        args.warmup = 0
     if args.bank:
         for i in range(args.reps):
             cb = c.clone()

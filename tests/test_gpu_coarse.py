@@ -85,6 +85,24 @@ def test_reduced_precision_p(prec, kind, tol):
     cg.close()
 
 
+@pytest.mark.parametrize("B", [2, 4])
+def test_liquid_only_grouping_matches_oracle(B):
+    # only phase 0 grouped (the other phases keep their values); kernels are
+    # renormalised over the grouped cells
+    d = synth.random_small((9, 10, 11), 3, r=3, n_sub=9, seed=19, d_zero_phase=False)
+    grouped = [1, 0, 0]
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, B, grouped)
+    cg = fd.Coarse(_dev_domain(d), B, fd.FP64, grouped=grouped)
+    assert np.max(np.abs(cg.matrix() - _offset_form(P, cg.coarse_shape, cg.K))) <= 1e-13
+    out, st = cg.step(to_dev(d.c0), stats=True)
+    want = coarse.step(p, P, d.c0, B, grouped)
+    assert np.max(np.abs(to_host(out) - want)) <= 1e-12 * np.abs(want).max()
+    assert abs(st["mass_out"] - st["mass_in"]) <= 1e-12 * st["mass_in"]
+    assert np.array_equal(to_host(out)[d.label != 0], d.c0[d.label != 0])
+    cg.close()
+
+
 def test_block_one_equals_the_fine_step():
     d = synth.random_small((10, 9, 11), 3, r=3, n_sub=15, seed=17)
     dom = _dev_domain(d)

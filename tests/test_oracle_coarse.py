@@ -71,3 +71,23 @@ def test_mass_conserved_and_immobile_cells_kept(B):
     for I in np.flatnonzero(has)[:10]:
         vals = got[mobile & (block == I)]
         assert np.all(vals == vals[0])
+
+
+def test_liquid_only_grouping_conserves_mass():
+    # only phase 0 grouped: the kernels are renormalised over the grouped
+    # cells, the other phases keep their values, mass is conserved
+    d = synth.random_small((8, 7, 9), 3, r=2, n_sub=10, seed=6, d_zero_phase=False)
+    p = _problem(d)
+    grouped = [1, 0, 0]
+    P = coarse.coarse_matrix(p, 3, grouped)
+    block, mobile, count = coarse.groups(d.label, d.d_phase, 3, grouped)
+    assert np.array_equal(mobile, d.label == 0)
+    has = count > 0
+    colsum = (count[:, None] * P)[:, has].sum(axis=0) / count[has]
+    assert np.max(np.abs(colsum - 1.0)) <= 1e-13
+    got = coarse.step(p, P, d.c0, 3, grouped)
+    assert np.array_equal(got[~mobile], d.c0[~mobile])
+    assert abs(got[mobile].sum() - d.c0[mobile].sum()) <= 1e-12 * d.c0.sum()
+    # the default grouping of this domain (every D > 0) is every cell
+    _, all_mobile, _ = coarse.groups(d.label, d.d_phase, 3)
+    assert all_mobile.all()
