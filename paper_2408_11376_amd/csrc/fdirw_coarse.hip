@@ -8,7 +8,7 @@
 // FP64 atomic per nonzero bin), and P = S / N_I is stored in the offset-major,
 // 16-byte-grouped layout of the kernel bank.  A coarse step is then
 //   mapping    C = mean of c over each group, on the coarse grid padded by K
-//   FDiRW      C' = P C (row form: one thread per node over the offsets)
+//   FDiRW      C' = P C (row form: 2K+1 threads per node, one per z offset)
 //   remapping  c'(i) = C'(node of i); cells outside every group keep c(i)
 #include "fdirw_device.h"
 #include "fdirw_launch.h"
@@ -170,54 +170,46 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
     }
 }
 
-// Eq. 14 on the coarse grid: one thread per node, C'_I = sum over the
-// (2K+1)^3 offsets o of P[o][I] C[I - o] (fixed order, FP64), with P in the
-// bank layout of element type T and C read from the padded grid.
+// Eq. 14 on the coarse grid: C'_I = sum over the (2K+1)^3 offsets o of
+// P[o][I] C[I - o] (FP64), with P in the bank layout of element type T and C
+// read from the padded grid.  2K+1 threads per node, one per z offset, each
+// summing its (2K+1)^2 terms in (y, x) order; the z partials are then added
+// in z order (a fixed order per node).
+template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
+template <> __device__ __forceinline__ double widen<double>(double v) { return v; }
+
+constexpr int APPLY_NT = 256;
+
 template <typename T>
-__global__ void coarse_apply_kernel(const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy,
-                                    int ncz, int K, double *__restrict__ cnew)
+__global__ void __launch_bounds__(APPLY_NT) coarse_apply_kernel(const T *__restrict__ P, const double *__restrict__ cpad,
+                                                                int ncx, int ncy, int ncz, int K,
+                                                                double *__restrict__ cnew)
 {
+    __shared__ double part[APPLY_NT];
     constexpr int zb = 16 / (int)sizeof(T);
     const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
     const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
     const int kw = 2 * K + 1, px = ncx + 2 * K, py = ncy + 2 * K;
-    for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < n_nodes;
-         I += (int64_t)gridDim.x * blockDim.x) {
+    const int per = APPLY_NT / kw;                                // nodes per workgroup
+    const int ln = threadIdx.x / kw, oz = threadIdx.x - ln * kw;
+    const int64_t I = blockIdx.x * (int64_t)per + ln;
+    double acc = 0.0;
+    if (ln < per && I < n_nodes) {
         const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
-        const T *p = P + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb;
-        double acc = 0.0;
+        const T *p = P + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb + (int64_t)oz * kw * kw * plane;
         int o = 0;
-        for (int oz = 0; oz < kw; ++oz)
-            for (int oy = 0; oy < kw; ++oy) {
-                // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
-                const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
-                for (int ox = 0; ox < kw; ++ox, ++o)
-                    acc = __builtin_fma((double)(float)p[o * plane], crow[-ox], acc);
-            }
-        cnew[I] = acc;
+        for (int oy = 0; oy < kw; ++oy) {
+            // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
+            const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
+            for (int ox = 0; ox < kw; ++ox, ++o) acc = __builtin_fma(widen<T>(p[o * plane]), crow[-ox], acc);
+        }
     }
-}
-
-template <>
-__global__ void coarse_apply_kernel<double>(const double *__restrict__ P, const double *__restrict__ cpad, int ncx,
-                                            int ncy, int ncz, int K, double *__restrict__ cnew)
-{
-    constexpr int zb = 2;
-    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
-    const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
-    const int kw = 2 * K + 1, px = ncx + 2 * K, py = ncy + 2 * K;
-    for (int64_t I = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; I < n_nodes;
-         I += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
-        const double *p = P + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb;
-        double acc = 0.0;
-        int o = 0;
-        for (int oz = 0; oz < kw; ++oz)
-            for (int oy = 0; oy < kw; ++oy) {
-                const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
-                for (int ox = 0; ox < kw; ++ox, ++o) acc = __builtin_fma(p[o * plane], crow[-ox], acc);
-            }
-        cnew[I] = acc;
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (ln < per && oz == 0 && I < n_nodes) {
+        double s = 0.0;
+        for (int k = 0; k < kw; ++k) s += part[ln * kw + k];
+        cnew[I] = s;
     }
 }
 
@@ -315,22 +307,25 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                double *cnew, hipStream_t st)
 {
-    const unsigned g = grid_for((int64_t)ncx * ncy * ncz);
+    const int per = APPLY_NT / (2 * K + 1);
+    if (per < 1) return hipErrorInvalidValue;
+    const int64_t nblk = ((int64_t)ncx * ncy * ncz + per - 1) / per;
+    const unsigned g = (unsigned)nblk;
     switch (prec) {
     case M_FP64:
-        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(256), 0, st, (const double *)P, cpad, ncx, ncy,
+        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(APPLY_NT), 0, st, (const double *)P, cpad, ncx, ncy,
                            ncz, K, cnew);
         break;
     case M_FP32:
-        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(256), 0, st, (const float *)P, cpad, ncx, ncy,
+        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(APPLY_NT), 0, st, (const float *)P, cpad, ncx, ncy,
                            ncz, K, cnew);
         break;
     case M_F16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(256), 0, st, (const _Float16 *)P, cpad, ncx,
+        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(APPLY_NT), 0, st, (const _Float16 *)P, cpad, ncx,
                            ncy, ncz, K, cnew);
         break;
     case M_BF16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(256), 0, st, (const __bf16 *)P, cpad, ncx,
+        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(APPLY_NT), 0, st, (const __bf16 *)P, cpad, ncx,
                            ncy, ncz, K, cnew);
         break;
     default: return hipErrorInvalidValue;
