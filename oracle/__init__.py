@@ -15,7 +15,8 @@ Functions (and the passage each follows):
   kernels         unit point-source responses = columns of P (Sec. 3.1, Eq. 9)
   step            superposition c_new = P c_old (Eq. 8, column/scatter form)
   field_sum       compensated FP64 mass of a field (mass balance, Eq. 7 role)
-  global_fd       the same explicit update on the whole domain (test reference)
+  global_fd       the same explicit update on the whole domain (test reference;
+                  optionally with Dirichlet cells, the far-field boundary of Eq. 8)
   support         structural support of a kernel (integer BFS, test reference)
 """
 from __future__ import annotations
@@ -58,6 +59,10 @@ def _load():
         lib.fo_coefficients.restype = None
         lib.fo_kernels.argtypes = [i32, i32, i32, P, P, P, i32, i32, P, i64, P, P]
         lib.fo_kernels.restype = None
+        lib.fo_kernels_fixed.argtypes = [i32, i32, i32, P, P, P, i32, i32, P, i64, P, P, P]
+        lib.fo_kernels_fixed.restype = None
+        lib.fo_global_fd_fixed.argtypes = [i32, i32, i32, P, P, P, i32, P, P, P, f64]
+        lib.fo_global_fd_fixed.restype = None
         lib.fo_step.argtypes = [i32, i32, i32, P, P, P, i32, i32, P, P, P]
         lib.fo_step.restype = i64
         lib.fo_global_fd.argtypes = [i32, i32, i32, P, P, P, i32, P, P]
@@ -131,14 +136,20 @@ class Problem:
     def _dims(self):
         return self.nx, self.ny, self.nz, _p(self.lx), _p(self.ly), _p(self.lz)
 
-    def kernels(self, src):
-        """G [n_src, W, W, W] (z, y, x relative to s - r) and mass [n_src]."""
+    def kernels(self, src, fixed=None):
+        """G [n_src, W, W, W] (z, y, x relative to s - r) and mass [n_src].
+        fixed: optional bool grid of Dirichlet cells held at 0 (absorbing)."""
         src = np.ascontiguousarray(src, dtype=np.int64).ravel()
         W = self.W
         G = np.empty((src.size, W, W, W))
         mass = np.empty(src.size)
         if src.size:
-            _load().fo_kernels(*self._dims(), self.r, self.n_sub, _p(src), src.size, _p(G), _p(mass))
+            if fixed is None:
+                _load().fo_kernels(*self._dims(), self.r, self.n_sub, _p(src), src.size, _p(G), _p(mass))
+            else:
+                f = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(self.label.shape)
+                _load().fo_kernels_fixed(*self._dims(), self.r, self.n_sub, _p(src), src.size, _p(G), _p(mass),
+                                         _p(f))
         return G, mass
 
     def step(self, c_old):
@@ -149,10 +160,17 @@ class Problem:
         used = _load().fo_step(*self._dims(), self.r, self.n_sub, _p(c_old), _p(c_new), _p(mm))
         return c_new, int(used), (float(mm[0]), float(mm[1]))
 
-    def global_fd(self, c, n_sub=None):
+    def global_fd(self, c, n_sub=None, fixed=None, fval: float = 0.0):
+        """Whole-domain explicit FD; fixed: optional bool grid of Dirichlet
+        cells holding fval from the start."""
         c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.label.shape)
         out = np.empty_like(c)
-        _load().fo_global_fd(*self._dims(), self.n_sub if n_sub is None else int(n_sub), _p(c), _p(out))
+        n = self.n_sub if n_sub is None else int(n_sub)
+        if fixed is None:
+            _load().fo_global_fd(*self._dims(), n, _p(c), _p(out))
+        else:
+            f = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(self.label.shape)
+            _load().fo_global_fd_fixed(*self._dims(), n, _p(c), _p(out), _p(f), float(fval))
         return out
 
     def support(self, s: int):

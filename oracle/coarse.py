@@ -28,9 +28,23 @@ Step (Eqs. 13-15):
     remapping   c'(i) = C'_I for every cell i of group I; c'(i) = c(i)  (Eq. 15)
                 for the cells outside every group
 
-The far-field term of Eq. 14 (P_BC c_far-field) is zero here: the domain walls
-are no-flux, as in the fine step.  With B = 1 every group is one cell and the
+Without a far field the term P_BC c_far-field of Eq. 14 is zero (no-flux
+domain walls, as in the fine step).  With B = 1 every group is one cell and the
 step is the fine step with renormalised kernels.
+
+Far field (Eqs. 7, 8, 10, 14).  Cells of the reservoir phases are the
+far-field boundary: Dirichlet cells that hold the uniform far-field
+concentration c_ff.  Then
+    G_j          the window kernel with the reservoir cells held at 0 (they
+                 absorb), not renormalised: the mass it loses is what leaves
+                 for the far field
+    S, P         as above from these kernels (over the grouped cells)
+    p_bc(i)      the whole-domain FD of n sub-steps from 0 with the reservoir
+                 cells held at 1 (the response to a unit boundary
+                 concentration); P_BC[I] = mean of p_bc over group I
+    step         C' = P C + P_BC c_ff, remapping as above, and then Eq. 7:
+                 c_ff' = (M_total - sum of c' over the non-reservoir cells)
+                 / V_ff, written into the reservoir cells.
 """
 from __future__ import annotations
 
@@ -42,10 +56,11 @@ def coarse_dims(shape, B: int):
     return ((nz + B - 1) // B, (ny + B - 1) // B, (nx + B - 1) // B)
 
 
-def groups(label, d_phase, B: int, grouped=None):
+def groups(label, d_phase, B: int, grouped=None, reservoir=None):
     """(block index of every cell [nz, ny, nx] int64, grouped-cell mask, N per
     node [n_nodes]) with nodes numbered (bz * ncy + by) * ncx + bx.
-    grouped: per-phase flags of the fast phases, or None for D > 0."""
+    grouped: per-phase flags of the fast phases, or None for D > 0;
+    reservoir: per-phase flags of the far-field boundary (never grouped)."""
     label = np.asarray(label)
     d_phase = np.asarray(d_phase, dtype=np.float64)
     nz, ny, nx = label.shape
@@ -53,22 +68,29 @@ def groups(label, d_phase, B: int, grouped=None):
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     block = ((z // B) * ncy + (y // B)) * ncx + (x // B)
     flags = d_phase > 0 if grouped is None else np.asarray(grouped, dtype=bool)
+    if reservoir is not None:
+        flags = flags & ~np.asarray(reservoir, dtype=bool)
     mobile = flags[label]
     count = np.bincount(block[mobile].ravel(), minlength=ncz * ncy * ncx).astype(np.float64)
     return block, mobile, count
 
 
-def coarse_matrix(problem, B: int, grouped=None) -> np.ndarray:
+def reservoir_mask(label, reservoir):
+    return np.asarray(reservoir, dtype=bool)[np.asarray(label)]
+
+
+def coarse_matrix(problem, B: int, grouped=None, reservoir=None) -> np.ndarray:
     """Dense P [n_nodes, n_nodes] (rows = destination I, columns = source J)."""
     label = problem.label
-    block, mobile, count = groups(label, problem.d_phase, B, grouped)
+    block, mobile, count = groups(label, problem.d_phase, B, grouped, reservoir)
     n_nodes = count.size
     shape = label.shape
     nz, ny, nx = shape
     r, W = problem.r, problem.W
     S = np.zeros((n_nodes, n_nodes))
     src = np.flatnonzero(mobile.ravel())
-    G, mass = problem.kernels(src)
+    fixed = None if reservoir is None else reservoir_mask(label, reservoir)
+    G, mass = problem.kernels(src, fixed)
     rel = np.arange(W) - r
     for q, s in enumerate(src):
         sz, sy, sx = np.unravel_index(s, shape)
@@ -77,25 +99,25 @@ def coarse_matrix(problem, B: int, grouped=None) -> np.ndarray:
         inside = np.ix_(Z[kz], Y[ky], X[kx])
         keep = mobile[inside]
         g = G[q][np.ix_(kz, ky, kx)][keep]
-        np.add.at(S[:, block.flat[s]], block[inside][keep], g / g.sum())
+        np.add.at(S[:, block.flat[s]], block[inside][keep], g / g.sum() if fixed is None else g)
     P = np.zeros_like(S)
     has = count > 0
     P[has] = S[has] / count[has, None]
     return P
 
 
-def mapping(c, label, d_phase, B: int, grouped=None) -> np.ndarray:
+def mapping(c, label, d_phase, B: int, grouped=None, reservoir=None) -> np.ndarray:
     """Eq. 13: the mean of c over each group (0 for blocks without a node)."""
-    block, mobile, count = groups(label, d_phase, B, grouped)
+    block, mobile, count = groups(label, d_phase, B, grouped, reservoir)
     tot = np.bincount(block[mobile].ravel(), weights=np.asarray(c)[mobile].ravel(), minlength=count.size)
     C = np.zeros_like(tot)
     C[count > 0] = tot[count > 0] / count[count > 0]
     return C
 
 
-def remapping(C, c_old, label, d_phase, B: int, grouped=None) -> np.ndarray:
+def remapping(C, c_old, label, d_phase, B: int, grouped=None, reservoir=None) -> np.ndarray:
     """Eq. 15: every grouped cell takes its node's value; other cells keep c_old."""
-    block, mobile, _ = groups(label, d_phase, B, grouped)
+    block, mobile, _ = groups(label, d_phase, B, grouped, reservoir)
     out = np.array(c_old, dtype=np.float64, copy=True)
     out[mobile] = np.asarray(C)[block[mobile]]
     return out
@@ -105,3 +127,24 @@ def step(problem, P, c, B: int, grouped=None) -> np.ndarray:
     """One coarse big step (Eqs. 13-15) with the matrix from coarse_matrix."""
     C = mapping(c, problem.label, problem.d_phase, B, grouped)
     return remapping(P @ C, c, problem.label, problem.d_phase, B, grouped)
+
+
+def p_bc(problem, B: int, grouped=None, reservoir=None) -> np.ndarray:
+    """P_BC [n_nodes]: group means of the whole-domain response to a unit
+    concentration held on the reservoir cells (0 elsewhere at the start)."""
+    fixed = reservoir_mask(problem.label, reservoir)
+    field = problem.global_fd(np.zeros(problem.label.shape), fixed=fixed, fval=1.0)
+    return mapping(field, problem.label, problem.d_phase, B, grouped, reservoir)
+
+
+def step_far_field(problem, P, pbc, c, c_ff: float, m_total: float, v_ff: float, B: int, grouped=None,
+                   reservoir=None):
+    """One coarse big step with the far field (Eqs. 14, 15, 7); returns
+    (c_new, c_ff_new)."""
+    C = mapping(c, problem.label, problem.d_phase, B, grouped, reservoir)
+    out = remapping(P @ C + pbc * c_ff, c, problem.label, problem.d_phase, B, grouped, reservoir)
+    res = reservoir_mask(problem.label, reservoir)
+    out[res] = 0.0
+    c_ff_new = (m_total - out.sum()) / v_ff
+    out[res] = c_ff_new
+    return out, c_ff_new

@@ -105,11 +105,13 @@ void fo_coefficients(int nx, int ny, int nz, const uint8_t *label,
 /* Explicit sub-steps on a box [lo, hi] (inclusive, per axis) of the grid with
  * no flux through the box walls.  g holds the box state (z, y, x order) on
  * entry and exit; tmp is scratch of the same size.  Jacobi: every cell reads
- * the state of the previous sub-step.  Neighbour order -x, +x, -y, +y, -z, +z. */
+ * the state of the previous sub-step.  Neighbour order -x, +x, -y, +y, -z, +z.
+ * fixed (may be NULL): grid mask of Dirichlet cells (the far-field boundary of
+ * Eq. 8), which hold the value fval after every sub-step. */
 static void box_substeps(int nx, int ny, int nz,
                          const double *lam_x, const double *lam_y, const double *lam_z,
                          const int lo[3], const int hi[3], int n_sub,
-                         double *g, double *tmp)
+                         double *g, double *tmp, const uint8_t *fixed, double fval)
 {
     (void)nz;
     int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
@@ -127,7 +129,7 @@ static void box_substeps(int nx, int ny, int nz,
                     if (j < by - 1) acc += lam_y[IDX(X, Y, Z)]     * (g[b + bx] - gx);
                     if (k > 0)      acc += lam_z[IDX(X, Y, Z - 1)] * (g[b - (int64_t)bx * by] - gx);
                     if (k < bz - 1) acc += lam_z[IDX(X, Y, Z)]     * (g[b + (int64_t)bx * by] - gx);
-                    tmp[b] = acc;
+                    tmp[b] = (fixed && fixed[IDX(X, Y, Z)]) ? fval : acc;
                 }
         memcpy(g, tmp, sizeof(double) * (size_t)bx * by * bz);
     }
@@ -143,10 +145,12 @@ static void window_box(int nx, int ny, int nz, int r, int sx, int sy, int sz, in
 }
 
 /* Window kernel of one source: the W^3 window kernel G_s (placed relative to
- * s - r, zeros outside the domain) and its mass.  work: 2 * W^3 doubles. */
+ * s - r, zeros outside the domain) and its mass.  work: 2 * W^3 doubles.
+ * fixed (may be NULL): Dirichlet cells held at 0 (they absorb). */
 static void kernel_one(int nx, int ny, int nz,
                        const double *lam_x, const double *lam_y, const double *lam_z,
-                       int r, int n_sub, int64_t s, double *G, double *mass, double *work)
+                       int r, int n_sub, int64_t s, double *G, double *mass, double *work,
+                       const uint8_t *fixed)
 {
     int W = 2 * r + 1;
     int sx = (int)(s % nx), sy = (int)((s / nx) % ny), sz = (int)(s / ((int64_t)nx * ny));
@@ -157,7 +161,7 @@ static void kernel_one(int nx, int ny, int nz,
     double *g = work, *tmp = work + nb;
     memset(g, 0, sizeof(double) * (size_t)nb);
     g[((int64_t)(sz - lo[2]) * by + (sy - lo[1])) * bx + (sx - lo[0])] = 1.0;
-    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, g, tmp);
+    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, g, tmp, fixed, 0.0);
     memset(G, 0, sizeof(double) * (size_t)W * W * W);
     for (int k = 0; k < bz; ++k)
         for (int j = 0; j < by; ++j)
@@ -168,11 +172,12 @@ static void kernel_one(int nx, int ny, int nz,
     if (mass) *mass = neumaier_sum(g, nb);
 }
 
-/* Kernels of a list of sources: G [n_src][W][W][W], mass [n_src]. */
-void fo_kernels(int nx, int ny, int nz,
-                const double *lam_x, const double *lam_y, const double *lam_z,
-                int r, int n_sub, const int64_t *src, int64_t n_src,
-                double *G, double *mass)
+/* Kernels of a list of sources: G [n_src][W][W][W], mass [n_src]; fixed (may
+ * be NULL): Dirichlet cells held at 0. */
+void fo_kernels_fixed(int nx, int ny, int nz,
+                      const double *lam_x, const double *lam_y, const double *lam_z,
+                      int r, int n_sub, const int64_t *src, int64_t n_src,
+                      double *G, double *mass, const uint8_t *fixed)
 {
     int64_t W3 = (int64_t)(2 * r + 1) * (2 * r + 1) * (2 * r + 1);
 #pragma omp parallel
@@ -181,9 +186,17 @@ void fo_kernels(int nx, int ny, int nz,
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < n_src; ++i)
             kernel_one(nx, ny, nz, lam_x, lam_y, lam_z, r, n_sub, src[i],
-                       G + i * W3, mass ? mass + i : NULL, work);
+                       G + i * W3, mass ? mass + i : NULL, work, fixed);
         free(work);
     }
+}
+
+void fo_kernels(int nx, int ny, int nz,
+                const double *lam_x, const double *lam_y, const double *lam_z,
+                int r, int n_sub, const int64_t *src, int64_t n_src,
+                double *G, double *mass)
+{
+    fo_kernels_fixed(nx, ny, nz, lam_x, lam_y, lam_z, r, n_sub, src, n_src, G, mass, NULL);
 }
 
 /* Superposition: c_new(x) = sum over sources s (ascending, c_old(s) != 0) of
@@ -251,7 +264,20 @@ void fo_global_fd(int nx, int ny, int nz,
     double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
     int lo[3] = {0, 0, 0}, hi[3] = {nx - 1, ny - 1, nz - 1};
     memcpy(out, c, sizeof(double) * (size_t)n);
-    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp);
+    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp, NULL, 0.0);
+    free(tmp);
+}
+
+/* The same with Dirichlet cells (mask fixed) holding fval from the start. */
+void fo_global_fd_fixed(int nx, int ny, int nz,
+                        const double *lam_x, const double *lam_y, const double *lam_z,
+                        int n_sub, const double *c, double *out, const uint8_t *fixed, double fval)
+{
+    int64_t n = (int64_t)nx * ny * nz;
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+    int lo[3] = {0, 0, 0}, hi[3] = {nx - 1, ny - 1, nz - 1};
+    for (int64_t i = 0; i < n; ++i) out[i] = fixed[i] ? fval : c[i];
+    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp, fixed, fval);
     free(tmp);
 }
 

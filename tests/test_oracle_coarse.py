@@ -91,3 +91,62 @@ def test_liquid_only_grouping_conserves_mass():
     # the default grouping of this domain (every D > 0) is every cell
     _, all_mobile, _ = coarse.groups(d.label, d.d_phase, 3)
     assert all_mobile.all()
+
+
+# ------------------------------------------------------------------ far field
+
+def test_far_field_two_cell_closed_form():
+    # one liquid cell next to one reservoir cell (same D): the kernel decays
+    # as (1 - lam)^n and the unit-boundary response is 1 - (1 - lam)^n
+    label = np.array([[[0, 1]]], dtype=np.uint8)
+    p = oracle.Problem(label, np.array([1.0, 1.0]), 1, 7, 1.0, 0.15)
+    res = [0, 1]
+    P = coarse.coarse_matrix(p, 1, reservoir=res)
+    pbc = coarse.p_bc(p, 1, reservoir=res)
+    q = (1.0 - 0.15) ** 7
+    assert abs(P[0, 0] - q) <= 1e-15
+    assert abs(pbc[0] - (1.0 - q)) <= 1e-15
+    assert P[1, 1] == 0.0 and pbc[1] == 0.0          # the reservoir block has no node
+
+
+def _far_field_domain(seed):
+    # x walls of reservoir phase 2; liquid 0 and a slow phase 1 inside
+    d = synth.random_small((5, 6, 7), 2, r=8, n_sub=9, seed=seed, d_zero_phase=False)
+    label = d.label.copy()
+    label[:, :, 0] = 2
+    label[:, :, -1] = 2
+    return label, np.array([1.0, 0.05, 1.0]), d.c0
+
+
+def test_far_field_uniform_state_is_stationary():
+    label, dph, _ = _far_field_domain(7)
+    p = oracle.Problem(label, dph, 8, 9, 1.0, 0.0)
+    res = [0, 0, 1]
+    for B in (1, 3):
+        P = coarse.coarse_matrix(p, B, reservoir=res)
+        pbc = coarse.p_bc(p, B, reservoir=res)
+        near = ~coarse.reservoir_mask(label, res)
+        v_ff = 40.0
+        c = np.ones(label.shape)
+        out, c_ff = coarse.step_far_field(p, P, pbc, c, 1.0, near.sum() + v_ff, v_ff, B, reservoir=res)
+        assert np.max(np.abs(out - 1.0)) <= 1e-13
+        assert abs(c_ff - 1.0) <= 1e-13
+
+
+def test_far_field_block_one_is_the_dirichlet_fd():
+    # windows covering the domain: Eq. 8 with P_BC equals the whole-domain FD
+    # with the reservoir cells held at c_ff, and Eq. 7 conserves the total
+    label, dph, c0 = _far_field_domain(8)
+    p = oracle.Problem(label, dph, 8, 9, 1.0, 0.0)
+    res = [0, 0, 1]
+    fixed = coarse.reservoir_mask(label, res)
+    P = coarse.coarse_matrix(p, 1, reservoir=res)
+    pbc = coarse.p_bc(p, 1, reservoir=res)
+    c_ff, v_ff = 0.3, 25.0
+    c = np.where(fixed, c_ff, c0)
+    m_total = c[~fixed].sum() + c_ff * v_ff
+    out, c_ff_new = coarse.step_far_field(p, P, pbc, c, c_ff, m_total, v_ff, 1, reservoir=res)
+    ref = p.global_fd(c, fixed=fixed, fval=c_ff)
+    assert np.max(np.abs(out[~fixed] - ref[~fixed])) <= 1e-13
+    assert np.all(out[fixed] == c_ff_new)
+    assert abs(out[~fixed].sum() + c_ff_new * v_ff - m_total) <= 1e-12 * m_total
