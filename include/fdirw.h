@@ -271,28 +271,51 @@ int fdirw_nn_load(void *nn, const char *path);
  * nonzero only for |I - J| <= K = ceil(r / block) per axis and is stored
  * offset-major in the precision `prec`; the product and its sum are FP64.
  * With block = 1 and the default grouping the step is the fine step with
- * renormalised kernels.  The far-field term of Eq. 14 is zero (no-flux
- * domain walls). */
+ * renormalised kernels.
+ * Far field (Eqs. 7, 8, 10, 14): cells of the reservoir phases are the
+ * far-field boundary, Dirichlet cells holding the uniform far-field
+ * concentration c_ff.  Their handle builds P from kernels in which those cells
+ * absorb (held at 0), not renormalised, and P_BC[I] = the mean over group I
+ * of the whole-domain FD response to a unit concentration held on them; a
+ * step is C' = P C + P_BC c_ff, the remapping, and then Eq. 7:
+ * c_ff' = (m_total - sum of c_out over the other cells) / v_ff.  Without
+ * reservoir phases the far-field term is zero (no-flux domain walls). */
 
 /* Builds the coarse operator of domain d (generating every fine kernel once,
  * FP64 for prec = FDIRW_FP64, FP32 otherwise; P stored as FP64, FP32,
  * FP16 (FDIRW_FP16_BANK) or BF16 (FDIRW_BF16_BANK)).  grouped (host, may be
  * NULL): d->n_phase flags, nonzero for the grouped phases; NULL groups every
- * phase with D > 0.  block: 1..256.  d->label is read only here.  *handle
+ * phase with D > 0.  reservoir (host, may be NULL): d->n_phase flags, nonzero
+ * for the far-field boundary phases (never grouped).  block: 1..256.  d->label is read only here.  *handle
  * receives a handle owning device memory of about 4 N + (2K+1)^3 x N_nodes x
  * element bytes; seconds (host, may be NULL) receives the build time.
  * Synchronises the stream.  The handle belongs to the current device.
  * Errors: E_ARG (also a block outside 1..256 or another precision),
  * E_UNSTABLE, E_NOMEM, E_DEVICE. */
-int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped, void *stream,
-                        void **handle, double *seconds);
+int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped,
+                        const uint8_t *reservoir, void *stream, void **handle, double *seconds);
 
 /* One coarse big step from c_in to c_out (N doubles each, not overlapping).
  * st (may be NULL) receives mass_in / mass_out (compensated FP64 sums, one
  * synchronisation each), n_sources = number of nodes, tuned_config_id =
  * block and kernel_seconds = device time of mapping + product + remapping.
- * Errors: E_ARG (null, overlap, another device), E_DEVICE. */
+ * Errors: E_ARG (null, overlap, another device, a handle with a far field),
+ * E_DEVICE. */
 int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *stream, fdirw_stats *st);
+
+/* One coarse big step with the far field (handle created with reservoir
+ * phases).  *c_ff (host, in / out): the far-field concentration of the step's
+ * start, replaced by the Eq. 7 value, which is also written into the
+ * far-field cells of c_out; m_total: the conserved total (sum of c over the
+ * cells outside the far field plus c_ff * v_ff at the start of the run);
+ * v_ff > 0: the far-field volume in cell units.  st (may be NULL): mass_in =
+ * m_total, mass_out = the same total after the step, kernel_seconds.
+ * Synchronises the stream.  Errors: E_ARG, E_NONFINITE, E_DEVICE. */
+int fdirw_coarse_step_far_field(void *handle, const double *c_in, double *c_out, double *c_ff, double m_total,
+                                double v_ff, void *stream, fdirw_stats *st);
+
+/* Copies P_BC (host, n_nodes doubles; zeros without a far field). */
+int fdirw_coarse_pbc(void *handle, double *pbc_host);
 
 /* shape5 (host, may be NULL) = {ncz, ncy, ncx, K, block}; *n_nodes (host,
  * may be NULL) = ncz * ncy * ncx, nodes numbered (bz * ncy + by) * ncx + bx. */

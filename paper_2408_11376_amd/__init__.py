@@ -12,8 +12,9 @@ Names follow the ABI:
     fdirw_nn_create, fdirw_nn_destroy, fdirw_nn_num_params,
     fdirw_nn_set_params, fdirw_nn_get_params, fdirw_nn_forward,
     fdirw_nn_backward, fdirw_nn_adam, fdirw_nn_save, fdirw_nn_load,
-    fdirw_coarse_create, fdirw_coarse_step, fdirw_coarse_shape,
-    fdirw_coarse_matrix, fdirw_coarse_destroy (wrapped by ``Coarse``)
+    fdirw_coarse_create, fdirw_coarse_step, fdirw_coarse_step_far_field,
+    fdirw_coarse_shape, fdirw_coarse_matrix, fdirw_coarse_pbc,
+    fdirw_coarse_destroy (wrapped by ``Coarse``)
 """
 from __future__ import annotations
 
@@ -85,7 +86,8 @@ ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run
                  "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
                  "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create", "fdirw_coarse_step",
-                 "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_destroy")
+                 "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_pbc",
+                 "fdirw_coarse_destroy")
 NN_RADIUS = 8
 
 _lib = None
@@ -125,8 +127,12 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_nn_adam.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
     lib.fdirw_nn_save.argtypes = [P, ctypes.c_char_p]
     lib.fdirw_nn_load.argtypes = [P, ctypes.c_char_p]
-    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, P, PP, ctypes.POINTER(ctypes.c_double)]
+    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, P, P, PP,
+                                        ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_coarse_step.argtypes = [P, P, P, P, S]
+    lib.fdirw_coarse_step_far_field.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                                ctypes.c_double, P, S]
+    lib.fdirw_coarse_pbc.argtypes = [P, P]
     lib.fdirw_coarse_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.fdirw_coarse_matrix.argtypes = [P, P]
     lib.fdirw_coarse_destroy.argtypes = [P]
@@ -134,7 +140,8 @@ def load_library(path: str = LIB_PATH):
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
               "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create",
-              "fdirw_coarse_step", "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_destroy"):
+              "fdirw_coarse_step", "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix",
+              "fdirw_coarse_pbc", "fdirw_coarse_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -367,21 +374,44 @@ def fdirw_field_sum(c, stream=None) -> float:
 
 # ----------------------------------------------------------------- coarse mesh
 
-def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, grouped=None, stream=None):
+def _phase_flags(dom: Domain, flags, name):
+    if flags is None:
+        return None
+    g = np.ascontiguousarray(flags, dtype=np.uint8)
+    if g.size != len(dom.d_phase):
+        raise ValueError(f"{name} needs one flag per phase")
+    return (ctypes.c_uint8 * g.size)(*g.tolist())
+
+
+def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, grouped=None, reservoir=None, stream=None):
     """Handle and build seconds of the coarse operator of ``dom``; ``grouped``:
-    per-phase flags of the grouped (fast) phases, None for every D > 0."""
+    per-phase flags of the grouped (fast) phases, None for every D > 0;
+    ``reservoir``: per-phase flags of the far-field boundary phases."""
     h = ctypes.c_void_p()
     sec = ctypes.c_double(0.0)
     ds = dom.c_struct()
-    flags = None
-    if grouped is not None:
-        g = np.ascontiguousarray(grouped, dtype=np.uint8)
-        if g.size != len(dom.d_phase):
-            raise ValueError("grouped needs one flag per phase")
-        flags = (ctypes.c_uint8 * g.size)(*g.tolist())
-    _check(load_library().fdirw_coarse_create(ctypes.byref(ds), int(block), _prec(prec), flags,
-                                              _stream_ptr(stream), ctypes.byref(h), ctypes.byref(sec)))
+    _check(load_library().fdirw_coarse_create(ctypes.byref(ds), int(block), _prec(prec),
+                                              _phase_flags(dom, grouped, "grouped"),
+                                              _phase_flags(dom, reservoir, "reservoir"), _stream_ptr(stream),
+                                              ctypes.byref(h), ctypes.byref(sec)))
     return h, sec.value
+
+
+def fdirw_coarse_step_far_field(handle, c_in, c_out, c_ff: float, m_total: float, v_ff: float, stream=None,
+                                stats: bool = False):
+    """Returns the new far-field concentration (and the stats dict)."""
+    st = fdirw_stats() if stats else None
+    cff = ctypes.c_double(float(c_ff))
+    _check(load_library().fdirw_coarse_step_far_field(handle, ctypes.c_void_p(c_in.data_ptr()),
+                                                      ctypes.c_void_p(c_out.data_ptr()), ctypes.byref(cff),
+                                                      float(m_total), float(v_ff), _stream_ptr(stream),
+                                                      ctypes.byref(st) if st is not None else None))
+    return (cff.value, st.as_dict()) if stats else cff.value
+
+
+def fdirw_coarse_pbc(handle, out: np.ndarray):
+    _check(load_library().fdirw_coarse_pbc(handle, ctypes.c_void_p(out.ctypes.data)))
+    return out
 
 
 def fdirw_coarse_step(handle, c_in, c_out, stream=None, stats: bool = False):
@@ -411,10 +441,11 @@ def fdirw_coarse_destroy(handle) -> None:
 class Coarse:
     """Coarse-mesh FDiRW operator of one geometry (Sec. 3.1, Eqs. 10-15):
     ``block``^3 groups of the grouped phases' cells (default: every D > 0),
-    P stored in ``prec`` (fp64, fp32, fp16_bank or bf16_bank)."""
+    P stored in ``prec`` (fp64, fp32, fp16_bank or bf16_bank); with
+    ``reservoir`` phases, the far-field boundary of Eqs. 7 and 14."""
 
-    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, grouped=None, stream=None):
-        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, grouped, stream)
+    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, grouped=None, reservoir=None, stream=None):
+        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, grouped, reservoir, stream)
         shp, self.n_nodes = fdirw_coarse_shape(self.handle)
         self.coarse_shape = tuple(shp[:3])
         self.K, self.block = shp[3], shp[4]
@@ -430,6 +461,22 @@ class Coarse:
             raise ValueError("field does not match the domain")
         st = fdirw_coarse_step(self.handle, c_in, c_out, stream, stats)
         return (c_out, st) if stats else c_out
+
+    def step_far_field(self, c_in, c_ff: float, m_total: float, v_ff: float, c_out=None, stream=None,
+                       stats: bool = False):
+        """One step with the far field: (c_out, new c_ff[, stats])."""
+        torch = _torch()
+        _dev_tensor(c_in, torch.float64, "c_in")
+        if c_out is None:
+            c_out = torch.empty_like(c_in)
+        _dev_tensor(c_out, torch.float64, "c_out")
+        if c_in.numel() != self.n or c_out.numel() != self.n:
+            raise ValueError("field does not match the domain")
+        r = fdirw_coarse_step_far_field(self.handle, c_in, c_out, c_ff, m_total, v_ff, stream, stats)
+        return (c_out,) + tuple(r) if stats else (c_out, r)
+
+    def p_bc(self) -> np.ndarray:
+        return fdirw_coarse_pbc(self.handle, np.empty(self.n_nodes))
 
     def matrix(self) -> np.ndarray:
         """P as [(2K+1)^3, n_nodes] float64: entry [o, I] = P[I][I - (o - K)]."""

@@ -24,8 +24,11 @@ __global__ void coarse_nodes_kernel(const uint8_t *__restrict__ label, CoarseTab
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
-        int v = -1;
-        if (tab.mobile[label[i]]) {
+        const unsigned l = label[i];
+        int v = COARSE_OUTSIDE;
+        if (tab.reservoir[l]) {
+            v = COARSE_RESERVOIR;
+        } else if (tab.mobile[l]) {
             v = ((z / B) * ncy + y / B) * ncx + x / B;
             atomicAdd(&count[v], 1.0);
         }
@@ -33,10 +36,35 @@ __global__ void coarse_nodes_kernel(const uint8_t *__restrict__ label, CoarseTab
     }
 }
 
-// One workgroup per grouped source: its fine window kernel over the grouped
-// cells, renormalised to unit mass there, summed per destination block into
-// S[offset][I] (offset = I - J + K per axis, J the source's block).
+// The window sub-steps of fdirw_device.h with the far-field boundary cells of
+// the window held at 0 after every sub-step (they absorb what reaches them).
 template <int M, int R>
+__device__ __forceinline__ void run_substeps_sink(SegVals<M, R> &G, const Seg<M, R> &c,
+                                                  typename Geo<M, R>::E *__restrict__ xb, const Place &p, int n_sub,
+                                                  const bool (&sink)[Geo<M, R>::L0])
+{
+    using G_ = Geo<M, R>;
+    constexpr int NCOL = G_::NCOL, L = G_::L0;
+    const int col = G_::PADC + p.col;
+    const int own = col * G_::ZS + p.seg * G_::SOFF;
+    const int tail_at = G_::TAIL + p.seg * NCOL + col;
+    const int head_at = G_::HEAD + p.seg * NCOL + col;
+    const int zlo_at = G_::TAIL + (p.seg > 0 ? p.seg - 1 : 0) * NCOL + col;
+    const int zhi_at = G_::HEAD + (p.seg < G_::NSEG - 1 ? p.seg + 1 : 0) * NCOL + col;
+    for (int step = 0; step < n_sub; ++step) {
+        one_substep<M, R>(G, c, (step & 1) ? xb + G_::XLEN : xb, p, own, tail_at, head_at, zlo_at, zhi_at);
+#pragma unroll
+        for (int k = 0; k < L; ++k)
+            if (sink[k]) G[k] = 0;
+    }
+}
+
+// One workgroup per grouped source: its fine window kernel over the grouped
+// cells, summed per destination block into S[offset][I] (offset = I - J + K
+// per axis, J the source's block).  Without a far field the kernel is
+// renormalised to unit mass over the grouped cells; with one (SINK) the
+// far-field cells absorb and the kernel keeps the mass that is left.
+template <int M, int R, bool SINK>
 __global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
 coarse_window_kernel(CoarseGenArgs a)
 {
@@ -64,11 +92,22 @@ coarse_window_kernel(CoarseGenArgs a)
         compute_diag<T::x32, M, R>(c);
         S G[L];
         init_delta<M, R>(G, p);
-        run_substeps<M, R>(G, c, xb, p, a.n_sub);
-        // the kernel's mass over the grouped cells (FP64, fixed order)
         const int X = sx - R + p.cx, Y = sy - R + p.cy;
         const bool inxy = p.act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
         bool grp[L];
+        if constexpr (SINK) {
+            bool sink[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const int Z = sz - R + p.j0 + k;
+                sink[k] = inxy && k < p.len && Z >= 0 && Z < a.nz &&
+                          a.node[((int64_t)Z * a.ny + Y) * a.nx + X] == COARSE_RESERVOIR;
+            }
+            run_substeps_sink<M, R>(G, c, xb, p, a.n_sub, sink);
+        } else {
+            run_substeps<M, R>(G, c, xb, p, a.n_sub);
+        }
+        // the kernel's mass over the grouped cells (FP64, fixed order)
         double part = 0.0;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
@@ -76,7 +115,7 @@ coarse_window_kernel(CoarseGenArgs a)
             grp[k] = inxy && k < p.len && Z >= 0 && Z < a.nz && a.node[((int64_t)Z * a.ny + Y) * a.nx + X] >= 0;
             if (grp[k]) part += (double)G[k];
         }
-        const double inv = 1.0 / block_sum<G_::NWAVE>(part, red);
+        const double inv = SINK ? 1.0 : 1.0 / block_sum<G_::NWAVE>(part, red);
         const int jx = sx / B, jy = sy / B, jz = sz / B;
         if (inxy) {
             const int oxy = (Y / B - jy + K) * KW + (X / B - jx + K);
@@ -183,6 +222,7 @@ constexpr int APPLY_NT = 256;
 template <typename T>
 __global__ void __launch_bounds__(APPLY_NT) coarse_apply_kernel(const T *__restrict__ P, const double *__restrict__ cpad,
                                                                 int ncx, int ncy, int ncz, int K,
+                                                                const double *__restrict__ pbc_pad, double c_ff,
                                                                 double *__restrict__ cnew)
 {
     __shared__ double part[APPLY_NT];
@@ -209,18 +249,61 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_kernel(const T *__restr
     if (ln < per && oz == 0 && I < n_nodes) {
         double s = 0.0;
         for (int k = 0; k < kw; ++k) s += part[ln * kw + k];
+        if (pbc_pad) {                                            // far-field term of Eq. 14
+            const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
+            s = __builtin_fma(pbc_pad[((int64_t)(z + K) * py + (y + K)) * px + (x + K)], c_ff, s);
+        }
         cnew[I] = s;
     }
 }
 
-// Eq. 15: every grouped cell takes its node's value, the others keep theirs.
+// Eq. 15: every grouped cell takes its node's value, the others keep theirs;
+// far-field cells are written 0 (the Eq. 7 value follows once the rest of the
+// field has been summed).
 __global__ void coarse_remap_kernel(const double *__restrict__ c_in, const int *__restrict__ node,
                                     const double *__restrict__ cnew, int64_t n, double *__restrict__ c_out)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int I = node[i];
-        c_out[i] = I >= 0 ? cnew[I] : c_in[i];
+        c_out[i] = I >= 0 ? cnew[I] : (I == COARSE_RESERVOIR ? 0.0 : c_in[i]);
+    }
+}
+
+// c[i] = v on the far-field cells.
+__global__ void coarse_fill_reservoir_kernel(const int *__restrict__ node, int64_t n, double v, double *__restrict__ c)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (node[i] == COARSE_RESERVOIR) c[i] = v;
+}
+
+// One explicit sub-step on the whole domain (no-flux walls) with the far-field
+// cells held at 1: the response p_BC to a unit boundary concentration (Eq. 8).
+// Terms in the order -x, +x, -y, +y, -z, +z; FP64 state, coefficients of type S.
+template <typename S>
+__global__ void coarse_pbc_substep_kernel(const S *__restrict__ lx, const int *__restrict__ node, int nx, int ny,
+                                          int nz, const double *__restrict__ in, double *__restrict__ out)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    const S *ly = lx + n, *lz = ly + n;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (node[i] == COARSE_RESERVOIR) {
+            out[i] = 1.0;
+            continue;
+        }
+        const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / sz);
+        const double g = in[i];
+        double acc = g;
+        if (x > 0) acc += (double)lx[i - 1] * (in[i - 1] - g);
+        if (x < nx - 1) acc += (double)lx[i] * (in[i + 1] - g);
+        if (y > 0) acc += (double)ly[i - sy] * (in[i - sy] - g);
+        if (y < ny - 1) acc += (double)ly[i] * (in[i + sy] - g);
+        if (z > 0) acc += (double)lz[i - sz] * (in[i - sz] - g);
+        if (z < nz - 1) acc += (double)lz[i] * (in[i + sz] - g);
+        out[i] = acc;
     }
 }
 
@@ -238,35 +321,65 @@ hipError_t launch_coarse_nodes(const uint8_t *label, const CoarseTable &tab, int
     return hipGetLastError();
 }
 
-template <int M, int R>
+template <int M, int R, bool SINK>
 static hipError_t launch_cw_mr(const CoarseGenArgs &a, hipStream_t st)
 {
     const int64_t nblk = a.n < 65536 * 16 ? a.n : 65536 * 16;
     if (nblk <= 0) return hipSuccess;
-    hipLaunchKernelGGL((coarse_window_kernel<M, R>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
+    hipLaunchKernelGGL((coarse_window_kernel<M, R, SINK>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
     return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool SINK>
 static hipError_t launch_cw_m(int r, const CoarseGenArgs &a, hipStream_t st)
 {
     switch (r) {
-    case 0: return launch_cw_mr<M, 0>(a, st);
-    case 1: return launch_cw_mr<M, 1>(a, st);
-    case 2: return launch_cw_mr<M, 2>(a, st);
-    case 3: return launch_cw_mr<M, 3>(a, st);
-    case 4: return launch_cw_mr<M, 4>(a, st);
-    case 5: return launch_cw_mr<M, 5>(a, st);
-    case 6: return launch_cw_mr<M, 6>(a, st);
-    case 7: return launch_cw_mr<M, 7>(a, st);
-    case 8: return launch_cw_mr<M, 8>(a, st);
+    case 0: return launch_cw_mr<M, 0, SINK>(a, st);
+    case 1: return launch_cw_mr<M, 1, SINK>(a, st);
+    case 2: return launch_cw_mr<M, 2, SINK>(a, st);
+    case 3: return launch_cw_mr<M, 3, SINK>(a, st);
+    case 4: return launch_cw_mr<M, 4, SINK>(a, st);
+    case 5: return launch_cw_mr<M, 5, SINK>(a, st);
+    case 6: return launch_cw_mr<M, 6, SINK>(a, st);
+    case 7: return launch_cw_mr<M, 7, SINK>(a, st);
+    case 8: return launch_cw_mr<M, 8, SINK>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_coarse_window(int fp64, int r, const CoarseGenArgs &a, hipStream_t st)
+hipError_t launch_coarse_window(int fp64, int sink, int r, const CoarseGenArgs &a, hipStream_t st)
 {
-    return fp64 ? launch_cw_m<M_FP64>(r, a, st) : launch_cw_m<M_FP32>(r, a, st);
+    if (sink) return fp64 ? launch_cw_m<M_FP64, true>(r, a, st) : launch_cw_m<M_FP32, true>(r, a, st);
+    return fp64 ? launch_cw_m<M_FP64, false>(r, a, st) : launch_cw_m<M_FP32, false>(r, a, st);
+}
+
+// n_sub sub-steps of coarse_pbc_substep_kernel from 0 (far-field cells 1),
+// ping-ponging between a and b; *result points to the final field.
+hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int nx, int ny, int nz, int n_sub,
+                                double *a, double *b, double **result, hipStream_t st)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipError_t e = launch_fill(a, n, 0.0, st);
+    if (e == hipSuccess) e = launch_coarse_fill_reservoir(node, n, 1.0, a, st);
+    double *in = a, *out = b;
+    for (int k = 0; k < n_sub && e == hipSuccess; ++k) {
+        if (fp64)
+            hipLaunchKernelGGL(coarse_pbc_substep_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                               (const double *)lam, node, nx, ny, nz, in, out);
+        else
+            hipLaunchKernelGGL(coarse_pbc_substep_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                               (const float *)lam, node, nx, ny, nz, in, out);
+        e = hipGetLastError();
+        double *t = in; in = out; out = t;
+    }
+    *result = in;
+    return e;
+}
+
+hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st)
+{
+    hipLaunchKernelGGL(coarse_fill_reservoir_kernel, dim3(grid_for(n)), dim3(256), 0, st, node, n, v, c);
+    return hipGetLastError();
 }
 
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
@@ -305,7 +418,7 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
 }
 
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               double *cnew, hipStream_t st)
+                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st)
 {
     const int per = APPLY_NT / (2 * K + 1);
     if (per < 1) return hipErrorInvalidValue;
@@ -313,20 +426,20 @@ hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int 
     const unsigned g = (unsigned)nblk;
     switch (prec) {
     case M_FP64:
-        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(APPLY_NT), 0, st, (const double *)P, cpad, ncx, ncy,
-                           ncz, K, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(APPLY_NT), 0, st, (const double *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
         break;
     case M_FP32:
-        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(APPLY_NT), 0, st, (const float *)P, cpad, ncx, ncy,
-                           ncz, K, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(APPLY_NT), 0, st, (const float *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
         break;
     case M_F16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(APPLY_NT), 0, st, (const _Float16 *)P, cpad, ncx,
-                           ncy, ncz, K, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(APPLY_NT), 0, st, (const _Float16 *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
         break;
     case M_BF16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(APPLY_NT), 0, st, (const __bf16 *)P, cpad, ncx,
-                           ncy, ncz, K, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(APPLY_NT), 0, st, (const __bf16 *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
         break;
     default: return hipErrorInvalidValue;
     }

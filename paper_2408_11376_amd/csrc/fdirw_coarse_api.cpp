@@ -37,10 +37,12 @@ struct Coarse {
     void *cpad = nullptr;           // double [(ncz+2K)(ncy+2K)(ncx+2K)]
     void *cnew = nullptr;           // double [n_nodes]
     void *part = nullptr;           // field-sum partials
+    bool far_field = false;         // reservoir (far-field boundary) phases present
+    void *pbc = nullptr;            // double, P_BC on the padded coarse grid (far field only)
 
     ~Coarse()
     {
-        for (void *p : {node, count, P, cpad, cnew, part})
+        for (void *p : {node, count, P, cpad, cnew, part, pbc})
             if (p) (void)hipFree(p);
     }
     int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
@@ -85,8 +87,8 @@ using namespace fdirw;
 
 extern "C" {
 
-int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped, void *stream,
-                        void **handle, double *seconds)
+int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped,
+                        const uint8_t *reservoir, void *stream, void **handle, double *seconds)
 {
     if (!handle) return fail(FDIRW_E_ARG, "handle is null");
     *handle = nullptr;
@@ -113,6 +115,8 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
     h->n_nodes = (int64_t)h->ncx * h->ncy * h->ncz;
     h->prec = prec;
     h->esz = bank_elem_bytes(prec);
+    if (reservoir)
+        for (int i = 0; i < d->n_phase; ++i) h->far_field = h->far_field || reservoir[i] != 0;
     const int zb = 16 / (int)h->esz;
     h->plane = (int64_t)((h->ncz + zb - 1) / zb) * h->ncy * h->ncx * zb;
     const int nb = h->nb();
@@ -132,15 +136,18 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
         if (!rc) rc = coarse_alloc(&h->cnew, (size_t)h->n_nodes * sizeof(double));
         if (!rc) rc = coarse_alloc(&h->part, (size_t)(2 * field_sum_blocks(h->n) + 2) * sizeof(double));
         if (!rc) rc = coarse_alloc((void **)&S, (size_t)nb * h->n_nodes * sizeof(double));
+        if (!rc && h->far_field) rc = coarse_alloc(&h->pbc, (size_t)n_pad * sizeof(double));
         if (rc) {
-            if (S) (void)hipFree(S);
+            (void)hipFree(S);
             delete h;
             return rc;
         }
         CoarseTable tab;
         std::memset(&tab, 0, sizeof tab);
-        for (int i = 0; i < d->n_phase; ++i)
+        for (int i = 0; i < d->n_phase; ++i) {
             tab.mobile[i] = (grouped ? grouped[i] != 0 : d->d_phase[i] > 0.0) ? 1 : 0;
+            tab.reservoir[i] = (reservoir && reservoir[i]) ? 1 : 0;
+        }
         // P entries of empty nodes and of the padding groups stay 0
         e = launch_fill((double *)h->count, h->n_nodes, 0.0, st);
         if (e == hipSuccess) e = launch_fill(S, (int64_t)nb * h->n_nodes, 0.0, st);
@@ -159,7 +166,26 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             a.ncx = h->ncx; a.ncy = h->ncy;
             a.n_nodes = h->n_nodes;
             a.S = S;
-            e = launch_coarse_window(prec == FDIRW_FP64, d->r, a, st);
+            e = launch_coarse_window(prec == FDIRW_FP64, h->far_field, d->r, a, st);
+        }
+        if (e == hipSuccess && h->far_field) {
+            // p_BC: the whole-domain FD from 0 with the far-field cells at 1,
+            // then its group means on the padded coarse grid
+            double *fa = nullptr;
+            if ((rc = coarse_alloc((void **)&fa, (size_t)2 * h->n * sizeof(double)))) {
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(S);
+                delete h;
+                return rc;
+            }
+            double *field = nullptr;
+            e = launch_coarse_pbc_fd(prec == FDIRW_FP64, lam, (const int *)h->node, d->nx, d->ny, d->nz, d->n_sub, fa,
+                                     fa + h->n, &field, st);
+            if (e == hipSuccess)
+                e = launch_coarse_map(field, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz,
+                                      block, h->ncx, h->ncy, h->ncz, h->K, (double *)h->pbc, st);
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(fa);
         }
         if (e == hipSuccess)
             e = launch_coarse_finalize(prec, S, (const double *)h->count, h->n_nodes, nb, h->ncx, h->ncy, h->ncz,
@@ -176,11 +202,45 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
     return FDIRW_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Mapping, product (with P_BC c_ff when pbc is set) and remapping; far-field
+// cells of c_out are left at 0.  kernel seconds of the three launches in *ks.
+int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double *pbc, double c_ff, hipStream_t st,
+                     double *ks)
+{
+    EventPair ev;
+    hipError_t e = ks ? ev.create() : hipSuccess;
+    if (ks && e == hipSuccess) e = hipEventRecord(ev.a, st);
+    if (e == hipSuccess)
+        e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
+                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st);
+    if (e == hipSuccess)
+        e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
+                                (double *)h->cnew, st);
+    if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
+    if (ks && e == hipSuccess) e = hipEventRecord(ev.b, st);
+    if (e != hipSuccess) return hip_fail(e, "coarse step launch");
+    if (ks) {
+        e = hipEventSynchronize(ev.b);
+        if (e != hipSuccess) return hip_fail(e, "coarse step");
+        *ks = ev.seconds();
+    }
+    return FDIRW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *stream, fdirw_stats *stats)
 {
     Coarse *h = (Coarse *)handle;
     int rc = check_handle(h);
     if (rc) return rc;
+    if (h->far_field) return fail(FDIRW_E_ARG, "the handle has far-field phases: use fdirw_coarse_step_far_field");
     if (!c_in || !c_out) return fail(FDIRW_E_ARG, "c_in and c_out must not be null");
     if (c_in == c_out) return fail(FDIRW_E_ARG, "c_in and c_out must not overlap");
     const auto t0 = std::chrono::steady_clock::now();
@@ -188,27 +248,76 @@ int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *str
     fdirw_stats loc;
     std::memset(&loc, 0, sizeof loc);
     if (stats && (rc = field_sum_h(h, c_in, st, &loc.mass_in))) return rc;
-    EventPair ev;
-    hipError_t e = stats ? ev.create() : hipSuccess;
-    if (stats && e == hipSuccess) e = hipEventRecord(ev.a, st);
-    if (e == hipSuccess)
-        e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
-                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st);
-    if (e == hipSuccess)
-        e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
-                                (double *)h->cnew, st);
-    if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
-    if (stats && e == hipSuccess) e = hipEventRecord(ev.b, st);
-    if (e != hipSuccess) return hip_fail(e, "coarse step launch");
+    if ((rc = coarse_apply_all(h, c_in, c_out, nullptr, 0.0, st, stats ? &loc.kernel_seconds : nullptr))) return rc;
     if (stats) {
         if ((rc = field_sum_h(h, c_out, st, &loc.mass_out))) return rc;
         loc.kmass_min = INFINITY;
         loc.kmass_max = -INFINITY;
         loc.n_sources = h->n_nodes;
         loc.tuned_config_id = h->B;
-        loc.kernel_seconds = ev.seconds();
         loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         *stats = loc;
+    }
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_step_far_field(void *handle, const double *c_in, double *c_out, double *c_ff, double m_total,
+                                double v_ff, void *stream, fdirw_stats *stats)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!h->far_field) return fail(FDIRW_E_ARG, "the handle has no far-field phase");
+    if (!c_in || !c_out || !c_ff) return fail(FDIRW_E_ARG, "c_in, c_out and c_ff must not be null");
+    if (c_in == c_out) return fail(FDIRW_E_ARG, "c_in and c_out must not overlap");
+    if (!(v_ff > 0.0) || !std::isfinite(v_ff)) return fail(FDIRW_E_ARG, "v_ff must be finite and > 0");
+    if (!std::isfinite(*c_ff) || !std::isfinite(m_total)) return fail(FDIRW_E_NONFINITE, "c_ff and m_total must be finite");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    double ks = 0.0;
+    if ((rc = coarse_apply_all(h, c_in, c_out, (const double *)h->pbc, *c_ff, st, stats ? &ks : nullptr))) return rc;
+    // Eq. 7: the far field holds what the near field does not
+    double near = 0.0;
+    if ((rc = field_sum_h(h, c_out, st, &near))) return rc;
+    const double cff = (m_total - near) / v_ff;
+    hipError_t e = launch_coarse_fill_reservoir((const int *)h->node, h->n, cff, c_out, st);
+    if (e != hipSuccess) return hip_fail(e, "far-field fill");
+    *c_ff = cff;
+    if (stats) {
+        fdirw_stats loc;
+        std::memset(&loc, 0, sizeof loc);
+        loc.mass_in = m_total;
+        loc.mass_out = near + cff * v_ff;
+        loc.kmass_min = INFINITY;
+        loc.kmass_max = -INFINITY;
+        loc.n_sources = h->n_nodes;
+        loc.tuned_config_id = h->B;
+        loc.kernel_seconds = ks;
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "far-field step");
+        loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *stats = loc;
+    }
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_pbc(void *handle, double *pbc_host)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!pbc_host) return fail(FDIRW_E_ARG, "pbc is null");
+    if (!h->far_field) {
+        for (int64_t I = 0; I < h->n_nodes; ++I) pbc_host[I] = 0.0;
+        return FDIRW_OK;
+    }
+    const int px = h->ncx + 2 * h->K, py = h->ncy + 2 * h->K, pz = h->ncz + 2 * h->K;
+    std::vector<double> pad((size_t)px * py * pz);
+    hipError_t e = hipMemcpy(pad.data(), h->pbc, pad.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "P_BC copy");
+    for (int64_t I = 0; I < h->n_nodes; ++I) {
+        const int x = (int)(I % h->ncx), y = (int)((I / h->ncx) % h->ncy), z = (int)(I / ((int64_t)h->ncx * h->ncy));
+        pbc_host[I] = pad[((size_t)(z + h->K) * py + (y + h->K)) * px + (x + h->K)];
     }
     return FDIRW_OK;
 }

@@ -52,14 +52,19 @@ struct BankArgs {
 // Coarse-mesh FDiRW (fdirw_coarse.hip).
 struct CoarseTable {
     uint8_t mobile[256];      // 1 if the phase is grouped (a fast phase)
+    uint8_t reservoir[256];   // 1 if the phase is the far-field boundary (Dirichlet cells)
 };
+
+// node[] values of the cells that are in no group.
+constexpr int COARSE_OUTSIDE = -1;     // keeps its value
+constexpr int COARSE_RESERVOIR = -2;   // far-field boundary cell
 
 struct CoarseGenArgs {
     int nx, ny, nz;
     int64_t n;
     int n_sub;
     const void *lx;           // coefficients as in LineArgs
-    const int *node;          // [N] node (block) index of a grouped cell, -1 otherwise
+    const int *node;          // [N] node (block) index of a grouped cell, else COARSE_OUTSIDE / _RESERVOIR
     int block, K;             // block edge B, offset reach K = ceil(r / B)
     int ncx, ncy;             // coarse grid (x, y extents)
     int64_t n_nodes;
@@ -104,13 +109,16 @@ int64_t bank_chat_elems(int nx, int ny, int nz, int r);
 hipError_t launch_bank_gather(int prec, int r, const BankArgs &a, hipStream_t st);   // a.chat given
 hipError_t launch_coarse_nodes(const uint8_t *label, const CoarseTable &tab, int nx, int ny, int nz, int B,
                                int ncx, int ncy, int *node, double *count, hipStream_t st);
-hipError_t launch_coarse_window(int fp64, int r, const CoarseGenArgs &a, hipStream_t st);
+hipError_t launch_coarse_window(int fp64, int sink, int r, const CoarseGenArgs &a, hipStream_t st);
+hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int nx, int ny, int nz, int n_sub,
+                                double *a, double *b, double **result, hipStream_t st);
+hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st);
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
                                   int ncy, int ncz, void *P, hipStream_t st);
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
                              int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st);
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               double *cnew, hipStream_t st);
+                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st);
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
                                hipStream_t st);
 int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes);   // offset-major bank, padded

@@ -168,3 +168,74 @@ def test_full_size_sampled_columns():
             want = S[I] / count[I] if count[I] > 0 else 0.0
             assert abs(got[o, I] - want) <= 1e-5 * max(abs(want), 1e-3), (J, o)
     cg.close()
+
+
+# ------------------------------------------------------------------ far field
+
+def _far_field_domain(seed, shape=(5, 6, 7)):
+    # x walls of reservoir phase 2 (the far-field boundary); liquid 0 and a
+    # slow phase 1 inside
+    d = synth.random_small(shape, 2, r=3, n_sub=9, seed=seed, d_zero_phase=False)
+    label = d.label.copy()
+    label[:, :, 0] = 2
+    label[:, :, -1] = 2
+    return label, np.array([1.0, 0.05, 1.0]), d.c0
+
+
+@pytest.mark.parametrize("B,prec,tol", [(1, fd.FP64, 1e-12), (3, fd.FP64, 1e-12), (2, fd.FP32, 1e-5)])
+def test_far_field_matches_oracle(B, prec, tol):
+    label, dph, c0 = _far_field_domain(20)
+    res = [0, 0, 1]
+    p = oracle.Problem(label, dph, 3, 9, 1.0, 0.0)
+    P = coarse.coarse_matrix(p, B, reservoir=res)
+    pbc = coarse.p_bc(p, B, reservoir=res)
+    cg = fd.Coarse(fd.Domain(label, dph, 3, 9, 1.0, 0.0), B, prec, reservoir=res)
+    assert np.max(np.abs(cg.matrix() - _offset_form(P, cg.coarse_shape, cg.K))) <= tol * 0.1
+    assert np.max(np.abs(cg.p_bc() - pbc)) <= tol * 0.1
+    fixed = coarse.reservoir_mask(label, res)
+    c_ff, v_ff = 0.4, 30.0
+    c = np.where(fixed, c_ff, c0)
+    m_total = c[~fixed].sum() + c_ff * v_ff
+    want, cff_want = coarse.step_far_field(p, P, pbc, c, c_ff, m_total, v_ff, B, reservoir=res)
+    out, cff, st = cg.step_far_field(to_dev(c), c_ff, m_total, v_ff, stats=True)
+    got = to_host(out)
+    assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
+    assert abs(cff - cff_want) <= tol * max(abs(cff_want), 1.0)
+    assert np.all(got[fixed] == cff)
+    assert abs(st["mass_out"] - m_total) <= 1e-12 * m_total
+    # a second step from the first
+    want2, cff_want2 = coarse.step_far_field(p, P, pbc, want, cff_want, m_total, v_ff, B, reservoir=res)
+    out2, cff2 = cg.step_far_field(out, cff, m_total, v_ff)
+    assert np.max(np.abs(to_host(out2) - want2)) <= tol * np.abs(want2).max()
+    assert abs(cff2 - cff_want2) <= tol * max(abs(cff_want2), 1.0)
+    cg.close()
+
+
+def test_far_field_uniform_state_is_stationary():
+    # windows covering the domain: the uniform state with c_ff = c stays put
+    label, dph, _ = _far_field_domain(21)
+    res = [0, 0, 1]
+    dom = fd.Domain(label, dph, 8, 9, 1.0, 0.0)
+    cg = fd.Coarse(dom, 2, fd.FP64, reservoir=res)
+    near = ~coarse.reservoir_mask(label, res)
+    c = np.full(label.shape, 0.7)
+    out, cff = cg.step_far_field(to_dev(c), 0.7, 0.7 * (near.sum() + 12.0), 12.0)
+    assert np.max(np.abs(to_host(out) - 0.7)) <= 1e-13
+    assert abs(cff - 0.7) <= 1e-13
+    cg.close()
+
+
+def test_far_field_errors():
+    label, dph, c0 = _far_field_domain(22)
+    dom = fd.Domain(label, dph, 2, 4, 1.0, 0.0)
+    cf = fd.Coarse(dom, 2, fd.FP64, reservoir=[0, 0, 1])
+    c = to_dev(c0)
+    with pytest.raises(fd.FdirwError):
+        cf.step(c)                                   # a far-field handle needs c_ff
+    with pytest.raises(fd.FdirwError):
+        cf.step_far_field(c, 0.1, 1.0, 0.0)          # v_ff must be > 0
+    cn = fd.Coarse(dom, 2, fd.FP64)
+    with pytest.raises(fd.FdirwError):
+        cn.step_far_field(c, 0.1, 1.0, 1.0)          # no far field on this handle
+    cf.close()
+    cn.close()
