@@ -12,7 +12,8 @@ Functions (and the passage each follows):
   resolve_dt      sub-step from the explicit stability limit (reading of the
                   unstated FD scheme, Sec. 3.1)
   coefficients    per-face lambda = harmonic-mean D * dt / h^2 (Eq. 1 D per phase)
-  kernels         unit point-source responses = columns of P (Sec. 3.1, Eq. 9)
+  kernels         unit point-source responses = columns of P (Sec. 3.1, Eq. 9),
+                  optionally with a steady flow (upwind advection, Sec. 5)
   step            superposition c_new = P c_old (Eq. 8, column/scatter form)
   field_sum       compensated FP64 mass of a field (mass balance, Eq. 7 role)
   global_fd       the same explicit update on the whole domain (test reference;
@@ -63,6 +64,10 @@ def _load():
         lib.fo_kernels_fixed.restype = None
         lib.fo_global_fd_fixed.argtypes = [i32, i32, i32, P, P, P, i32, P, P, P, f64]
         lib.fo_global_fd_fixed.restype = None
+        lib.fo_kernels_general.argtypes = [i32, i32, i32, P, P, P, i32, i32, P, i64, P, P, P, P, P, P]
+        lib.fo_kernels_general.restype = None
+        lib.fo_global_fd_general.argtypes = [i32, i32, i32, P, P, P, i32, P, P, P, f64, P, P, P]
+        lib.fo_global_fd_general.restype = None
         lib.fo_step.argtypes = [i32, i32, i32, P, P, P, i32, i32, P, P, P]
         lib.fo_step.restype = i64
         lib.fo_global_fd.argtypes = [i32, i32, i32, P, P, P, i32, P, P]
@@ -117,13 +122,22 @@ def coefficients(label, d_phase, h: float = 1.0, dt: float = 0.0):
 
 
 class Problem:
-    """A domain with its face coefficients, ready for kernels/step calls."""
+    """A domain with its face coefficients, ready for kernels/step calls.
 
-    def __init__(self, label, d_phase, r: int, n_sub: int, h: float = 1.0, dt: float = 0.0):
+    velocity (optional): [3, nz, ny, nx] steady flow on the owned +x, +y, +z
+    face of every cell (h per unit time, positive towards +x / +y / +z); the
+    kernels then include first-order upwind advection with Courant numbers
+    u dt / h (the steady-flow extension of P, Sec. 5)."""
+
+    def __init__(self, label, d_phase, r: int, n_sub: int, h: float = 1.0, dt: float = 0.0, velocity=None):
         self.label, self.nx, self.ny, self.nz = _grid(label)
         self.d_phase = np.ascontiguousarray(d_phase, dtype=np.float64)
         self.r, self.n_sub, self.h = int(r), int(n_sub), float(h)
         self.lx, self.ly, self.lz, self.dt = coefficients(self.label, self.d_phase, h, dt)
+        self.nu = None
+        if velocity is not None:
+            u = np.asarray(velocity, dtype=np.float64).reshape((3,) + self.label.shape)
+            self.nu = [np.ascontiguousarray(u[a] * self.dt / self.h) for a in range(3)]
 
     @classmethod
     def from_domain(cls, dom):
@@ -144,12 +158,11 @@ class Problem:
         G = np.empty((src.size, W, W, W))
         mass = np.empty(src.size)
         if src.size:
-            if fixed is None:
-                _load().fo_kernels(*self._dims(), self.r, self.n_sub, _p(src), src.size, _p(G), _p(mass))
-            else:
-                f = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(self.label.shape)
-                _load().fo_kernels_fixed(*self._dims(), self.r, self.n_sub, _p(src), src.size, _p(G), _p(mass),
-                                         _p(f))
+            f = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8).reshape(self.label.shape)
+            nu = self.nu if self.nu is not None else [None, None, None]
+            _load().fo_kernels_general(*self._dims(), self.r, self.n_sub, _p(src), src.size, _p(G), _p(mass),
+                                       None if f is None else _p(f),
+                                       *[None if v is None else _p(v) for v in nu])
         return G, mass
 
     def step(self, c_old):
@@ -166,11 +179,10 @@ class Problem:
         c = np.ascontiguousarray(c, dtype=np.float64).reshape(self.label.shape)
         out = np.empty_like(c)
         n = self.n_sub if n_sub is None else int(n_sub)
-        if fixed is None:
-            _load().fo_global_fd(*self._dims(), n, _p(c), _p(out))
-        else:
-            f = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(self.label.shape)
-            _load().fo_global_fd_fixed(*self._dims(), n, _p(c), _p(out), _p(f), float(fval))
+        f = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8).reshape(self.label.shape)
+        nu = self.nu if self.nu is not None else [None, None, None]
+        _load().fo_global_fd_general(*self._dims(), n, _p(c), _p(out), None if f is None else _p(f), float(fval),
+                                     *[None if v is None else _p(v) for v in nu])
         return out
 
     def support(self, s: int):

@@ -107,11 +107,17 @@ void fo_coefficients(int nx, int ny, int nz, const uint8_t *label,
  * entry and exit; tmp is scratch of the same size.  Jacobi: every cell reads
  * the state of the previous sub-step.  Neighbour order -x, +x, -y, +y, -z, +z.
  * fixed (may be NULL): grid mask of Dirichlet cells (the far-field boundary of
- * Eq. 8), which hold the value fval after every sub-step. */
+ * Eq. 8), which hold the value fval after every sub-step.
+ * nu_x / nu_y / nu_z (NULL, or all three): signed Courant numbers u dt / h of
+ * a steady flow on the owned +x / +y / +z face of each cell (positive towards
+ * +x / +y / +z); the advective flux through a face is first-order upwind,
+ * nu * (value of the upstream cell), added after the diffusive terms in the
+ * same neighbour order (the flow extension of Sec. 5). */
 static void box_substeps(int nx, int ny, int nz,
                          const double *lam_x, const double *lam_y, const double *lam_z,
                          const int lo[3], const int hi[3], int n_sub,
-                         double *g, double *tmp, const uint8_t *fixed, double fval)
+                         double *g, double *tmp, const uint8_t *fixed, double fval,
+                         const double *nu_x, const double *nu_y, const double *nu_z)
 {
     (void)nz;
     int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
@@ -129,6 +135,16 @@ static void box_substeps(int nx, int ny, int nz,
                     if (j < by - 1) acc += lam_y[IDX(X, Y, Z)]     * (g[b + bx] - gx);
                     if (k > 0)      acc += lam_z[IDX(X, Y, Z - 1)] * (g[b - (int64_t)bx * by] - gx);
                     if (k < bz - 1) acc += lam_z[IDX(X, Y, Z)]     * (g[b + (int64_t)bx * by] - gx);
+                    if (nu_x) {
+                        /* inflow through the lower face, outflow through the upper face */
+                        double v;
+                        if (i > 0)      { v = nu_x[IDX(X - 1, Y, Z)]; acc += v > 0.0 ? v * g[b - 1] : v * gx; }
+                        if (i < bx - 1) { v = nu_x[IDX(X, Y, Z)];     acc -= v > 0.0 ? v * gx : v * g[b + 1]; }
+                        if (j > 0)      { v = nu_y[IDX(X, Y - 1, Z)]; acc += v > 0.0 ? v * g[b - bx] : v * gx; }
+                        if (j < by - 1) { v = nu_y[IDX(X, Y, Z)];     acc -= v > 0.0 ? v * gx : v * g[b + bx]; }
+                        if (k > 0)      { v = nu_z[IDX(X, Y, Z - 1)]; acc += v > 0.0 ? v * g[b - (int64_t)bx * by] : v * gx; }
+                        if (k < bz - 1) { v = nu_z[IDX(X, Y, Z)];     acc -= v > 0.0 ? v * gx : v * g[b + (int64_t)bx * by]; }
+                    }
                     tmp[b] = (fixed && fixed[IDX(X, Y, Z)]) ? fval : acc;
                 }
         memcpy(g, tmp, sizeof(double) * (size_t)bx * by * bz);
@@ -150,7 +166,7 @@ static void window_box(int nx, int ny, int nz, int r, int sx, int sy, int sz, in
 static void kernel_one(int nx, int ny, int nz,
                        const double *lam_x, const double *lam_y, const double *lam_z,
                        int r, int n_sub, int64_t s, double *G, double *mass, double *work,
-                       const uint8_t *fixed)
+                       const uint8_t *fixed, const double *nu_x, const double *nu_y, const double *nu_z)
 {
     int W = 2 * r + 1;
     int sx = (int)(s % nx), sy = (int)((s / nx) % ny), sz = (int)(s / ((int64_t)nx * ny));
@@ -161,7 +177,7 @@ static void kernel_one(int nx, int ny, int nz,
     double *g = work, *tmp = work + nb;
     memset(g, 0, sizeof(double) * (size_t)nb);
     g[((int64_t)(sz - lo[2]) * by + (sy - lo[1])) * bx + (sx - lo[0])] = 1.0;
-    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, g, tmp, fixed, 0.0);
+    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, g, tmp, fixed, 0.0, nu_x, nu_y, nu_z);
     memset(G, 0, sizeof(double) * (size_t)W * W * W);
     for (int k = 0; k < bz; ++k)
         for (int j = 0; j < by; ++j)
@@ -173,11 +189,13 @@ static void kernel_one(int nx, int ny, int nz,
 }
 
 /* Kernels of a list of sources: G [n_src][W][W][W], mass [n_src]; fixed (may
- * be NULL): Dirichlet cells held at 0. */
-void fo_kernels_fixed(int nx, int ny, int nz,
-                      const double *lam_x, const double *lam_y, const double *lam_z,
-                      int r, int n_sub, const int64_t *src, int64_t n_src,
-                      double *G, double *mass, const uint8_t *fixed)
+ * be NULL): Dirichlet cells held at 0; nu_* (may be NULL): flow Courant
+ * numbers as in box_substeps. */
+void fo_kernels_general(int nx, int ny, int nz,
+                        const double *lam_x, const double *lam_y, const double *lam_z,
+                        int r, int n_sub, const int64_t *src, int64_t n_src,
+                        double *G, double *mass, const uint8_t *fixed,
+                        const double *nu_x, const double *nu_y, const double *nu_z)
 {
     int64_t W3 = (int64_t)(2 * r + 1) * (2 * r + 1) * (2 * r + 1);
 #pragma omp parallel
@@ -186,9 +204,17 @@ void fo_kernels_fixed(int nx, int ny, int nz,
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < n_src; ++i)
             kernel_one(nx, ny, nz, lam_x, lam_y, lam_z, r, n_sub, src[i],
-                       G + i * W3, mass ? mass + i : NULL, work, fixed);
+                       G + i * W3, mass ? mass + i : NULL, work, fixed, nu_x, nu_y, nu_z);
         free(work);
     }
+}
+
+void fo_kernels_fixed(int nx, int ny, int nz,
+                      const double *lam_x, const double *lam_y, const double *lam_z,
+                      int r, int n_sub, const int64_t *src, int64_t n_src,
+                      double *G, double *mass, const uint8_t *fixed)
+{
+    fo_kernels_general(nx, ny, nz, lam_x, lam_y, lam_z, r, n_sub, src, n_src, G, mass, fixed, NULL, NULL, NULL);
 }
 
 void fo_kernels(int nx, int ny, int nz,
@@ -264,21 +290,30 @@ void fo_global_fd(int nx, int ny, int nz,
     double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
     int lo[3] = {0, 0, 0}, hi[3] = {nx - 1, ny - 1, nz - 1};
     memcpy(out, c, sizeof(double) * (size_t)n);
-    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp, NULL, 0.0);
+    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp, NULL, 0.0, NULL, NULL, NULL);
     free(tmp);
 }
 
-/* The same with Dirichlet cells (mask fixed) holding fval from the start. */
-void fo_global_fd_fixed(int nx, int ny, int nz,
-                        const double *lam_x, const double *lam_y, const double *lam_z,
-                        int n_sub, const double *c, double *out, const uint8_t *fixed, double fval)
+/* The same with Dirichlet cells (mask fixed, may be NULL) holding fval from
+ * the start and an optional flow (nu_*, may be NULL). */
+void fo_global_fd_general(int nx, int ny, int nz,
+                          const double *lam_x, const double *lam_y, const double *lam_z,
+                          int n_sub, const double *c, double *out, const uint8_t *fixed, double fval,
+                          const double *nu_x, const double *nu_y, const double *nu_z)
 {
     int64_t n = (int64_t)nx * ny * nz;
     double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
     int lo[3] = {0, 0, 0}, hi[3] = {nx - 1, ny - 1, nz - 1};
-    for (int64_t i = 0; i < n; ++i) out[i] = fixed[i] ? fval : c[i];
-    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp, fixed, fval);
+    for (int64_t i = 0; i < n; ++i) out[i] = (fixed && fixed[i]) ? fval : c[i];
+    box_substeps(nx, ny, nz, lam_x, lam_y, lam_z, lo, hi, n_sub, out, tmp, fixed, fval, nu_x, nu_y, nu_z);
     free(tmp);
+}
+
+void fo_global_fd_fixed(int nx, int ny, int nz,
+                        const double *lam_x, const double *lam_y, const double *lam_z,
+                        int n_sub, const double *c, double *out, const uint8_t *fixed, double fval)
+{
+    fo_global_fd_general(nx, ny, nz, lam_x, lam_y, lam_z, n_sub, c, out, fixed, fval, NULL, NULL, NULL);
 }
 
 /* Test-only reference: structural support of G_s, i.e. the window cells
