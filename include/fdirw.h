@@ -157,6 +157,20 @@ int fdirw_coefficients(const fdirw_domain *d, void *stream, double *lam, double 
 int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src, int64_t n_src,
                   void *G, double *mass);
 
+/* Window kernels with a steady flow (the extension of P to diffusion with a
+ * steady flow, Sec. 5): the explicit update of fdirw_kernels plus a
+ * first-order upwind advective flux through every face, Courant number
+ * nu_f = u_f dt / h; a face that leaves the window or the domain carries
+ * neither diffusion nor flow.  velocity: 3N doubles, u on the face from cell i
+ * to its +x, +y, +z neighbour (entries of the last plane of each axis are not
+ * read), in units of h per unit time, positive towards +x / +y / +z.  prec:
+ * FP64 or FP32 (E_UNSUPPORTED otherwise).  G and mass as in fdirw_kernels;
+ * the kernels are not renormalised.  Errors: E_ARG, E_UNSUPPORTED,
+ * E_UNSTABLE (also when 6 lambda + the outflow Courant numbers of a cell
+ * exceed 1). */
+int fdirw_kernels_flow(const fdirw_domain *d, const fdirw_opts *o, const double *velocity, const int64_t *src,
+                       int64_t n_src, void *G, double *mass);
+
 /* One big step of the superposition (Eq. 8, column form):
  * c_out[i][x] = sum over s of c_in[i][s] * G_s(x) for each domain i.  d, c_in,
  * c_out and st are (host) arrays of n_dom entries; c_in[i] and c_out[i] point
@@ -286,14 +300,17 @@ int fdirw_nn_load(void *nn, const char *path);
  * FP16 (FDIRW_FP16_BANK) or BF16 (FDIRW_BF16_BANK)).  grouped (host, may be
  * NULL): d->n_phase flags, nonzero for the grouped phases; NULL groups every
  * phase with D > 0.  reservoir (host, may be NULL): d->n_phase flags, nonzero
- * for the far-field boundary phases (never grouped).  block: 1..256.  d->label is read only here.  *handle
+ * for the far-field boundary phases (never grouped).  velocity (may be NULL):
+ * a steady flow as in fdirw_kernels_flow; P and P_BC then include it (the
+ * kernels are the flow kernels, generated in chunks of sources).  block: 1..256.  d->label is read only here.  *handle
  * receives a handle owning device memory of about 4 N + (2K+1)^3 x N_nodes x
  * element bytes; seconds (host, may be NULL) receives the build time.
  * Synchronises the stream.  The handle belongs to the current device.
  * Errors: E_ARG (also a block outside 1..256 or another precision),
  * E_UNSTABLE, E_NOMEM, E_DEVICE. */
 int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped,
-                        const uint8_t *reservoir, void *stream, void **handle, double *seconds);
+                        const uint8_t *reservoir, const double *velocity, void *stream, void **handle,
+                        double *seconds);
 
 /* One coarse big step from c_in to c_out (N doubles each, not overlapping).
  * st (may be NULL) receives mass_in / mass_out (compensated FP64 sums, one

@@ -7,7 +7,7 @@ the current stream.  There is no CPU fallback: if the library is missing the
 import of a function raises.
 
 Names follow the ABI:
-    fdirw_coefficients, fdirw_kernels, fdirw_step, fdirw_run,
+    fdirw_coefficients, fdirw_kernels, fdirw_kernels_flow, fdirw_step, fdirw_run,
     fdirw_field_sum, fdirw_last_error, fdirw_release, fdirw_abi_version,
     fdirw_nn_create, fdirw_nn_destroy, fdirw_nn_num_params,
     fdirw_nn_set_params, fdirw_nn_get_params, fdirw_nn_forward,
@@ -81,7 +81,7 @@ class fdirw_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
-ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run",
+ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_run",
                  "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version",
                  "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.fdirw_coefficients.argtypes = [D, P, P, ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_kernels.argtypes = [D, O, P, ctypes.c_int64, P, P]
+    lib.fdirw_kernels_flow.argtypes = [D, O, P, P, ctypes.c_int64, P, P]
     lib.fdirw_step.argtypes = [D, ctypes.c_int32, O, PP, PP, S]
     lib.fdirw_run.argtypes = [D, ctypes.c_int32, O, ctypes.c_int32, PP, PP, S]
     lib.fdirw_field_sum.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double)]
@@ -127,7 +128,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_nn_adam.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
     lib.fdirw_nn_save.argtypes = [P, ctypes.c_char_p]
     lib.fdirw_nn_load.argtypes = [P, ctypes.c_char_p]
-    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, P, P, PP,
+    lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, P, P, P, PP,
                                         ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_coarse_step.argtypes = [P, P, P, P, S]
     lib.fdirw_coarse_step_far_field.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
@@ -136,7 +137,8 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_coarse_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.fdirw_coarse_matrix.argtypes = [P, P]
     lib.fdirw_coarse_destroy.argtypes = [P]
-    for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_step", "fdirw_run", "fdirw_field_sum",
+    for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_run",
+              "fdirw_field_sum",
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
               "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create",
@@ -295,6 +297,33 @@ def fdirw_kernels(dom: Domain, src, prec=FP32, stream=None, G=None, mass=None, t
     return G, mass
 
 
+def fdirw_kernels_flow(dom: Domain, velocity, src, prec=FP32, stream=None, G=None, mass=None):
+    """Window kernels with the steady flow ``velocity`` (float64 device tensor
+    [3, nz, ny, nx]: u on the owned +x, +y, +z faces, h per unit time)."""
+    torch = _torch()
+    o = make_opts(prec, stream)
+    src = _dev_tensor(src, torch.int64, "src")
+    _dev_tensor(velocity, torch.float64, "velocity")
+    if velocity.numel() != 3 * dom.n:
+        raise ValueError("velocity must hold 3 N doubles")
+    n_src = src.numel()
+    W = dom.W
+    gdt = torch.float64 if o.prec == FP64 else torch.float32
+    if G is None:
+        G = torch.empty((n_src, W, W, W), dtype=gdt, device=src.device)
+    _dev_tensor(G, gdt, "G")
+    if G.numel() != n_src * W ** 3:
+        raise ValueError("G has the wrong size")
+    if mass is None:
+        mass = torch.empty(n_src, dtype=torch.float64, device=src.device)
+    _dev_tensor(mass, torch.float64, "mass")
+    ds = dom.c_struct()
+    _check(load_library().fdirw_kernels_flow(ctypes.byref(ds), ctypes.byref(o), ctypes.c_void_p(velocity.data_ptr()),
+                                             ctypes.c_void_p(src.data_ptr()), n_src, ctypes.c_void_p(G.data_ptr()),
+                                             ctypes.c_void_p(mass.data_ptr())))
+    return G, mass
+
+
 def _ptr_array(ts):
     arr = (ctypes.c_void_p * len(ts))()
     for i, t in enumerate(ts):
@@ -383,16 +412,24 @@ def _phase_flags(dom: Domain, flags, name):
     return (ctypes.c_uint8 * g.size)(*g.tolist())
 
 
-def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, grouped=None, reservoir=None, stream=None):
+def fdirw_coarse_create(dom: Domain, block: int, prec=FP16_BANK, grouped=None, reservoir=None, velocity=None,
+                        stream=None):
     """Handle and build seconds of the coarse operator of ``dom``; ``grouped``:
     per-phase flags of the grouped (fast) phases, None for every D > 0;
-    ``reservoir``: per-phase flags of the far-field boundary phases."""
+    ``reservoir``: per-phase flags of the far-field boundary phases;
+    ``velocity``: optional steady flow (float64 device tensor [3, nz, ny, nx])."""
     h = ctypes.c_void_p()
     sec = ctypes.c_double(0.0)
     ds = dom.c_struct()
+    vptr = None
+    if velocity is not None:
+        _dev_tensor(velocity, _torch().float64, "velocity")
+        if velocity.numel() != 3 * dom.n:
+            raise ValueError("velocity must hold 3 N doubles")
+        vptr = ctypes.c_void_p(velocity.data_ptr())
     _check(load_library().fdirw_coarse_create(ctypes.byref(ds), int(block), _prec(prec),
                                               _phase_flags(dom, grouped, "grouped"),
-                                              _phase_flags(dom, reservoir, "reservoir"), _stream_ptr(stream),
+                                              _phase_flags(dom, reservoir, "reservoir"), vptr, _stream_ptr(stream),
                                               ctypes.byref(h), ctypes.byref(sec)))
     return h, sec.value
 
@@ -444,8 +481,9 @@ class Coarse:
     P stored in ``prec`` (fp64, fp32, fp16_bank or bf16_bank); with
     ``reservoir`` phases, the far-field boundary of Eqs. 7 and 14."""
 
-    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, grouped=None, reservoir=None, stream=None):
-        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, grouped, reservoir, stream)
+    def __init__(self, dom: Domain, block: int = 5, prec=FP16_BANK, grouped=None, reservoir=None, velocity=None,
+                 stream=None):
+        self.handle, self.build_seconds = fdirw_coarse_create(dom, block, prec, grouped, reservoir, velocity, stream)
         shp, self.n_nodes = fdirw_coarse_shape(self.handle)
         self.coarse_shape = tuple(shp[:3])
         self.K, self.block = shp[3], shp[4]

@@ -265,6 +265,27 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     return FDIRW_OK;
 }
 
+// Checks that the explicit scheme with the flow u is stable: for every cell
+// the six lambda plus the outflow Courant numbers must not exceed 1.
+int flow_stable(const fdirw_domain *d, int fp64, const void *lam, const double *u, double dt, hipStream_t st,
+                DevCache &dc)
+{
+    int rc;
+    if ((rc = ensure(dc.flags, 16 * sizeof(unsigned)))) return rc;
+    unsigned long long *mx = (unsigned long long *)dc.flags.p + 4;
+    hipError_t e = launch_fill_u32((unsigned *)mx, 2, 0u, st);
+    if (e == hipSuccess) e = launch_flow_stability(fp64, lam, u, d->nx, d->ny, d->nz, dt / d->h, mx, st);
+    unsigned long long h_mx = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_mx, mx, sizeof h_mx, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "flow stability check");
+    double v;
+    std::memcpy(&v, &h_mx, sizeof v);
+    if (!(v <= 1.0 + 1e-12))
+        return fail(FDIRW_E_UNSTABLE, "flow: 6 lambda + outflow Courant number reaches %g > 1 (reduce dt or u)", v);
+    return FDIRW_OK;
+}
+
 }  // namespace fdirw
 
 using namespace fdirw;
@@ -337,6 +358,49 @@ int fdirw_kernels(const fdirw_domain *d, const fdirw_opts *o, const int64_t *src
     a.offset_major = 0;
     e = launch_window(o->prec, d->r, a, st);
     if (e != hipSuccess) return hip_fail(e, "window kernel launch");
+    return FDIRW_OK;
+}
+
+int fdirw_kernels_flow(const fdirw_domain *d, const fdirw_opts *o, const double *velocity, const int64_t *src,
+                       int64_t n_src, void *G, double *mass)
+{
+    int rc = check_domain(d);
+    if (rc) return rc;
+    if ((rc = check_opts(o))) return rc;
+    if (o->prec != FDIRW_FP64 && o->prec != FDIRW_FP32)
+        return fail(FDIRW_E_UNSUPPORTED, "flow kernels are generated in FP64 or FP32 only");
+    if (o->gen != FDIRW_GEN_FD) return fail(FDIRW_E_UNSUPPORTED, "flow kernels are FD kernels");
+    if (n_src < 0) return fail(FDIRW_E_ARG, "n_src < 0");
+    if (!velocity) return fail(FDIRW_E_ARG, "velocity is null");
+    if (n_src == 0) return FDIRW_OK;
+    if (!src || !G) return fail(FDIRW_E_ARG, "src and G must not be null");
+    std::lock_guard<std::mutex> lk(g_mu);
+    DevCache &dc = cache_for_current_device();
+    hipStream_t st = (hipStream_t)o->stream;
+    const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+    if ((rc = ensure(dc.flags, 16 * sizeof(unsigned)))) return rc;
+    unsigned *bad = (unsigned *)dc.flags.p + 12;
+    hipError_t e = launch_src_check(src, n_src, n, bad, st);
+    unsigned h_bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "source check");
+    if (h_bad) return fail(FDIRW_E_ARG, "a source index is outside [0, %lld)", (long long)n);
+    Geometry g;
+    const void *lam = nullptr;
+    if ((rc = coef_buffers(d, o->prec, st, dc, &g, &lam))) return rc;
+    if ((rc = flow_stable(d, o->prec == FDIRW_FP64, lam, velocity, g.dt, st, dc))) return rc;
+    FlowArgs a;
+    a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.n = n;
+    a.n_sub = d->n_sub;
+    a.lam = lam;
+    a.u = velocity;
+    a.dt = g.dt; a.h = d->h;
+    a.src = src; a.src_base = 0; a.n_src = n_src;
+    a.node = nullptr;
+    a.G = G; a.mass = mass;
+    e = launch_flow_window(o->prec == FDIRW_FP64, d->r, a, st);
+    if (e != hipSuccess) return hip_fail(e, "flow window kernel launch");
     return FDIRW_OK;
 }
 

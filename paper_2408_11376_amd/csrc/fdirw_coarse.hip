@@ -140,6 +140,66 @@ coarse_window_kernel(CoarseGenArgs a)
     }
 }
 
+// The binning of coarse_window_kernel for kernels generated elsewhere (the
+// flow kernels): G holds the W^3 window kernels of the sources src_base +
+// 0 .. n_src-1 (entries of sources outside every group are not read).
+constexpr int BIN_NT = 256;
+
+template <typename T, int R, bool SINK>
+__global__ void __launch_bounds__(BIN_NT) coarse_bin_kernel(CoarseGenArgs a, const T *__restrict__ G,
+                                                            int64_t src_base, int64_t n_src)
+{
+    constexpr int W = 2 * R + 1, W2 = W * W, W3 = W2 * W;
+    __shared__ double bins[W3];
+    __shared__ double red[BIN_NT / 64];
+    for (int i = threadIdx.x; i < W3; i += BIN_NT) bins[i] = 0.0;
+    const int B = a.block, K = a.K, KW = 2 * a.K + 1, nb = KW * KW * KW;
+    for (int64_t q = blockIdx.x; q < n_src; q += gridDim.x) {
+        const int64_t s = src_base + q;
+        if (a.node[s] < 0) continue;                              // uniform per block
+        const int sx = (int)(s % a.nx), sy = (int)((s / a.nx) % a.ny), sz = (int)(s / ((int64_t)a.nx * a.ny));
+        const int jx = sx / B, jy = sy / B, jz = sz / B;
+        const T *g = G + q * (int64_t)W3;
+        double part = 0.0;
+        for (int w = threadIdx.x; w < W3; w += BIN_NT) {
+            const int X = sx - R + w % W, Y = sy - R + (w / W) % W, Z = sz - R + w / W2;
+            if (X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz &&
+                a.node[((int64_t)Z * a.ny + Y) * a.nx + X] >= 0)
+                part += (double)g[w];
+        }
+        double inv = 1.0;
+        if (!SINK) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+            __syncthreads();
+            double m = red[0];
+            for (int k = 1; k < BIN_NT / 64; ++k) m += red[k];
+            inv = 1.0 / m;
+        }
+        __syncthreads();
+        for (int w = threadIdx.x; w < W3; w += BIN_NT) {
+            const int X = sx - R + w % W, Y = sy - R + (w / W) % W, Z = sz - R + w / W2;
+            if (X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz &&
+                a.node[((int64_t)Z * a.ny + Y) * a.nx + X] >= 0 && g[w] != T(0))
+                atomicAdd(&bins[((Z / B - jz + K) * KW + (Y / B - jy + K)) * KW + (X / B - jx + K)],
+                          (double)g[w] * inv);
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < nb; o += BIN_NT) {
+            const double v = bins[o];
+            if (v != 0.0) {
+                const int oz = o / (KW * KW), oy = (o / KW) % KW, ox = o % KW;
+                const int64_t I = ((int64_t)(jz + oz - K) * a.ncy + (jy + oy - K)) * a.ncx + (jx + ox - K);
+                atomicAdd(&a.S[(int64_t)o * a.n_nodes + I], v);
+                bins[o] = 0.0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // P[o][I] = S[o][I] / N_I in the bank layout of element type B: per offset
 // plane the coarse cells are ordered [z / zb][y][x][z % zb].
 template <typename B>
@@ -280,10 +340,12 @@ __global__ void coarse_fill_reservoir_kernel(const int *__restrict__ node, int64
 
 // One explicit sub-step on the whole domain (no-flux walls) with the far-field
 // cells held at 1: the response p_BC to a unit boundary concentration (Eq. 8).
-// Terms in the order -x, +x, -y, +y, -z, +z; FP64 state, coefficients of type S.
+// Terms in the order -x, +x, -y, +y, -z, +z, then the upwind flow terms in the
+// same order (u null: no flow); FP64 state, coefficients of type S.
 template <typename S>
 __global__ void coarse_pbc_substep_kernel(const S *__restrict__ lx, const int *__restrict__ node, int nx, int ny,
-                                          int nz, const double *__restrict__ in, double *__restrict__ out)
+                                          int nz, const double *__restrict__ u, double cour,
+                                          const double *__restrict__ in, double *__restrict__ out)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     const S *ly = lx + n, *lz = ly + n;
@@ -303,6 +365,17 @@ __global__ void coarse_pbc_substep_kernel(const S *__restrict__ lx, const int *_
         if (y < ny - 1) acc += (double)ly[i] * (in[i + sy] - g);
         if (z > 0) acc += (double)lz[i - sz] * (in[i - sz] - g);
         if (z < nz - 1) acc += (double)lz[i] * (in[i + sz] - g);
+        if (u) {
+            // upwind flow: inflow through the lower faces, outflow through the upper
+            const double *ux = u, *uy = ux + n, *uz = uy + n;
+            double v;
+            if (x > 0) { v = ux[i - 1] * cour; acc += v > 0.0 ? v * in[i - 1] : v * g; }
+            if (x < nx - 1) { v = ux[i] * cour; acc -= v > 0.0 ? v * g : v * in[i + 1]; }
+            if (y > 0) { v = uy[i - sy] * cour; acc += v > 0.0 ? v * in[i - sy] : v * g; }
+            if (y < ny - 1) { v = uy[i] * cour; acc -= v > 0.0 ? v * g : v * in[i + sy]; }
+            if (z > 0) { v = uz[i - sz] * cour; acc += v > 0.0 ? v * in[i - sz] : v * g; }
+            if (z < nz - 1) { v = uz[i] * cour; acc -= v > 0.0 ? v * g : v * in[i + sz]; }
+        }
         out[i] = acc;
     }
 }
@@ -356,7 +429,7 @@ hipError_t launch_coarse_window(int fp64, int sink, int r, const CoarseGenArgs &
 // n_sub sub-steps of coarse_pbc_substep_kernel from 0 (far-field cells 1),
 // ping-ponging between a and b; *result points to the final field.
 hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int nx, int ny, int nz, int n_sub,
-                                double *a, double *b, double **result, hipStream_t st)
+                                const double *u, double cour, double *a, double *b, double **result, hipStream_t st)
 {
     const int64_t n = (int64_t)nx * ny * nz;
     hipError_t e = launch_fill(a, n, 0.0, st);
@@ -365,10 +438,10 @@ hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int 
     for (int k = 0; k < n_sub && e == hipSuccess; ++k) {
         if (fp64)
             hipLaunchKernelGGL(coarse_pbc_substep_kernel<double>, dim3(grid_for(n)), dim3(256), 0, st,
-                               (const double *)lam, node, nx, ny, nz, in, out);
+                               (const double *)lam, node, nx, ny, nz, u, cour, in, out);
         else
             hipLaunchKernelGGL(coarse_pbc_substep_kernel<float>, dim3(grid_for(n)), dim3(256), 0, st,
-                               (const float *)lam, node, nx, ny, nz, in, out);
+                               (const float *)lam, node, nx, ny, nz, u, cour, in, out);
         e = hipGetLastError();
         double *t = in; in = out; out = t;
     }
@@ -380,6 +453,38 @@ hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, do
 {
     hipLaunchKernelGGL(coarse_fill_reservoir_kernel, dim3(grid_for(n)), dim3(256), 0, st, node, n, v, c);
     return hipGetLastError();
+}
+
+template <typename T, bool SINK>
+static hipError_t launch_bin_t(int r, const CoarseGenArgs &a, const T *G, int64_t src_base, int64_t n_src,
+                               hipStream_t st)
+{
+    const int64_t nblk = n_src < 65536 * 16 ? n_src : 65536 * 16;
+    if (nblk <= 0) return hipSuccess;
+    const dim3 g((unsigned)nblk), b(BIN_NT);
+    switch (r) {
+    case 0: hipLaunchKernelGGL((coarse_bin_kernel<T, 0, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 1: hipLaunchKernelGGL((coarse_bin_kernel<T, 1, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 2: hipLaunchKernelGGL((coarse_bin_kernel<T, 2, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 3: hipLaunchKernelGGL((coarse_bin_kernel<T, 3, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 4: hipLaunchKernelGGL((coarse_bin_kernel<T, 4, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 5: hipLaunchKernelGGL((coarse_bin_kernel<T, 5, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 6: hipLaunchKernelGGL((coarse_bin_kernel<T, 6, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 7: hipLaunchKernelGGL((coarse_bin_kernel<T, 7, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    case 8: hipLaunchKernelGGL((coarse_bin_kernel<T, 8, SINK>), g, b, 0, st, a, G, src_base, n_src); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, const void *G, int64_t src_base,
+                             int64_t n_src, hipStream_t st)
+{
+    if (fp64)
+        return sink ? launch_bin_t<double, true>(r, a, (const double *)G, src_base, n_src, st)
+                    : launch_bin_t<double, false>(r, a, (const double *)G, src_base, n_src, st);
+    return sink ? launch_bin_t<float, true>(r, a, (const float *)G, src_base, n_src, st)
+                : launch_bin_t<float, false>(r, a, (const float *)G, src_base, n_src, st);
 }
 
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,

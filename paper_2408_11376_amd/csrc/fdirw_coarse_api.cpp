@@ -88,7 +88,8 @@ using namespace fdirw;
 extern "C" {
 
 int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped,
-                        const uint8_t *reservoir, void *stream, void **handle, double *seconds)
+                        const uint8_t *reservoir, const double *velocity, void *stream, void **handle,
+                        double *seconds)
 {
     if (!handle) return fail(FDIRW_E_ARG, "handle is null");
     *handle = nullptr;
@@ -129,6 +130,7 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
         Geometry g;
         const void *lam = nullptr;
         rc = coef_buffers(d, prec == FDIRW_FP64 ? FDIRW_FP64 : FDIRW_FP32, st, dc, &g, &lam);
+        if (!rc && velocity) rc = flow_stable(d, prec == FDIRW_FP64, lam, velocity, g.dt, st, dc);
         if (!rc) rc = coarse_alloc(&h->node, (size_t)h->n * sizeof(int));
         if (!rc) rc = coarse_alloc(&h->count, (size_t)h->n_nodes * sizeof(double));
         if (!rc) rc = coarse_alloc(&h->P, (size_t)nb * h->plane * h->esz);
@@ -166,7 +168,41 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             a.ncx = h->ncx; a.ncy = h->ncy;
             a.n_nodes = h->n_nodes;
             a.S = S;
-            e = launch_coarse_window(prec == FDIRW_FP64, h->far_field, d->r, a, st);
+            if (!velocity) {
+                e = launch_coarse_window(prec == FDIRW_FP64, h->far_field, d->r, a, st);
+            } else {
+                // flow kernels, generated in chunks of sources into a scratch
+                // buffer and binned like the fused build
+                const int64_t W = 2 * d->r + 1, W3 = W * W * W;
+                const size_t esz = prec == FDIRW_FP64 ? 8 : 4;
+                int64_t chunk = (int64_t)((size_t)512 << 20) / (W3 * (int64_t)esz);
+                if (chunk < 1) chunk = 1;
+                if (chunk > h->n) chunk = h->n;
+                void *Gc = nullptr;
+                if ((rc = coarse_alloc(&Gc, (size_t)chunk * W3 * esz))) {
+                    (void)hipStreamSynchronize(st);
+                    (void)hipFree(S);
+                    delete h;
+                    return rc;
+                }
+                for (int64_t base = 0; base < h->n && e == hipSuccess; base += chunk) {
+                    const int64_t cnt = base + chunk <= h->n ? chunk : h->n - base;
+                    FlowArgs f;
+                    f.nx = d->nx; f.ny = d->ny; f.nz = d->nz; f.n = h->n;
+                    f.n_sub = d->n_sub;
+                    f.lam = lam;
+                    f.u = velocity;
+                    f.dt = g.dt; f.h = d->h;
+                    f.src = nullptr; f.src_base = base; f.n_src = cnt;
+                    f.node = (const int *)h->node;
+                    f.G = Gc; f.mass = nullptr;
+                    e = launch_flow_window(prec == FDIRW_FP64, d->r, f, st);
+                    if (e == hipSuccess)
+                        e = launch_coarse_bin(prec == FDIRW_FP64, h->far_field, d->r, a, Gc, base, cnt, st);
+                }
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(Gc);
+            }
         }
         if (e == hipSuccess && h->far_field) {
             // p_BC: the whole-domain FD from 0 with the far-field cells at 1,
@@ -179,8 +215,8 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                 return rc;
             }
             double *field = nullptr;
-            e = launch_coarse_pbc_fd(prec == FDIRW_FP64, lam, (const int *)h->node, d->nx, d->ny, d->nz, d->n_sub, fa,
-                                     fa + h->n, &field, st);
+            e = launch_coarse_pbc_fd(prec == FDIRW_FP64, lam, (const int *)h->node, d->nx, d->ny, d->nz, d->n_sub,
+                                     velocity, g.dt / d->h, fa, fa + h->n, &field, st);
             if (e == hipSuccess)
                 e = launch_coarse_map(field, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz,
                                       block, h->ncx, h->ncy, h->ncz, h->K, (double *)h->pbc, st);

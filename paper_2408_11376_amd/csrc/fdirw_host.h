@@ -71,6 +71,8 @@ int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, 
 int step_batched(const fdirw_domain *d, int n_dom, const fdirw_opts *o, const double *const *c_in,
                  double *const *c_out, fdirw_stats *st, DevCache &dc, hipStream_t stream);
 int batch_config_count();
+int flow_stable(const fdirw_domain *d, int fp64, const void *lam, const double *u, double dt, hipStream_t st,
+                DevCache &dc);
 int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out, fdirw_stats *st,
             DevCache &dc, hipStream_t stream);
 

@@ -71,6 +71,22 @@ struct CoarseGenArgs {
     double *S;                // [(2K+1)^3][n_nodes] sums of renormalised kernels, 0 at launch
 };
 
+// Window kernels with a steady flow (fdirw_flow.hip).
+struct FlowArgs {
+    int nx, ny, nz;
+    int64_t n;
+    int n_sub;
+    const void *lam;          // [3][N] face coefficients (double for FP64, else float)
+    const double *u;          // [3][N] flow on the owned +x, +y, +z faces (h per unit time)
+    double dt, h;             // Courant number = u dt / h
+    const int64_t *src;       // sources, or null: src_base + 0 .. n_src-1
+    int64_t src_base;
+    int64_t n_src;
+    const int *node;          // coarse node index per cell (skips and far-field sinks), or null
+    void *G;                  // [n_src][W^3] of the state type, or null
+    double *mass;             // [n_src], or null
+};
+
 // Batched persistent launch (fdirw_batched.hip).
 struct BatchDom {
     int nx, ny, nz, r, n_sub;
@@ -111,12 +127,17 @@ hipError_t launch_coarse_nodes(const uint8_t *label, const CoarseTable &tab, int
                                int ncx, int ncy, int *node, double *count, hipStream_t st);
 hipError_t launch_coarse_window(int fp64, int sink, int r, const CoarseGenArgs &a, hipStream_t st);
 hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int nx, int ny, int nz, int n_sub,
-                                double *a, double *b, double **result, hipStream_t st);
+                                const double *u, double cour, double *a, double *b, double **result, hipStream_t st);
 hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st);
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
                                   int ncy, int ncz, void *P, hipStream_t st);
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
                              int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st);
+hipError_t launch_flow_window(int fp64, int r, const FlowArgs &a, hipStream_t st);
+hipError_t launch_flow_stability(int fp64, const void *lam, const double *u, int nx, int ny, int nz, double cour,
+                                 unsigned long long *out, hipStream_t st);
+hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, const void *G, int64_t src_base,
+                             int64_t n_src, hipStream_t st);
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                const double *pbc_pad, double c_ff, double *cnew, hipStream_t st);
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
