@@ -1,7 +1,7 @@
 """One fused FDiRW step on a seeded porous grid, for profiler runs.
 
     python -m paper_2408_11376_amd.profile_step --n 96 --prec fp32 [--copy-mib 1024] [--gen nn] [--bank 1]
-        [--coarse B]
+        [--coarse B] [--flow U]
 
 Runs one untimed warm-up step, then ``--reps`` steps of the config-2 style
 workload (GRF porous grid, r = 8, 200 sub-steps) at edge ``--n``.  With
@@ -13,7 +13,9 @@ disabled, so every kernel is the network's) instead of the FD kernels.  With
 kernel once in a bank of the precision ``--prec`` (fp32, fp16_bank, ...) and
 applies it for one big step.  With ``--coarse B`` the coarse-mesh operator
 over B^3 blocks is built once (P stored in ``--prec``) and each repetition is
-one coarse step.
+one coarse step.  With ``--flow U`` each repetition generates the window
+kernels of a 64^3-cell sample of sources with a seeded steady flow of
+magnitude up to U (fdirw_kernels_flow, precision ``--prec``).
 """
 import argparse
 import os
@@ -35,6 +37,7 @@ def main():
     ap.add_argument("--gen", default="fd", choices=["fd", "nn"])
     ap.add_argument("--bank", type=int, default=0)
     ap.add_argument("--coarse", type=int, default=0)
+    ap.add_argument("--flow", type=float, default=0.0)
     args = ap.parse_args()
     import torch
     import synth
@@ -46,6 +49,21 @@ def main():
     kw = {}
     if args.gen == "nn":
         kw = {"nn": fd.Surrogate(d.n_sub, seed=0), "audit_tol": 1e30, "audit_samples": 1}
+    if args.flow > 0.0:
+        u = torch.from_numpy((synth.uniform(99, 3 * d.n).reshape((3,) + d.shape) * 2.0 - 1.0) * args.flow).cuda()
+        src = torch.arange(0, d.n, max(1, d.n // 262144), dtype=torch.int64, device="cuda")
+        for i in range(args.reps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            fd.fdirw_kernels_flow(dom, u, src, prec=args.prec)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            print(f"[profile_step] n={args.n} flow {args.flow} prec={args.prec} rep {i}: {src.numel()} kernels in "
+                  f"{ms:.1f} ms", flush=True)
+        args.reps = 0
+        args.warmup = 0
     if args.coarse:
         cg = fd.Coarse(dom, args.coarse, args.prec)
         print(f"[profile_step] n={args.n} coarse block {args.coarse} prec={args.prec}: {cg.n_nodes} nodes, "
