@@ -227,6 +227,54 @@ def config3(seed: int = 14, count: int = 64, lo: int = 32, hi: int = 128):
     return doms
 
 
+# Values of the wasteform-particle case (Table 1, particle radius 50 h): grid
+# spacing, fast sub-step and big step, diffusivity and free-energy coefficient
+# (A / RT) per phase, equilibrium and initial concentrations, rate constant of
+# the interface reaction and the far-field liquid volume (1.80e-10 mL = 1.8e8
+# cells of (10 nm)^3).  Plain data; the solver decides what to do with them.
+TABLE1 = {
+    "h": 10e-9, "dt_fd": 0.5e-6, "dt": 500e-6,
+    "D_S": 1.0e-17, "D_L": 1.0e-14, "A_S_RT": 2.0e3, "A_L_RT": 2.0e3,
+    "c_eq_S": 1.0, "c_eq_L": 1.0e-5, "c0_S": 1.0e-6, "c0_L": 2.12e-3,
+    "k": 0.05, "V_ff_cells": 1.8e8,
+}
+
+# phase labels of the particle geometry
+PHASE_NEAR_LIQUID, PHASE_SOLID, PHASE_FAR_LIQUID = 0, 1, 2
+
+
+def particle(n: int, r_p: float, shell: float = 5.0, porosity: float = 0.3, corr_len: float = 3.0,
+             seed: int = 21):
+    """Porous particle of radius ``r_p`` centred in an n^3 grid (the geometry of
+    Fig. 1): cells whose centre lies within ``r_p`` of the grid centre are
+    solid unless a thresholded Gaussian random field (``grf_mask`` with the
+    given correlation length, a ``porosity`` share of the grid) marks them as
+    pore; pores and the liquid shell up to ``r_p + shell`` are the near-field
+    liquid, every other cell is far-field liquid.  Returns uint8 labels
+    (PHASE_NEAR_LIQUID / PHASE_SOLID / PHASE_FAR_LIQUID)."""
+    g = np.arange(n, dtype=np.float64) + 0.5 - 0.5 * n
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    d2 = xx * xx + yy * yy + zz * zz
+    pore = grf_mask((n, n, n), corr_len, 1.0 - porosity, seed) == 0
+    label = np.full((n, n, n), PHASE_FAR_LIQUID, dtype=np.uint8)
+    label[d2 <= (r_p + shell) ** 2] = PHASE_NEAR_LIQUID
+    label[(d2 <= r_p * r_p) & ~pore] = PHASE_SOLID
+    return label
+
+
+def particle_case(n: int = 192, r_p: float = 50.0, r: int = 8, n_sub: int = 200, seed: int = 21):
+    """The wasteform-particle workload: ``particle`` labels, Table 1 values,
+    the initial concentrations c0_S in the solid and c0_L in every liquid cell,
+    window radius r and n_sub fast sub-steps of dt_fd per big step.  Returns
+    (Domain, dict of the Table 1 values)."""
+    t = dict(TABLE1)
+    label = particle(n, r_p, seed=seed)
+    c0 = np.where(label == PHASE_SOLID, t["c0_S"], t["c0_L"])
+    d_phase = np.array([t["D_L"], t["D_S"], t["D_L"]])
+    return Domain(label=label, d_phase=d_phase, c0=c0, r=r, n_sub=n_sub, dt=t["dt_fd"], h=t["h"],
+                  name=f"particle{n}_R{int(r_p)}"), t
+
+
 def random_small(shape, n_phase: int, r: int, n_sub: int, seed: int, dt: float = 0.0,
                  d_zero_phase: bool = True) -> Domain:
     """Small random multi-phase domain for parity and edge-case tests.
