@@ -347,6 +347,81 @@ int fdirw_coarse_matrix(void *handle, double *P_host);
 /* Frees the handle (NULL is accepted). */
 int fdirw_coarse_destroy(void *handle);
 
+/* ------------------------------------------------------------------ integrated solver
+ * The near-field solver of a porous particle in a waste solution (Sec. 2,
+ * Eqs. 1-7; flowchart of Sec. 3.4).  Every phase has a role: near-field liquid
+ * (fast diffusion), solid (slow diffusion) or far-field liquid (the uniform
+ * reservoir of Eq. 7, held in its cells as a Dirichlet boundary).  One field c
+ * holds the liquid concentration in liquid cells and the solid concentration
+ * in solid cells.  Inside a phase A_m and c_m^eq are constant, so Eq. 1 with
+ * Eqs. 2-3 is a diffusion with coefficient D_m A_m / RT; the two media meet
+ * only through the interface reaction.  One big step dt = n_sub * d->dt runs,
+ * in the flowchart's order:
+ *   1. fast diffusion: the coarse far-field step (fdirw_coarse_step_far_field)
+ *      of the near-field liquid, its kernels walled by the solid, with
+ *      P_BC c_ff of the step's start; solid cells keep their value
+ *   2. absorption (Eqs. 4-6): for every face between a near-field liquid cell
+ *      and a solid cell, d c_S / dt = k f_L f_S = -d c_L / dt integrated
+ *      exactly over dt for the pair: with a = c_L - c_L^eq, b = c_S^eq - c_S
+ *      and d = (b - a) k dt / (c_L^eq c_S^eq), the liquid cell gives
+ *      a b (e^d - 1) / (b e^d - a) to the solid cell (nothing while a <= 0);
+ *      the faces go in six groups in which no cell appears twice: x faces
+ *      between cells 2i and 2i+1, then 2i+1 and 2i+2, then y, then z
+ *   3. slow diffusion: n_sub_solid explicit sub-steps of dt / n_sub_solid in
+ *      the solid, harmonic-mean faces between solid cells, liquid cells walls
+ *   4. far field (Eq. 7): c_ff = (m_total - Q_L - Q_S) / v_ff, Q_L and Q_S
+ *      the sums of c over the near-field liquid and the solid cells, written
+ *      into the far-field cells.
+ * Steps run on the stream without host synchronisation (c_ff stays on the
+ * device between them). */
+enum { FDIRW_ROLE_LIQUID = 0, FDIRW_ROLE_SOLID = 1, FDIRW_ROLE_FAR_FIELD = 2 };
+
+typedef struct {
+    const uint8_t *role;       /* (host) d->n_phase roles, FDIRW_ROLE_*                        */
+    const double *a_over_rt;   /* (host) d->n_phase values of A_m / RT (Eqs. 2-3), finite and
+                                  >= 0; NULL: 1 for every phase                              */
+    double k;                  /* rate constant of Eq. 4 (per unit time of d->dt), >= 0     */
+    double c_eq_liquid;        /* c_L^eq of Eq. 5, > 0                                      */
+    double c_eq_solid;         /* c_S^eq of Eq. 6, > 0                                      */
+    int32_t n_sub_solid;       /* explicit solid sub-steps per big step, >= 1               */
+    double v_far_field;        /* V_L^far-field of Eq. 7 in cell volumes, > 0               */
+} fdirw_mp_params;
+
+/* Builds the solver of domain d: d->d_phase holds D_m per phase, d->dt > 0
+ * the fast sub-step, d->n_sub the fast sub-steps of one big step, d->r the
+ * window radius of the liquid kernels; block and prec as in
+ * fdirw_coarse_create (the liquid's coarse operator, with the near-field
+ * liquid phases grouped and the far-field phases as reservoir).  Checks the
+ * explicit limits 6 max(D A / RT) d->dt / h^2 <= 1 over the liquid phases and
+ * 6 max(D A / RT) (dt / n_sub_solid) / h^2 <= 1 over the solid phases.  Lists
+ * the interface faces once.  d->label must stay valid and unchanged while the
+ * handle lives (the solid step reads it).  *handle owns about 4 N + 8 N bytes
+ * and 8 bytes per interface face besides the coarse operator; seconds (host,
+ * may be NULL) receives the build time.  Synchronises the stream.
+ * Errors: E_ARG, E_UNSTABLE, E_NOMEM, E_DEVICE. */
+int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t block, int32_t prec, void *stream,
+                    void **handle, double *seconds);
+
+/* n_steps >= 0 big steps on c (device, N doubles, in place).  *c_ff (host, in /
+ * out): the far-field concentration at the start, replaced by the value after
+ * the last step; m_total: the conserved total Sum c_{S+L}(t0) of Eq. 7 (sum
+ * over the non-far-field cells plus c_ff v_ff at the start of the run).
+ * history (host, may be NULL): n_steps rows of {Q_L, Q_S, c_ff} after each
+ * step.  st (may be NULL): mass_in = m_total, mass_out = Q_L + Q_S + c_ff v_ff
+ * after the last step, kernel_seconds = device time of the steps, seconds.
+ * Synchronises the stream once at the end.  The handle's scratch is shared by
+ * its calls: calls on one handle must not overlap.
+ * Errors: E_ARG (null, another device), E_NONFINITE, E_NOMEM, E_DEVICE. */
+int fdirw_mp_step(void *handle, double *c, double *c_ff, double m_total, int32_t n_steps, double *history,
+                  void *stream, fdirw_stats *st);
+
+/* Number of interface faces (host, may be NULL) and the coarse handle of the
+ * liquid step (owned by the solver; valid while it lives). */
+int fdirw_mp_info(const void *handle, int64_t *n_faces, void **coarse);
+
+/* Frees the solver (NULL is accepted). */
+int fdirw_mp_destroy(void *handle);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char *fdirw_last_error(void);
 

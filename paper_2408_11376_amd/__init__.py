@@ -87,7 +87,7 @@ ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "f
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
                  "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create", "fdirw_coarse_step",
                  "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_pbc",
-                 "fdirw_coarse_destroy")
+                 "fdirw_coarse_destroy", "fdirw_mp_create", "fdirw_mp_step", "fdirw_mp_info", "fdirw_mp_destroy")
 NN_RADIUS = 8
 
 _lib = None
@@ -137,13 +137,19 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_coarse_shape.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
     lib.fdirw_coarse_matrix.argtypes = [P, P]
     lib.fdirw_coarse_destroy.argtypes = [P]
+    lib.fdirw_mp_create.argtypes = [D, ctypes.POINTER(fdirw_mp_params), ctypes.c_int32, ctypes.c_int32, P, PP,
+                                    ctypes.POINTER(ctypes.c_double)]
+    lib.fdirw_mp_step.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int32, P, P, S]
+    lib.fdirw_mp_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), PP]
+    lib.fdirw_mp_destroy.argtypes = [P]
     for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_run",
               "fdirw_field_sum",
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
               "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create",
               "fdirw_coarse_step", "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix",
-              "fdirw_coarse_pbc", "fdirw_coarse_destroy"):
+              "fdirw_coarse_pbc", "fdirw_coarse_destroy", "fdirw_mp_create", "fdirw_mp_step", "fdirw_mp_info",
+              "fdirw_mp_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -531,6 +537,86 @@ class Coarse:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- integrated solver
+
+ROLE_LIQUID, ROLE_SOLID, ROLE_FAR_FIELD = 0, 1, 2
+
+
+class fdirw_mp_params(ctypes.Structure):
+    _fields_ = [("role", ctypes.POINTER(ctypes.c_uint8)), ("a_over_rt", ctypes.POINTER(ctypes.c_double)),
+                ("k", ctypes.c_double), ("c_eq_liquid", ctypes.c_double), ("c_eq_solid", ctypes.c_double),
+                ("n_sub_solid", ctypes.c_int32), ("v_far_field", ctypes.c_double)]
+
+
+class Multiphysics:
+    """The integrated near-field solver of one geometry (Sec. 2, Eqs. 1-7):
+    per-phase ``role`` (ROLE_*), ``a_over_rt`` (A / RT, None for 1), the
+    interface law (``k``, ``c_eq_liquid``, ``c_eq_solid``), ``n_sub_solid``
+    solid sub-steps per big step and the far-field volume ``v_far_field`` in
+    cells; the liquid's coarse operator with ``block`` and ``prec``.
+    ``dom.dt`` is the fast sub-step, the big step is ``dom.n_sub * dom.dt``."""
+
+    def __init__(self, dom: Domain, role, k: float, c_eq_liquid: float, c_eq_solid: float, v_far_field: float,
+                 a_over_rt=None, n_sub_solid: int = 1, block: int = 5, prec=FP16_BANK, stream=None):
+        n_phase = len(dom.d_phase)
+        self._role = np.ascontiguousarray(role, dtype=np.uint8)
+        if self._role.size != n_phase:
+            raise ValueError("role needs one entry per phase")
+        self._a = None if a_over_rt is None else np.ascontiguousarray(a_over_rt, dtype=np.float64)
+        if self._a is not None and self._a.size != n_phase:
+            raise ValueError("a_over_rt needs one entry per phase")
+        p = fdirw_mp_params()
+        p.role = self._role.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.a_over_rt = None if self._a is None else self._a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.k, p.c_eq_liquid, p.c_eq_solid = float(k), float(c_eq_liquid), float(c_eq_solid)
+        p.n_sub_solid, p.v_far_field = int(n_sub_solid), float(v_far_field)
+        self.dom = dom                         # the solver reads dom.label while it lives
+        self.n = dom.n
+        self.v_far_field = float(v_far_field)
+        h = ctypes.c_void_p()
+        sec = ctypes.c_double(0.0)
+        ds = dom.c_struct()
+        _check(load_library().fdirw_mp_create(ctypes.byref(ds), ctypes.byref(p), int(block), _prec(prec),
+                                              _stream_ptr(stream), ctypes.byref(h), ctypes.byref(sec)))
+        self.handle, self.build_seconds = h, sec.value
+        nf = ctypes.c_int64(0)
+        ch = ctypes.c_void_p()
+        _check(load_library().fdirw_mp_info(self.handle, ctypes.byref(nf), ctypes.byref(ch)))
+        self.n_faces = int(nf.value)
+        shp, self.n_nodes = fdirw_coarse_shape(ch)
+        self.K, self.block = shp[3], shp[4]
+
+    def step(self, c, c_ff: float, m_total: float, n_steps: int = 1, stream=None, stats: bool = False):
+        """n_steps big steps on the float64 device tensor c (in place); returns
+        (c_ff after the last step, history [n_steps, 3] of Q_L, Q_S, c_ff[, stats])."""
+        torch = _torch()
+        _dev_tensor(c, torch.float64, "c")
+        if c.numel() != self.n:
+            raise ValueError("field does not match the domain")
+        cff = ctypes.c_double(float(c_ff))
+        hist = np.zeros((int(n_steps), 3))
+        st = fdirw_stats() if stats else None
+        _check(load_library().fdirw_mp_step(self.handle, ctypes.c_void_p(c.data_ptr()), ctypes.byref(cff),
+                                            float(m_total), int(n_steps), ctypes.c_void_p(hist.ctypes.data),
+                                            _stream_ptr(stream), ctypes.byref(st) if st is not None else None))
+        return (cff.value, hist, st.as_dict()) if stats else (cff.value, hist)
+
+    def close(self):
+        if self.handle:
+            fdirw_mp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fdirw_mp_destroy(handle):
+    _check(load_library().fdirw_mp_destroy(handle))
 
 
 # ----------------------------------------------------------------- surrogate

@@ -283,6 +283,7 @@ template <typename T>
 __global__ void __launch_bounds__(APPLY_NT) coarse_apply_kernel(const T *__restrict__ P, const double *__restrict__ cpad,
                                                                 int ncx, int ncy, int ncz, int K,
                                                                 const double *__restrict__ pbc_pad, double c_ff,
+                                                                const double *__restrict__ cff_dev,
                                                                 double *__restrict__ cnew)
 {
     __shared__ double part[APPLY_NT];
@@ -311,7 +312,8 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_kernel(const T *__restr
         for (int k = 0; k < kw; ++k) s += part[ln * kw + k];
         if (pbc_pad) {                                            // far-field term of Eq. 14
             const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
-            s = __builtin_fma(pbc_pad[((int64_t)(z + K) * py + (y + K)) * px + (x + K)], c_ff, s);
+            s = __builtin_fma(pbc_pad[((int64_t)(z + K) * py + (y + K)) * px + (x + K)], cff_dev ? *cff_dev : c_ff,
+                              s);
         }
         cnew[I] = s;
     }
@@ -523,7 +525,8 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
 }
 
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st)
+                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st,
+                               const double *cff_dev)
 {
     const int per = APPLY_NT / (2 * K + 1);
     if (per < 1) return hipErrorInvalidValue;
@@ -532,19 +535,19 @@ hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int 
     switch (prec) {
     case M_FP64:
         hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(APPLY_NT), 0, st, (const double *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
         break;
     case M_FP32:
         hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(APPLY_NT), 0, st, (const float *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
         break;
     case M_F16BANK:
         hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(APPLY_NT), 0, st, (const _Float16 *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
         break;
     case M_BF16BANK:
         hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(APPLY_NT), 0, st, (const __bf16 *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cnew);
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
         break;
     default: return hipErrorInvalidValue;
     }

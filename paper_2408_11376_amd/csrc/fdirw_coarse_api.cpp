@@ -245,7 +245,7 @@ namespace {
 // Mapping, product (with P_BC c_ff when pbc is set) and remapping; far-field
 // cells of c_out are left at 0.  kernel seconds of the three launches in *ks.
 int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double *pbc, double c_ff, hipStream_t st,
-                     double *ks)
+                     double *ks, const double *cff_dev = nullptr)
 {
     EventPair ev;
     hipError_t e = ks ? ev.create() : hipSuccess;
@@ -255,7 +255,7 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
                               h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st);
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
-                                (double *)h->cnew, st);
+                                (double *)h->cnew, st, cff_dev);
     if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
     if (ks && e == hipSuccess) e = hipEventRecord(ev.b, st);
     if (e != hipSuccess) return hip_fail(e, "coarse step launch");
@@ -268,6 +268,24 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
 }
 
 }  // namespace
+
+namespace fdirw {
+
+// The fast step of the integrated solver: mapping, product with P_BC c_ff read
+// from device memory (far-field handles) and remapping; far-field cells of
+// c_out are left at 0.
+int coarse_fast_step(void *handle, const double *c_in, double *c_out, const double *cff_dev, hipStream_t st)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    return coarse_apply_all(h, c_in, c_out, h->far_field ? (const double *)h->pbc : nullptr, 0.0, st, nullptr,
+                            h->far_field ? cff_dev : nullptr);
+}
+
+const int *coarse_node(const void *handle) { return (const int *)((const Coarse *)handle)->node; }
+
+}  // namespace fdirw
 
 extern "C" {
 

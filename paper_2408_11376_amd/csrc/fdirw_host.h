@@ -76,6 +76,10 @@ int flow_stable(const fdirw_domain *d, int fp64, const void *lam, const double *
 int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out, fdirw_stats *st,
             DevCache &dc, hipStream_t stream);
 
+// Coarse handle internals used by the integrated solver (fdirw_coarse_api.cpp).
+int coarse_fast_step(void *handle, const double *c_in, double *c_out, const double *cff_dev, hipStream_t st);
+const int *coarse_node(const void *handle);
+
 // Bytes per stored kernel value of a precision mode in the bank.
 inline size_t bank_elem_bytes(int prec)
 {

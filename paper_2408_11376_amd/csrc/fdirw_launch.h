@@ -139,9 +139,31 @@ hipError_t launch_flow_stability(int fp64, const void *lam, const double *u, int
 hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, const void *G, int64_t src_base,
                              int64_t n_src, hipStream_t st);
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st);
+                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st,
+                               const double *cff_dev = nullptr);   // cff_dev set: c_ff read from it
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
                                hipStream_t st);
+// Integrated near-field solver (fdirw_mp.hip).  Cell roles come from the
+// coarse node index: >= 0 near-field liquid, COARSE_RESERVOIR far field,
+// COARSE_OUTSIDE solid.
+struct SolidTable {
+    double d[256];            // D A / RT of every solid phase, 0 for the others
+};
+struct MpFaceLists {
+    int64_t off[6];           // start of each face pass in the list
+    int64_t cap[6];           // entries reserved for each pass
+};
+constexpr int MP_SUM_BLOCKS = 1024;
+hipError_t launch_mp_faces(const int *node, int nx, int ny, int nz, const MpFaceLists &lists, int64_t *list,
+                           unsigned long long *count, hipStream_t st);
+hipError_t launch_mp_react(const int64_t *faces, int64_t n_faces, int64_t stride, double *c, double c_eq_l,
+                           double c_eq_s, double kappa_dt, hipStream_t st);
+hipError_t launch_mp_solid(const uint8_t *label, const SolidTable &tab, int nx, int ny, int nz, double dt, double h,
+                           const double *in, double *out, hipStream_t st);
+hipError_t launch_mp_balance(const int *node, const double *c, int64_t n, double *part, double m_total, double v_ff,
+                             double *cff, double *hist_row, hipStream_t st);
+hipError_t launch_mp_far_fill(const int *node, int64_t n, const double *cff, const double *src, double *dst,
+                              hipStream_t st);
 int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes);   // offset-major bank, padded
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, int64_t n, unsigned v, hipStream_t st);

@@ -1,0 +1,235 @@
+"""GPU parity of the integrated near-field solver (Sec. 2, Eqs. 1-7; the
+flowchart of Sec. 3.4) through the C ABI against the oracle (pinned in
+test_oracle_multiphysics.py and test_oracle_coarse.py).
+
+Bars: with FP64 P the field, c_ff and the history of Q_L, Q_S, c_ff to 1e-12
+of their maxima; FP32 P to 1e-6; FP16 / BF16 P: relative L1 of the field
+1e-3 / 5e-3 (the reaction, the solid step and the balance are FP64 on both
+sides).  The Eq. 7 balance Q_L + Q_S + c_ff V_ff = M_total to 1e-12 always."""
+import numpy as np
+import pytest
+
+import synth
+from helpers import to_dev, to_host
+from oracle import coarse
+from oracle import multiphysics as mp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2408_11376_amd as fd  # noqa: E402
+
+ROLE = np.array([mp.ROLE_LIQUID, mp.ROLE_SOLID, mp.ROLE_FAR])
+
+
+def _case(n=12, r_p=3.5, seed=91, c_ff=0.2):
+    label = synth.particle(n, r_p, shell=2.0, porosity=0.3, corr_len=1.5, seed=seed)
+    u = synth.uniform(seed + 1, label.size).reshape(label.shape)
+    c0 = np.where(label == synth.PHASE_SOLID, 1e-4 * u, 0.2 + 0.05 * u)
+    c0[label == synth.PHASE_FAR_LIQUID] = c_ff
+    return label, c0
+
+
+def _run_both(label, c0, c_ff, n_steps, B, prec, n_sub_solid=1, r=3, n_sub=6, h=1.0, dt_fd=0.5,
+              d_phase=(1.0, 0.02, 1.0), a_rt=(0.15, 0.5, 0.15), k=0.3, c_eq_l=0.01, c_eq_s=1.0, v_ff=500.0,
+              oracle_too=True):
+    d_phase, a_rt = np.array(d_phase), np.array(a_rt)
+    far = label == synth.PHASE_FAR_LIQUID
+    m_total = c0[~far].sum() + v_ff * c_ff
+    dom = fd.Domain(label, d_phase, r, n_sub, h, dt_fd)
+    solver = fd.Multiphysics(dom, ROLE, k, c_eq_l, c_eq_s, v_ff, a_over_rt=a_rt, n_sub_solid=n_sub_solid, block=B,
+                             prec=prec)
+    c = to_dev(c0)
+    cff, hist, st = solver.step(c, c_ff, m_total, n_steps, stats=True)
+    got = to_host(c)
+    solver.close()
+    want = None
+    if oracle_too:
+        m = mp.Model(label, d_phase, a_rt, ROLE, r, n_sub, h, dt_fd, B, k, c_eq_l, c_eq_s, n_sub_solid, v_ff)
+        want = m.run(c0, c_ff, m_total, n_steps)
+    return (got, cff, hist, st, m_total), want
+
+
+@pytest.mark.parametrize("B,n_sub_solid,seed", [(1, 1, 91), (2, 2, 92), (3, 3, 93)])
+def test_matches_oracle_fp64(B, n_sub_solid, seed):
+    label, c0 = _case(seed=seed)
+    (got, cff, hist, st, m_total), (want, cff_w, hist_w) = _run_both(label, c0, 0.2, 4, B, fd.FP64,
+                                                                      n_sub_solid=n_sub_solid)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+    assert abs(cff - cff_w) <= 1e-12 * abs(cff_w)
+    assert np.max(np.abs(hist - hist_w) / np.abs(hist_w).max(axis=0)) <= 1e-12
+    assert np.max(np.abs(hist[:, 0] + hist[:, 1] + 500.0 * hist[:, 2] - m_total)) <= 1e-12 * m_total
+    assert abs(st["mass_out"] - m_total) <= 1e-12 * m_total
+    # the particle absorbs every step
+    assert np.all(np.diff(hist[:, 1]) > 0)
+
+
+@pytest.mark.parametrize("prec,kind,tol", [(fd.FP32, "max", 1e-6), (fd.FP16_BANK, "l1", 1e-3),
+                                           (fd.BF16_BANK, "l1", 5e-3)])
+def test_reduced_precision_p(prec, kind, tol):
+    label, c0 = _case(seed=94)
+    (got, cff, hist, st, m_total), (want, cff_w, hist_w) = _run_both(label, c0, 0.2, 3, 2, prec)
+    if kind == "max":
+        assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
+    else:
+        assert np.abs(got - want).sum() <= tol * np.abs(want).sum()
+    assert abs(cff - cff_w) <= 10 * tol * abs(cff_w)
+    assert np.max(np.abs(hist[:, 0] + hist[:, 1] + 500.0 * hist[:, 2] - m_total)) <= 1e-12 * m_total
+
+
+def test_table1_units():
+    # SI values of Table 1 (D A / RT gives lambda = 0.1 per fast sub-step in
+    # the liquid and 0.1 per big step in the solid); a short big step of 20
+    # fast sub-steps so that r = 4 windows hold the kernels
+    t = synth.TABLE1
+    label = synth.particle(14, 4.0, shell=2.0, porosity=0.3, corr_len=1.5, seed=95)
+    c0 = np.where(label == synth.PHASE_SOLID, t["c0_S"], t["c0_L"])
+    (got, cff, hist, st, m_total), (want, cff_w, hist_w) = _run_both(
+        label, c0, t["c0_L"], 3, 2, fd.FP64, n_sub_solid=1, r=4, n_sub=20, h=t["h"], dt_fd=t["dt_fd"],
+        d_phase=(t["D_L"], t["D_S"], t["D_L"]), a_rt=(t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]), k=t["k"],
+        c_eq_l=t["c_eq_L"], c_eq_s=t["c_eq_S"], v_ff=t["V_ff_cells"])
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+    assert abs(cff - cff_w) <= 1e-12 * abs(cff_w)
+    assert np.max(np.abs(hist - hist_w) / np.abs(hist_w).max(axis=0)) <= 1e-12
+
+
+def test_without_far_field_or_solid_and_zero_steps():
+    label, c0 = _case(seed=96)
+    # no far-field phase: the far-field label acts as near-field liquid
+    role = np.array([mp.ROLE_LIQUID, mp.ROLE_SOLID, mp.ROLE_LIQUID])
+    dom = fd.Domain(label, np.array([1.0, 0.02, 1.0]), 3, 6, 1.0, 0.5)
+    s = fd.Multiphysics(dom, role, 0.3, 0.01, 1.0, 500.0, a_over_rt=np.array([0.15, 0.5, 0.15]), block=2,
+                        prec=fd.FP64)
+    m = mp.Model(label, np.array([1.0, 0.02, 1.0]), np.array([0.15, 0.5, 0.15]), role, 3, 6, 1.0, 0.5, 2, 0.3,
+                 0.01, 1.0, 1, 500.0)
+    m_total = c0.sum() + 500.0 * 0.2
+    c = to_dev(c0)
+    cff, hist = s.step(c, 0.2, m_total, 2)
+    want, cff_w, hist_w = m.run(c0, 0.2, m_total, 2)
+    assert np.max(np.abs(to_host(c) - want)) <= 1e-12 * np.abs(want).max()
+    assert abs(cff - cff_w) <= 1e-12 * abs(cff_w)
+    # zero steps leave everything alone
+    before = to_host(c).copy()
+    cff0, hist0 = s.step(c, 0.123, m_total, 0)
+    assert cff0 == 0.123 and hist0.shape == (0, 3) and np.array_equal(to_host(c), before)
+    s.close()
+    # no solid phase: the step is the coarse far-field step
+    role = np.array([mp.ROLE_LIQUID, mp.ROLE_LIQUID, mp.ROLE_FAR])
+    s = fd.Multiphysics(dom, role, 0.3, 0.01, 1.0, 500.0, a_over_rt=np.array([0.15, 0.5, 0.15]), block=2,
+                        prec=fd.FP64)
+    assert s.n_faces == 0
+    m = mp.Model(label, np.array([1.0, 0.02, 1.0]), np.array([0.15, 0.5, 0.15]), role, 3, 6, 1.0, 0.5, 2, 0.3,
+                 0.01, 1.0, 1, 500.0)
+    far = label == synth.PHASE_FAR_LIQUID
+    m_total = c0[~far].sum() + 500.0 * 0.2
+    c = to_dev(c0)
+    cff, hist = s.step(c, 0.2, m_total, 2)
+    want, cff_w, hist_w = m.run(c0, 0.2, m_total, 2)
+    assert np.max(np.abs(to_host(c) - want)) <= 1e-12 * np.abs(want).max()
+    assert np.all(hist[:, 1] == 0.0)
+    s.close()
+
+
+def test_errors():
+    label, c0 = _case(seed=97)
+    dom = fd.Domain(label, np.array([1.0, 0.02, 1.0]), 3, 6, 1.0, 0.5)
+    a = np.array([0.15, 0.5, 0.15])
+    # solid: 6 * 0.01 * 3 = 0.18 is stable; 100x the coefficient needs 20 sub-steps
+    with pytest.raises(fd.FdirwError):
+        fd.Multiphysics(dom, ROLE, 0.3, 0.01, 1.0, 500.0, a_over_rt=np.array([0.15, 50.0, 0.15]), n_sub_solid=2)
+    fd.Multiphysics(dom, ROLE, 0.3, 0.01, 1.0, 500.0, a_over_rt=np.array([0.15, 50.0, 0.15]), n_sub_solid=20).close()
+    with pytest.raises(fd.FdirwError):        # liquid: 6 * 1.5 * 0.5 > 1
+        fd.Multiphysics(dom, ROLE, 0.3, 0.01, 1.0, 500.0, a_over_rt=np.array([1.5, 0.5, 0.15]))
+    with pytest.raises(fd.FdirwError):
+        fd.Multiphysics(fd.Domain(label, np.array([1.0, 0.02, 1.0]), 3, 6, 1.0, 0.0), ROLE, 0.3, 0.01, 1.0, 500.0,
+                        a_over_rt=a)         # the fast sub-step must be given
+    with pytest.raises(fd.FdirwError):
+        fd.Multiphysics(dom, np.array([0, 1, 3]), 0.3, 0.01, 1.0, 500.0, a_over_rt=a)
+    with pytest.raises(fd.FdirwError):
+        fd.Multiphysics(dom, ROLE, -1.0, 0.01, 1.0, 500.0, a_over_rt=a)
+    with pytest.raises(fd.FdirwError):
+        fd.Multiphysics(dom, ROLE, 0.3, 0.0, 1.0, 500.0, a_over_rt=a)
+    with pytest.raises(fd.FdirwError):
+        fd.Multiphysics(dom, ROLE, 0.3, 0.01, 1.0, 500.0, a_over_rt=a, prec=fd.FP16X32)
+    s = fd.Multiphysics(dom, ROLE, 0.3, 0.01, 1.0, 500.0, a_over_rt=a)
+    with pytest.raises(fd.FdirwError):
+        s.step(to_dev(c0), float("nan"), 1.0, 1)
+    s.close()
+
+
+def test_full_size_reaction_solid_and_balance_match_oracle():
+    # the 192^3 particle of the benchmark with r = 0 windows (the kernels are
+    # the unit point itself, so the fast step is C + P_BC c_ff, pinned by the
+    # oracle's whole-domain FD): the interface, solid and Eq. 7 kernels over
+    # the full grid in the launch shapes of the benchmark
+    dom_s, t = synth.particle_case(192, 50.0, r=0, n_sub=200)
+    label = dom_s.label
+    far = label == synth.PHASE_FAR_LIQUID
+    c0 = dom_s.c0.copy()
+    u = synth.uniform(98, label.size).reshape(label.shape)
+    c0[label == synth.PHASE_SOLID] *= 1.0 + u[label == synth.PHASE_SOLID]
+    c_ff = t["c0_L"]
+    v_ff = t["V_ff_cells"]
+    a_rt = np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]])
+    m_total = c0[~far].sum() + v_ff * c_ff
+    dom = fd.Domain.from_synth(dom_s)
+    s = fd.Multiphysics(dom, ROLE, t["k"], t["c_eq_L"], t["c_eq_S"], v_ff, a_over_rt=a_rt, block=1, prec=fd.FP64)
+    c = to_dev(c0)
+    cff, hist = s.step(c, c_ff, m_total, 2)
+    got = to_host(c)
+    s.close()
+    liquid = mp.liquid_problem(label, dom_s.d_phase, a_rt, ROLE, 0, 200, dom_s.h, dom_s.dt)
+    grouped, reservoir = ROLE == mp.ROLE_LIQUID, ROLE == mp.ROLE_FAR
+    pbc = coarse.p_bc(liquid, 1, grouped, reservoir)
+    import scipy.sparse
+    m = mp.Model(label, dom_s.d_phase, a_rt, ROLE, 0, 200, dom_s.h, dom_s.dt, 1, t["k"], t["c_eq_L"], t["c_eq_S"],
+                 1, v_ff, P=scipy.sparse.identity(label.size, format="csr"), pbc=pbc)
+    want, cff_w, hist_w = m.run(c0, c_ff, m_total, 2)
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+    assert abs(cff - cff_w) <= 1e-12 * abs(cff_w)
+    assert np.max(np.abs(hist - hist_w) / np.abs(hist_w).max(axis=0)) <= 1e-12
+
+
+def test_full_size_step_is_the_coarse_step_plus_the_coupling():
+    # the benchmark's workload (192^3 particle, r = 8, 200 fast sub-steps,
+    # 5^3 blocks, FP16 P): with k = 0 and a still solid the integrated step is
+    # the coarse far-field step; with the Table 1 values the balance closes and
+    # the absorption behaves
+    dom_s, t = synth.particle_case(192, 50.0)
+    label = dom_s.label
+    far = label == synth.PHASE_FAR_LIQUID
+    liq, sol = label == synth.PHASE_NEAR_LIQUID, label == synth.PHASE_SOLID
+    a_rt = np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]])
+    v_ff, c_ff = t["V_ff_cells"], t["c0_L"]
+    c0 = dom_s.c0
+    m_total = c0[~far].sum() + v_ff * c_ff
+    dom = fd.Domain.from_synth(dom_s)
+    # k = 0, solid coefficient 0
+    still = fd.Multiphysics(dom, ROLE, 0.0, t["c_eq_L"], t["c_eq_S"], v_ff, a_over_rt=a_rt * np.array([1, 0, 1]),
+                            block=5, prec=fd.FP16_BANK)
+    c = to_dev(c0)
+    cff, _ = still.step(c, c_ff, m_total, 1)
+    still.close()
+    d_liq = dom_s.d_phase * a_rt * np.array([1.0, 0.0, 1.0])
+    cg = fd.Coarse(fd.Domain(label, d_liq, dom_s.r, dom_s.n_sub, dom_s.h, dom_s.dt), 5, fd.FP16_BANK,
+                   grouped=[1, 0, 0], reservoir=[0, 0, 1])
+    ref, cff_ref = cg.step_far_field(to_dev(c0), c_ff, m_total, v_ff)
+    cg.close()
+    got, ref = to_host(c), to_host(ref)
+    assert np.array_equal(got[~far], ref[~far])
+    assert abs(cff - cff_ref) <= 1e-13 * abs(cff_ref)
+    # the full coupling, Table 1 values
+    s = fd.Multiphysics(dom, ROLE, t["k"], t["c_eq_L"], t["c_eq_S"], v_ff, a_over_rt=a_rt, block=5,
+                        prec=fd.FP16_BANK)
+    assert s.n_faces > 100000
+    c = to_dev(c0)
+    cff, hist = s.step(c, c_ff, m_total, 5)
+    s.close()
+    out = to_host(c)
+    assert np.max(np.abs(hist[:, 0] + hist[:, 1] + v_ff * hist[:, 2] - m_total)) <= 1e-12 * m_total
+    assert np.all(np.diff(hist[:, 1]) > 0) and np.all(np.diff(hist[:, 2]) < 0)
+    assert out[sol].max() <= t["c_eq_S"] and out[liq].min() >= 0.0
+    assert np.all(out[far] == cff)

@@ -216,3 +216,12 @@ def test_absorption_kinetics_conserve_and_fill_the_solid():
     assert np.all(np.diff(hist[:, 1]) > 0) and np.all(np.diff(hist[:, 2]) < 0)
     assert np.all(out[liq] >= m.c_eq_l * (1 - 1e-14))
     assert np.all(out[sol] <= m.c_eq_s)
+
+
+def test_zero_radius_windows_give_the_identity_operator():
+    # r = 0: every kernel is the unit point (no neighbour inside the window),
+    # also with absorbing far-field cells, so P = I for B = 1
+    m = _particle_model(n=7, r_p=2.0, r=0, n_sub=4, B=1)
+    assert np.array_equal(m.P, np.diag(np.diag(m.P)))
+    liq = mp.masks(m.label, m.role)[0].ravel()
+    assert np.array_equal(np.diag(m.P)[liq], np.ones(liq.sum()))
