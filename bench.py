@@ -301,6 +301,74 @@ def coarse_leg(fd, d, dom, c0, c1, args):
     return out
 
 
+def mp_bytes_per_step(n_cells, n_far, n_faces, n_nodes, K, p_bytes, n_sub_solid):
+    """Algorithmic HBM bytes of one integrated big step: every grid-wide pass
+    reads (and writes) each cell once; far-field cells are only rewritten."""
+    kw3 = (2 * K + 1) ** 3
+    b = 12 * n_cells                      # mapping: c, node
+    b += kw3 * n_nodes * p_bytes + 16 * n_nodes   # product: P, C, C'
+    b += 20 * n_cells                     # remapping: node, c_in, c_out
+    b += 8 * n_faces + 32 * n_faces       # reaction: face entry, two cells read + written
+    b += 17 * n_cells * n_sub_solid       # solid: label, c in, c out
+    b += 12 * n_cells                     # balance: node, c
+    b += 4 * n_cells + 8 * n_far          # far field: node, far cells written
+    if n_sub_solid % 2 == 0:
+        b += 16 * (n_cells - n_far)       # result back into c
+    return b
+
+
+def mp_leg(fd, args):
+    """The integrated near-field solver (Sec. 2, Eqs. 1-7, flowchart of Sec.
+    3.4) on the paper's particle case: a porous particle of radius 50 cells in
+    the 192^3 grid (near-field shell of 5 cells, the rest far field), Table 1
+    values, liquid kernels of r = 8 and 200 fast sub-steps (big step 100 us;
+    Table 1's 500 us would need windows of r ~ 40), 5^3 coarse blocks.  Per
+    storage precision of P: build time, device time per big step over
+    ``--mp-steps`` chained steps, interface faces, the Eq. 7 balance residual
+    and the solid uptake."""
+    import torch
+    import synth
+    n = args.n
+    d, t = synth.particle_case(n, 50.0 * n / 192.0)
+    role = [fd.ROLE_LIQUID, fd.ROLE_SOLID, fd.ROLE_FAR_FIELD]
+    a_rt = np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]])
+    far = d.label == synth.PHASE_FAR_LIQUID
+    v_ff, c_ff0 = t["V_ff_cells"], t["c0_L"]
+    m_total = float(d.c0[~far].sum()) + v_ff * c_ff0
+    dom = fd.Domain.from_synth(d)
+    out = {"workload": f"particle{n}_R{int(50 * n / 192)}", "r": d.r, "n_sub": d.n_sub, "block": 5,
+           "big_step_s": d.n_sub * d.dt, "near_liquid_cells": int((d.label == synth.PHASE_NEAR_LIQUID).sum()),
+           "solid_cells": int((d.label == synth.PHASE_SOLID).sum()), "steps": args.mp_steps}
+    stream = torch.cuda.current_stream()
+    for prec in ("fp32", "fp16_bank"):
+        log(f"integrated {prec}: building the liquid operator")
+        s = fd.Multiphysics(dom, role, t["k"], t["c_eq_L"], t["c_eq_S"], v_ff, a_over_rt=a_rt, block=5, prec=prec)
+        c = torch.from_numpy(d.c0).cuda()
+        s.step(c, c_ff0, m_total, 1)                       # warm-up
+        c.copy_(torch.from_numpy(d.c0))
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        cff, hist, st = s.step(c, c_ff0, m_total, args.mp_steps, stats=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.mp_steps
+        resid = float(np.max(np.abs(hist[:, 0] + hist[:, 1] + v_ff * hist[:, 2] - m_total))) / m_total
+        pb = 4 if prec == "fp32" else 2
+        byts = mp_bytes_per_step(d.n, int(far.sum()), s.n_faces, s.n_nodes, s.K, pb, 1)
+        rec = {"build_seconds": s.build_seconds, "ms_per_step": ms, "kernel_ms_per_step": 1e3 * st["kernel_seconds"] / args.mp_steps,
+               "nodes": s.n_nodes, "interface_faces": s.n_faces, "balance_rel_residual": resid,
+               "solid_uptake_Q_S": [float(hist[0, 1]), float(hist[-1, 1])], "c_ff_end": cff,
+               "hbm_bytes_per_step": byts, "hbm_GBps": byts / (ms * 1e-3) / 1e9,
+               "hbm_frac": byts / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+               "seconds_per_physical_0p5s": ms * 1e-3 * 0.5 / (d.n_sub * d.dt)}
+        out[prec] = rec
+        s.close()
+        log(f"integrated {prec}: {ms:.4f} ms / big step, {s.n_faces} faces, balance {resid:.1e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -315,6 +383,8 @@ def main():
                     help="Adam steps of the surrogate before its step is timed (0: skip the surrogate)")
     ap.add_argument("--batched", type=int, default=1, help="also time the 64-domain batched step (0: skip)")
     ap.add_argument("--bank", type=int, default=1, help="also time fdirw_run with FP32 and FP16 kernel banks (0: skip)")
+    ap.add_argument("--mp-steps", type=int, default=50,
+                    help="big steps of the integrated-solver leg (particle case); 0: skip the leg")
     ap.add_argument("--coarse-block", type=int, default=5,
                     help="block edge of the coarse-mesh leg (the paper's 1/125 nodes); 0: skip the leg")
     args = ap.parse_args()
@@ -390,6 +460,8 @@ def main():
         extra["bank"] = bank_leg(fd, d, dom, c0, fields.get("fp32"), args)
     if args.coarse_block > 0:
         extra["coarse"] = coarse_leg(fd, d, dom, c0, fields.get("fp32"), args)
+    if args.mp_steps > 0:
+        extra["integrated"] = mp_leg(fd, args)
 
     if "fp32" in fields:
         ref = fields["fp32"]

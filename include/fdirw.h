@@ -394,10 +394,13 @@ typedef struct {
  * liquid phases grouped and the far-field phases as reservoir).  Checks the
  * explicit limits 6 max(D A / RT) d->dt / h^2 <= 1 over the liquid phases and
  * 6 max(D A / RT) (dt / n_sub_solid) / h^2 <= 1 over the solid phases.  Lists
- * the interface faces once.  d->label must stay valid and unchanged while the
- * handle lives (the solid step reads it).  *handle owns about 4 N + 8 N bytes
- * and 8 bytes per interface face besides the coarse operator; seconds (host,
- * may be NULL) receives the build time.  Synchronises the stream.
+ * once the interface faces, the active cells (near-field liquid and solid)
+ * and the solid cells with their face coefficients; a step then touches the
+ * active cells only, and the far-field cells once per fdirw_mp_step call.
+ * d->label is read only here; N must be below 2^31.  *handle owns about 8 N
+ * bytes (a second field) plus 4 bytes per active cell, 88 per solid cell and
+ * 8 per interface face besides the coarse operator; seconds (host, may be
+ * NULL) receives the build time.  Synchronises the stream.
  * Errors: E_ARG, E_UNSTABLE, E_NOMEM, E_DEVICE. */
 int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t block, int32_t prec, void *stream,
                     void **handle, double *seconds);

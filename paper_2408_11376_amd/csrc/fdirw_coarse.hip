@@ -219,12 +219,69 @@ __global__ void coarse_finalize_kernel(const double *__restrict__ S, const doubl
     }
 }
 
-// Eq. 13 on the coarse grid padded by K (halo and empty blocks 0).  One
-// workgroup per coarse (by, bz) row of blocks: each thread sums one fine x
-// column over the block's B x B (y, z) rows (coalesced across the threads),
-// then one thread per block adds its B columns in x order: a fixed order, so
-// the mapping is deterministic.  Workgroups with bz or by in the halo write
-// that halo row of zeros.
+// Eq. 13 on the coarse grid padded by K, for grids where most blocks hold
+// grouped cells.  One workgroup per (by, bz) row of blocks: each thread sums
+// one fine x column over the block's B x B (z, y) rows (coalesced across the
+// threads, eight loads in flight), then one thread per block adds its B
+// columns in x order: a fixed order, so the mapping is deterministic.  Blocks
+// without grouped cells read nothing and keep the 0 written when the handle
+// was built, as does the halo.
+__global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__restrict__ c,
+                                                             const int *__restrict__ node,
+                                                             const double *__restrict__ count, int nx, int ny, int nz,
+                                                             int B, int ncx, int ncy, int K, double *__restrict__ cpad)
+{
+    __shared__ double col[256];
+    const int px = ncx + 2 * K, py = ncy + 2 * K;
+    const int by = blockIdx.x, bz = blockIdx.y;
+    double *row = cpad + ((int64_t)(bz + K) * py + (by + K)) * px;
+    const int y0 = by * B, z0 = bz * B;
+    const int y1 = min(ny, y0 + B), z1 = min(nz, z0 + B);
+    const double *cnt = count + ((int64_t)bz * ncy + by) * ncx;
+    for (int xb0 = 0; xb0 < ncx; xb0 += 256 / B) {               // blocks of this pass
+        const int nbk = min(256 / B, ncx - xb0);
+        const int x = xb0 * B + threadIdx.x;
+        double s = 0.0;
+        const bool used = threadIdx.x < nbk * B && cnt[xb0 + threadIdx.x / B] > 0.0;
+        if (used && x < nx) {
+            const int ny_b = y1 - y0, n_q = (z1 - z0) * ny_b;
+            for (int q0 = 0; q0 < n_q; q0 += 8) {
+                int64_t at[8];
+                int nd[8];
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q0 + u < n_q ? q0 + u : n_q - 1;
+                    at[u] = ((int64_t)(z0 + q / ny_b) * ny + (y0 + q % ny_b)) * nx + x;
+                    nd[u] = node[at[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = nd[u] >= 0 ? c[at[u]] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (q0 + u < n_q && nd[u] >= 0) s += v[u];
+            }
+        }
+        __syncthreads();                                          // col of the previous pass is read
+        col[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < nbk) {
+            const int bx = xb0 + threadIdx.x;
+            const double nI = cnt[bx];
+            if (nI > 0.0) {
+                double t = 0.0;
+                for (int k = 0; k < B; ++k) t += col[threadIdx.x * B + k];
+                row[K + bx] = t / nI;
+            }
+        }
+    }
+}
+
+// Eq. 13 on the coarse grid padded by K, for sparse grids.  One wave per node: lane l sums the
+// grouped cells l, l + 64, ... of the node's block (cells in z, y, x order),
+// the lanes are combined by a fixed butterfly, and lane 0 writes the mean.
+// Empty nodes return at once: their padded entries and the halo hold the 0
+// written when the handle was built.
 constexpr int MAP_NT = 256;
 
 __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
@@ -232,90 +289,99 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
                                                             int B, int ncx, int ncy, int ncz, int K,
                                                             double *__restrict__ cpad)
 {
-    __shared__ double col[MAP_NT];
-    const int px = ncx + 2 * K, py = ncy + 2 * K;
-    const int byp = blockIdx.x, bzp = blockIdx.y;                 // padded coarse (y, z)
-    const int by = byp - K, bz = bzp - K;
-    double *row = cpad + ((int64_t)bzp * py + byp) * px;
-    const bool inside = by >= 0 && by < ncy && bz >= 0 && bz < ncz;
-    for (int x0 = 0; x0 < px; x0 += MAP_NT) {                     // halo rows, and the x halo
-        const int x = x0 + threadIdx.x;
-        if (x < px && (!inside || x < K || x >= K + ncx)) row[x] = 0.0;
+    const int64_t I = blockIdx.x * (int64_t)(MAP_NT / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
+    if (I >= n_nodes) return;                                     // uniform per wave
+    const double nI = count[I];
+    if (!(nI > 0.0)) return;
+    const int bx = (int)(I % ncx), by = (int)((I / ncx) % ncy), bz = (int)(I / ((int64_t)ncx * ncy));
+    const int x0 = bx * B, y0 = by * B, z0 = bz * B;
+    const int wx = min(nx, x0 + B) - x0, wy = min(ny, y0 + B) - y0, wz = min(nz, z0 + B) - z0;
+    const int n_cells = wx * wy * wz;
+    double s = 0.0;
+    for (int q0 = lane; q0 < n_cells; q0 += 4 * 64) {
+        int64_t at[4];
+        int nd[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + 64 * u < n_cells ? q0 + 64 * u : q0;
+            const int dz = q / (wx * wy), rem = q - dz * wx * wy, dy = rem / wx, dx = rem - dy * wx;
+            at[u] = ((int64_t)(z0 + dz) * ny + (y0 + dy)) * nx + (x0 + dx);
+            nd[u] = node[at[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = nd[u] >= 0 ? c[at[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q0 + 64 * u < n_cells && nd[u] >= 0) s += v[u];
     }
-    if (!inside) return;                                          // uniform per block
-    const int y0 = by * B, z0 = bz * B;
-    const int y1 = min(ny, y0 + B), z1 = min(nz, z0 + B);
-    for (int xb0 = 0; xb0 < ncx; xb0 += MAP_NT / B) {             // blocks of this pass
-        const int nbk = min(MAP_NT / B, ncx - xb0);
-        const int x = xb0 * B + threadIdx.x;
-        double s = 0.0;
-        if (threadIdx.x < nbk * B && x < nx) {
-            for (int z = z0; z < z1; ++z)
-                for (int y = y0; y < y1; ++y) {
-                    const int64_t j = ((int64_t)z * ny + y) * nx + x;
-                    if (node[j] >= 0) s += c[j];
-                }
-        }
-        __syncthreads();                                          // col of the previous pass is read
-        col[threadIdx.x] = s;
-        __syncthreads();
-        if (threadIdx.x < nbk) {
-            const int bx = xb0 + threadIdx.x;
-            const double nI = count[((int64_t)bz * ncy + by) * ncx + bx];
-            double t = 0.0;
-            for (int k = 0; k < B; ++k) t += col[threadIdx.x * B + k];
-            row[K + bx] = nI > 0.0 ? t / nI : 0.0;
-        }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) {
+        const int px = ncx + 2 * K, py = ncy + 2 * K;
+        cpad[((int64_t)(bz + K) * py + (by + K)) * px + (bx + K)] = s / nI;
     }
 }
 
 // Eq. 14 on the coarse grid: C'_I = sum over the (2K+1)^3 offsets o of
 // P[o][I] C[I - o] (FP64), with P in the bank layout of element type T and C
-// read from the padded grid.  2K+1 threads per node, one per z offset, each
-// summing its (2K+1)^2 terms in (y, x) order; the z partials are then added
-// in z order (a fixed order per node).
+// read from the padded grid.  A wave takes 64 nodes that are consecutive in
+// the layout (64 / zb chunks of zb = 16 / sizeof(T) nodes along z), so every
+// P load of the wave is one contiguous 128..512-byte run; wave w of the
+// workgroup takes the offsets with oz = w (w, w + nw, ... if 2K+1 > 16
+// waves), summing its terms in (oy, ox) order; the wave partials of a node
+// are then added in wave order (a fixed order per node).
 template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
 template <> __device__ __forceinline__ double widen<double>(double v) { return v; }
 
-constexpr int APPLY_NT = 256;
+constexpr int APPLY_MAX_WAVES = 16;
 
 template <typename T>
-__global__ void __launch_bounds__(APPLY_NT) coarse_apply_kernel(const T *__restrict__ P, const double *__restrict__ cpad,
-                                                                int ncx, int ncy, int ncz, int K,
-                                                                const double *__restrict__ pbc_pad, double c_ff,
-                                                                const double *__restrict__ cff_dev,
-                                                                double *__restrict__ cnew)
+__global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
+    const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz, int K,
+    const double *__restrict__ pbc_pad, double c_ff, const double *__restrict__ cff_dev,
+    const double *__restrict__ count, double *__restrict__ cnew)
 {
-    __shared__ double part[APPLY_NT];
     constexpr int zb = 16 / (int)sizeof(T);
-    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
-    const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
+    __shared__ double part[APPLY_MAX_WAVES * 64];
     const int kw = 2 * K + 1, px = ncx + 2 * K, py = ncy + 2 * K;
-    const int per = APPLY_NT / kw;                                // nodes per workgroup
-    const int ln = threadIdx.x / kw, oz = threadIdx.x - ln * kw;
-    const int64_t I = blockIdx.x * (int64_t)per + ln;
+    const int nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
+    const int64_t plane = n_chunks * zb;
+    const int64_t ch = blockIdx.x * (int64_t)(64 / zb) + lane / zb;   // (zg, y, x) chunk
+    const int j = lane % zb;
     double acc = 0.0;
-    if (ln < per && I < n_nodes) {
-        const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
-        const T *p = P + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb + (int64_t)oz * kw * kw * plane;
-        int o = 0;
-        for (int oy = 0; oy < kw; ++oy) {
-            // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
-            const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
-            for (int ox = 0; ox < kw; ++ox, ++o) acc = __builtin_fma(widen<T>(p[o * plane]), crow[-ox], acc);
+    int x = 0, y = 0, z = ncz;
+    if (ch < n_chunks) {
+        x = (int)(ch % ncx);
+        y = (int)((ch / ncx) % ncy);
+        z = (int)(ch / ((int64_t)ncx * ncy)) * zb + j;
+    }
+    // nodes without grouped cells are never read back: skipped
+    if (z < ncz && !(count[((int64_t)z * ncy + y) * ncx + x] > 0.0)) z = ncz;
+    if (z < ncz) {
+        for (int oz = w; oz < kw; oz += nw) {
+            const T *p = P + ch * zb + j + (int64_t)oz * kw * kw * plane;
+            int o = 0;
+            for (int oy = 0; oy < kw; ++oy) {
+                // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
+                const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
+                for (int ox = 0; ox < kw; ++ox, ++o) acc = __builtin_fma(widen<T>(p[o * plane]), crow[-ox], acc);
+            }
         }
     }
     part[threadIdx.x] = acc;
     __syncthreads();
-    if (ln < per && oz == 0 && I < n_nodes) {
+    if (w == 0 && z < ncz) {
         double s = 0.0;
-        for (int k = 0; k < kw; ++k) s += part[ln * kw + k];
-        if (pbc_pad) {                                            // far-field term of Eq. 14
-            const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
+        for (int k = 0; k < nw; ++k) s += part[k * 64 + lane];
+        if (pbc_pad)                                              // far-field term of Eq. 14
             s = __builtin_fma(pbc_pad[((int64_t)(z + K) * py + (y + K)) * px + (x + K)], cff_dev ? *cff_dev : c_ff,
                               s);
-        }
-        cnew[I] = s;
+        cnew[((int64_t)z * ncy + y) * ncx + x] = s;
     }
 }
 
@@ -516,38 +582,50 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
 }
 
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
-                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st)
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense)
 {
-    if (B > MAP_NT) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(coarse_map_kernel, dim3((unsigned)(ncy + 2 * K), (unsigned)(ncz + 2 * K)), dim3(MAP_NT), 0,
-                       st, c, node, count, nx, ny, nz, B, ncx, ncy, ncz, K, cpad);
+    if (dense && B <= 256) {
+        if (ncx <= 0 || ncy <= 0 || ncz <= 0) return hipSuccess;
+        hipLaunchKernelGGL(coarse_map_rows_kernel, dim3((unsigned)ncy, (unsigned)ncz), dim3(256), 0, st, c, node,
+                           count, nx, ny, nz, B, ncx, ncy, K, cpad);
+        return hipGetLastError();
+    }
+    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
+    const int64_t g = (n_nodes + MAP_NT / 64 - 1) / (MAP_NT / 64);
+    if (g <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coarse_map_kernel, dim3((unsigned)g), dim3(MAP_NT), 0, st, c, node, count, nx, ny, nz, B, ncx,
+                       ncy, ncz, K, cpad);
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st,
-                               const double *cff_dev)
+                               const double *pbc_pad, double c_ff, const double *count, double *cnew,
+                               hipStream_t st, const double *cff_dev)
 {
-    const int per = APPLY_NT / (2 * K + 1);
-    if (per < 1) return hipErrorInvalidValue;
-    const int64_t nblk = ((int64_t)ncx * ncy * ncz + per - 1) / per;
-    const unsigned g = (unsigned)nblk;
+    const int kw = 2 * K + 1;
+    const int nw = kw < APPLY_MAX_WAVES ? kw : APPLY_MAX_WAVES;
+    const size_t esz = prec == M_FP64 ? 8 : (prec == M_FP32 ? 4 : 2);
+    const int zb = (int)(16 / esz);
+    const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
+    const unsigned g = (unsigned)((n_chunks * zb + 63) / 64);
+    const size_t lds = 0;
+    if (g == 0) return hipSuccess;
     switch (prec) {
     case M_FP64:
-        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(APPLY_NT), 0, st, (const double *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(64 * nw), lds, st, (const double *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
         break;
     case M_FP32:
-        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(APPLY_NT), 0, st, (const float *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(64 * nw), lds, st, (const float *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
         break;
     case M_F16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(APPLY_NT), 0, st, (const _Float16 *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(64 * nw), lds, st, (const _Float16 *)P,
+                           cpad, ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
         break;
     case M_BF16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(APPLY_NT), 0, st, (const __bf16 *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, cnew);
+        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(64 * nw), lds, st, (const __bf16 *)P, cpad,
+                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
         break;
     default: return hipErrorInvalidValue;
     }

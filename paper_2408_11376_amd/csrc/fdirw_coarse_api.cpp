@@ -38,6 +38,7 @@ struct Coarse {
     void *cnew = nullptr;           // double [n_nodes]
     void *part = nullptr;           // field-sum partials
     bool far_field = false;         // reservoir (far-field boundary) phases present
+    bool dense = true;              // most nodes hold grouped cells (mapping by rows of blocks)
     void *pbc = nullptr;            // double, P_BC on the padded coarse grid (far field only)
 
     ~Coarse()
@@ -150,14 +151,26 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             tab.mobile[i] = (grouped ? grouped[i] != 0 : d->d_phase[i] > 0.0) ? 1 : 0;
             tab.reservoir[i] = (reservoir && reservoir[i]) ? 1 : 0;
         }
-        // P entries of empty nodes and of the padding groups stay 0
+        // P entries of empty nodes and of the padding groups stay 0, and so do
+        // the halo and the empty nodes of the padded coarse fields
         e = launch_fill((double *)h->count, h->n_nodes, 0.0, st);
+        if (e == hipSuccess) e = launch_fill((double *)h->cpad, n_pad, 0.0, st);
+        if (e == hipSuccess && h->pbc) e = launch_fill((double *)h->pbc, n_pad, 0.0, st);
         if (e == hipSuccess) e = launch_fill(S, (int64_t)nb * h->n_nodes, 0.0, st);
         if (e == hipSuccess)
             e = launch_fill_u32((unsigned *)h->P, (int64_t)((size_t)nb * h->plane * h->esz / 4), 0u, st);
         if (e == hipSuccess)
             e = launch_coarse_nodes(d->label, tab, d->nx, d->ny, d->nz, block, h->ncx, h->ncy, (int *)h->node,
                                     (double *)h->count, st);
+        if (e == hipSuccess) {
+            // the mapping's shape: by rows of blocks when most nodes hold cells
+            std::vector<double> hc((size_t)h->n_nodes);
+            e = hipMemcpyAsync(hc.data(), h->count, hc.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            int64_t used = 0;
+            for (double v : hc) used += v > 0.0;
+            h->dense = 2 * used >= h->n_nodes;
+        }
         if (e == hipSuccess) {
             CoarseGenArgs a;
             a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.n = h->n;
@@ -219,7 +232,7 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                                      velocity, g.dt / d->h, fa, fa + h->n, &field, st);
             if (e == hipSuccess)
                 e = launch_coarse_map(field, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz,
-                                      block, h->ncx, h->ncy, h->ncz, h->K, (double *)h->pbc, st);
+                                      block, h->ncx, h->ncy, h->ncz, h->K, (double *)h->pbc, st, h->dense);
             (void)hipStreamSynchronize(st);
             (void)hipFree(fa);
         }
@@ -252,10 +265,10 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
     if (ks && e == hipSuccess) e = hipEventRecord(ev.a, st);
     if (e == hipSuccess)
         e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
-                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st);
+                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense);
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
-                                (double *)h->cnew, st, cff_dev);
+                                (const double *)h->count, (double *)h->cnew, st, cff_dev);
     if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
     if (ks && e == hipSuccess) e = hipEventRecord(ev.b, st);
     if (e != hipSuccess) return hip_fail(e, "coarse step launch");
@@ -271,16 +284,23 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
 
 namespace fdirw {
 
-// The fast step of the integrated solver: mapping, product with P_BC c_ff read
-// from device memory (far-field handles) and remapping; far-field cells of
-// c_out are left at 0.
-int coarse_fast_step(void *handle, const double *c_in, double *c_out, const double *cff_dev, hipStream_t st)
+// Mapping and product of the fast step of the integrated solver, with P_BC
+// c_ff read from device memory (far-field handles); *cnew receives the node
+// values C' (the caller remaps).
+int coarse_map_apply(void *handle, const double *c_in, const double *cff_dev, hipStream_t st, const double **cnew)
 {
     Coarse *h = (Coarse *)handle;
     int rc = check_handle(h);
     if (rc) return rc;
-    return coarse_apply_all(h, c_in, c_out, h->far_field ? (const double *)h->pbc : nullptr, 0.0, st, nullptr,
-                            h->far_field ? cff_dev : nullptr);
+    hipError_t e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
+                                     h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense);
+    if (e == hipSuccess)
+        e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
+                                h->far_field ? (const double *)h->pbc : nullptr, 0.0, (const double *)h->count,
+                                (double *)h->cnew, st, h->far_field ? cff_dev : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "coarse mapping / product launch");
+    *cnew = (const double *)h->cnew;
+    return FDIRW_OK;
 }
 
 const int *coarse_node(const void *handle) { return (const int *)((const Coarse *)handle)->node; }

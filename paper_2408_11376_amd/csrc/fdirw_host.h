@@ -77,7 +77,7 @@ int step_nn(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, doub
             DevCache &dc, hipStream_t stream);
 
 // Coarse handle internals used by the integrated solver (fdirw_coarse_api.cpp).
-int coarse_fast_step(void *handle, const double *c_in, double *c_out, const double *cff_dev, hipStream_t st);
+int coarse_map_apply(void *handle, const double *c_in, const double *cff_dev, hipStream_t st, const double **cnew);
 const int *coarse_node(const void *handle);
 
 // Bytes per stored kernel value of a precision mode in the bank.

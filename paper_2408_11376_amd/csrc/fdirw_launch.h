@@ -131,37 +131,76 @@ hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int 
 hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st);
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
                                   int ncy, int ncz, void *P, hipStream_t st);
+// writes the nodes with grouped cells only: cpad must be zeroed once; dense:
+// one workgroup per row of blocks (most blocks hold grouped cells), else one
+// wave per node
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
-                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st);
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense);
 hipError_t launch_flow_window(int fp64, int r, const FlowArgs &a, hipStream_t st);
 hipError_t launch_flow_stability(int fp64, const void *lam, const double *u, int nx, int ny, int nz, double cour,
                                  unsigned long long *out, hipStream_t st);
 hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, const void *G, int64_t src_base,
                              int64_t n_src, hipStream_t st);
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               const double *pbc_pad, double c_ff, double *cnew, hipStream_t st,
-                               const double *cff_dev = nullptr);   // cff_dev set: c_ff read from it
+                               const double *pbc_pad, double c_ff, const double *count, double *cnew,
+                               hipStream_t st, const double *cff_dev = nullptr);   // cff_dev set: c_ff read from it
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
                                hipStream_t st);
 // Integrated near-field solver (fdirw_mp.hip).  Cell roles come from the
 // coarse node index: >= 0 near-field liquid, COARSE_RESERVOIR far field,
-// COARSE_OUTSIDE solid.
-struct SolidTable {
-    double d[256];            // D A / RT of every solid phase, 0 for the others
+// COARSE_OUTSIDE solid.  Per-phase tables live in device memory, not in
+// kernel arguments (every workgroup reads them).
+// Tiles of the fused local kernel: MP_TX x MP_TY x MP_TZ cells and a halo of
+// MP_H cells on every side in LDS.
+constexpr int MP_TX = 16, MP_TY = 8, MP_TZ = 8, MP_H = 3;
+constexpr int MP_BX = MP_TX + 2 * MP_H, MP_BY = MP_TY + 2 * MP_H, MP_BZ = MP_TZ + 2 * MP_H;
+constexpr int MP_BOX = MP_BX * MP_BY * MP_BZ;
+constexpr int MP_PAIR_CAP = 1024;     // interface pairs of a tile staged in LDS (the rest read from memory)
+constexpr int MP_SUM_BLOCKS = 256;    // most workgroups of the balance kernel
+constexpr int MP_CHUNK = 1024;        // cells per workgroup of the list kernels
+struct MpLocalArgs {
+    int nx, ny, nz;
+    const int *tiles;                 // tile indices (tz * nty + ty) * ntx + tx
+    int64_t n_tiles;
+    const int *pair_off;              // [6 n_tiles + 1] start of each tile's pass in pairs
+    const uint16_t *pairs;            // interface pairs, (q << 1) | (lower cell solid)
+    const int *node;
+    const uint8_t *label;
+    const double *dsol;               // [256] D A / RT of every solid phase, 0 for the others
+    const double *cnew;               // node values after the product
+    const double *c_in;               // the step's input field (solid cells)
+    double *out;                      // the step's output field (active cells written)
+    double c_eq_l, c_eq_s, kappa_dt;
+    int solid;                        // 1: one solid sub-step and the Eq. 7 balance
+    double dt_s, h;
+    double *part;                     // 2 * n_tiles doubles
+    double m_total, v_ff;
+    double *cff, *hist_row;
 };
-struct MpFaceLists {
-    int64_t off[6];           // start of each face pass in the list
-    int64_t cap[6];           // entries reserved for each pass
-};
-constexpr int MP_SUM_BLOCKS = 1024;
-hipError_t launch_mp_faces(const int *node, int nx, int ny, int nz, const MpFaceLists &lists, int64_t *list,
-                           unsigned long long *count, hipStream_t st);
-hipError_t launch_mp_react(const int64_t *faces, int64_t n_faces, int64_t stride, double *c, double c_eq_l,
-                           double c_eq_s, double kappa_dt, hipStream_t st);
-hipError_t launch_mp_solid(const uint8_t *label, const SolidTable &tab, int nx, int ny, int nz, double dt, double h,
-                           const double *in, double *out, hipStream_t st);
-hipError_t launch_mp_balance(const int *node, const double *c, int64_t n, double *part, double m_total, double v_ff,
-                             double *cff, double *hist_row, hipStream_t st);
+int64_t mp_tile_count(int nx, int ny, int nz);
+hipError_t launch_mp_faces(const int *node, int nx, int ny, int nz, unsigned long long *count, hipStream_t st);
+hipError_t launch_mp_tile_flags(const int *node, int nx, int ny, int nz, int *flag, hipStream_t st);
+// list null: counts into cnt[6 n_tiles]; else entries at list[off[6 t + p]..]
+hipError_t launch_mp_tile_pairs(const int *node, int nx, int ny, int nz, const int *tiles, int64_t n_tiles,
+                                const int *off, uint16_t *list, int *cnt, hipStream_t st);
+// the fused local kernel, then (a.solid) the Eq. 7 finish from its partials
+hipError_t launch_mp_local(const MpLocalArgs &a, hipStream_t st);
+// sorted lists: mode 0 active cells (not far field), mode 1 solid cells;
+// chunk_count / chunk_off hold ceil(n / MP_CHUNK) entries
+hipError_t launch_mp_list_count(const int *node, int64_t n, int mode, int *chunk_count, hipStream_t st);
+hipError_t launch_mp_list_write(const int *node, int64_t n, int mode, const int64_t *chunk_off, int *list,
+                                hipStream_t st);
+// inv: [N] ints preset to -1; lam [6][n_sol] doubles, nb [6][n_sol] ints
+// dsol: [256] D A / RT of every solid phase (0 for the others), device memory
+hipError_t launch_mp_solid_prep(const int *sol, int64_t n_sol, const uint8_t *label, const double *dsol,
+                                int *inv, int nx, int ny, int nz, double dt, double h, double *lam, int *nb,
+                                hipStream_t st);
+// n_sub sub-steps of the solid cells of field, in place (a, b: n_sol doubles)
+hipError_t launch_mp_solid(const int *sol, int64_t n_sol, const double *lam, const int *nb, int nx, int ny,
+                           int n_sub, double *field, double *a, double *b, hipStream_t st);
+unsigned mp_balance_blocks(int64_t n_act);   // part needs 2 x this many doubles
+hipError_t launch_mp_balance(const int *act, int64_t n_act, const int *node, const double *c, double *part,
+                             double m_total, double v_ff, double *cff, double *hist_row, hipStream_t st);
 hipError_t launch_mp_far_fill(const int *node, int64_t n, const double *cff, const double *src, double *dst,
                               hipStream_t st);
 int64_t bank_elems(int nx, int ny, int nz, int r, int elem_bytes);   // offset-major bank, padded

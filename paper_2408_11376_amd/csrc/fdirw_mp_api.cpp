@@ -3,11 +3,19 @@
 // 2408.11376).
 //
 // A handle owns the coarse operator of the liquid (built by
-// fdirw_coarse_create on the domain with the solid walled off), the six lists
-// of interface faces, a second field buffer and the far-field value on the
-// device.  A step launches, in order: mapping / product / remapping, the six
-// reaction passes, the solid sub-steps, the two-level balance of Eq. 7 and
-// the far-field fill; nothing returns to the host between steps.
+// fdirw_coarse_create on the domain with the solid walled off), the list of
+// tiles that hold an active cell (near-field liquid or solid), a copy of the
+// labels, the sorted lists of the active and of the solid cells with the
+// solid step's face coefficients (used when a big step has several solid
+// sub-steps), a second field buffer and the far-field value on the device.
+// A step is four launches: mapping, product, the fused local kernel
+// (remapping, the six reaction passes, one solid sub-step and the Eq. 7 sums,
+// tile by tile) and the Eq. 7 finish; with several solid sub-steps the fused
+// kernel stops after the reaction and the solid list and the balance kernels
+// follow.  The
+// steps alternate between the caller's field and the second buffer, and the
+// far-field cells are written once, after the last step.  Nothing returns to
+// the host between steps.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -32,23 +40,30 @@ struct Mp {
     double kappa_dt = 0.0;              // k dt / (c_L^eq c_S^eq)
     double c_eq_l = 1.0, c_eq_s = 1.0, v_ff = 1.0;
     int n_sub_solid = 1;
-    bool has_solid = false;
-    const uint8_t *label = nullptr;     // caller's labels (device)
-    SolidTable solid;
+    double solid[256];                  // D A / RT of every solid phase, 0 for the others
+    void *dsol = nullptr;               // device copy of solid
     void *coarse = nullptr;
-    MpFaceLists lists;
-    int64_t n_pass[6] = {0, 0, 0, 0, 0, 0};
-    int64_t n_faces = 0;
-    void *faces = nullptr;              // int64 entries of the six passes
+    int64_t n_faces = 0;                // interface faces (liquid / solid)
+    int64_t n_tiles = 0;
+    void *tiles = nullptr;              // int [n_tiles] tiles of the fused local kernel
+    void *pair_off = nullptr;           // int [6 n_tiles + 1] start of each tile's reaction pass
+    void *pairs = nullptr;              // uint16 interface pairs of every tile's box
+    void *label = nullptr;              // uint8 [N] copy of the labels
+    int64_t n_act = 0, n_sol = 0;
+    void *act = nullptr;                // int [n_act] active cells, ascending
+    void *sol = nullptr;                // int [n_sol] solid cells, ascending
+    void *slam = nullptr;               // double [6][n_sol] face coefficients of the solid step
+    void *snb = nullptr;                // int [6][n_sol] solid neighbours (list positions)
+    void *sa = nullptr, *sb = nullptr;  // double [n_sol] sub-step values
     void *tmp = nullptr;                // double [N]
-    void *part = nullptr;               // double [2 * MP_SUM_BLOCKS]
+    void *part = nullptr;               // double [2 * max(MP_SUM_BLOCKS, n_tiles)]
     void *cff = nullptr;                // double [1]
     void *hist = nullptr;               // double [3 * hist_cap]
     int64_t hist_cap = 0;
 
     ~Mp()
     {
-        for (void *p : {faces, tmp, part, cff, hist})
+        for (void *p : {tiles, pair_off, pairs, label, dsol, act, sol, slam, snb, sa, sb, tmp, part, cff, hist})
             if (p) (void)hipFree(p);
         if (coarse) (void)fdirw_coarse_destroy(coarse);
     }
@@ -92,6 +107,44 @@ int check_params(const fdirw_domain *d, const fdirw_mp_params *p)
     return FDIRW_OK;
 }
 
+// Sorted list of the cells of one kind (launch_mp_list_* mode) into *list
+// (allocated here; *count entries).
+int build_list(const int *node, int64_t n, int mode, hipStream_t st, void **list, int64_t *count)
+{
+    const int64_t chunks = (n + MP_CHUNK - 1) / MP_CHUNK;
+    int *cc = nullptr;
+    int64_t *off = nullptr;
+    int rc = mp_alloc((void **)&cc, (size_t)chunks * sizeof(int));
+    if (!rc) rc = mp_alloc((void **)&off, (size_t)chunks * sizeof(int64_t));
+    std::vector<int> hc((size_t)chunks);
+    std::vector<int64_t> ho((size_t)chunks);
+    hipError_t e = hipSuccess;
+    if (!rc) {
+        e = launch_mp_list_count(node, n, mode, cc, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), cc, hc.size() * sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    int64_t total = 0;
+    if (!rc && e == hipSuccess) {
+        for (int64_t k = 0; k < chunks; ++k) {
+            ho[(size_t)k] = total;
+            total += hc[(size_t)k];
+        }
+        rc = mp_alloc(list, (size_t)total * sizeof(int));
+    }
+    if (!rc && e == hipSuccess) {
+        e = hipMemcpyAsync(off, ho.data(), ho.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = launch_mp_list_write(node, n, mode, off, (int *)*list, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(cc);
+    (void)hipFree(off);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "cell list");
+    *count = total;
+    return FDIRW_OK;
+}
+
 }  // namespace
 
 }  // namespace fdirw
@@ -115,17 +168,15 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
     std::vector<double> d_liq(d->n_phase), coef(d->n_phase);
     std::vector<uint8_t> grouped(d->n_phase), reservoir(d->n_phase);
     double dsol_max = 0.0;
-    bool has_solid = false;
+    if ((int64_t)d->nx * d->ny * d->nz > 0x7fffffffLL)
+        return fail(FDIRW_E_ARG, "the integrated solver indexes cells with 32-bit integers (N < 2^31)");
     for (int i = 0; i < d->n_phase; ++i) {
         coef[i] = d->d_phase[i] * (p->a_over_rt ? p->a_over_rt[i] : 1.0);
         if (!std::isfinite(coef[i])) return fail(FDIRW_E_ARG, "D A / RT of phase %d is not finite", i);
         d_liq[i] = p->role[i] == FDIRW_ROLE_SOLID ? 0.0 : coef[i];
         grouped[i] = p->role[i] == FDIRW_ROLE_LIQUID;
         reservoir[i] = p->role[i] == FDIRW_ROLE_FAR_FIELD;
-        if (p->role[i] == FDIRW_ROLE_SOLID) {
-            has_solid = true;
-            dsol_max = std::fmax(dsol_max, coef[i]);
-        }
+        if (p->role[i] == FDIRW_ROLE_SOLID) dsol_max = std::fmax(dsol_max, coef[i]);
     }
     const double dt = (double)d->n_sub * d->dt;
     const double dts = dt / p->n_sub_solid;
@@ -147,10 +198,8 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
     h->kappa_dt = p->k / (p->c_eq_liquid * p->c_eq_solid) * dt;
     h->v_ff = p->v_far_field;
     h->n_sub_solid = p->n_sub_solid;
-    h->has_solid = has_solid;
-    h->label = d->label;
-    std::memset(&h->solid, 0, sizeof h->solid);
-    for (int i = 0; i < d->n_phase; ++i) h->solid.d[i] = p->role[i] == FDIRW_ROLE_SOLID ? coef[i] : 0.0;
+    std::memset(h->solid, 0, sizeof h->solid);
+    for (int i = 0; i < d->n_phase; ++i) h->solid[i] = p->role[i] == FDIRW_ROLE_SOLID ? coef[i] : 0.0;
     fdirw_domain dl = *d;
     dl.d_phase = d_liq.data();
     if ((rc = fdirw_coarse_create(&dl, block, prec, grouped.data(), reservoir.data(), nullptr, stream, &h->coarse,
@@ -159,55 +208,126 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
         delete h;
         return rc;
     }
-    // interface faces: count, reserve, list
+    // interface faces (counted for the caller), the tiles that hold an active
+    // cell, a copy of the labels
+    const int *node = coarse_node(h->coarse);
+    const int64_t nt = mp_tile_count(d->nx, d->ny, d->nz);
     unsigned long long *cnt = nullptr;
+    int *flag = nullptr;
     rc = mp_alloc((void **)&cnt, 6 * sizeof(unsigned long long));
+    if (!rc) rc = mp_alloc((void **)&flag, (size_t)nt * sizeof(int));
     if (!rc) rc = mp_alloc(&h->tmp, (size_t)h->n * sizeof(double));
-    if (!rc) rc = mp_alloc(&h->part, (size_t)2 * MP_SUM_BLOCKS * sizeof(double));
+    if (!rc) rc = mp_alloc(&h->label, (size_t)h->n);
+    if (!rc) rc = mp_alloc(&h->dsol, sizeof h->solid);
     if (!rc) rc = mp_alloc(&h->cff, sizeof(double));
     if (rc) {
         (void)hipFree(cnt);
+        (void)hipFree(flag);
         delete h;
         return rc;
     }
-    const int *node = coarse_node(h->coarse);
-    std::memset(&h->lists, 0, sizeof h->lists);
     unsigned long long hc[6];
+    std::vector<int> hflag((size_t)nt);
     hipError_t e = launch_fill_u32((unsigned *)cnt, 12, 0u, st);
-    if (e == hipSuccess) e = launch_mp_faces(node, d->nx, d->ny, d->nz, h->lists, nullptr, cnt, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->label, d->label, (size_t)h->n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->dsol, h->solid, sizeof h->solid, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_mp_faces(node, d->nx, d->ny, d->nz, cnt, st);
+    if (e == hipSuccess) e = launch_mp_tile_flags(node, d->nx, d->ny, d->nz, flag, st);
     if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hflag.data(), flag, hflag.size() * sizeof(int), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) {
-        int64_t off = 0;
-        for (int k = 0; k < 6; ++k) {
-            h->lists.off[k] = off;
-            h->lists.cap[k] = (int64_t)hc[k];
-            h->n_pass[k] = (int64_t)hc[k];
-            off += (int64_t)hc[k];
+    (void)hipFree(cnt);
+    (void)hipFree(flag);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "interface faces and tiles");
+    }
+    h->n_faces = 0;
+    for (int k = 0; k < 6; ++k) h->n_faces += (int64_t)hc[k];
+    std::vector<int> tl;
+    for (int64_t t = 0; t < nt; ++t)
+        if (hflag[(size_t)t]) tl.push_back((int)t);
+    h->n_tiles = (int64_t)tl.size();
+    const int64_t n_part = h->n_tiles > MP_SUM_BLOCKS ? h->n_tiles : MP_SUM_BLOCKS;
+    rc = mp_alloc(&h->tiles, tl.size() * sizeof(int));
+    if (!rc) rc = mp_alloc(&h->part, (size_t)2 * n_part * sizeof(double));
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    if (!tl.empty()) {
+        e = hipMemcpyAsync(h->tiles, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "tile list");
         }
-        h->n_faces = off;
-        if ((rc = mp_alloc(&h->faces, (size_t)off * sizeof(int64_t)))) {
-            (void)hipFree(cnt);
+    }
+    // every tile's interface pairs per reaction pass: count, scan, list
+    {
+        const size_t n6 = (size_t)6 * h->n_tiles;
+        int *pc = nullptr;
+        rc = mp_alloc((void **)&pc, n6 * sizeof(int));
+        if (!rc) rc = mp_alloc(&h->pair_off, (n6 + 1) * sizeof(int));
+        std::vector<int> hcnt(n6), hoff(n6 + 1, 0);
+        if (!rc) {
+            e = launch_mp_tile_pairs(node, d->nx, d->ny, d->nz, (const int *)h->tiles, h->n_tiles, nullptr, nullptr,
+                                     pc, st);
+            if (e == hipSuccess && n6) e = hipMemcpyAsync(hcnt.data(), pc, n6 * sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            int64_t tot = 0;
+            for (size_t k = 0; k < n6; ++k) {
+                hoff[k] = (int)tot;
+                tot += hcnt[k];
+            }
+            hoff[n6] = (int)tot;
+            if (tot > 0x7fffffffLL) rc = fail(FDIRW_E_ARG, "too many interface pairs");
+            if (!rc && e == hipSuccess) rc = mp_alloc(&h->pairs, (size_t)tot * sizeof(uint16_t));
+            if (!rc && e == hipSuccess)
+                e = hipMemcpyAsync(h->pair_off, hoff.data(), hoff.size() * sizeof(int), hipMemcpyHostToDevice, st);
+            if (!rc && e == hipSuccess)
+                e = launch_mp_tile_pairs(node, d->nx, d->ny, d->nz, (const int *)h->tiles, h->n_tiles,
+                                         (const int *)h->pair_off, (uint16_t *)h->pairs, pc, st);
+            std::vector<int> hcnt2(n6);
+            if (!rc && e == hipSuccess && n6)
+                e = hipMemcpyAsync(hcnt2.data(), pc, n6 * sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (!rc && e == hipSuccess && hcnt2 != hcnt) rc = fail(FDIRW_E_DEVICE, "interface pair count changed");
+        }
+        (void)hipFree(pc);
+        if (!rc && e != hipSuccess) rc = hip_fail(e, "interface pairs");
+        if (rc) {
             delete h;
             return rc;
         }
-        e = launch_fill_u32((unsigned *)cnt, 12, 0u, st);
-        if (e == hipSuccess)
-            e = launch_mp_faces(node, d->nx, d->ny, d->nz, h->lists, (int64_t *)h->faces, cnt, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e == hipSuccess)
-            for (int k = 0; k < 6; ++k)
-                if ((int64_t)hc[k] != h->n_pass[k]) {
-                    (void)hipFree(cnt);
-                    delete h;
-                    return fail(FDIRW_E_DEVICE, "interface face count changed between passes");
-                }
     }
-    (void)hipFree(cnt);
+    // the active and solid lists, and the solid step's coefficients
+    if ((rc = build_list(node, h->n, 0, st, &h->act, &h->n_act)) ||
+        (rc = build_list(node, h->n, 1, st, &h->sol, &h->n_sol))) {
+        delete h;
+        return rc;
+    }
+    int *inv = nullptr;
+    rc = mp_alloc((void **)&inv, (size_t)h->n * sizeof(int));
+    if (!rc) rc = mp_alloc(&h->slam, (size_t)6 * h->n_sol * sizeof(double));
+    if (!rc) rc = mp_alloc(&h->snb, (size_t)6 * h->n_sol * sizeof(int));
+    if (!rc) rc = mp_alloc(&h->sa, (size_t)h->n_sol * sizeof(double));
+    if (!rc) rc = mp_alloc(&h->sb, (size_t)h->n_sol * sizeof(double));
+    if (rc) {
+        (void)hipFree(inv);
+        delete h;
+        return rc;
+    }
+    e = launch_fill_u32((unsigned *)inv, h->n, 0xffffffffu, st);
+    if (e == hipSuccess)
+        e = launch_mp_solid_prep((const int *)h->sol, h->n_sol, d->label, (const double *)h->dsol, inv, d->nx, d->ny,
+                                 d->nz, dts,
+                                 d->h, (double *)h->slam, (int *)h->snb, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(inv);
     if (e != hipSuccess) {
         delete h;
-        return hip_fail(e, "interface faces");
+        return hip_fail(e, "solid coefficients");
     }
     if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *handle = h;
@@ -239,29 +359,50 @@ int fdirw_mp_step(void *handle, double *c, double *c_ff, double m_total, int32_t
     if (e != hipSuccess) return hip_fail(e, "integrated step set-up");
     const int *node = coarse_node(h->coarse);
     double *tmp = (double *)h->tmp;
-    const int64_t stride[3] = {1, h->nx, (int64_t)h->nx * h->ny};
+    MpLocalArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.nx = h->nx; a.ny = h->ny; a.nz = h->nz;
+    a.tiles = (const int *)h->tiles;
+    a.n_tiles = h->n_tiles;
+    a.pair_off = (const int *)h->pair_off;
+    a.pairs = (const uint16_t *)h->pairs;
+    a.node = node;
+    a.label = (const uint8_t *)h->label;
+    a.dsol = (const double *)h->dsol;
+    a.c_eq_l = h->c_eq_l; a.c_eq_s = h->c_eq_s; a.kappa_dt = h->kappa_dt;
+    a.solid = h->n_sub_solid == 1 && h->n_tiles > 0;
+    a.dt_s = h->dt / h->n_sub_solid;
+    a.h = h->h;
+    a.part = (double *)h->part;
+    a.m_total = m_total;
+    a.v_ff = h->v_ff;
+    a.cff = (double *)h->cff;
     for (int s = 0; s < n_steps; ++s) {
-        // 1. fast diffusion of the near-field liquid: c -> tmp
-        if ((rc = coarse_fast_step(h->coarse, c, tmp, (const double *)h->cff, st))) return rc;
-        // 2. absorption at the interface, in place on tmp
-        for (int k = 0; k < 6 && e == hipSuccess; ++k)
-            e = launch_mp_react((const int64_t *)h->faces + h->lists.off[k], h->n_pass[k], stride[k / 2], tmp,
-                                h->c_eq_l, h->c_eq_s, h->kappa_dt, st);
-        // 3. slow diffusion in the solid, ping-pong between tmp and c
-        double *cur = tmp, *nxt = c;
-        if (h->has_solid)
-            for (int k = 0; k < h->n_sub_solid && e == hipSuccess; ++k) {
-                e = launch_mp_solid(h->label, h->solid, h->nx, h->ny, h->nz, h->dt / h->n_sub_solid, h->h, cur, nxt,
-                                    st);
-                double *t = cur; cur = nxt; nxt = t;
-            }
-        // 4. Eq. 7 and the far-field cells; the result ends in c
-        if (e == hipSuccess)
-            e = launch_mp_balance(node, cur, h->n, (double *)h->part, m_total, h->v_ff, (double *)h->cff,
-                                  (double *)h->hist + 3 * (int64_t)s, st);
-        if (e == hipSuccess) e = launch_mp_far_fill(node, h->n, (const double *)h->cff, cur, c, st);
+        double *in = (s % 2 == 0) ? c : tmp, *out = (s % 2 == 0) ? tmp : c;
+        double *row = (double *)h->hist + 3 * (int64_t)s;
+        // 1. fast diffusion of the near-field liquid: mapping and product
+        if ((rc = coarse_map_apply(h->coarse, in, (const double *)h->cff, st, &a.cnew))) return rc;
+        // remapping, the reaction passes and (one sub-step) the solid step
+        // and Eq. 7, tile by tile
+        a.c_in = in;
+        a.out = out;
+        a.hist_row = row;
+        e = launch_mp_local(a, st);
+        if (e == hipSuccess && !a.solid) {
+            // several solid sub-steps on the solid list (or no active tile),
+            // then Eq. 7
+            e = launch_mp_solid((const int *)h->sol, h->n_sol, (const double *)h->slam, (const int *)h->snb, h->nx,
+                                h->ny, h->n_sub_solid, out, (double *)h->sa, (double *)h->sb, st);
+            if (e == hipSuccess)
+                e = launch_mp_balance((const int *)h->act, h->n_act, node, out, (double *)h->part, m_total,
+                                      h->v_ff, (double *)h->cff, row, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "integrated step launch");
     }
+    // the far-field cells take c_ff; after an odd count the field is in tmp
+    if (n_steps > 0 && (e = launch_mp_far_fill(node, h->n, (const double *)h->cff, n_steps % 2 ? tmp : c, c, st)) !=
+                           hipSuccess)
+        return hip_fail(e, "far-field fill");
     if (stats && (e = hipEventRecord(ev.b, st)) != hipSuccess) return hip_fail(e, "event record");
     double cff = *c_ff;
     e = hipMemcpyAsync(&cff, h->cff, sizeof(double), hipMemcpyDeviceToHost, st);

@@ -13,7 +13,10 @@ disabled, so every kernel is the network's) instead of the FD kernels.  With
 kernel once in a bank of the precision ``--prec`` (fp32, fp16_bank, ...) and
 applies it for one big step.  With ``--coarse B`` the coarse-mesh operator
 over B^3 blocks is built once (P stored in ``--prec``) and each repetition is
-one coarse step.  With ``--flow U`` each repetition generates the window
+one coarse step.  With ``--mp K`` the integrated near-field solver of the
+particle case (porous particle of radius 50 n / 192, Table 1 values, coarse
+blocks of 5, P in ``--prec``) is built once and each repetition runs K big
+steps.  With ``--flow U`` each repetition generates the window
 kernels of a 64^3-cell sample of sources with a seeded steady flow of
 magnitude up to U (fdirw_kernels_flow, precision ``--prec``).
 """
@@ -38,6 +41,7 @@ def main():
     ap.add_argument("--bank", type=int, default=0)
     ap.add_argument("--coarse", type=int, default=0)
     ap.add_argument("--flow", type=float, default=0.0)
+    ap.add_argument("--mp", type=int, default=0)
     args = ap.parse_args()
     import torch
     import synth
@@ -62,6 +66,24 @@ def main():
             ms = ev0.elapsed_time(ev1)
             print(f"[profile_step] n={args.n} flow {args.flow} prec={args.prec} rep {i}: {src.numel()} kernels in "
                   f"{ms:.1f} ms", flush=True)
+        args.reps = 0
+        args.warmup = 0
+    if args.mp:
+        import numpy as np
+        dp, t = synth.particle_case(args.n, 50.0 * args.n / 192.0)
+        far = dp.label == synth.PHASE_FAR_LIQUID
+        m_total = float(dp.c0[~far].sum()) + t["V_ff_cells"] * t["c0_L"]
+        s = fd.Multiphysics(fd.Domain.from_synth(dp), [fd.ROLE_LIQUID, fd.ROLE_SOLID, fd.ROLE_FAR_FIELD], t["k"],
+                            t["c_eq_L"], t["c_eq_S"], t["V_ff_cells"],
+                            a_over_rt=np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]]), block=5, prec=args.prec)
+        print(f"[profile_step] n={args.n} integrated prec={args.prec}: {s.n_nodes} nodes, {s.n_faces} faces, "
+              f"build {s.build_seconds:.2f} s", flush=True)
+        cp = torch.from_numpy(dp.c0).cuda()
+        for i in range(args.reps):
+            cff, hist, st = s.step(cp, t["c0_L"], m_total, args.mp, stats=True)
+            print(f"[profile_step] integrated rep {i}: {args.mp} big steps, "
+                  f"{st['kernel_seconds'] * 1e3 / args.mp:.4f} ms / step, Q_S {hist[-1, 1]:.4g}", flush=True)
+        s.close()
         args.reps = 0
         args.warmup = 0
     if args.coarse:
