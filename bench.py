@@ -301,19 +301,17 @@ def coarse_leg(fd, d, dom, c0, c1, args):
     return out
 
 
-def mp_bytes_per_step(n_cells, n_far, n_faces, n_nodes, K, p_bytes, n_sub_solid):
-    """Algorithmic HBM bytes of one integrated big step: every grid-wide pass
-    reads (and writes) each cell once; far-field cells are only rewritten."""
+def mp_bytes_per_step(n_liq, n_sol, n_used_nodes, K, p_bytes):
+    """Algorithmic HBM bytes of one integrated big step, which touches the
+    active cells only: the mapping reads value and node index of every
+    near-field liquid cell; the product reads P and C of the nodes that hold
+    cells and writes C'; the fused local kernel reads node index and value (and
+    the label of a solid cell) of every active cell and writes its value.  The
+    far-field cells are written once per call, not per step."""
     kw3 = (2 * K + 1) ** 3
-    b = 12 * n_cells                      # mapping: c, node
-    b += kw3 * n_nodes * p_bytes + 16 * n_nodes   # product: P, C, C'
-    b += 20 * n_cells                     # remapping: node, c_in, c_out
-    b += 8 * n_faces + 32 * n_faces       # reaction: face entry, two cells read + written
-    b += 17 * n_cells * n_sub_solid       # solid: label, c in, c out
-    b += 12 * n_cells                     # balance: node, c
-    b += 4 * n_cells + 8 * n_far          # far field: node, far cells written
-    if n_sub_solid % 2 == 0:
-        b += 16 * (n_cells - n_far)       # result back into c
+    b = 12 * n_liq
+    b += n_used_nodes * (kw3 * p_bytes + 16)
+    b += 20 * (n_liq + n_sol) + n_sol
     return b
 
 
@@ -356,12 +354,16 @@ def mp_leg(fd, args):
         ms = ev0.elapsed_time(ev1) / args.mp_steps
         resid = float(np.max(np.abs(hist[:, 0] + hist[:, 1] + v_ff * hist[:, 2] - m_total))) / m_total
         pb = 4 if prec == "fp32" else 2
-        byts = mp_bytes_per_step(d.n, int(far.sum()), s.n_faces, s.n_nodes, s.K, pb, 1)
+        liq = d.label == synth.PHASE_NEAR_LIQUID
+        blk = (np.arange(n) // 5)
+        used = np.unique(((blk[:, None, None] * 1000 + blk[None, :, None]) * 1000 + blk[None, None, :])[liq]).size
+        byts = mp_bytes_per_step(int(liq.sum()), int((d.label == synth.PHASE_SOLID).sum()), used, s.K, pb)
         rec = {"build_seconds": s.build_seconds, "ms_per_step": ms, "kernel_ms_per_step": 1e3 * st["kernel_seconds"] / args.mp_steps,
                "nodes": s.n_nodes, "interface_faces": s.n_faces, "balance_rel_residual": resid,
                "solid_uptake_Q_S": [float(hist[0, 1]), float(hist[-1, 1])], "c_ff_end": cff,
-               "hbm_bytes_per_step": byts, "hbm_GBps": byts / (ms * 1e-3) / 1e9,
+               "nodes_with_cells": used, "hbm_bytes_per_step": byts, "hbm_GBps": byts / (ms * 1e-3) / 1e9,
                "hbm_frac": byts / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+               "bound": "launch and memory latency (4 dependent launches per step)",
                "seconds_per_physical_0p5s": ms * 1e-3 * 0.5 / (d.n_sub * d.dt)}
         out[prec] = rec
         s.close()
