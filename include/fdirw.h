@@ -47,6 +47,8 @@ extern "C" {
 
 #define FDIRW_ABI_VERSION 1
 #define FDIRW_MAX_RADIUS 8   /* largest window radius r supported (W = 17) */
+#define FDIRW_MAX_COARSE_RADIUS 128   /* largest r of the coarse operator (node windows beyond 8) */
+#define FDIRW_MAX_COARSE_K 8          /* ... with ceil(r / block) at most this */
 #define FDIRW_MAX_PHASES 256
 
 typedef enum fdirw_status {
@@ -286,6 +288,15 @@ int fdirw_nn_load(void *nn, const char *path);
  * offset-major in the precision `prec`; the product and its sum are FP64.
  * With block = 1 and the default grouping the step is the fine step with
  * renormalised kernels.
+ * Node windows: for d->r above FDIRW_MAX_RADIUS (up to
+ * FDIRW_MAX_COARSE_RADIUS, with K = ceil(r / block) <= FDIRW_MAX_COARSE_K)
+ * the column of group J is instead one FD of unit mass on every grouped cell
+ * of J, on the window made of J's block and the K blocks around it (clipped
+ * at the domain, walls at its faces), scaled to N_J over the grouped cells
+ * (not scaled with a far field): by linearity the sum of the point-source
+ * kernels of J's cells on that shared window; with block = 1 it is the
+ * point-source window of radius r.  Its state lives in HBM (batches of
+ * nodes, one launch per sub-step).
  * Far field (Eqs. 7, 8, 10, 14): cells of the reservoir phases are the
  * far-field boundary, Dirichlet cells holding the uniform far-field
  * concentration c_ff.  Their handle builds P from kernels in which those cells
@@ -302,11 +313,13 @@ int fdirw_nn_load(void *nn, const char *path);
  * phase with D > 0.  reservoir (host, may be NULL): d->n_phase flags, nonzero
  * for the far-field boundary phases (never grouped).  velocity (may be NULL):
  * a steady flow as in fdirw_kernels_flow; P and P_BC then include it (the
- * kernels are the flow kernels, generated in chunks of sources).  block: 1..256.  d->label is read only here.  *handle
+ * kernels are the flow kernels, generated in chunks of sources; r <= 8 only).  block: 1..256.  d->label is read
+ * only here.  *handle
  * receives a handle owning device memory of about 4 N + (2K+1)^3 x N_nodes x
  * element bytes; seconds (host, may be NULL) receives the build time.
  * Synchronises the stream.  The handle belongs to the current device.
- * Errors: E_ARG (also a block outside 1..256 or another precision),
+ * Errors: E_ARG (also a block outside 1..256, another precision or K above
+ * FDIRW_MAX_COARSE_K), E_UNSUPPORTED (a flow with r above FDIRW_MAX_RADIUS),
  * E_UNSTABLE, E_NOMEM, E_DEVICE. */
 int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped,
                         const uint8_t *reservoir, const double *velocity, void *stream, void **handle,

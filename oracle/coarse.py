@@ -28,6 +28,12 @@ Step (Eqs. 13-15):
     remapping   c'(i) = C'_I for every cell i of group I; c'(i) = c(i)  (Eq. 15)
                 for the cells outside every group
 
+Node windows (radius r > 8).  The per-source windows stop at r = 8; beyond
+it the column of group J is the FD of unit mass on all of J's grouped cells at
+once, on the window made of J's block and K = ceil(r / B) blocks around it
+(coarse_matrix_node_windows).  With B = 1 that is the per-source window of
+radius r.
+
 Without a far field the term P_BC c_far-field of Eq. 14 is zero (no-flux
 domain walls, as in the fine step).  With B = 1 every group is one cell and the
 step is the fine step with renormalised kernels.
@@ -49,6 +55,8 @@ concentration c_ff.  Then
 from __future__ import annotations
 
 import numpy as np
+
+from . import Problem
 
 
 def coarse_dims(shape, B: int):
@@ -79,8 +87,67 @@ def reservoir_mask(label, reservoir):
     return np.asarray(reservoir, dtype=bool)[np.asarray(label)]
 
 
+# Largest window radius of the per-source kernels; beyond it P comes from node
+# windows (coarse_matrix_node_windows).
+MAX_SOURCE_WINDOW_RADIUS = 8
+
+
 def coarse_matrix(problem, B: int, grouped=None, reservoir=None) -> np.ndarray:
-    """Dense P [n_nodes, n_nodes] (rows = destination I, columns = source J)."""
+    """Dense P [n_nodes, n_nodes] (rows = destination I, columns = source J):
+    from the per-source window kernels for r <= 8, from node windows beyond."""
+    if problem.r > MAX_SOURCE_WINDOW_RADIUS:
+        return coarse_matrix_node_windows(problem, B, grouped, reservoir)
+    return coarse_matrix_source_windows(problem, B, grouped, reservoir)
+
+
+def coarse_matrix_node_windows(problem, B: int, grouped=None, reservoir=None) -> np.ndarray:
+    """P from node windows: the column of group J is one whole-window FD of
+    unit mass on every grouped cell of J, on the window made of J's block and
+    the K = ceil(r / B) blocks around it on every side (clipped at the domain;
+    its faces are walls), binned over the groups it reaches.  Without a far
+    field the column is scaled to N_J over the grouped cells (the sum of N_J
+    unit kernels renormalised over the grouped cells); with one, the far-field
+    cells absorb (held at 0) and nothing is rescaled.  By linearity the column
+    is the sum of the point-source kernels of J's cells on that shared window."""
+    label = problem.label
+    block, mobile, count = groups(label, problem.d_phase, B, grouped, reservoir)
+    S = np.zeros((count.size, count.size))
+    for J in np.flatnonzero(count > 0):
+        S[:, J] = node_window_column(problem, B, int(J), grouped, reservoir)
+    P = np.zeros_like(S)
+    has = count > 0
+    P[has] = S[has] / count[has, None]
+    return P
+
+
+def node_window_column(problem, B: int, J: int, grouped=None, reservoir=None) -> np.ndarray:
+    """Column J of S (before the division by N_I) from the node window of
+    group J: dense over the n_nodes destinations."""
+    label = problem.label
+    block, mobile, count = groups(label, problem.d_phase, B, grouped, reservoir)
+    nz, ny, nx = label.shape
+    ncz, ncy, ncx = coarse_dims(label.shape, B)
+    K = -(-problem.r // B)
+    fixed = None if reservoir is None else reservoir_mask(label, reservoir)
+    bz, rem = divmod(int(J), ncy * ncx)
+    by, bx = divmod(rem, ncx)
+    win = (slice(max(0, (bz - K) * B), min(nz, (bz + K + 1) * B)),
+           slice(max(0, (by - K) * B), min(ny, (by + K + 1) * B)),
+           slice(max(0, (bx - K) * B), min(nx, (bx + K + 1) * B)))
+    sub = Problem(label[win], problem.d_phase, 0, problem.n_sub, problem.h, problem.dt)
+    keep = mobile[win]
+    c = ((block[win] == J) & keep).astype(np.float64)
+    G = sub.global_fd(c, fixed=None if fixed is None else fixed[win], fval=0.0)
+    g = G[keep]
+    if fixed is None:
+        g = g * (count[J] / g.sum())
+    col = np.zeros(count.size)
+    np.add.at(col, block[win][keep], g)
+    return col
+
+
+def coarse_matrix_source_windows(problem, B: int, grouped=None, reservoir=None) -> np.ndarray:
+    """P from the per-source window kernels of every grouped cell."""
     label = problem.label
     block, mobile, count = groups(label, problem.d_phase, B, grouped, reservoir)
     n_nodes = count.size

@@ -93,7 +93,7 @@ static void release_all()
 
 // ----------------------------------------------------------------- validation
 
-int check_domain(const fdirw_domain *d)
+int check_domain(const fdirw_domain *d, int max_r)
 {
     if (!d) return fail(FDIRW_E_ARG, "domain is null");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1)
@@ -108,8 +108,7 @@ int check_domain(const fdirw_domain *d)
     for (int i = 0; i < d->n_phase; ++i)
         if (!std::isfinite(d->d_phase[i]) || d->d_phase[i] < 0.0)
             return fail(FDIRW_E_ARG, "d_phase[%d] = %g must be finite and >= 0", i, d->d_phase[i]);
-    if (d->r < 0 || d->r > FDIRW_MAX_RADIUS)
-        return fail(FDIRW_E_ARG, "r = %d outside 0..%d", d->r, FDIRW_MAX_RADIUS);
+    if (d->r < 0 || d->r > max_r) return fail(FDIRW_E_ARG, "r = %d outside 0..%d", d->r, max_r);
     if (d->n_sub < 0) return fail(FDIRW_E_ARG, "n_sub = %d must be >= 0", d->n_sub);
     if (!std::isfinite(d->dt)) return fail(FDIRW_E_ARG, "dt must be finite");
     return FDIRW_OK;

@@ -200,6 +200,120 @@ __global__ void __launch_bounds__(BIN_NT) coarse_bin_kernel(CoarseGenArgs a, con
     }
 }
 
+// Node windows (window radius beyond the per-source kernels).  The column of
+// group J is one FD of unit mass on every grouped cell of J, on the window of
+// wb = (2K+1) B cells per axis made of J's block and the K blocks around it
+// (clipped at the domain; faces leaving it are walls), for a batch of nodes at
+// a time: state [batch][wb^3] in HBM, one launch per sub-step.
+template <typename St>
+__global__ void nodewin_init_kernel(NodeWinArgs a, St *__restrict__ g)
+{
+    const int64_t wb3 = (int64_t)a.wb * a.wb * a.wb;
+    const int64_t total = wb3 * a.n_batch;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int jb = (int)(t / wb3);
+        const int64_t q = t - jb * wb3;
+        const int J = a.batch[jb];
+        const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
+        const int X = (bx - a.K) * a.B + (int)(q % a.wb), Y = (by - a.K) * a.B + (int)((q / a.wb) % a.wb);
+        const int Z = (bz - a.K) * a.B + (int)(q / ((int64_t)a.wb * a.wb));
+        const bool in = X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz;
+        g[t] = (in && a.node[((int64_t)Z * a.ny + Y) * a.nx + X] == J) ? St(1) : St(0);
+    }
+}
+
+// One explicit sub-step of every window of the batch: terms in the order -x,
+// +x, -y, +y, -z, +z over faces inside both the window and the domain
+// (coefficients of the domain's owned faces); cells outside the domain stay
+// 0, and far-field cells are held at 0 when a.sink (they absorb).
+template <typename St>
+__global__ void nodewin_substep_kernel(NodeWinArgs a, const St *__restrict__ in, St *__restrict__ out)
+{
+    const int wb = a.wb;
+    const int64_t wb2 = (int64_t)wb * wb, wb3 = wb2 * wb;
+    const int64_t total = wb3 * a.n_batch;
+    const St *lx = (const St *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
+    const int64_t sy = a.nx, sz = (int64_t)a.nx * a.ny;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int jb = (int)(t / wb3);
+        const int64_t q = t - jb * wb3;
+        const int J = a.batch[jb];
+        const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
+        const int qx = (int)(q % wb), qy = (int)((q / wb) % wb), qz = (int)(q / wb2);
+        const int X = (bx - a.K) * a.B + qx, Y = (by - a.K) * a.B + qy, Z = (bz - a.K) * a.B + qz;
+        if (!(X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz)) {
+            out[t] = St(0);
+            continue;
+        }
+        const int64_t i = Z * sz + Y * sy + X;
+        if (a.sink && a.node[i] == COARSE_RESERVOIR) {
+            out[t] = St(0);
+            continue;
+        }
+        const St gv = in[t];
+        St acc = gv;
+        if (qx > 0 && X > 0) acc += lx[i - 1] * (in[t - 1] - gv);
+        if (qx < wb - 1 && X < a.nx - 1) acc += lx[i] * (in[t + 1] - gv);
+        if (qy > 0 && Y > 0) acc += ly[i - sy] * (in[t - wb] - gv);
+        if (qy < wb - 1 && Y < a.ny - 1) acc += ly[i] * (in[t + wb] - gv);
+        if (qz > 0 && Z > 0) acc += lz[i - sz] * (in[t - wb2] - gv);
+        if (qz < wb - 1 && Z < a.nz - 1) acc += lz[i] * (in[t + wb2] - gv);
+        out[t] = acc;
+    }
+}
+
+// Binning of the batch's windows, one workgroup per node J: wave w sums the
+// grouped cells of destination block o = w, w + waves, ... (lanes over the
+// block's cells in z, y, x order, a fixed butterfly), the bins are added in
+// offset order for the scale (N_J over their total without a far field, 1
+// with one), and S[o][I] = bin, I = J + o - K: one writer per entry.
+constexpr int NODEWIN_BIN_NT = 256;
+
+template <typename St>
+__global__ void __launch_bounds__(NODEWIN_BIN_NT) nodewin_bin_kernel(NodeWinArgs a, const St *__restrict__ g,
+                                                                    const double *__restrict__ count,
+                                                                    double *__restrict__ S)
+{
+    __shared__ double bins[17 * 17 * 17];
+    __shared__ double scale;
+    const int jb = blockIdx.x;
+    const int J = a.batch[jb];
+    const int KW = 2 * a.K + 1, nb = KW * KW * KW, B = a.B, wb = a.wb;
+    const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
+    const St *gw = g + (int64_t)jb * wb * wb * wb;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nwave = NODEWIN_BIN_NT / 64;
+    for (int o = w; o < nb; o += nwave) {
+        const int ox = o % KW, oy = (o / KW) % KW, oz = o / (KW * KW);
+        double sum = 0.0;
+        for (int c = lane; c < B * B * B; c += 64) {
+            const int cx = c % B, cy = (c / B) % B, cz = c / (B * B);
+            const int X = (bx - a.K + ox) * B + cx, Y = (by - a.K + oy) * B + cy, Z = (bz - a.K + oz) * B + cz;
+            if (X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz &&
+                a.node[((int64_t)Z * a.ny + Y) * a.nx + X] >= 0)
+                sum += (double)gw[((int64_t)(oz * B + cz) * wb + (oy * B + cy)) * wb + (ox * B + cx)];
+        }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) sum += __shfl_xor(sum, m, 64);
+        if (lane == 0) bins[o] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int o = 0; o < nb; ++o) tot += bins[o];
+        scale = a.sink ? 1.0 : (tot > 0.0 ? count[J] / tot : 0.0);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < nb; o += NODEWIN_BIN_NT) {
+        const int ox = o % KW, oy = (o / KW) % KW, oz = o / (KW * KW);
+        const int Ix = bx + ox - a.K, Iy = by + oy - a.K, Iz = bz + oz - a.K;
+        if (Ix < 0 || Ix >= a.ncx || Iy < 0 || Iy >= a.ncy || Iz < 0 || Iz >= a.ncz) continue;
+        const int64_t I = ((int64_t)Iz * a.ncy + Iy) * a.ncx + Ix;
+        S[(int64_t)o * a.n_nodes + I] = bins[o] * scale;
+    }
+}
+
 // P[o][I] = S[o][I] / N_I in the bank layout of element type B: per offset
 // plane the coarse cells are ordered [z / zb][y][x][z % zb].
 template <typename B>
@@ -515,6 +629,42 @@ hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int 
     }
     *result = in;
     return e;
+}
+
+hipError_t launch_nodewin(int fp64, const NodeWinArgs &a, int n_sub, void *ga, void *gb, const double *count,
+                          double *S, hipStream_t st)
+{
+    if (a.n_batch <= 0) return hipSuccess;
+    if (2 * a.K + 1 > 17) return hipErrorInvalidValue;
+    const int64_t total = (int64_t)a.wb * a.wb * a.wb * a.n_batch;
+    const unsigned g = grid_for(total);
+    hipError_t e;
+    if (fp64) {
+        double *in = (double *)ga, *out = (double *)gb;
+        hipLaunchKernelGGL(nodewin_init_kernel<double>, dim3(g), dim3(256), 0, st, a, in);
+        e = hipGetLastError();
+        for (int k = 0; k < n_sub && e == hipSuccess; ++k) {
+            hipLaunchKernelGGL(nodewin_substep_kernel<double>, dim3(g), dim3(256), 0, st, a, (const double *)in, out);
+            e = hipGetLastError();
+            double *t = in; in = out; out = t;
+        }
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(nodewin_bin_kernel<double>, dim3((unsigned)a.n_batch), dim3(NODEWIN_BIN_NT), 0, st, a,
+                               (const double *)in, count, S);
+    } else {
+        float *in = (float *)ga, *out = (float *)gb;
+        hipLaunchKernelGGL(nodewin_init_kernel<float>, dim3(g), dim3(256), 0, st, a, in);
+        e = hipGetLastError();
+        for (int k = 0; k < n_sub && e == hipSuccess; ++k) {
+            hipLaunchKernelGGL(nodewin_substep_kernel<float>, dim3(g), dim3(256), 0, st, a, (const float *)in, out);
+            e = hipGetLastError();
+            float *t = in; in = out; out = t;
+        }
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(nodewin_bin_kernel<float>, dim3((unsigned)a.n_batch), dim3(NODEWIN_BIN_NT), 0, st, a,
+                               (const float *)in, count, S);
+    }
+    return e == hipSuccess ? hipGetLastError() : e;
 }
 
 hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st)

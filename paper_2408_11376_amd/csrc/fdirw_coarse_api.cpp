@@ -94,9 +94,14 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
 {
     if (!handle) return fail(FDIRW_E_ARG, "handle is null");
     *handle = nullptr;
-    int rc = check_domain(d);
+    int rc = check_domain(d, FDIRW_MAX_COARSE_RADIUS);
     if (rc) return rc;
     if (block < 1 || block > 256) return fail(FDIRW_E_ARG, "block = %d outside 1..256", block);
+    const bool node_windows = d->r > FDIRW_MAX_RADIUS;
+    if (node_windows && (d->r + block - 1) / block > FDIRW_MAX_COARSE_K)
+        return fail(FDIRW_E_ARG, "r = %d needs ceil(r / block) <= %d (block = %d)", d->r, FDIRW_MAX_COARSE_K, block);
+    if (node_windows && velocity)
+        return fail(FDIRW_E_UNSUPPORTED, "steady flow needs r <= %d (per-source kernels)", FDIRW_MAX_RADIUS);
     if (prec != FDIRW_FP64 && prec != FDIRW_FP32 && prec != FDIRW_FP16_BANK && prec != FDIRW_BF16_BANK)
         return fail(FDIRW_E_ARG, "coarse P precision must be FP64, FP32, FP16_BANK or BF16_BANK (got %d)", prec);
     const auto t0 = std::chrono::steady_clock::now();
@@ -170,6 +175,48 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             int64_t used = 0;
             for (double v : hc) used += v > 0.0;
             h->dense = 2 * used >= h->n_nodes;
+            if (node_windows && e == hipSuccess) {
+                // node windows: the nodes with cells in batches of at most
+                // ~2 GB of window state
+                std::vector<int> ids;
+                for (int64_t I = 0; I < h->n_nodes; ++I)
+                    if (hc[(size_t)I] > 0.0) ids.push_back((int)I);
+                const int K = h->K, wb = (2 * K + 1) * block;
+                const size_t esz = prec == FDIRW_FP64 ? 8 : 4;
+                const size_t per = (size_t)wb * wb * wb * esz * 2;
+                int64_t nbat = (int64_t)(((size_t)2 << 30) / per);
+                if (nbat < 1) nbat = 1;
+                if (nbat > (int64_t)ids.size()) nbat = (int64_t)ids.size();
+                int *dids = nullptr;
+                void *ga = nullptr, *gb = nullptr;
+                rc = coarse_alloc((void **)&dids, ids.size() * sizeof(int));
+                if (!rc) rc = coarse_alloc(&ga, (size_t)nbat * wb * wb * wb * esz);
+                if (!rc) rc = coarse_alloc(&gb, (size_t)nbat * wb * wb * wb * esz);
+                if (!rc && !ids.empty())
+                    e = hipMemcpyAsync(dids, ids.data(), ids.size() * sizeof(int), hipMemcpyHostToDevice, st);
+                NodeWinArgs w;
+                w.nx = d->nx; w.ny = d->ny; w.nz = d->nz; w.n = h->n;
+                w.B = block; w.K = K; w.ncx = h->ncx; w.ncy = h->ncy; w.ncz = h->ncz;
+                w.n_nodes = h->n_nodes;
+                w.lx = lam;
+                w.node = (const int *)h->node;
+                w.wb = wb;
+                w.sink = h->far_field ? 1 : 0;
+                for (int64_t b0 = 0; !rc && e == hipSuccess && b0 < (int64_t)ids.size(); b0 += nbat) {
+                    w.batch = dids + b0;
+                    w.n_batch = (int)(b0 + nbat <= (int64_t)ids.size() ? nbat : (int64_t)ids.size() - b0);
+                    e = launch_nodewin(prec == FDIRW_FP64, w, d->n_sub, ga, gb, (const double *)h->count, S, st);
+                }
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(dids);
+                (void)hipFree(ga);
+                (void)hipFree(gb);
+                if (rc) {
+                    (void)hipFree(S);
+                    delete h;
+                    return rc;
+                }
+            }
         }
         if (e == hipSuccess) {
             CoarseGenArgs a;
@@ -181,7 +228,9 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             a.ncx = h->ncx; a.ncy = h->ncy;
             a.n_nodes = h->n_nodes;
             a.S = S;
-            if (!velocity) {
+            if (node_windows) {
+                // built above
+            } else if (!velocity) {
                 e = launch_coarse_window(prec == FDIRW_FP64, h->far_field, d->r, a, st);
             } else {
                 // flow kernels, generated in chunks of sources into a scratch

@@ -58,7 +58,7 @@ int ensure(Buf &b, size_t bytes);
 DevCache &cache_for_current_device();
 std::mutex &cache_mutex();
 
-int check_domain(const fdirw_domain *d);
+int check_domain(const fdirw_domain *d, int max_r = FDIRW_MAX_RADIUS);
 int check_opts(const fdirw_opts *o);
 int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double *lam64, float *lam32, Geometry *g);
 int coef_buffers(const fdirw_domain *d, int prec, hipStream_t st, DevCache &dc, Geometry *g, const void **lam);

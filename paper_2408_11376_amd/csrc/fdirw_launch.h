@@ -126,6 +126,23 @@ hipError_t launch_bank_gather(int prec, int r, const BankArgs &a, hipStream_t st
 hipError_t launch_coarse_nodes(const uint8_t *label, const CoarseTable &tab, int nx, int ny, int nz, int B,
                                int ncx, int ncy, int *node, double *count, hipStream_t st);
 hipError_t launch_coarse_window(int fp64, int sink, int r, const CoarseGenArgs &a, hipStream_t st);
+// Node windows of the coarse build (radius beyond the per-source kernels).
+struct NodeWinArgs {
+    int nx, ny, nz;
+    int64_t n;                // cells
+    int B, K, ncx, ncy, ncz;
+    int64_t n_nodes;
+    const void *lx;           // owned face coefficients [3][N], FP64 (fp64) or FP32
+    const int *node;
+    const int *batch;         // node ids of this batch
+    int n_batch;
+    int wb;                   // window edge (2K + 1) B
+    int sink;                 // far-field cells absorb
+};
+// S [(2K+1)^3][n_nodes] entries of the batch's nodes are written (not added);
+// ga, gb: n_batch * wb^3 elements each; 2K + 1 <= 17
+hipError_t launch_nodewin(int fp64, const NodeWinArgs &a, int n_sub, void *ga, void *gb, const double *count,
+                          double *S, hipStream_t st);
 hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int nx, int ny, int nz, int n_sub,
                                 const double *u, double cour, double *a, double *b, double **result, hipStream_t st);
 hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st);

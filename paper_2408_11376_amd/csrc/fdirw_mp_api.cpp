@@ -158,7 +158,7 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
 {
     if (!handle) return fail(FDIRW_E_ARG, "handle is null");
     *handle = nullptr;
-    int rc = check_domain(d);
+    int rc = check_domain(d, FDIRW_MAX_COARSE_RADIUS);
     if (rc) return rc;
     if ((rc = check_params(d, p))) return rc;
     const auto t0 = std::chrono::steady_clock::now();

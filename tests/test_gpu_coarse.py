@@ -239,3 +239,75 @@ def test_far_field_errors():
         cn.step_far_field(c, 0.1, 1.0, 1.0)          # no far field on this handle
     cf.close()
     cn.close()
+
+
+@pytest.mark.parametrize("B,r,far,prec,tol", [(2, 9, False, fd.FP64, 1e-13), (3, 11, True, fd.FP64, 1e-13),
+                                             (2, 16, False, fd.FP64, 1e-13), (2, 12, True, fd.FP32, 1e-6)])
+def test_node_windows_match_oracle(B, r, far, prec, tol):
+    # radius above the per-source kernels: P from node windows (FD of a whole
+    # group on its block and the K blocks around it)
+    d = synth.random_small((13, 9, 26), 3, r=r, n_sub=10, seed=60 + r)
+    label = d.label.copy()
+    dph = np.array(list(d.d_phase) + [1.0])
+    res = None
+    if far:
+        label[:, :, -1] = len(dph) - 1
+        res = [0] * (len(dph) - 1) + [1]
+    p = oracle.Problem(label, dph, r, 10, d.h, 0.1)
+    P = coarse.coarse_matrix(p, B, reservoir=res)
+    cg = fd.Coarse(fd.Domain(label, dph, r, 10, d.h, 0.1), B, prec, reservoir=res)
+    assert np.max(np.abs(cg.matrix() - _offset_form(P, cg.coarse_shape, cg.K))) <= tol
+    if far:
+        fixed = coarse.reservoir_mask(label, res)
+        c = np.where(fixed, 0.3, d.c0)
+        m_total = c[~fixed].sum() + 0.3 * 50.0
+        want, cff_w = coarse.step_far_field(p, P, coarse.p_bc(p, B, reservoir=res), c, 0.3, m_total, 50.0, B,
+                                            reservoir=res)
+        out, cff = cg.step_far_field(to_dev(c), 0.3, m_total, 50.0)
+        assert abs(cff - cff_w) <= 10 * tol * abs(cff_w)
+    else:
+        want = coarse.step(p, P, d.c0, B)
+        out = cg.step(to_dev(d.c0))
+    assert np.max(np.abs(to_host(out) - want)) <= 10 * tol * np.abs(want).max()
+    cg.close()
+
+
+def test_node_window_limits():
+    d = synth.random_small((8, 8, 8), 2, r=20, n_sub=3, seed=70)
+    with pytest.raises(fd.FdirwError):                            # K = ceil(20 / 2) = 10 > 8
+        fd.Coarse(fd.Domain(d.label, d.d_phase, 20, 3, d.h, 0.1), 2, fd.FP64)
+    u = to_dev(np.zeros((3,) + d.label.shape))
+    with pytest.raises(fd.FdirwError):                            # flow kernels stop at r = 8
+        fd.Coarse(fd.Domain(d.label, d.d_phase, 10, 3, d.h, 0.1), 2, fd.FP64, velocity=u)
+
+
+@pytest.mark.slow
+def test_full_size_node_window_columns():
+    # the particle case with Table 1's big step: r = 40, 1000 fast sub-steps,
+    # 5^3 blocks, FP32 build, liquid walled off from the solid, far field;
+    # three sampled node columns against the oracle's node windows
+    dom_s, t = synth.particle_case(192, 50.0, r=40, n_sub=1000)
+    a_rt = np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]])
+    d_liq = dom_s.d_phase * a_rt * np.array([1.0, 0.0, 1.0])
+    res = [0, 0, 1]
+    grouped = [1, 0, 0]
+    cg = fd.Coarse(fd.Domain(dom_s.label, d_liq, 40, 1000, dom_s.h, dom_s.dt), 5, fd.FP32, grouped=grouped,
+                   reservoir=res)
+    assert cg.K == 8
+    got = cg.matrix()
+    p = oracle.Problem(dom_s.label, d_liq, 40, 1000, dom_s.h, dom_s.dt)
+    _, _, count = coarse.groups(dom_s.label, d_liq, 5, grouped, res)
+    ncz, ncy, ncx = cg.coarse_shape
+    used = np.flatnonzero(count > 0)
+    kw = 2 * cg.K + 1
+    for J in used[[0, len(used) // 2, len(used) - 1]]:
+        col = coarse.node_window_column(p, 5, int(J), grouped, res)
+        jz, rem = divmod(int(J), ncy * ncx)
+        jy, jx = divmod(rem, ncx)
+        for I in np.flatnonzero(col):
+            iz, rem = divmod(int(I), ncy * ncx)
+            iy, ix = divmod(rem, ncx)
+            o = ((iz - jz + cg.K) * kw + (iy - jy + cg.K)) * kw + (ix - jx + cg.K)
+            want = col[I] / count[I]
+            assert abs(got[o, I] - want) <= 1e-5 * max(abs(want), 1e-4), (J, I)
+    cg.close()

@@ -233,3 +233,13 @@ def test_full_size_step_is_the_coarse_step_plus_the_coupling():
     assert np.all(np.diff(hist[:, 1]) > 0) and np.all(np.diff(hist[:, 2]) < 0)
     assert out[sol].max() <= t["c_eq_S"] and out[liq].min() >= 0.0
     assert np.all(out[far] == cff)
+
+
+@pytest.mark.parametrize("prec,tol", [(fd.FP64, 1e-12), (fd.FP32, 1e-6)])
+def test_node_window_liquid_operator_matches_oracle(prec, tol):
+    # a big step longer than the r = 8 kernels reach: r = 12 node windows
+    label, c0 = _case(n=16, r_p=4.0, seed=99)
+    (got, cff, hist, st, m_total), (want, cff_w, hist_w) = _run_both(label, c0, 0.2, 3, 2, prec, r=12, n_sub=30)
+    assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
+    assert abs(cff - cff_w) <= tol * abs(cff_w)
+    assert np.max(np.abs(hist[:, 0] + hist[:, 1] + 500.0 * hist[:, 2] - m_total)) <= 1e-12 * m_total

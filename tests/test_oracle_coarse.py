@@ -150,3 +150,51 @@ def test_far_field_block_one_is_the_dirichlet_fd():
     assert np.max(np.abs(out[~fixed] - ref[~fixed])) <= 1e-13
     assert np.all(out[fixed] == c_ff_new)
     assert abs(out[~fixed].sum() + c_ff_new * v_ff - m_total) <= 1e-12 * m_total
+
+
+def test_node_windows_with_block_one_are_the_source_windows():
+    # B = 1: the window of node J is the point-source window of radius r, so
+    # both constructions give the same P (r = 10 > 8: windows shorter than the
+    # domain along z)
+    d = synth.random_small((24, 4, 5), 3, r=10, n_sub=7, seed=41)
+    p = _problem(d)
+    got = coarse.coarse_matrix_node_windows(p, 1)
+    want = coarse.coarse_matrix_source_windows(p, 1)
+    assert np.max(np.abs(got - want)) <= 1e-13
+    assert np.max(np.abs(coarse.coarse_matrix(p, 1) - got)) == 0.0    # r > 8 takes the node windows
+
+
+@pytest.mark.parametrize("B", [2, 3])
+def test_node_windows_covering_equal_aggregated_operator(B):
+    # windows larger than the domain: the node column is A M^n of the
+    # indicator of group J, so S = A M^n A^T as for the source windows
+    d = synth.random_small((3, 4, 5), 3, r=9, n_sub=4, seed=42)
+    p = _problem(d)
+    M = np.linalg.matrix_power(dense_operator(d.label, d.d_phase, p.dt, p.h), d.n_sub)
+    block, mobile, count = coarse.groups(d.label, d.d_phase, B)
+    A = np.zeros((count.size, d.label.size))
+    A[block.ravel()[mobile.ravel()], np.flatnonzero(mobile.ravel())] = 1.0
+    S = A @ M @ A.T
+    ref = np.zeros_like(S)
+    ref[count > 0] = S[count > 0] / count[count > 0, None]
+    assert np.max(np.abs(coarse.coarse_matrix_node_windows(p, B) - ref)) <= 1e-13
+
+
+def test_node_windows_far_field_covering_equal_source_windows():
+    # with absorbing far-field cells and covering windows both constructions
+    # are sums of the same absorbed kernels
+    d = synth.random_small((6, 5, 7), 3, r=9, n_sub=5, seed=43)
+    label = d.label.copy()
+    label[:, :, 0] = 2
+    dph = np.array([1.0, 0.3, 1.0])
+    p = oracle.Problem(label, dph, 9, 5, 1.0, 0.1)
+    res = [0, 0, 1]
+    got = coarse.coarse_matrix_node_windows(p, 2, reservoir=res)
+    want = coarse.coarse_matrix_source_windows(p, 2, reservoir=res)
+    assert np.max(np.abs(got - want)) <= 1e-13
+    # mass only leaves, through the far field: N_I P[I, J] summed over I is at
+    # most N_J, and below it for groups next to the far-field cells
+    _, _, count = coarse.groups(label, dph, 2, reservoir=res)
+    has = count > 0
+    out = (count[:, None] * got).sum(axis=0)[has] / count[has]
+    assert np.all(out <= 1.0 + 1e-13) and np.any(out < 0.999)
