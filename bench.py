@@ -319,55 +319,62 @@ def mp_leg(fd, args):
     """The integrated near-field solver (Sec. 2, Eqs. 1-7, flowchart of Sec.
     3.4) on the paper's particle case: a porous particle of radius 50 cells in
     the 192^3 grid (near-field shell of 5 cells, the rest far field), Table 1
-    values, liquid kernels of r = 8 and 200 fast sub-steps (big step 100 us;
-    Table 1's 500 us would need windows of r ~ 40), 5^3 coarse blocks.  Per
-    storage precision of P: build time, device time per big step over
-    ``--mp-steps`` chained steps, interface faces, the Eq. 7 balance residual
-    and the solid uptake."""
+    values, 5^3 coarse blocks.  Two big steps: 200 fast sub-steps (100 us) with
+    the per-source kernels of r = 8 (the workload's r and n), P in FP32 and in
+    FP16; and Table 1's own 1000 sub-steps (500 us) with node windows of r = 40
+    (K = 8), P in FP16.  Per case: build time, device time per big step over
+    ``--mp-steps`` chained steps, interface faces, the Eq. 7 balance residual,
+    the solid uptake and the device time for 0.5 s of physical time."""
     import torch
     import synth
     n = args.n
-    d, t = synth.particle_case(n, 50.0 * n / 192.0)
-    role = [fd.ROLE_LIQUID, fd.ROLE_SOLID, fd.ROLE_FAR_FIELD]
-    a_rt = np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]])
-    far = d.label == synth.PHASE_FAR_LIQUID
-    v_ff, c_ff0 = t["V_ff_cells"], t["c0_L"]
-    m_total = float(d.c0[~far].sum()) + v_ff * c_ff0
-    dom = fd.Domain.from_synth(d)
-    out = {"workload": f"particle{n}_R{int(50 * n / 192)}", "r": d.r, "n_sub": d.n_sub, "block": 5,
-           "big_step_s": d.n_sub * d.dt, "near_liquid_cells": int((d.label == synth.PHASE_NEAR_LIQUID).sum()),
-           "solid_cells": int((d.label == synth.PHASE_SOLID).sum()), "steps": args.mp_steps}
+    r_p = 50.0 * n / 192.0
+    out = {"workload": f"particle{n}_R{int(r_p)}", "block": 5, "steps": args.mp_steps}
     stream = torch.cuda.current_stream()
-    for prec in ("fp32", "fp16_bank"):
-        log(f"integrated {prec}: building the liquid operator")
-        s = fd.Multiphysics(dom, role, t["k"], t["c_eq_L"], t["c_eq_S"], v_ff, a_over_rt=a_rt, block=5, prec=prec)
-        c = torch.from_numpy(d.c0).cuda()
-        s.step(c, c_ff0, m_total, 1)                       # warm-up
-        c.copy_(torch.from_numpy(d.c0))
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        cff, hist, st = s.step(c, c_ff0, m_total, args.mp_steps, stats=True)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.mp_steps
-        resid = float(np.max(np.abs(hist[:, 0] + hist[:, 1] + v_ff * hist[:, 2] - m_total))) / m_total
-        pb = 4 if prec == "fp32" else 2
+    cases = [("dt100us_r8", 8, 200, ("fp32", "fp16_bank")), ("dt500us_r40", 40, 1000, ("fp16_bank",))]
+    for name, r, n_sub, precs in cases:
+        d, t = synth.particle_case(n, r_p, r=r, n_sub=n_sub)
+        role = [fd.ROLE_LIQUID, fd.ROLE_SOLID, fd.ROLE_FAR_FIELD]
+        a_rt = np.array([t["A_L_RT"], t["A_S_RT"], t["A_L_RT"]])
+        far = d.label == synth.PHASE_FAR_LIQUID
         liq = d.label == synth.PHASE_NEAR_LIQUID
+        v_ff, c_ff0 = t["V_ff_cells"], t["c0_L"]
+        m_total = float(d.c0[~far].sum()) + v_ff * c_ff0
+        dom = fd.Domain.from_synth(d)
         blk = (np.arange(n) // 5)
         used = np.unique(((blk[:, None, None] * 1000 + blk[None, :, None]) * 1000 + blk[None, None, :])[liq]).size
-        byts = mp_bytes_per_step(int(liq.sum()), int((d.label == synth.PHASE_SOLID).sum()), used, s.K, pb)
-        rec = {"build_seconds": s.build_seconds, "ms_per_step": ms, "kernel_ms_per_step": 1e3 * st["kernel_seconds"] / args.mp_steps,
-               "nodes": s.n_nodes, "interface_faces": s.n_faces, "balance_rel_residual": resid,
-               "solid_uptake_Q_S": [float(hist[0, 1]), float(hist[-1, 1])], "c_ff_end": cff,
-               "nodes_with_cells": used, "hbm_bytes_per_step": byts, "hbm_GBps": byts / (ms * 1e-3) / 1e9,
-               "hbm_frac": byts / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
-               "bound": "launch and memory latency (4 dependent launches per step)",
-               "seconds_per_physical_0p5s": ms * 1e-3 * 0.5 / (d.n_sub * d.dt)}
-        out[prec] = rec
-        s.close()
-        log(f"integrated {prec}: {ms:.4f} ms / big step, {s.n_faces} faces, balance {resid:.1e}")
+        case = {"r": r, "n_sub": n_sub, "big_step_s": n_sub * d.dt, "near_liquid_cells": int(liq.sum()),
+                "solid_cells": int((d.label == synth.PHASE_SOLID).sum()), "nodes_with_cells": used}
+        for prec in precs:
+            log(f"integrated {name} {prec}: building the liquid operator")
+            s = fd.Multiphysics(dom, role, t["k"], t["c_eq_L"], t["c_eq_S"], v_ff, a_over_rt=a_rt, block=5,
+                                prec=prec)
+            c = torch.from_numpy(d.c0).cuda()
+            s.step(c, c_ff0, m_total, 1)                   # warm-up
+            c.copy_(torch.from_numpy(d.c0))
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            cff, hist, st = s.step(c, c_ff0, m_total, args.mp_steps, stats=True)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / args.mp_steps
+            resid = float(np.max(np.abs(hist[:, 0] + hist[:, 1] + v_ff * hist[:, 2] - m_total))) / m_total
+            pb = 4 if prec == "fp32" else 2
+            byts = mp_bytes_per_step(int(liq.sum()), case["solid_cells"], used, s.K, pb)
+            case[prec] = {
+                "build_seconds": s.build_seconds, "ms_per_step": ms,
+                "kernel_ms_per_step": 1e3 * st["kernel_seconds"] / args.mp_steps, "K": s.K,
+                "interface_faces": s.n_faces, "balance_rel_residual": resid,
+                "solid_uptake_Q_S": [float(hist[0, 1]), float(hist[-1, 1])], "c_ff_end": cff,
+                "hbm_bytes_per_step": byts, "hbm_GBps": byts / (ms * 1e-3) / 1e9,
+                "hbm_frac": byts / (ms * 1e-3) / (PEAK_HBM_GBS * 1e9),
+                "seconds_per_physical_0p5s": ms * 1e-3 * 0.5 / (n_sub * d.dt)}
+            s.close()
+            log(f"integrated {name} {prec}: build {case[prec]['build_seconds']:.2f} s, {ms:.4f} ms / big step, "
+                f"{case[prec]['seconds_per_physical_0p5s']:.3f} s per 0.5 s physical, balance {resid:.1e}")
+        out[name] = case
     return out
 
 

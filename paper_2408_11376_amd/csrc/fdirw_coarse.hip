@@ -452,15 +452,16 @@ template <> __device__ __forceinline__ double widen<double>(double v) { return v
 
 constexpr int APPLY_MAX_WAVES = 16;
 
-template <typename T>
+template <typename T, int KW>
 __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
-    const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz, int K,
+    const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz,
     const double *__restrict__ pbc_pad, double c_ff, const double *__restrict__ cff_dev,
     const double *__restrict__ count, double *__restrict__ cnew)
 {
     constexpr int zb = 16 / (int)sizeof(T);
+    constexpr int K = (KW - 1) / 2, kw = KW;                      // the x offsets unrolled: kw loads in flight
     __shared__ double part[APPLY_MAX_WAVES * 64];
-    const int kw = 2 * K + 1, px = ncx + 2 * K, py = ncy + 2 * K;
+    const int px = ncx + 2 * K, py = ncy + 2 * K;
     const int nw = blockDim.x >> 6;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
@@ -483,7 +484,16 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
             for (int oy = 0; oy < kw; ++oy) {
                 // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
                 const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
-                for (int ox = 0; ox < kw; ++ox, ++o) acc = __builtin_fma(widen<T>(p[o * plane]), crow[-ox], acc);
+                T pv[kw];
+                double cv[kw];
+#pragma unroll
+                for (int ox = 0; ox < kw; ++ox) {
+                    pv[ox] = p[(o + ox) * plane];
+                    cv[ox] = crow[-ox];
+                }
+#pragma unroll
+                for (int ox = 0; ox < kw; ++ox) acc = __builtin_fma(widen<T>(pv[ox]), cv[ox], acc);
+                o += kw;
             }
         }
     }
@@ -748,38 +758,50 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
     return hipGetLastError();
 }
 
+template <typename T, int KW>
+static void apply_kw(const void *P, const double *cpad, int ncx, int ncy, int ncz, const double *pbc_pad,
+                     double c_ff, const double *cff_dev, const double *count, double *cnew, hipStream_t st)
+{
+    constexpr int nw = KW < APPLY_MAX_WAVES ? KW : APPLY_MAX_WAVES;
+    constexpr int zb = 16 / (int)sizeof(T);
+    const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
+    const unsigned g = (unsigned)((n_chunks * zb + 63) / 64);
+    if (g == 0) return;
+    hipLaunchKernelGGL((coarse_apply_kernel<T, KW>), dim3(g), dim3(64 * nw), 0, st, (const T *)P, cpad, ncx, ncy,
+                       ncz, pbc_pad, c_ff, cff_dev, count, cnew);
+}
+
+template <typename T>
+static hipError_t apply_t(int K, const void *P, const double *cpad, int ncx, int ncy, int ncz,
+                          const double *pbc_pad, double c_ff, const double *cff_dev, const double *count,
+                          double *cnew, hipStream_t st)
+{
+    switch (K) {
+    case 0: apply_kw<T, 1>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 1: apply_kw<T, 3>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 2: apply_kw<T, 5>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 3: apply_kw<T, 7>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 4: apply_kw<T, 9>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 5: apply_kw<T, 11>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 6: apply_kw<T, 13>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 7: apply_kw<T, 15>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    case 8: apply_kw<T, 17>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                const double *pbc_pad, double c_ff, const double *count, double *cnew,
                                hipStream_t st, const double *cff_dev)
 {
-    const int kw = 2 * K + 1;
-    const int nw = kw < APPLY_MAX_WAVES ? kw : APPLY_MAX_WAVES;
-    const size_t esz = prec == M_FP64 ? 8 : (prec == M_FP32 ? 4 : 2);
-    const int zb = (int)(16 / esz);
-    const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
-    const unsigned g = (unsigned)((n_chunks * zb + 63) / 64);
-    const size_t lds = 0;
-    if (g == 0) return hipSuccess;
     switch (prec) {
-    case M_FP64:
-        hipLaunchKernelGGL(coarse_apply_kernel<double>, dim3(g), dim3(64 * nw), lds, st, (const double *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
-        break;
-    case M_FP32:
-        hipLaunchKernelGGL(coarse_apply_kernel<float>, dim3(g), dim3(64 * nw), lds, st, (const float *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
-        break;
-    case M_F16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<_Float16>, dim3(g), dim3(64 * nw), lds, st, (const _Float16 *)P,
-                           cpad, ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
-        break;
-    case M_BF16BANK:
-        hipLaunchKernelGGL(coarse_apply_kernel<__bf16>, dim3(g), dim3(64 * nw), lds, st, (const __bf16 *)P, cpad,
-                           ncx, ncy, ncz, K, pbc_pad, c_ff, cff_dev, count, cnew);
-        break;
+    case M_FP64: return apply_t<double>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
+    case M_FP32: return apply_t<float>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
+    case M_F16BANK: return apply_t<_Float16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
+    case M_BF16BANK: return apply_t<__bf16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,

@@ -16,7 +16,9 @@ over B^3 blocks is built once (P stored in ``--prec``) and each repetition is
 one coarse step.  With ``--mp K`` the integrated near-field solver of the
 particle case (porous particle of radius 50 n / 192, Table 1 values, coarse
 blocks of 5, P in ``--prec``) is built once and each repetition runs K big
-steps.  With ``--flow U`` each repetition generates the window
+steps (``--mp-r`` / ``--mp-nsub``: window radius and fast sub-steps of the
+liquid's operator, 8 / 200 by default; 40 / 1000 is Table 1's big step).  With
+``--flow U`` each repetition generates the window
 kernels of a 64^3-cell sample of sources with a seeded steady flow of
 magnitude up to U (fdirw_kernels_flow, precision ``--prec``).
 """
@@ -42,6 +44,8 @@ def main():
     ap.add_argument("--coarse", type=int, default=0)
     ap.add_argument("--flow", type=float, default=0.0)
     ap.add_argument("--mp", type=int, default=0)
+    ap.add_argument("--mp-r", type=int, default=8)
+    ap.add_argument("--mp-nsub", type=int, default=200)
     args = ap.parse_args()
     import torch
     import synth
@@ -70,7 +74,7 @@ def main():
         args.warmup = 0
     if args.mp:
         import numpy as np
-        dp, t = synth.particle_case(args.n, 50.0 * args.n / 192.0)
+        dp, t = synth.particle_case(args.n, 50.0 * args.n / 192.0, r=args.mp_r, n_sub=args.mp_nsub)
         far = dp.label == synth.PHASE_FAR_LIQUID
         m_total = float(dp.c0[~far].sum()) + t["V_ff_cells"] * t["c0_L"]
         s = fd.Multiphysics(fd.Domain.from_synth(dp), [fd.ROLE_LIQUID, fd.ROLE_SOLID, fd.ROLE_FAR_FIELD], t["k"],
