@@ -183,6 +183,8 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
     const double cfl = 6.0 * dsol_max * dts / (d->h * d->h);
     if (cfl > 1.0 + 1e-12)
         return fail(FDIRW_E_UNSTABLE, "solid: 6 max(D A / RT) dt_s / h^2 = %.17g > 1 (raise n_sub_solid)", cfl);
+    const double kappa_dt = p->k / (p->c_eq_liquid * p->c_eq_solid) * dt;
+    if (!std::isfinite(kappa_dt)) return fail(FDIRW_E_ARG, "k dt / (c_eq_liquid c_eq_solid) is not finite");
     auto *h = new (std::nothrow) Mp;
     if (!h) return fail(FDIRW_E_NOMEM, "solver handle");
     if (hipGetDevice(&h->dev) != hipSuccess) {
@@ -195,7 +197,7 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
     h->dt = dt;
     h->c_eq_l = p->c_eq_liquid;
     h->c_eq_s = p->c_eq_solid;
-    h->kappa_dt = p->k / (p->c_eq_liquid * p->c_eq_solid) * dt;
+    h->kappa_dt = kappa_dt;
     h->v_ff = p->v_far_field;
     h->n_sub_solid = p->n_sub_solid;
     std::memset(h->solid, 0, sizeof h->solid);
