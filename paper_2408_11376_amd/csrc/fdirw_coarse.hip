@@ -452,11 +452,13 @@ template <> __device__ __forceinline__ double widen<double>(double v) { return v
 
 constexpr int APPLY_MAX_WAVES = 16;
 
+// groups (optional): the 64-position groups of P's layout to run (those that
+// hold a node with cells); else every group.
 template <typename T, int KW>
 __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
     const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz,
     const double *__restrict__ pbc_pad, double c_ff, const double *__restrict__ cff_dev,
-    const double *__restrict__ count, double *__restrict__ cnew)
+    const double *__restrict__ count, double *__restrict__ cnew, const int *__restrict__ groups)
 {
     constexpr int zb = 16 / (int)sizeof(T);
     constexpr int K = (KW - 1) / 2, kw = KW;                      // the x offsets unrolled: kw loads in flight
@@ -466,7 +468,8 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
     const int64_t plane = n_chunks * zb;
-    const int64_t ch = blockIdx.x * (int64_t)(64 / zb) + lane / zb;   // (zg, y, x) chunk
+    const int64_t grp = groups ? groups[blockIdx.x] : blockIdx.x;     // 64 nodes of the layout
+    const int64_t ch = grp * (64 / zb) + lane / zb;                    // (zg, y, x) chunk
     const int j = lane % zb;
     double acc = 0.0;
     int x = 0, y = 0, z = ncz;
@@ -759,47 +762,67 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
 }
 
 template <typename T, int KW>
-static void apply_kw(const void *P, const double *cpad, int ncx, int ncy, int ncz, const double *pbc_pad,
-                     double c_ff, const double *cff_dev, const double *count, double *cnew, hipStream_t st)
+static hipError_t apply_kw(const void *P, const double *cpad, int ncx, int ncy, int ncz, const double *pbc_pad,
+                           double c_ff, const double *cff_dev, const double *count, double *cnew,
+                           const int *groups, int64_t n_groups, hipStream_t st)
 {
     constexpr int nw = KW < APPLY_MAX_WAVES ? KW : APPLY_MAX_WAVES;
     constexpr int zb = 16 / (int)sizeof(T);
     const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
-    const unsigned g = (unsigned)((n_chunks * zb + 63) / 64);
-    if (g == 0) return;
+    const unsigned g = groups ? (unsigned)n_groups : (unsigned)((n_chunks * zb + 63) / 64);
+    if (g == 0) return hipSuccess;
     hipLaunchKernelGGL((coarse_apply_kernel<T, KW>), dim3(g), dim3(64 * nw), 0, st, (const T *)P, cpad, ncx, ncy,
-                       ncz, pbc_pad, c_ff, cff_dev, count, cnew);
+                       ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups);
+    return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t apply_t(int K, const void *P, const double *cpad, int ncx, int ncy, int ncz,
                           const double *pbc_pad, double c_ff, const double *cff_dev, const double *count,
-                          double *cnew, hipStream_t st)
+                          double *cnew, const int *groups, int64_t n_groups, hipStream_t st)
 {
+#define FDIRW_APPLY_CASE(k)                                                                                        \
+    case k:                                                                                                       \
+        return apply_kw<T, 2 * k + 1>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,        \
+                                      n_groups, st);
     switch (K) {
-    case 0: apply_kw<T, 1>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 1: apply_kw<T, 3>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 2: apply_kw<T, 5>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 3: apply_kw<T, 7>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 4: apply_kw<T, 9>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 5: apply_kw<T, 11>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 6: apply_kw<T, 13>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 7: apply_kw<T, 15>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
-    case 8: apply_kw<T, 17>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st); break;
+        FDIRW_APPLY_CASE(0)
+        FDIRW_APPLY_CASE(1)
+        FDIRW_APPLY_CASE(2)
+        FDIRW_APPLY_CASE(3)
+        FDIRW_APPLY_CASE(4)
+        FDIRW_APPLY_CASE(5)
+        FDIRW_APPLY_CASE(6)
+        FDIRW_APPLY_CASE(7)
+        FDIRW_APPLY_CASE(8)
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+#undef FDIRW_APPLY_CASE
+}
+
+int64_t coarse_apply_positions(int prec, int ncx, int ncy, int ncz)
+{
+    const int zb = 16 / (prec == M_FP64 ? 8 : (prec == M_FP32 ? 4 : 2));
+    return (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
 }
 
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                const double *pbc_pad, double c_ff, const double *count, double *cnew,
-                               hipStream_t st, const double *cff_dev)
+                               hipStream_t st, const double *cff_dev, const int *groups, int64_t n_groups)
 {
     switch (prec) {
-    case M_FP64: return apply_t<double>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
-    case M_FP32: return apply_t<float>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
-    case M_F16BANK: return apply_t<_Float16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
-    case M_BF16BANK: return apply_t<__bf16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, st);
+    case M_FP64:
+        return apply_t<double>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
+                               n_groups, st);
+    case M_FP32:
+        return apply_t<float>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
+                              n_groups, st);
+    case M_F16BANK:
+        return apply_t<_Float16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
+                                 n_groups, st);
+    case M_BF16BANK:
+        return apply_t<__bf16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
+                               n_groups, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -40,10 +40,12 @@ struct Coarse {
     bool far_field = false;         // reservoir (far-field boundary) phases present
     bool dense = true;              // most nodes hold grouped cells (mapping by rows of blocks)
     void *pbc = nullptr;            // double, P_BC on the padded coarse grid (far field only)
+    void *groups = nullptr;         // int [n_groups]: 64-position groups of P's layout holding a node with cells
+    int64_t n_groups = 0;
 
     ~Coarse()
     {
-        for (void *p : {node, count, P, cpad, cnew, part, pbc})
+        for (void *p : {node, count, P, cpad, cnew, part, pbc, groups})
             if (p) (void)hipFree(p);
     }
     int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
@@ -175,6 +177,32 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             int64_t used = 0;
             for (double v : hc) used += v > 0.0;
             h->dense = 2 * used >= h->n_nodes;
+            // the product's 64-position groups of P's layout that hold a node with cells
+            if (e == hipSuccess) {
+                const int zb = 16 / (int)h->esz;
+                const int64_t npos = (int64_t)((h->ncz + zb - 1) / zb) * h->ncy * h->ncx * zb;
+                std::vector<int> gl;
+                for (int64_t g0 = 0; g0 < npos; g0 += 64) {
+                    bool any = false;
+                    for (int64_t t = g0; t < g0 + 64 && t < npos && !any; ++t) {
+                        const int64_t ch = t / zb;
+                        const int x = (int)(ch % h->ncx), y = (int)((ch / h->ncx) % h->ncy);
+                        const int z = (int)(ch / ((int64_t)h->ncx * h->ncy)) * zb + (int)(t % zb);
+                        any = z < h->ncz && hc[(size_t)(((int64_t)z * h->ncy + y) * h->ncx + x)] > 0.0;
+                    }
+                    if (any) gl.push_back((int)(g0 / 64));
+                }
+                h->n_groups = (int64_t)gl.size();
+                rc = coarse_alloc(&h->groups, gl.size() * sizeof(int));
+                if (!rc && !gl.empty())
+                    e = hipMemcpyAsync(h->groups, gl.data(), gl.size() * sizeof(int), hipMemcpyHostToDevice, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (rc) {
+                    (void)hipFree(S);
+                    delete h;
+                    return rc;
+                }
+            }
             if (node_windows && e == hipSuccess) {
                 // node windows: the nodes with cells in batches of at most
                 // ~2 GB of window state
@@ -317,7 +345,8 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
                               h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense);
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
-                                (const double *)h->count, (double *)h->cnew, st, cff_dev);
+                                (const double *)h->count, (double *)h->cnew, st, cff_dev,
+                                (const int *)h->groups, h->n_groups);
     if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
     if (ks && e == hipSuccess) e = hipEventRecord(ev.b, st);
     if (e != hipSuccess) return hip_fail(e, "coarse step launch");
@@ -346,7 +375,8 @@ int coarse_map_apply(void *handle, const double *c_in, const double *cff_dev, hi
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
                                 h->far_field ? (const double *)h->pbc : nullptr, 0.0, (const double *)h->count,
-                                (double *)h->cnew, st, h->far_field ? cff_dev : nullptr);
+                                (double *)h->cnew, st, h->far_field ? cff_dev : nullptr,
+                                (const int *)h->groups, h->n_groups);
     if (e != hipSuccess) return hip_fail(e, "coarse mapping / product launch");
     *cnew = (const double *)h->cnew;
     return FDIRW_OK;

@@ -160,7 +160,10 @@ hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, 
                              int64_t n_src, hipStream_t st);
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                const double *pbc_pad, double c_ff, const double *count, double *cnew,
-                               hipStream_t st, const double *cff_dev = nullptr);   // cff_dev set: c_ff read from it
+                               hipStream_t st, const double *cff_dev = nullptr,    // cff_dev set: c_ff read from it
+                               const int *groups = nullptr, int64_t n_groups = 0);   // the 64-node groups to run
+// positions of P's layout (nodes padded to zb along z); group g covers [64 g, 64 g + 64)
+int64_t coarse_apply_positions(int prec, int ncx, int ncy, int ncz);
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
                                hipStream_t st);
 // Integrated near-field solver (fdirw_mp.hip).  Cell roles come from the
@@ -172,7 +175,8 @@ hipError_t launch_coarse_remap(const double *c_in, const int *node, const double
 constexpr int MP_TX = 16, MP_TY = 8, MP_TZ = 8, MP_H = 3;
 constexpr int MP_BX = MP_TX + 2 * MP_H, MP_BY = MP_TY + 2 * MP_H, MP_BZ = MP_TZ + 2 * MP_H;
 constexpr int MP_BOX = MP_BX * MP_BY * MP_BZ;
-constexpr int MP_PAIR_CAP = 1024;     // interface pairs of a tile staged in LDS (the rest read from memory)
+constexpr int MP_PAIR_CAP = 512;      // interface pairs of a tile staged in LDS (the rest read from memory)
+constexpr int MP_MAX_SOLID_PHASES = 126;   // solid phases the fused kernel's role byte can tell apart
 constexpr int MP_SUM_BLOCKS = 256;    // most workgroups of the balance kernel
 constexpr int MP_CHUNK = 1024;        // cells per workgroup of the list kernels
 struct MpLocalArgs {
@@ -182,8 +186,8 @@ struct MpLocalArgs {
     const int *pair_off;              // [6 n_tiles + 1] start of each tile's pass in pairs
     const uint16_t *pairs;            // interface pairs, (q << 1) | (lower cell solid)
     const int *node;
-    const uint8_t *label;
-    const double *dsol;               // [256] D A / RT of every solid phase, 0 for the others
+    const uint8_t *scode;             // [N] compact solid-phase index of every cell (solid cells read)
+    const double *dsolc;              // D A / RT of the solid phases, by compact index
     const double *cnew;               // node values after the product
     const double *c_in;               // the step's input field (solid cells)
     double *out;                      // the step's output field (active cells written)
@@ -196,6 +200,9 @@ struct MpLocalArgs {
 };
 int64_t mp_tile_count(int nx, int ny, int nz);
 hipError_t launch_mp_faces(const int *node, int nx, int ny, int nz, unsigned long long *count, hipStream_t st);
+// scode[i] = table256[label[i]]
+hipError_t launch_mp_code(const uint8_t *label, int64_t n, const unsigned char *table256, uint8_t *scode,
+                          hipStream_t st);
 hipError_t launch_mp_tile_flags(const int *node, int nx, int ny, int nz, int *flag, hipStream_t st);
 // list null: counts into cnt[6 n_tiles]; else entries at list[off[6 t + p]..]
 hipError_t launch_mp_tile_pairs(const int *node, int nx, int ny, int nz, const int *tiles, int64_t n_tiles,

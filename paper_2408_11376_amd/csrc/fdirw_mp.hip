@@ -208,10 +208,10 @@ __global__ void mp_solid_scatter_kernel(const int *__restrict__ sol, int64_t n_s
         field[sol[k]] = v[k];
 }
 
-// Block-wide fixed-order tree sum of two values (every thread gets them).
-__device__ void mp_block_sum2(double &a, double &b)
+// Block-wide fixed-order tree sum of two values (every thread gets them), in
+// the caller's LDS scratch (2 x MP_NT doubles).
+__device__ void mp_block_sum2_in(double &a, double &b, double *sa, double *sb)
 {
-    __shared__ double sa[MP_NT], sb[MP_NT];
     __syncthreads();
     sa[threadIdx.x] = a;
     sb[threadIdx.x] = b;
@@ -225,6 +225,12 @@ __device__ void mp_block_sum2(double &a, double &b)
     }
     a = sa[0];
     b = sb[0];
+}
+
+__device__ void mp_block_sum2(double &a, double &b)
+{
+    __shared__ double sa[MP_NT], sb[MP_NT];
+    mp_block_sum2_in(a, b, sa, sb);
 }
 
 // Eq. 7 from the per-workgroup partials of the previous launch (Q_L in
@@ -387,12 +393,10 @@ __device__ __forceinline__ void mp_pass(double *v, const uint16_t *pl, const uin
 // exactly the values of the whole-grid passes.
 __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
 {
+    // 39.8 KB: four workgroups per CU
     __shared__ double v[MP_BOX];
-    __shared__ signed char role[MP_BOX];                          // 0 liquid, 1 solid, -1 none
-    __shared__ unsigned char lab[MP_BOX];
-    __shared__ double dsol[256];
+    __shared__ signed char role[MP_BOX];                          // -1 none, 0 liquid, 1 + s solid of phase s
     __shared__ uint16_t pl[MP_PAIR_CAP];
-    for (int k = threadIdx.x; k < 256; k += MP_NT) dsol[k] = a.dsol[k];
     const int t = a.tiles[blockIdx.x];
     int x0, y0, z0;
     mp_tile_origin(t, a.nx, a.ny, x0, y0, z0);
@@ -422,16 +426,17 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
             nd[u] = in ? a.node[gi[u]] : NONE;
         }
         double val[ROUND];
-        int lb[ROUND];                                            // ints: no packing, no early waits
+        int sc[ROUND];                                            // ints: no packing, no early waits
 #pragma unroll
         for (int u = 0; u < ROUND; ++u) {
             val[u] = 0.0;
-            lb[u] = 0;
+            sc[u] = -1;
             if (nd[u] >= 0) {
                 val[u] = a.cnew[nd[u]];
+                sc[u] = 0;
             } else if (nd[u] == COARSE_OUTSIDE) {
                 val[u] = a.c_in[gi[u]];
-                lb[u] = a.label[gi[u]];
+                sc[u] = 1 + a.scode[gi[u]];
             }
         }
 #pragma unroll
@@ -439,8 +444,7 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
             const int q = q0 + u * MP_NT;
             if (q < MP_BOX) {
                 v[q] = val[u];
-                role[q] = mp_role(nd[u]);
-                lab[q] = (unsigned char)lb[u];
+                role[q] = (signed char)sc[u];
             }
         }
     }
@@ -466,15 +470,16 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
             sl += g;
         } else {
             if (a.solid) {
-                const double di = dsol[lab[q]];
+                const double di = a.dsolc[r - 1];
                 double acc = g;
                 if (di > 0.0) {
                     const int nbq[6] = {q - 1, q + 1, q - MP_BX, q + MP_BX, q - MP_BX * MP_BY, q + MP_BX * MP_BY};
 #pragma unroll
                     for (int f = 0; f < 6; ++f) {
                         const int qq = nbq[f];
-                        if (role[qq] != 1) continue;
-                        const double dj = dsol[lab[qq]];
+                        const int rq = role[qq];
+                        if (rq < 1) continue;
+                        const double dj = a.dsolc[rq - 1];
                         if (!(dj > 0.0)) continue;
                         const double df = (2.0 * di) * dj / (di + dj);
                         acc += (df * a.dt_s) / hh * (v[qq] - g);
@@ -487,11 +492,33 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
         a.out[i] = g;
     }
     if (!a.solid) return;
-    mp_block_sum2(sl, ss);
+    mp_block_sum2_in(sl, ss, v, v + MP_NT);                       // v is no longer read
     if (threadIdx.x == 0) {
         a.part[blockIdx.x] = sl;
         a.part[gridDim.x + blockIdx.x] = ss;
     }
+}
+
+// scode[i] = compact solid-phase index of cell i (the fused kernel's solid
+// coefficient table), from the labels.
+struct MpCodeTable {
+    unsigned char s[256];
+};
+
+__global__ void mp_code_kernel(const uint8_t *__restrict__ label, int64_t n, MpCodeTable tab,
+                               uint8_t *__restrict__ scode)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        scode[i] = tab.s[label[i]];
+}
+
+hipError_t launch_mp_code(const uint8_t *label, int64_t n, const unsigned char *table256, uint8_t *scode,
+                          hipStream_t st)
+{
+    MpCodeTable t;
+    for (int k = 0; k < 256; ++k) t.s[k] = table256[k];
+    hipLaunchKernelGGL(mp_code_kernel, dim3(mp_grid(n)), dim3(MP_NT), 0, st, label, n, t, scode);
+    return hipGetLastError();
 }
 
 // Marks the tiles that hold an active cell (flag per tile).

@@ -41,14 +41,15 @@ struct Mp {
     double c_eq_l = 1.0, c_eq_s = 1.0, v_ff = 1.0;
     int n_sub_solid = 1;
     double solid[256];                  // D A / RT of every solid phase, 0 for the others
-    void *dsol = nullptr;               // device copy of solid
+    void *dsol = nullptr;               // device copy of solid (by label)
+    void *dsolc = nullptr;              // D A / RT of the solid phases by compact index
     void *coarse = nullptr;
     int64_t n_faces = 0;                // interface faces (liquid / solid)
     int64_t n_tiles = 0;
     void *tiles = nullptr;              // int [n_tiles] tiles of the fused local kernel
     void *pair_off = nullptr;           // int [6 n_tiles + 1] start of each tile's reaction pass
     void *pairs = nullptr;              // uint16 interface pairs of every tile's box
-    void *label = nullptr;              // uint8 [N] copy of the labels
+    void *scode = nullptr;              // uint8 [N] compact solid-phase index of every cell
     int64_t n_act = 0, n_sol = 0;
     void *act = nullptr;                // int [n_act] active cells, ascending
     void *sol = nullptr;                // int [n_sol] solid cells, ascending
@@ -63,7 +64,7 @@ struct Mp {
 
     ~Mp()
     {
-        for (void *p : {tiles, pair_off, pairs, label, dsol, act, sol, slam, snb, sa, sb, tmp, part, cff, hist})
+        for (void *p : {tiles, pair_off, pairs, scode, dsol, dsolc, act, sol, slam, snb, sa, sb, tmp, part, cff, hist})
             if (p) (void)hipFree(p);
         if (coarse) (void)fdirw_coarse_destroy(coarse);
     }
@@ -219,8 +220,9 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
     rc = mp_alloc((void **)&cnt, 6 * sizeof(unsigned long long));
     if (!rc) rc = mp_alloc((void **)&flag, (size_t)nt * sizeof(int));
     if (!rc) rc = mp_alloc(&h->tmp, (size_t)h->n * sizeof(double));
-    if (!rc) rc = mp_alloc(&h->label, (size_t)h->n);
+    if (!rc) rc = mp_alloc(&h->scode, (size_t)h->n);
     if (!rc) rc = mp_alloc(&h->dsol, sizeof h->solid);
+    if (!rc) rc = mp_alloc(&h->dsolc, sizeof h->solid);
     if (!rc) rc = mp_alloc(&h->cff, sizeof(double));
     if (rc) {
         (void)hipFree(cnt);
@@ -231,8 +233,26 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
     unsigned long long hc[6];
     std::vector<int> hflag((size_t)nt);
     hipError_t e = launch_fill_u32((unsigned *)cnt, 12, 0u, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h->label, d->label, (size_t)h->n, hipMemcpyDeviceToDevice, st);
+    // compact indices of the solid phases (the fused kernel's role byte)
+    unsigned char sidx[256];
+    double dc[256];
+    std::memset(sidx, 0, sizeof sidx);
+    int n_solid_phases = 0;
+    for (int i = 0; i < d->n_phase; ++i)
+        if (p->role[i] == FDIRW_ROLE_SOLID) {
+            sidx[i] = (unsigned char)n_solid_phases;
+            dc[n_solid_phases++] = h->solid[i];
+        }
+    if (n_solid_phases > MP_MAX_SOLID_PHASES) {
+        (void)hipFree(cnt);
+        (void)hipFree(flag);
+        delete h;
+        return fail(FDIRW_E_UNSUPPORTED, "%d solid phases: at most %d", n_solid_phases, MP_MAX_SOLID_PHASES);
+    }
+    if (e == hipSuccess) e = launch_mp_code(d->label, h->n, sidx, (uint8_t *)h->scode, st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->dsol, h->solid, sizeof h->solid, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && n_solid_phases)
+        e = hipMemcpyAsync(h->dsolc, dc, n_solid_phases * sizeof(double), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_mp_faces(node, d->nx, d->ny, d->nz, cnt, st);
     if (e == hipSuccess) e = launch_mp_tile_flags(node, d->nx, d->ny, d->nz, flag, st);
     if (e == hipSuccess) e = hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, st);
@@ -369,8 +389,8 @@ int fdirw_mp_step(void *handle, double *c, double *c_ff, double m_total, int32_t
     a.pair_off = (const int *)h->pair_off;
     a.pairs = (const uint16_t *)h->pairs;
     a.node = node;
-    a.label = (const uint8_t *)h->label;
-    a.dsol = (const double *)h->dsol;
+    a.scode = (const uint8_t *)h->scode;
+    a.dsolc = (const double *)h->dsolc;
     a.c_eq_l = h->c_eq_l; a.c_eq_s = h->c_eq_s; a.kappa_dt = h->kappa_dt;
     a.solid = h->n_sub_solid == 1 && h->n_tiles > 0;
     a.dt_s = h->dt / h->n_sub_solid;
