@@ -205,22 +205,19 @@ __global__ void __launch_bounds__(BIN_NT) coarse_bin_kernel(CoarseGenArgs a, con
 // wb = (2K+1) B cells per axis made of J's block and the K blocks around it
 // (clipped at the domain; faces leaving it are walls), for a batch of nodes at
 // a time: state [batch][wb^3] in HBM, one launch per sub-step.
+// Grid: x over the window's cells (32-bit indices), y over the batch's nodes.
 template <typename St>
 __global__ void nodewin_init_kernel(NodeWinArgs a, St *__restrict__ g)
 {
-    const int64_t wb3 = (int64_t)a.wb * a.wb * a.wb;
-    const int64_t total = wb3 * a.n_batch;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int jb = (int)(t / wb3);
-        const int64_t q = t - jb * wb3;
-        const int J = a.batch[jb];
-        const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
-        const int X = (bx - a.K) * a.B + (int)(q % a.wb), Y = (by - a.K) * a.B + (int)((q / a.wb) % a.wb);
-        const int Z = (bz - a.K) * a.B + (int)(q / ((int64_t)a.wb * a.wb));
-        const bool in = X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz;
-        g[t] = (in && a.node[((int64_t)Z * a.ny + Y) * a.nx + X] == J) ? St(1) : St(0);
-    }
+    const int wb = a.wb, wb2 = wb * wb, wb3 = wb2 * wb;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= wb3) return;
+    const int jb = blockIdx.y;
+    const int J = a.batch[jb];
+    const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
+    const int X = (bx - a.K) * a.B + q % wb, Y = (by - a.K) * a.B + (q / wb) % wb, Z = (bz - a.K) * a.B + q / wb2;
+    const bool in = X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz;
+    g[(int64_t)jb * wb3 + q] = (in && a.node[((int64_t)Z * a.ny + Y) * a.nx + X] == J) ? St(1) : St(0);
 }
 
 // One explicit sub-step of every window of the batch: terms in the order -x,
@@ -228,40 +225,38 @@ __global__ void nodewin_init_kernel(NodeWinArgs a, St *__restrict__ g)
 // (coefficients of the domain's owned faces); cells outside the domain stay
 // 0, and far-field cells are held at 0 when a.sink (they absorb).
 template <typename St>
-__global__ void nodewin_substep_kernel(NodeWinArgs a, const St *__restrict__ in, St *__restrict__ out)
+__global__ void nodewin_substep_kernel(NodeWinArgs a, const St *__restrict__ in_all, St *__restrict__ out_all)
 {
-    const int wb = a.wb;
-    const int64_t wb2 = (int64_t)wb * wb, wb3 = wb2 * wb;
-    const int64_t total = wb3 * a.n_batch;
+    const int wb = a.wb, wb2 = wb * wb, wb3 = wb2 * wb;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= wb3) return;
+    const int jb = blockIdx.y;
+    const St *in = in_all + (int64_t)jb * wb3;
+    St *out = out_all + (int64_t)jb * wb3;
+    const int J = a.batch[jb];
+    const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
+    const int qx = q % wb, qy = (q / wb) % wb, qz = q / wb2;
+    const int X = (bx - a.K) * a.B + qx, Y = (by - a.K) * a.B + qy, Z = (bz - a.K) * a.B + qz;
+    if (!(X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz)) {
+        out[q] = St(0);
+        return;
+    }
     const St *lx = (const St *)a.lx, *ly = lx + a.n, *lz = ly + a.n;
     const int64_t sy = a.nx, sz = (int64_t)a.nx * a.ny;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int jb = (int)(t / wb3);
-        const int64_t q = t - jb * wb3;
-        const int J = a.batch[jb];
-        const int bx = J % a.ncx, by = (J / a.ncx) % a.ncy, bz = J / (a.ncx * a.ncy);
-        const int qx = (int)(q % wb), qy = (int)((q / wb) % wb), qz = (int)(q / wb2);
-        const int X = (bx - a.K) * a.B + qx, Y = (by - a.K) * a.B + qy, Z = (bz - a.K) * a.B + qz;
-        if (!(X >= 0 && X < a.nx && Y >= 0 && Y < a.ny && Z >= 0 && Z < a.nz)) {
-            out[t] = St(0);
-            continue;
-        }
-        const int64_t i = Z * sz + Y * sy + X;
-        if (a.sink && a.node[i] == COARSE_RESERVOIR) {
-            out[t] = St(0);
-            continue;
-        }
-        const St gv = in[t];
-        St acc = gv;
-        if (qx > 0 && X > 0) acc += lx[i - 1] * (in[t - 1] - gv);
-        if (qx < wb - 1 && X < a.nx - 1) acc += lx[i] * (in[t + 1] - gv);
-        if (qy > 0 && Y > 0) acc += ly[i - sy] * (in[t - wb] - gv);
-        if (qy < wb - 1 && Y < a.ny - 1) acc += ly[i] * (in[t + wb] - gv);
-        if (qz > 0 && Z > 0) acc += lz[i - sz] * (in[t - wb2] - gv);
-        if (qz < wb - 1 && Z < a.nz - 1) acc += lz[i] * (in[t + wb2] - gv);
-        out[t] = acc;
+    const int64_t i = Z * sz + Y * sy + X;
+    if (a.sink && a.node[i] == COARSE_RESERVOIR) {
+        out[q] = St(0);
+        return;
     }
+    const St gv = in[q];
+    St acc = gv;
+    if (qx > 0 && X > 0) acc += lx[i - 1] * (in[q - 1] - gv);
+    if (qx < wb - 1 && X < a.nx - 1) acc += lx[i] * (in[q + 1] - gv);
+    if (qy > 0 && Y > 0) acc += ly[i - sy] * (in[q - wb] - gv);
+    if (qy < wb - 1 && Y < a.ny - 1) acc += ly[i] * (in[q + wb] - gv);
+    if (qz > 0 && Z > 0) acc += lz[i - sz] * (in[q - wb2] - gv);
+    if (qz < wb - 1 && Z < a.nz - 1) acc += lz[i] * (in[q + wb2] - gv);
+    out[q] = acc;
 }
 
 // Binning of the batch's windows, one workgroup per node J: wave w sums the
@@ -649,15 +644,15 @@ hipError_t launch_nodewin(int fp64, const NodeWinArgs &a, int n_sub, void *ga, v
 {
     if (a.n_batch <= 0) return hipSuccess;
     if (2 * a.K + 1 > 17) return hipErrorInvalidValue;
-    const int64_t total = (int64_t)a.wb * a.wb * a.wb * a.n_batch;
-    const unsigned g = grid_for(total);
+    if ((int64_t)a.wb * a.wb * a.wb > 0x7fffffffLL || a.n_batch > 65535) return hipErrorInvalidValue;
+    const dim3 g((unsigned)(((int64_t)a.wb * a.wb * a.wb + 255) / 256), (unsigned)a.n_batch);
     hipError_t e;
     if (fp64) {
         double *in = (double *)ga, *out = (double *)gb;
-        hipLaunchKernelGGL(nodewin_init_kernel<double>, dim3(g), dim3(256), 0, st, a, in);
+        hipLaunchKernelGGL(nodewin_init_kernel<double>, g, dim3(256), 0, st, a, in);
         e = hipGetLastError();
         for (int k = 0; k < n_sub && e == hipSuccess; ++k) {
-            hipLaunchKernelGGL(nodewin_substep_kernel<double>, dim3(g), dim3(256), 0, st, a, (const double *)in, out);
+            hipLaunchKernelGGL(nodewin_substep_kernel<double>, g, dim3(256), 0, st, a, (const double *)in, out);
             e = hipGetLastError();
             double *t = in; in = out; out = t;
         }
@@ -666,10 +661,10 @@ hipError_t launch_nodewin(int fp64, const NodeWinArgs &a, int n_sub, void *ga, v
                                (const double *)in, count, S);
     } else {
         float *in = (float *)ga, *out = (float *)gb;
-        hipLaunchKernelGGL(nodewin_init_kernel<float>, dim3(g), dim3(256), 0, st, a, in);
+        hipLaunchKernelGGL(nodewin_init_kernel<float>, g, dim3(256), 0, st, a, in);
         e = hipGetLastError();
         for (int k = 0; k < n_sub && e == hipSuccess; ++k) {
-            hipLaunchKernelGGL(nodewin_substep_kernel<float>, dim3(g), dim3(256), 0, st, a, (const float *)in, out);
+            hipLaunchKernelGGL(nodewin_substep_kernel<float>, g, dim3(256), 0, st, a, (const float *)in, out);
             e = hipGetLastError();
             float *t = in; in = out; out = t;
         }

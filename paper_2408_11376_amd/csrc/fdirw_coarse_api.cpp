@@ -104,6 +104,12 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
         return fail(FDIRW_E_ARG, "r = %d needs ceil(r / block) <= %d (block = %d)", d->r, FDIRW_MAX_COARSE_K, block);
     if (node_windows && velocity)
         return fail(FDIRW_E_UNSUPPORTED, "steady flow needs r <= %d (per-source kernels)", FDIRW_MAX_RADIUS);
+    if (node_windows) {
+        const int64_t wb = (int64_t)(2 * ((d->r + block - 1) / block) + 1) * block;
+        if (wb * wb * wb > 0x7fffffffLL)
+            return fail(FDIRW_E_ARG, "node window of %lld^3 cells is too large (block %d, r %d)", (long long)wb, block,
+                        d->r);
+    }
     if (prec != FDIRW_FP64 && prec != FDIRW_FP32 && prec != FDIRW_FP16_BANK && prec != FDIRW_BF16_BANK)
         return fail(FDIRW_E_ARG, "coarse P precision must be FP64, FP32, FP16_BANK or BF16_BANK (got %d)", prec);
     const auto t0 = std::chrono::steady_clock::now();
@@ -214,6 +220,7 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                 const size_t per = (size_t)wb * wb * wb * esz * 2;
                 int64_t nbat = (int64_t)(((size_t)2 << 30) / per);
                 if (nbat < 1) nbat = 1;
+                if (nbat > 65535) nbat = 65535;
                 if (nbat > (int64_t)ids.size()) nbat = (int64_t)ids.size();
                 int *dids = nullptr;
                 void *ga = nullptr, *gb = nullptr;
