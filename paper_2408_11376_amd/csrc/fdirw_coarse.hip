@@ -396,12 +396,14 @@ constexpr int MAP_NT = 256;
 __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
                                                             const double *__restrict__ count, int nx, int ny, int nz,
                                                             int B, int ncx, int ncy, int ncz, int K,
-                                                            double *__restrict__ cpad)
+                                                            double *__restrict__ cpad, const int *__restrict__ used,
+                                                            int64_t n_used)
 {
-    const int64_t I = blockIdx.x * (int64_t)(MAP_NT / 64) + (threadIdx.x >> 6);
+    const int64_t wv = blockIdx.x * (int64_t)(MAP_NT / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
-    if (I >= n_nodes) return;                                     // uniform per wave
+    if (wv >= (used ? n_used : n_nodes)) return;                  // uniform per wave
+    const int64_t I = used ? used[wv] : wv;
     const double nI = count[I];
     if (!(nI > 0.0)) return;
     const int bx = (int)(I % ncx), by = (int)((I / ncx) % ncy), bz = (int)(I / ((int64_t)ncx * ncy));
@@ -740,7 +742,8 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
 }
 
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
-                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense)
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense,
+                             const int *used, int64_t n_used)
 {
     if (dense && B <= 256) {
         if (ncx <= 0 || ncy <= 0 || ncz <= 0) return hipSuccess;
@@ -748,11 +751,11 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
                            count, nx, ny, nz, B, ncx, ncy, K, cpad);
         return hipGetLastError();
     }
-    const int64_t n_nodes = (int64_t)ncx * ncy * ncz;
-    const int64_t g = (n_nodes + MAP_NT / 64 - 1) / (MAP_NT / 64);
+    const int64_t waves = used ? n_used : (int64_t)ncx * ncy * ncz;
+    const int64_t g = (waves + MAP_NT / 64 - 1) / (MAP_NT / 64);
     if (g <= 0) return hipSuccess;
     hipLaunchKernelGGL(coarse_map_kernel, dim3((unsigned)g), dim3(MAP_NT), 0, st, c, node, count, nx, ny, nz, B, ncx,
-                       ncy, ncz, K, cpad);
+                       ncy, ncz, K, cpad, used, n_used);
     return hipGetLastError();
 }
 

@@ -42,10 +42,12 @@ struct Coarse {
     void *pbc = nullptr;            // double, P_BC on the padded coarse grid (far field only)
     void *groups = nullptr;         // int [n_groups]: 64-position groups of P's layout holding a node with cells
     int64_t n_groups = 0;
+    void *used = nullptr;           // int [n_used]: the nodes with cells (sparse mapping)
+    int64_t n_used = 0;
 
     ~Coarse()
     {
-        for (void *p : {node, count, P, cpad, cnew, part, pbc, groups})
+        for (void *p : {node, count, P, cpad, cnew, part, pbc, groups, used})
             if (p) (void)hipFree(p);
     }
     int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
@@ -199,9 +201,16 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                     if (any) gl.push_back((int)(g0 / 64));
                 }
                 h->n_groups = (int64_t)gl.size();
+                std::vector<int> ul;
+                for (int64_t I = 0; I < h->n_nodes; ++I)
+                    if (hc[(size_t)I] > 0.0) ul.push_back((int)I);
+                h->n_used = (int64_t)ul.size();
                 rc = coarse_alloc(&h->groups, gl.size() * sizeof(int));
+                if (!rc) rc = coarse_alloc(&h->used, ul.size() * sizeof(int));
                 if (!rc && !gl.empty())
                     e = hipMemcpyAsync(h->groups, gl.data(), gl.size() * sizeof(int), hipMemcpyHostToDevice, st);
+                if (!rc && e == hipSuccess && !ul.empty())
+                    e = hipMemcpyAsync(h->used, ul.data(), ul.size() * sizeof(int), hipMemcpyHostToDevice, st);
                 if (e == hipSuccess) e = hipStreamSynchronize(st);
                 if (rc) {
                     (void)hipFree(S);
@@ -316,7 +325,8 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                                      velocity, g.dt / d->h, fa, fa + h->n, &field, st);
             if (e == hipSuccess)
                 e = launch_coarse_map(field, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz,
-                                      block, h->ncx, h->ncy, h->ncz, h->K, (double *)h->pbc, st, h->dense);
+                                      block, h->ncx, h->ncy, h->ncz, h->K, (double *)h->pbc, st, h->dense,
+                                      (const int *)h->used, h->n_used);
             (void)hipStreamSynchronize(st);
             (void)hipFree(fa);
         }
@@ -349,7 +359,8 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
     if (ks && e == hipSuccess) e = hipEventRecord(ev.a, st);
     if (e == hipSuccess)
         e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
-                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense);
+                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense,
+                              (const int *)h->used, h->n_used);
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
                                 (const double *)h->count, (double *)h->cnew, st, cff_dev,
@@ -378,7 +389,8 @@ int coarse_map_apply(void *handle, const double *c_in, const double *cff_dev, hi
     int rc = check_handle(h);
     if (rc) return rc;
     hipError_t e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
-                                     h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense);
+                                     h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense,
+                              (const int *)h->used, h->n_used);
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
                                 h->far_field ? (const double *)h->pbc : nullptr, 0.0, (const double *)h->count,

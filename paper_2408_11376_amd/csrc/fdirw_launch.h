@@ -152,7 +152,8 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
 // one workgroup per row of blocks (most blocks hold grouped cells), else one
 // wave per node
 hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
-                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense);
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense,
+                             const int *used = nullptr, int64_t n_used = 0);   // used: the nodes with cells
 hipError_t launch_flow_window(int fp64, int r, const FlowArgs &a, hipStream_t st);
 hipError_t launch_flow_stability(int fp64, const void *lam, const double *u, int nx, int ny, int nz, double cour,
                                  unsigned long long *out, hipStream_t st);
