@@ -338,12 +338,11 @@ __global__ void coarse_finalize_kernel(const double *__restrict__ S, const doubl
 __global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__restrict__ c,
                                                              const int *__restrict__ node,
                                                              const double *__restrict__ count, int nx, int ny, int nz,
-                                                             int B, int ncx, int ncy, int K, double *__restrict__ cpad)
+                                                             int B, int ncx, int ncy, CoarsePad pad,
+                                                             double *__restrict__ cpad)
 {
     __shared__ double col[256];
-    const int px = ncx + 2 * K, py = ncy + 2 * K;
     const int by = blockIdx.x, bz = blockIdx.y;
-    double *row = cpad + ((int64_t)(bz + K) * py + (by + K)) * px;
     const int y0 = by * B, z0 = bz * B;
     const int y1 = min(ny, y0 + B), z1 = min(nz, z0 + B);
     const double *cnt = count + ((int64_t)bz * ncy + by) * ncx;
@@ -380,7 +379,7 @@ __global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__re
             if (nI > 0.0) {
                 double t = 0.0;
                 for (int k = 0; k < B; ++k) t += col[threadIdx.x * B + k];
-                row[K + bx] = t / nI;
+                cpad[coarse_pad_at(pad, bx, by, bz)] = t / nI;
             }
         }
     }
@@ -395,7 +394,7 @@ constexpr int MAP_NT = 256;
 
 __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
                                                             const double *__restrict__ count, int nx, int ny, int nz,
-                                                            int B, int ncx, int ncy, int ncz, int K,
+                                                            int B, int ncx, int ncy, int ncz, CoarsePad pad,
                                                             double *__restrict__ cpad, const int *__restrict__ used,
                                                             int64_t n_used)
 {
@@ -430,29 +429,40 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) {
-        const int px = ncx + 2 * K, py = ncy + 2 * K;
-        cpad[((int64_t)(bz + K) * py + (by + K)) * px + (bx + K)] = s / nI;
-    }
+    if (lane == 0) cpad[coarse_pad_at(pad, bx, by, bz)] = s / nI;
 }
 
 // Eq. 14 on the coarse grid: C'_I = sum over the (2K+1)^3 offsets o of
-// P[o][I] C[I - o] (FP64), with P in the bank layout of element type T and C
-// read from the padded grid.  A wave takes 64 nodes that are consecutive in
-// the layout (64 / zb chunks of zb = 16 / sizeof(T) nodes along z), so every
+// P[o][I] C[I - o] (FP64), with P in the bank layout of element type T (for
+// each offset, chunks of zb = 16 / sizeof(T) nodes consecutive along z; the
+// chunks ordered x fastest).  Two shapes, fixed by K together with the padded
+// grid's layout (coarse_pad).
+//
+// coarse_apply_rows_kernel (K < COARSE_CHUNK_MIN_K, C padded x fastest): a wave
+// takes 64 nodes that are consecutive in the layout (64 / zb chunks), so every
 // P load of the wave is one contiguous 128..512-byte run; wave w of the
-// workgroup takes the offsets with oz = w (w, w + nw, ... if 2K+1 > 16
-// waves), summing its terms in (oy, ox) order; the wave partials of a node
-// are then added in wave order (a fixed order per node).
+// workgroup takes the offsets with oz = w, summing its terms in (oy, ox)
+// order; the wave partials of a node are then added in wave order.
+//
+// coarse_apply_chunks_kernel (K >= COARSE_CHUNK_MIN_K, C padded z fastest): one
+// lane takes one chunk of the list of chunks holding a node with cells (64
+// chunks per wave; the zb entries of P of a chunk are one 16-byte load) and
+// one range of offset pairs (oy, ox): for each pair it loads the chunk's C
+// column (zb + 2K values, shared by the 2K + 1 z offsets) and, for oz = 0 ..
+// 2K, the zb entries of P, so each P element is read once and each load
+// serves zb nodes.  Terms are summed in (oy, ox, oz) order within a range;
+// coarse_apply_sum_kernel adds the ranges in order.
+//
+// Either way the sum of every node has one fixed order.
 template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
 template <> __device__ __forceinline__ double widen<double>(double v) { return v; }
 
 constexpr int APPLY_MAX_WAVES = 16;
 
-// groups (optional): the 64-position groups of P's layout to run (those that
-// hold a node with cells); else every group.
+// groups: the 64-position groups of P's layout to run (those that hold a node
+// with cells).
 template <typename T, int KW>
-__global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
+__global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_rows_kernel(
     const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz,
     const double *__restrict__ pbc_pad, double c_ff, const double *__restrict__ cff_dev,
     const double *__restrict__ count, double *__restrict__ cnew, const int *__restrict__ groups)
@@ -465,8 +475,7 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
     const int64_t plane = n_chunks * zb;
-    const int64_t grp = groups ? groups[blockIdx.x] : blockIdx.x;     // 64 nodes of the layout
-    const int64_t ch = grp * (64 / zb) + lane / zb;                    // (zg, y, x) chunk
+    const int64_t ch = (int64_t)groups[blockIdx.x] * (64 / zb) + lane / zb;   // (zg, y, x) chunk
     const int j = lane % zb;
     double acc = 0.0;
     int x = 0, y = 0, z = ncz;
@@ -482,7 +491,7 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
             const T *p = P + ch * zb + j + (int64_t)oz * kw * kw * plane;
             int o = 0;
             for (int oy = 0; oy < kw; ++oy) {
-                // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...)
+                // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...), x fastest
                 const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
                 T pv[kw];
                 double cv[kw];
@@ -503,10 +512,101 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_kernel(
         double s = 0.0;
         for (int k = 0; k < nw; ++k) s += part[k * 64 + lane];
         if (pbc_pad)                                              // far-field term of Eq. 14
-            s = __builtin_fma(pbc_pad[((int64_t)(z + K) * py + (y + K)) * px + (x + K)], cff_dev ? *cff_dev : c_ff,
-                              s);
+            s = __builtin_fma(pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)],
+                              cff_dev ? *cff_dev : c_ff, s);
         cnew[((int64_t)z * ncy + y) * ncx + x] = s;
     }
+}
+
+constexpr int APPLY_NT = 256;
+
+template <typename T, int KW>
+__global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
+    const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz,
+    const int *__restrict__ chunks, int64_t n_chunks, int64_t n_chunk_pad, int pairs_per_range, int n_split,
+    double *__restrict__ part)
+{
+    constexpr int zb = 16 / (int)sizeof(T);
+    constexpr int K = (KW - 1) / 2, NC = zb + 2 * K;               // C column: zb nodes and 2K neighbours
+    const int64_t n_waves = (n_chunk_pad / 64) * n_split;
+    const int64_t wv = blockIdx.x * (int64_t)(APPLY_NT / 64) + (threadIdx.x >> 6);
+    if (wv >= n_waves) return;                                    // uniform per wave
+    const int lane = threadIdx.x & 63;
+    const int split = (int)(wv % n_split);
+    const int64_t ci = (wv / n_split) * 64 + lane;                // slot in the chunk list
+    double acc[zb];
+#pragma unroll
+    for (int j = 0; j < zb; ++j) acc[j] = 0.0;
+    if (ci < n_chunks) {
+        const int64_t ch = chunks[ci];                            // (zg, y, x) chunk of P's layout
+        const int x = (int)(ch % ncx), y = (int)((ch / ncx) % ncy);
+        const int z0 = (int)(ch / ((int64_t)ncx * ncy)) * zb;
+        const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
+        const CoarsePad pad = coarse_pad(ncx, ncy, ncz, K);
+        const T *p0 = P + ch * zb;
+        const int q0 = split * pairs_per_range;
+        const int q1 = q0 + pairs_per_range < KW * KW ? q0 + pairs_per_range : KW * KW;
+        for (int q = q0; q < q1; ++q) {
+            const int oy = q / KW, ox = q - oy * KW;
+            // padded z of node z0 + j and offset oz: z0 + j - oz + 2K, i.e. column entry j + 2K - oz
+            const double *colp = cpad + coarse_pad_at(pad, x - ox + K, y - oy + K, z0 - K);
+            double col[NC];
+#pragma unroll
+            for (int t = 0; t < NC; t += 2) {
+                const double2 v = *(const double2 *)(colp + t);
+                col[t] = v.x;
+                col[t + 1] = v.y;
+            }
+            uint4 pv[KW];
+#pragma unroll
+            for (int oz = 0; oz < KW; ++oz) pv[oz] = *(const uint4 *)(p0 + ((int64_t)(oz * KW + oy) * KW + ox) * plane);
+#pragma unroll
+            for (int oz = 0; oz < KW; ++oz) {
+                T e[zb];
+                __builtin_memcpy(e, &pv[oz], 16);
+#pragma unroll
+                for (int j = 0; j < zb; ++j) acc[j] = __builtin_fma(widen<T>(e[j]), col[j + 2 * K - oz], acc[j]);
+            }
+        }
+    }
+    double *out = part + ((int64_t)split * n_chunk_pad + ci) * zb;
+#pragma unroll
+    for (int j = 0; j < zb; j += 2) *(double2 *)(out + j) = make_double2(acc[j], acc[j + 1]);
+}
+
+// C'_I = the ranges' partial sums added in range order, plus P_BC c_ff with a
+// far field; nodes without grouped cells are never read back and not written.
+__global__ void coarse_apply_sum_kernel(const double *__restrict__ part, const int *__restrict__ chunks,
+                                        int64_t n_chunks, int64_t n_chunk_pad, int n_split, int zb, int ncx, int ncy,
+                                        int ncz, int K, const double *__restrict__ count,
+                                        const double *__restrict__ pbc_pad, double c_ff,
+                                        const double *__restrict__ cff_dev, double *__restrict__ cnew)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_chunks * zb) return;
+    const int64_t ci = t / zb;
+    const int j = (int)(t - ci * zb);
+    const int64_t ch = chunks[ci];
+    const int x = (int)(ch % ncx), y = (int)((ch / ncx) % ncy);
+    const int z = (int)(ch / ((int64_t)ncx * ncy)) * zb + j;
+    if (z >= ncz) return;
+    const int64_t I = ((int64_t)z * ncy + y) * ncx + x;
+    if (!(count[I] > 0.0)) return;
+    // ranges added in order; sixteen loads in flight ahead of the additions
+    const double *pp = part + ci * zb + j;
+    const int64_t stride = n_chunk_pad * zb;
+    double s = 0.0;
+    for (int k = 0; k < n_split; k += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = k + u < n_split ? pp[(int64_t)(k + u) * stride] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (k + u < n_split) s += v[u];
+    }
+    if (pbc_pad)                                                  // far-field term of Eq. 14
+        s = __builtin_fma(pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)], cff_dev ? *cff_dev : c_ff, s);
+    cnew[I] = s;
 }
 
 // Eq. 15: every grouped cell takes its node's value, the others keep theirs;
@@ -748,41 +848,86 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
     if (dense && B <= 256) {
         if (ncx <= 0 || ncy <= 0 || ncz <= 0) return hipSuccess;
         hipLaunchKernelGGL(coarse_map_rows_kernel, dim3((unsigned)ncy, (unsigned)ncz), dim3(256), 0, st, c, node,
-                           count, nx, ny, nz, B, ncx, ncy, K, cpad);
+                           count, nx, ny, nz, B, ncx, ncy, coarse_pad(ncx, ncy, ncz, K), cpad);
         return hipGetLastError();
     }
     const int64_t waves = used ? n_used : (int64_t)ncx * ncy * ncz;
     const int64_t g = (waves + MAP_NT / 64 - 1) / (MAP_NT / 64);
     if (g <= 0) return hipSuccess;
     hipLaunchKernelGGL(coarse_map_kernel, dim3((unsigned)g), dim3(MAP_NT), 0, st, c, node, count, nx, ny, nz, B, ncx,
-                       ncy, ncz, K, cpad, used, n_used);
+                       ncy, ncz, coarse_pad(ncx, ncy, ncz, K), cpad, used, n_used);
     return hipGetLastError();
 }
 
-template <typename T, int KW>
-static hipError_t apply_kw(const void *P, const double *cpad, int ncx, int ncy, int ncz, const double *pbc_pad,
-                           double c_ff, const double *cff_dev, const double *count, double *cnew,
-                           const int *groups, int64_t n_groups, hipStream_t st)
+int coarse_apply_zb(int prec) { return 16 / (prec == M_FP64 ? 8 : (prec == M_FP32 ? 4 : 2)); }
+
+// Offset pairs per range and the number of ranges: enough waves in flight to
+// cover the chip (~8 per CU), whole pairs per range.
+static void apply_ranges(int K, int64_t n_chunks, int *pairs_per_range, int *n_split)
 {
-    constexpr int nw = KW < APPLY_MAX_WAVES ? KW : APPLY_MAX_WAVES;
-    constexpr int zb = 16 / (int)sizeof(T);
-    const int64_t n_chunks = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx;
-    const unsigned g = groups ? (unsigned)n_groups : (unsigned)((n_chunks * zb + 63) / 64);
-    if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL((coarse_apply_kernel<T, KW>), dim3(g), dim3(64 * nw), 0, st, (const T *)P, cpad, ncx, ncy,
-                       ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups);
+    const int n_pairs = (2 * K + 1) * (2 * K + 1);
+    const int64_t groups = (n_chunks + 63) / 64;
+    int64_t want = groups > 0 ? (2048 + groups - 1) / groups : 1;
+    if (want > n_pairs) want = n_pairs;
+    if (want < 1) want = 1;
+    *pairs_per_range = (int)((n_pairs + want - 1) / want);
+    *n_split = (n_pairs + *pairs_per_range - 1) / *pairs_per_range;
+}
+
+int coarse_apply_split(int K, int64_t n_chunks)
+{
+    if (K < COARSE_CHUNK_MIN_K) return 1;
+    int ppr = 0, ns = 0;
+    apply_ranges(K, n_chunks, &ppr, &ns);
+    return ns;
+}
+
+int64_t coarse_apply_part_elems(int prec, int K, int64_t n_chunks)
+{
+    if (K < COARSE_CHUNK_MIN_K) return 0;
+    const int64_t pad = (n_chunks + 63) / 64 * 64;
+    return (int64_t)coarse_apply_split(K, n_chunks) * pad * coarse_apply_zb(prec);
+}
+
+// Arguments of either product shape.
+struct ApplyCall {
+    const void *P;
+    const double *cpad;
+    int ncx, ncy, ncz;
+    const double *pbc_pad;
+    double c_ff;
+    const double *cff_dev, *count;
+    double *cnew;
+    const int *list;
+    int64_t n_list;
+    int ppr, ns;
+    double *part;
+};
+
+template <typename T, int KW>
+static hipError_t apply_kw(const ApplyCall &a, hipStream_t st)
+{
+    constexpr int K = (KW - 1) / 2;
+    if constexpr (K < COARSE_CHUNK_MIN_K) {
+        constexpr int nw = KW < APPLY_MAX_WAVES ? KW : APPLY_MAX_WAVES;
+        hipLaunchKernelGGL((coarse_apply_rows_kernel<T, KW>), dim3((unsigned)a.n_list), dim3(64 * nw), 0, st,
+                           (const T *)a.P, a.cpad, a.ncx, a.ncy, a.ncz, a.pbc_pad, a.c_ff, a.cff_dev, a.count, a.cnew,
+                           a.list);
+    } else {
+        const int64_t pad = (a.n_list + 63) / 64 * 64;
+        const int64_t waves = pad / 64 * a.ns;
+        const int64_t g = (waves + APPLY_NT / 64 - 1) / (APPLY_NT / 64);
+        hipLaunchKernelGGL((coarse_apply_chunks_kernel<T, KW>), dim3((unsigned)g), dim3(APPLY_NT), 0, st,
+                           (const T *)a.P, a.cpad, a.ncx, a.ncy, a.ncz, a.list, a.n_list, pad, a.ppr, a.ns, a.part);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t apply_t(int K, const void *P, const double *cpad, int ncx, int ncy, int ncz,
-                          const double *pbc_pad, double c_ff, const double *cff_dev, const double *count,
-                          double *cnew, const int *groups, int64_t n_groups, hipStream_t st)
+static hipError_t apply_t(int K, const ApplyCall &a, hipStream_t st)
 {
 #define FDIRW_APPLY_CASE(k)                                                                                        \
-    case k:                                                                                                       \
-        return apply_kw<T, 2 * k + 1>(P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,        \
-                                      n_groups, st);
+    case k: return apply_kw<T, 2 * k + 1>(a, st);
     switch (K) {
         FDIRW_APPLY_CASE(0)
         FDIRW_APPLY_CASE(1)
@@ -798,31 +943,33 @@ static hipError_t apply_t(int K, const void *P, const double *cpad, int ncx, int
 #undef FDIRW_APPLY_CASE
 }
 
-int64_t coarse_apply_positions(int prec, int ncx, int ncy, int ncz)
-{
-    const int zb = 16 / (prec == M_FP64 ? 8 : (prec == M_FP32 ? 4 : 2));
-    return (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
-}
-
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                const double *pbc_pad, double c_ff, const double *count, double *cnew,
-                               hipStream_t st, const double *cff_dev, const int *groups, int64_t n_groups)
+                               hipStream_t st, const double *cff_dev, const int *list, int64_t n_list,
+                               int n_split, double *part)
 {
+    if (n_list <= 0) return hipSuccess;
+    if (K < 0 || K > 8) return hipErrorInvalidValue;
+    ApplyCall a{P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, list, n_list, 0, 1, part};
+    if (K >= COARSE_CHUNK_MIN_K) {
+        apply_ranges(K, n_list, &a.ppr, &a.ns);
+        if (a.ns != n_split) return hipErrorInvalidValue;         // part was sized for another split
+    }
+    hipError_t e;
     switch (prec) {
-    case M_FP64:
-        return apply_t<double>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
-                               n_groups, st);
-    case M_FP32:
-        return apply_t<float>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
-                              n_groups, st);
-    case M_F16BANK:
-        return apply_t<_Float16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
-                                 n_groups, st);
-    case M_BF16BANK:
-        return apply_t<__bf16>(K, P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, groups,
-                               n_groups, st);
+    case M_FP64: e = apply_t<double>(K, a, st); break;
+    case M_FP32: e = apply_t<float>(K, a, st); break;
+    case M_F16BANK: e = apply_t<_Float16>(K, a, st); break;
+    case M_BF16BANK: e = apply_t<__bf16>(K, a, st); break;
     default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess || K < COARSE_CHUNK_MIN_K) return e;
+    const int zb = coarse_apply_zb(prec);
+    const int64_t nt = n_list * zb;
+    hipLaunchKernelGGL(coarse_apply_sum_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, part, list,
+                       n_list, (n_list + 63) / 64 * 64, a.ns, zb, ncx, ncy, ncz, K, count, pbc_pad, c_ff, cff_dev,
+                       cnew);
+    return hipGetLastError();
 }
 
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,

@@ -34,20 +34,22 @@ struct Coarse {
     void *node = nullptr;           // int [N]
     void *count = nullptr;          // double [n_nodes]
     void *P = nullptr;              // esz * (2K+1)^3 * plane bytes
-    void *cpad = nullptr;           // double [(ncz+2K)(ncy+2K)(ncx+2K)]
+    void *cpad = nullptr;           // double [coarse_pad(...).size]: the padded coarse grid
     void *cnew = nullptr;           // double [n_nodes]
     void *part = nullptr;           // field-sum partials
     bool far_field = false;         // reservoir (far-field boundary) phases present
     bool dense = true;              // most nodes hold grouped cells (mapping by rows of blocks)
     void *pbc = nullptr;            // double, P_BC on the padded coarse grid (far field only)
-    void *groups = nullptr;         // int [n_groups]: 64-position groups of P's layout holding a node with cells
-    int64_t n_groups = 0;
+    void *list = nullptr;           // int [n_list]: the product's units of P's layout holding a node with cells
+    int64_t n_list = 0;             // (64-position groups for K < COARSE_CHUNK_MIN_K, else chunks)
+    void *apart = nullptr;          // double: the product's partial sums, n_split ranges of offset pairs
+    int n_split = 1;
     void *used = nullptr;           // int [n_used]: the nodes with cells (sparse mapping)
     int64_t n_used = 0;
 
     ~Coarse()
     {
-        for (void *p : {node, count, P, cpad, cnew, part, pbc, groups, used})
+        for (void *p : {node, count, P, cpad, cnew, part, pbc, list, apart, used})
             if (p) (void)hipFree(p);
     }
     int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
@@ -137,7 +139,7 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
     const int zb = 16 / (int)h->esz;
     h->plane = (int64_t)((h->ncz + zb - 1) / zb) * h->ncy * h->ncx * zb;
     const int nb = h->nb();
-    const int64_t n_pad = (int64_t)(h->ncx + 2 * h->K) * (h->ncy + 2 * h->K) * (h->ncz + 2 * h->K);
+    const int64_t n_pad = coarse_pad(h->ncx, h->ncy, h->ncz, h->K).size;
     double *S = nullptr;
     hipError_t e = hipSuccess;
     {
@@ -185,30 +187,36 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             int64_t used = 0;
             for (double v : hc) used += v > 0.0;
             h->dense = 2 * used >= h->n_nodes;
-            // the product's 64-position groups of P's layout that hold a node with cells
+            // the product's units of P's layout that hold a node with cells:
+            // chunks (zb nodes along z), or groups of 64 / zb chunks for small K
             if (e == hipSuccess) {
-                const int zb = 16 / (int)h->esz;
-                const int64_t npos = (int64_t)((h->ncz + zb - 1) / zb) * h->ncy * h->ncx * zb;
+                const int zb = coarse_apply_zb(prec);
+                const int64_t n_ch = (int64_t)((h->ncz + zb - 1) / zb) * h->ncy * h->ncx;
+                const int64_t per = h->K >= COARSE_CHUNK_MIN_K ? 1 : 64 / zb;    // chunks per unit
                 std::vector<int> gl;
-                for (int64_t g0 = 0; g0 < npos; g0 += 64) {
+                for (int64_t u0 = 0; u0 < n_ch; u0 += per) {
                     bool any = false;
-                    for (int64_t t = g0; t < g0 + 64 && t < npos && !any; ++t) {
-                        const int64_t ch = t / zb;
+                    for (int64_t ch = u0; ch < u0 + per && ch < n_ch && !any; ++ch) {
                         const int x = (int)(ch % h->ncx), y = (int)((ch / h->ncx) % h->ncy);
-                        const int z = (int)(ch / ((int64_t)h->ncx * h->ncy)) * zb + (int)(t % zb);
-                        any = z < h->ncz && hc[(size_t)(((int64_t)z * h->ncy + y) * h->ncx + x)] > 0.0;
+                        const int z0 = (int)(ch / ((int64_t)h->ncx * h->ncy)) * zb;
+                        for (int z = z0; z < z0 + zb && z < h->ncz && !any; ++z)
+                            any = hc[(size_t)(((int64_t)z * h->ncy + y) * h->ncx + x)] > 0.0;
                     }
-                    if (any) gl.push_back((int)(g0 / 64));
+                    if (any) gl.push_back((int)(u0 / per));
                 }
-                h->n_groups = (int64_t)gl.size();
+                h->n_list = (int64_t)gl.size();
+                h->n_split = coarse_apply_split(h->K, h->n_list);
                 std::vector<int> ul;
                 for (int64_t I = 0; I < h->n_nodes; ++I)
                     if (hc[(size_t)I] > 0.0) ul.push_back((int)I);
                 h->n_used = (int64_t)ul.size();
-                rc = coarse_alloc(&h->groups, gl.size() * sizeof(int));
+                rc = coarse_alloc(&h->list, gl.size() * sizeof(int));
                 if (!rc) rc = coarse_alloc(&h->used, ul.size() * sizeof(int));
+                if (!rc)
+                    rc = coarse_alloc(&h->apart,
+                                      (size_t)coarse_apply_part_elems(prec, h->K, h->n_list) * sizeof(double));
                 if (!rc && !gl.empty())
-                    e = hipMemcpyAsync(h->groups, gl.data(), gl.size() * sizeof(int), hipMemcpyHostToDevice, st);
+                    e = hipMemcpyAsync(h->list, gl.data(), gl.size() * sizeof(int), hipMemcpyHostToDevice, st);
                 if (!rc && e == hipSuccess && !ul.empty())
                     e = hipMemcpyAsync(h->used, ul.data(), ul.size() * sizeof(int), hipMemcpyHostToDevice, st);
                 if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -364,7 +372,7 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
     if (e == hipSuccess)
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
                                 (const double *)h->count, (double *)h->cnew, st, cff_dev,
-                                (const int *)h->groups, h->n_groups);
+                                (const int *)h->list, h->n_list, h->n_split, (double *)h->apart);
     if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
     if (ks && e == hipSuccess) e = hipEventRecord(ev.b, st);
     if (e != hipSuccess) return hip_fail(e, "coarse step launch");
@@ -395,7 +403,7 @@ int coarse_map_apply(void *handle, const double *c_in, const double *cff_dev, hi
         e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
                                 h->far_field ? (const double *)h->pbc : nullptr, 0.0, (const double *)h->count,
                                 (double *)h->cnew, st, h->far_field ? cff_dev : nullptr,
-                                (const int *)h->groups, h->n_groups);
+                                (const int *)h->list, h->n_list, h->n_split, (double *)h->apart);
     if (e != hipSuccess) return hip_fail(e, "coarse mapping / product launch");
     *cnew = (const double *)h->cnew;
     return FDIRW_OK;
@@ -483,13 +491,13 @@ int fdirw_coarse_pbc(void *handle, double *pbc_host)
         for (int64_t I = 0; I < h->n_nodes; ++I) pbc_host[I] = 0.0;
         return FDIRW_OK;
     }
-    const int px = h->ncx + 2 * h->K, py = h->ncy + 2 * h->K, pz = h->ncz + 2 * h->K;
-    std::vector<double> pad((size_t)px * py * pz);
+    const CoarsePad cp = coarse_pad(h->ncx, h->ncy, h->ncz, h->K);
+    std::vector<double> pad((size_t)cp.size);
     hipError_t e = hipMemcpy(pad.data(), h->pbc, pad.size() * sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "P_BC copy");
     for (int64_t I = 0; I < h->n_nodes; ++I) {
         const int x = (int)(I % h->ncx), y = (int)((I / h->ncx) % h->ncy), z = (int)(I / ((int64_t)h->ncx * h->ncy));
-        pbc_host[I] = pad[((size_t)(z + h->K) * py + (y + h->K)) * px + (x + h->K)];
+        pbc_host[I] = pad[(size_t)coarse_pad_at(cp, x, y, z)];
     }
     return FDIRW_OK;
 }

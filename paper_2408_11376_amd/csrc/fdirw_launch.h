@@ -148,6 +148,40 @@ hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int 
 hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st);
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
                                   int ncy, int ncz, void *P, hipStream_t st);
+// The coarse grid padded by K on every side: node (x, y, z) sits at
+// (x + K) sx + (y + K) sy + (z + K) sz.  Two layouts, fixed by K: for small
+// windows x fastest (the product with one lane per node reads runs along x);
+// for K >= COARSE_CHUNK_MIN_K z fastest, with the z extent ncz rounded up to
+// 8, plus 2K (the product with one lane per chunk of P's layout reads one
+// contiguous, 16-byte aligned z column per offset pair).
+constexpr int COARSE_CHUNK_MIN_K = 4;
+struct CoarsePad {
+    int K;
+    int64_t sx, sy, sz, size;
+};
+__host__ __device__ inline CoarsePad coarse_pad(int ncx, int ncy, int ncz, int K)
+{
+    CoarsePad p;
+    p.K = K;
+    const int64_t px = ncx + 2 * K, py = ncy + 2 * K;
+    if (K >= COARSE_CHUNK_MIN_K) {
+        const int64_t pz = (ncz + 7) / 8 * 8 + 2 * K;
+        p.sz = 1;
+        p.sy = pz;
+        p.sx = py * pz;
+        p.size = px * py * pz;
+    } else {
+        p.sx = 1;
+        p.sy = px;
+        p.sz = px * py;
+        p.size = px * py * (ncz + 2 * K);
+    }
+    return p;
+}
+__host__ __device__ inline int64_t coarse_pad_at(const CoarsePad &p, int x, int y, int z)
+{
+    return (x + p.K) * p.sx + (y + p.K) * p.sy + (z + p.K) * p.sz;
+}
 // writes the nodes with grouped cells only: cpad must be zeroed once; dense:
 // one workgroup per row of blocks (most blocks hold grouped cells), else one
 // wave per node
@@ -159,12 +193,20 @@ hipError_t launch_flow_stability(int fp64, const void *lam, const double *u, int
                                  unsigned long long *out, hipStream_t st);
 hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, const void *G, int64_t src_base,
                              int64_t n_src, hipStream_t st);
+// Product C' = P C (+ P_BC c_ff) over the nodes of the listed units of P's
+// layout (a chunk: zb = 16 / element size nodes along z at one (x, y)).  K <
+// COARSE_CHUNK_MIN_K: list = the 64-position groups holding a node with cells,
+// one lane per node; else list = the chunks holding a node with cells, one
+// lane per chunk, the offset pairs (oy, ox) split into n_split ranges whose
+// partial sums go to part (coarse_apply_part_elems doubles) and are added in
+// range order by a second launch.
 hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
                                const double *pbc_pad, double c_ff, const double *count, double *cnew,
-                               hipStream_t st, const double *cff_dev = nullptr,    // cff_dev set: c_ff read from it
-                               const int *groups = nullptr, int64_t n_groups = 0);   // the 64-node groups to run
-// positions of P's layout (nodes padded to zb along z); group g covers [64 g, 64 g + 64)
-int64_t coarse_apply_positions(int prec, int ncx, int ncy, int ncz);
+                               hipStream_t st, const double *cff_dev,    // cff_dev set: c_ff read from it
+                               const int *list, int64_t n_list, int n_split, double *part);
+int coarse_apply_zb(int prec);                                  // nodes per chunk
+int coarse_apply_split(int K, int64_t n_chunks);                // the number of pair ranges (1 below the chunk K)
+int64_t coarse_apply_part_elems(int prec, int K, int64_t n_chunks);
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,
                                hipStream_t st);
 // Integrated near-field solver (fdirw_mp.hip).  Cell roles come from the

@@ -43,8 +43,10 @@ def _offset_form(P, cshape, K):
     return out
 
 
+# K = ceil(r / B) from 1 to 5: K >= 4 runs the product with one lane per chunk
+# of P's layout and a second, ordered summing launch (ragged z chunks here)
 CASES = [((6, 7, 5), 2, 6, 2, 11), ((9, 8, 10), 3, 10, 3, 12), ((5, 4, 6), 2, 5, 8, 13), ((7, 6, 8), 2, 8, 1, 14),
-         ((3, 1, 70), 2, 4, 5, 15)]
+         ((3, 1, 70), 2, 4, 5, 15), ((7, 6, 5), 4, 6, 1, 21), ((9, 5, 6), 5, 7, 1, 22), ((11, 5, 6), 8, 6, 2, 23)]
 
 
 @pytest.mark.parametrize("shape,r,n_sub,B,seed", CASES)
@@ -67,14 +69,16 @@ def test_matrix_and_step_fp64_match_oracle(shape, r, n_sub, B, seed):
     cg.close()
 
 
+@pytest.mark.parametrize("B,r", [(3, 3), (1, 5)])
 @pytest.mark.parametrize("prec,kind,tol", [(fd.FP32, "max", 1e-6), (fd.FP16_BANK, "l1", 1e-3),
                                            (fd.BF16_BANK, "l1", 5e-3)])
-def test_reduced_precision_p(prec, kind, tol):
-    d = synth.random_small((12, 11, 13), 3, r=3, n_sub=12, seed=16)
+def test_reduced_precision_p(prec, kind, tol, B, r):
+    d = synth.random_small((12, 11, 13), 3, r=r, n_sub=12, seed=16)
     p = oracle.Problem.from_domain(d)
-    P = coarse.coarse_matrix(p, 3)
-    want = coarse.step(p, P, d.c0, 3)
-    cg = fd.Coarse(_dev_domain(d), 3, prec)
+    P = coarse.coarse_matrix(p, B)
+    want = coarse.step(p, P, d.c0, B)
+    cg = fd.Coarse(_dev_domain(d), B, prec)
+    assert cg.K == -(-r // B)
     out, st = cg.step(to_dev(d.c0), stats=True)
     got = to_host(out)
     if kind == "max":
