@@ -231,6 +231,7 @@ struct MpLocalArgs {
     const int *node;
     const uint8_t *scode;             // [N] compact solid-phase index of every cell (solid cells read)
     const double *dsolc;              // D A / RT of the solid phases, by compact index
+    int n_solid;                      // entries of dsolc
     const double *cnew;               // node values after the product
     const double *c_in;               // the step's input field (solid cells)
     double *out;                      // the step's output field (active cells written)

@@ -396,7 +396,8 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
     // 39.8 KB: four workgroups per CU
     __shared__ double v[MP_BOX];
     __shared__ signed char role[MP_BOX];                          // -1 none, 0 liquid, 1 + s solid of phase s
-    __shared__ uint16_t pl[MP_PAIR_CAP];
+    __shared__ __align__(8) uint16_t pl[MP_PAIR_CAP];            // then the solid lambda table
+    static_assert(MP_PAIR_CAP * sizeof(uint16_t) >= MP_MAX_SOLID_PHASES * sizeof(double), "lambda table");
     const int t = a.tiles[blockIdx.x];
     int x0, y0, z0;
     mp_tile_origin(t, a.nx, a.ny, x0, y0, z0);
@@ -456,9 +457,17 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
     mp_pass<1>(v, pl, gl, po[3] - pbase, po[4] - pbase, a);
     mp_pass<2>(v, pl, gl, po[4] - pbase, po[5] - pbase, a);
     mp_pass<2>(v, pl, gl, po[5] - pbase, po[6] - pbase, a);
-    // one solid sub-step, the writes and the partial sums
+    // one solid sub-step, the writes and the partial sums.  The pair list is
+    // no longer read (the last pass ended with a barrier): its LDS takes
+    // lambda = D A / RT dt_s / h^2 of every solid phase by compact index, the
+    // face value being the harmonic mean of the two cells' lambdas
     double sl = 0.0, ss = 0.0;
-    const double hh = a.h * a.h;
+    double *lam = reinterpret_cast<double *>(pl);
+    if (a.solid) {
+        const double sc = a.dt_s / (a.h * a.h);
+        for (int k = threadIdx.x; k < a.n_solid; k += MP_NT) lam[k] = a.dsolc[k] * sc;
+        __syncthreads();
+    }
     for (int m = threadIdx.x; m < MP_TX * MP_TY * MP_TZ; m += MP_NT) {
         const int lx = MP_H + m % MP_TX, ly = MP_H + (m / MP_TX) % MP_TY, lz = MP_H + m / (MP_TX * MP_TY);
         const int q = (lz * MP_BY + ly) * MP_BX + lx;
@@ -470,19 +479,18 @@ __global__ void __launch_bounds__(MP_NT) mp_local_kernel(MpLocalArgs a)
             sl += g;
         } else {
             if (a.solid) {
-                const double di = a.dsolc[r - 1];
+                const double li = lam[r - 1];
                 double acc = g;
-                if (di > 0.0) {
+                if (li > 0.0) {
                     const int nbq[6] = {q - 1, q + 1, q - MP_BX, q + MP_BX, q - MP_BX * MP_BY, q + MP_BX * MP_BY};
 #pragma unroll
                     for (int f = 0; f < 6; ++f) {
                         const int qq = nbq[f];
                         const int rq = role[qq];
                         if (rq < 1) continue;
-                        const double dj = a.dsolc[rq - 1];
-                        if (!(dj > 0.0)) continue;
-                        const double df = (2.0 * di) * dj / (di + dj);
-                        acc += (df * a.dt_s) / hh * (v[qq] - g);
+                        const double lj = lam[rq - 1];
+                        if (!(lj > 0.0)) continue;
+                        acc += (2.0 * li) * lj / (li + lj) * (v[qq] - g);
                     }
                 }
                 g = acc;

@@ -34,6 +34,7 @@ namespace {
 
 struct Mp {
     int dev = -1;
+    int n_solid = 0;                    // solid phases (compact indices 0 .. n_solid - 1)
     int nx = 0, ny = 0, nz = 0;
     int64_t n = 0;
     double h = 1.0, dt = 0.0;           // grid spacing, big step
@@ -243,6 +244,7 @@ int fdirw_mp_create(const fdirw_domain *d, const fdirw_mp_params *p, int32_t blo
             sidx[i] = (unsigned char)n_solid_phases;
             dc[n_solid_phases++] = h->solid[i];
         }
+    h->n_solid = n_solid_phases;
     if (n_solid_phases > MP_MAX_SOLID_PHASES) {
         (void)hipFree(cnt);
         (void)hipFree(flag);
@@ -391,6 +393,7 @@ int fdirw_mp_step(void *handle, double *c, double *c_ff, double m_total, int32_t
     a.node = node;
     a.scode = (const uint8_t *)h->scode;
     a.dsolc = (const double *)h->dsolc;
+    a.n_solid = h->n_solid;
     a.c_eq_l = h->c_eq_l; a.c_eq_s = h->c_eq_s; a.kappa_dt = h->kappa_dt;
     a.solid = h->n_sub_solid == 1 && h->n_tiles > 0;
     a.dt_s = h->dt / h->n_sub_solid;
