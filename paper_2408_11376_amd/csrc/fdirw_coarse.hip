@@ -310,13 +310,16 @@ __global__ void __launch_bounds__(NODEWIN_BIN_NT) nodewin_bin_kernel(NodeWinArgs
 }
 
 // P[o][I] = S[o][I] / N_I in the bank layout of element type B: per offset
-// plane the coarse cells are ordered [z / zb][y][x][z % zb].
+// plane of `plane` elements, chunks of zb nodes along z, chunk (z / zb, y, x)
+// (x fastest) at its own index or, with slot, at slot[chunk] (the compact
+// layout of the listed chunks; nodes of unlisted chunks hold no cells and are
+// not stored).
 template <typename B>
 __global__ void coarse_finalize_kernel(const double *__restrict__ S, const double *__restrict__ count,
-                                       int64_t n_nodes, int nb, int ncx, int ncy, int ncz, B *__restrict__ P)
+                                       int64_t n_nodes, int nb, int ncx, int ncy, int ncz, const int *__restrict__ slot,
+                                       int64_t plane, B *__restrict__ P)
 {
     constexpr int zb = 16 / (int)sizeof(B);
-    const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
     const int64_t total = (int64_t)nb * n_nodes;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -324,7 +327,9 @@ __global__ void coarse_finalize_kernel(const double *__restrict__ S, const doubl
         const int x = (int)(I % ncx), y = (int)((I / ncx) % ncy), z = (int)(I / ((int64_t)ncx * ncy));
         const double nI = count[I];
         const double v = nI > 0.0 ? S[i] / nI : 0.0;
-        P[o * plane + (((int64_t)(z / zb) * ncy + y) * ncx + x) * zb + z % zb] = (B)v;
+        const int64_t ch = ((int64_t)(z / zb) * ncy + y) * ncx + x;
+        const int64_t at = slot ? slot[ch] : ch;
+        if (at >= 0) P[o * plane + at * zb + z % zb] = (B)v;
     }
 }
 
@@ -451,7 +456,9 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
 // column (zb + 2K values, shared by the 2K + 1 z offsets) and, for oz = 0 ..
 // 2K, the zb entries of P, so each P element is read once and each load
 // serves zb nodes.  Terms are summed in (oy, ox, oz) order within a range;
-// coarse_apply_sum_kernel adds the ranges in order.
+// coarse_apply_sum_kernel adds the ranges of a node in a fixed order (ranges
+// in order within contiguous blocks, then the block sums in order).  P is
+// stored compactly: the listed chunks only, in list order.
 //
 // Either way the sum of every node has one fixed order.
 template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
@@ -541,9 +548,9 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
         const int64_t ch = chunks[ci];                            // (zg, y, x) chunk of P's layout
         const int x = (int)(ch % ncx), y = (int)((ch / ncx) % ncy);
         const int z0 = (int)(ch / ((int64_t)ncx * ncy)) * zb;
-        const int64_t plane = (int64_t)((ncz + zb - 1) / zb) * ncy * ncx * zb;
+        const int64_t plane = n_chunks * zb;                      // P stored compactly in list order
         const CoarsePad pad = coarse_pad(ncx, ncy, ncz, K);
-        const T *p0 = P + ch * zb;
+        const T *p0 = P + ci * zb;
         const int q0 = split * pairs_per_range;
         const int q1 = q0 + pairs_per_range < KW * KW ? q0 + pairs_per_range : KW * KW;
         for (int q = q0; q < q1; ++q) {
@@ -574,8 +581,13 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
     for (int j = 0; j < zb; j += 2) *(double2 *)(out + j) = make_double2(acc[j], acc[j + 1]);
 }
 
-// C'_I = the ranges' partial sums added in range order, plus P_BC c_ff with a
-// far field; nodes without grouped cells are never read back and not written.
+// C'_I = the ranges' partial sums added in a fixed order, plus P_BC c_ff with
+// a far field; nodes without grouped cells are never read back and not
+// written.  SUM_TP consecutive lanes share a node: lane u adds the u-th
+// contiguous block of ranges in order (sixteen loads in flight), and the
+// first lane adds the SUM_TP block sums in lane order.
+constexpr int SUM_TP = 8;
+
 __global__ void coarse_apply_sum_kernel(const double *__restrict__ part, const int *__restrict__ chunks,
                                         int64_t n_chunks, int64_t n_chunk_pad, int n_split, int zb, int ncx, int ncy,
                                         int ncz, int K, const double *__restrict__ count,
@@ -583,30 +595,49 @@ __global__ void coarse_apply_sum_kernel(const double *__restrict__ part, const i
                                         const double *__restrict__ cff_dev, double *__restrict__ cnew)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= n_chunks * zb) return;
-    const int64_t ci = t / zb;
-    const int j = (int)(t - ci * zb);
-    const int64_t ch = chunks[ci];
-    const int x = (int)(ch % ncx), y = (int)((ch / ncx) % ncy);
-    const int z = (int)(ch / ((int64_t)ncx * ncy)) * zb + j;
-    if (z >= ncz) return;
-    const int64_t I = ((int64_t)z * ncy + y) * ncx + x;
-    if (!(count[I] > 0.0)) return;
-    // ranges added in order; sixteen loads in flight ahead of the additions
-    const double *pp = part + ci * zb + j;
-    const int64_t stride = n_chunk_pad * zb;
-    double s = 0.0;
-    for (int k = 0; k < n_split; k += 16) {
-        double v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = k + u < n_split ? pp[(int64_t)(k + u) * stride] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (k + u < n_split) s += v[u];
+    const int64_t slot = t / SUM_TP;                              // (chunk slot, entry) of the node
+    const int sub = (int)(t % SUM_TP);
+    // every lane reaches the shuffles below: no early return
+    bool valid = slot < n_chunks * zb;
+    int64_t ci = 0, I = 0;
+    int j = 0, x = 0, y = 0, z = 0;
+    if (valid) {
+        ci = slot / zb;
+        j = (int)(slot - ci * zb);
+        const int64_t ch = chunks[ci];
+        x = (int)(ch % ncx);
+        y = (int)((ch / ncx) % ncy);
+        z = (int)(ch / ((int64_t)ncx * ncy)) * zb + j;
+        valid = z < ncz;
+        if (valid) {
+            I = ((int64_t)z * ncy + y) * ncx + x;
+            valid = count[I] > 0.0;
+        }
     }
+    double s = 0.0;
+    if (valid) {
+        const int per = (n_split + SUM_TP - 1) / SUM_TP;
+        const int k0 = sub * per, k1 = k0 + per < n_split ? k0 + per : n_split;
+        const double *pp = part + ci * zb + j;
+        const int64_t stride = n_chunk_pad * zb;
+        for (int k = k0; k < k1; k += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = k + u < k1 ? pp[(int64_t)(k + u) * stride] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (k + u < k1) s += v[u];
+        }
+    }
+    const int base = (int)(threadIdx.x & 63) & ~(SUM_TP - 1);
+    double tot = 0.0;
+#pragma unroll
+    for (int u = 0; u < SUM_TP; ++u) tot += __shfl(s, base + u, 64);
+    if (!valid || sub != 0) return;
     if (pbc_pad)                                                  // far-field term of Eq. 14
-        s = __builtin_fma(pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)], cff_dev ? *cff_dev : c_ff, s);
-    cnew[I] = s;
+        tot = __builtin_fma(pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)], cff_dev ? *cff_dev : c_ff,
+                            tot);
+    cnew[I] = tot;
 }
 
 // Eq. 15: every grouped cell takes its node's value, the others keep theirs;
@@ -816,25 +847,25 @@ hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, 
 }
 
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
-                                  int ncy, int ncz, void *P, hipStream_t st)
+                                  int ncy, int ncz, const int *slot, int64_t plane, void *P, hipStream_t st)
 {
     const unsigned g = grid_for((int64_t)nb * n_nodes);
     switch (prec) {
     case M_FP64:
         hipLaunchKernelGGL(coarse_finalize_kernel<double>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
-                           ncy, ncz, (double *)P);
+                           ncy, ncz, slot, plane, (double *)P);
         break;
     case M_FP32:
         hipLaunchKernelGGL(coarse_finalize_kernel<float>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
-                           ncy, ncz, (float *)P);
+                           ncy, ncz, slot, plane, (float *)P);
         break;
     case M_F16BANK:
         hipLaunchKernelGGL(coarse_finalize_kernel<_Float16>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
-                           ncy, ncz, (_Float16 *)P);
+                           ncy, ncz, slot, plane, (_Float16 *)P);
         break;
     case M_BF16BANK:
         hipLaunchKernelGGL(coarse_finalize_kernel<__bf16>, dim3(g), dim3(256), 0, st, S, count, n_nodes, nb, ncx,
-                           ncy, ncz, (__bf16 *)P);
+                           ncy, ncz, slot, plane, (__bf16 *)P);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -965,7 +996,7 @@ hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int 
     }
     if (e != hipSuccess || K < COARSE_CHUNK_MIN_K) return e;
     const int zb = coarse_apply_zb(prec);
-    const int64_t nt = n_list * zb;
+    const int64_t nt = n_list * zb * SUM_TP;
     hipLaunchKernelGGL(coarse_apply_sum_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, part, list,
                        n_list, (n_list + 63) / 64 * 64, a.ns, zb, ncx, ncy, ncz, K, count, pbc_pad, c_ff, cff_dev,
                        cnew);

@@ -30,7 +30,8 @@ struct Coarse {
     int64_t n_nodes = 0;
     int prec = FDIRW_FP64;          // storage of P: FP64, FP32, FP16_BANK or BF16_BANK
     size_t esz = 8;
-    int64_t plane = 0;              // elements of one offset plane of P (grouped layout)
+    int64_t plane = 0;              // elements of one offset plane of P (bank layout; compact for K >= 4)
+    std::vector<int> slot;          // K >= 4: chunk -> its place in P's compact layout (-1: not stored)
     void *node = nullptr;           // int [N]
     void *count = nullptr;          // double [n_nodes]
     void *P = nullptr;              // esz * (2K+1)^3 * plane bytes
@@ -151,7 +152,6 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
         if (!rc && velocity) rc = flow_stable(d, prec == FDIRW_FP64, lam, velocity, g.dt, st, dc);
         if (!rc) rc = coarse_alloc(&h->node, (size_t)h->n * sizeof(int));
         if (!rc) rc = coarse_alloc(&h->count, (size_t)h->n_nodes * sizeof(double));
-        if (!rc) rc = coarse_alloc(&h->P, (size_t)nb * h->plane * h->esz);
         if (!rc) rc = coarse_alloc(&h->cpad, (size_t)n_pad * sizeof(double));
         if (!rc) rc = coarse_alloc(&h->cnew, (size_t)h->n_nodes * sizeof(double));
         if (!rc) rc = coarse_alloc(&h->part, (size_t)(2 * field_sum_blocks(h->n) + 2) * sizeof(double));
@@ -174,8 +174,6 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
         if (e == hipSuccess) e = launch_fill((double *)h->cpad, n_pad, 0.0, st);
         if (e == hipSuccess && h->pbc) e = launch_fill((double *)h->pbc, n_pad, 0.0, st);
         if (e == hipSuccess) e = launch_fill(S, (int64_t)nb * h->n_nodes, 0.0, st);
-        if (e == hipSuccess)
-            e = launch_fill_u32((unsigned *)h->P, (int64_t)((size_t)nb * h->plane * h->esz / 4), 0u, st);
         if (e == hipSuccess)
             e = launch_coarse_nodes(d->label, tab, d->nx, d->ny, d->nz, block, h->ncx, h->ncy, (int *)h->node,
                                     (double *)h->count, st);
@@ -210,7 +208,17 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                 for (int64_t I = 0; I < h->n_nodes; ++I)
                     if (hc[(size_t)I] > 0.0) ul.push_back((int)I);
                 h->n_used = (int64_t)ul.size();
-                rc = coarse_alloc(&h->list, gl.size() * sizeof(int));
+                // P: every chunk of the grid (K < 4) or the listed chunks only,
+                // in list order (K >= 4); entries never written stay 0
+                if (per == 1) {
+                    h->plane = h->n_list * zb;
+                    h->slot.assign((size_t)n_ch, -1);
+                    for (size_t k = 0; k < gl.size(); ++k) h->slot[(size_t)gl[k]] = (int)k;
+                }
+                rc = coarse_alloc(&h->P, (size_t)nb * h->plane * h->esz);
+                if (!rc && h->plane > 0)
+                    e = launch_fill_u32((unsigned *)h->P, (int64_t)((size_t)nb * h->plane * h->esz / 4), 0u, st);
+                if (!rc) rc = coarse_alloc(&h->list, gl.size() * sizeof(int));
                 if (!rc) rc = coarse_alloc(&h->used, ul.size() * sizeof(int));
                 if (!rc)
                     rc = coarse_alloc(&h->apart,
@@ -338,10 +346,20 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
             (void)hipStreamSynchronize(st);
             (void)hipFree(fa);
         }
+        int *dslot = nullptr;
+        if (e == hipSuccess && !h->slot.empty()) {
+            if (coarse_alloc((void **)&dslot, h->slot.size() * sizeof(int))) e = hipErrorOutOfMemory;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(dslot, h->slot.data(), h->slot.size() * sizeof(int), hipMemcpyHostToDevice, st);
+        }
         if (e == hipSuccess)
             e = launch_coarse_finalize(prec, S, (const double *)h->count, h->n_nodes, nb, h->ncx, h->ncy, h->ncz,
-                                       h->P, st);
+                                       dslot, h->plane, h->P, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (dslot) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(dslot);
+        }
     }
     (void)hipFree(S);
     if (e != hipSuccess) {
@@ -529,7 +547,13 @@ int fdirw_coarse_matrix(void *handle, double *P_host)
         for (int64_t I = 0; I < h->n_nodes; ++I) {
             const int x = (int)(I % h->ncx), y = (int)((I / h->ncx) % h->ncy);
             const int z = (int)(I / ((int64_t)h->ncx * h->ncy));
-            const size_t k = (size_t)o * h->plane + (((size_t)(z / zb) * h->ncy + y) * h->ncx + x) * zb + z % zb;
+            const size_t ch = ((size_t)(z / zb) * h->ncy + y) * h->ncx + x;
+            const int64_t at = h->slot.empty() ? (int64_t)ch : h->slot[ch];
+            if (at < 0) {                                         // not stored: a node without cells
+                P_host[(size_t)o * h->n_nodes + I] = 0.0;
+                continue;
+            }
+            const size_t k = (size_t)o * h->plane + (size_t)at * zb + z % zb;
             double v;
             if (h->prec == FDIRW_FP64) {
                 std::memcpy(&v, raw.data() + k * 8, 8);

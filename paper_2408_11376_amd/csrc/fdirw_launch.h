@@ -146,8 +146,10 @@ hipError_t launch_nodewin(int fp64, const NodeWinArgs &a, int n_sub, void *ga, v
 hipError_t launch_coarse_pbc_fd(int fp64, const void *lam, const int *node, int nx, int ny, int nz, int n_sub,
                                 const double *u, double cour, double *a, double *b, double **result, hipStream_t st);
 hipError_t launch_coarse_fill_reservoir(const int *node, int64_t n, double v, double *c, hipStream_t st);
+// slot null: every chunk at its own index (plane = all chunks x zb); else the
+// listed chunks only, chunk c at slot[c] (-1: not stored; plane = list x zb)
 hipError_t launch_coarse_finalize(int prec, const double *S, const double *count, int64_t n_nodes, int nb, int ncx,
-                                  int ncy, int ncz, void *P, hipStream_t st);
+                                  int ncy, int ncz, const int *slot, int64_t plane, void *P, hipStream_t st);
 // The coarse grid padded by K on every side: node (x, y, z) sits at
 // (x + K) sx + (y + K) sy + (z + K) sz.  Two layouts, fixed by K: for small
 // windows x fastest (the product with one lane per node reads runs along x);
