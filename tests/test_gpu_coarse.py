@@ -89,11 +89,12 @@ def test_reduced_precision_p(prec, kind, tol, B, r):
     cg.close()
 
 
-@pytest.mark.parametrize("B", [2, 4])
-def test_liquid_only_grouping_matches_oracle(B):
+@pytest.mark.parametrize("B,r", [(2, 3), (4, 3), (1, 4)])
+def test_liquid_only_grouping_matches_oracle(B, r):
     # only phase 0 grouped (the other phases keep their values); kernels are
-    # renormalised over the grouped cells
-    d = synth.random_small((9, 10, 11), 3, r=3, n_sub=9, seed=19, d_zero_phase=False)
+    # renormalised over the grouped cells.  B = 1, r = 4 (K = 4): many chunks
+    # of P's layout hold no grouped node and are not stored
+    d = synth.random_small((9, 10, 11), 3, r=r, n_sub=9, seed=19, d_zero_phase=False)
     grouped = [1, 0, 0]
     p = oracle.Problem.from_domain(d)
     P = coarse.coarse_matrix(p, B, grouped)
