@@ -368,8 +368,10 @@ __global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__re
                     at[u] = ((int64_t)(z0 + q / ny_b) * ny + (y0 + q % ny_b)) * nx + x;
                     nd[u] = node[at[u]];
                 }
+                // values loaded with their node indices (every at[] is a cell
+                // of the domain), only the grouped ones added
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = nd[u] >= 0 ? c[at[u]] : 0.0;
+                for (int u = 0; u < 8; ++u) v[u] = c[at[u]];
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
                     if (q0 + u < n_q && nd[u] >= 0) s += v[u];
@@ -427,7 +429,7 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
             nd[u] = node[at[u]];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = nd[u] >= 0 ? c[at[u]] : 0.0;
+        for (int u = 0; u < 4; ++u) v[u] = c[at[u]];                  // with the indices; grouped ones added
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (q0 + 64 * u < n_cells && nd[u] >= 0) s += v[u];
