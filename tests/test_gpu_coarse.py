@@ -137,6 +137,31 @@ def test_two_steps_and_errors():
     cg.close()
 
 
+@pytest.mark.parametrize("B,r,prec", [(3, 3, "FP16_BANK"), (1, 5, "FP16_BANK"), (1, 5, "FP64"), (2, 9, "FP32")])
+def test_step_is_deterministic(B, r, prec):
+    # the product sums every node in one fixed order (no atomics in the step):
+    # the same handle gives bit-identical fields for the same input, in both
+    # product shapes (K = 1: one lane per node; K = 5: one lane per chunk and
+    # the ordered summing launch) and with a far field
+    d = synth.random_small((11, 10, 13), 3, r=r, n_sub=8, seed=24)
+    cg = fd.Coarse(_dev_domain(d), B, getattr(fd, prec))
+    assert cg.K == -(-r // B)
+    c = to_dev(d.c0)
+    a = to_host(cg.step(c))
+    b = to_host(cg.step(c))
+    assert np.array_equal(a, b)
+    cg.close()
+    label, dph, c0 = _far_field_domain(20)
+    res = [0, 0, 1]
+    cg = fd.Coarse(fd.Domain(label, dph, r, 9, 1.0, 0.0), B, getattr(fd, prec), reservoir=res)
+    c = to_dev(np.where(coarse.reservoir_mask(label, res), 0.4, c0))
+    m_total = float(to_host(c).sum()) + 0.4 * 30.0
+    o1, f1 = cg.step_far_field(c, 0.4, m_total, 30.0)
+    o2, f2 = cg.step_far_field(c, 0.4, m_total, 30.0)
+    assert np.array_equal(to_host(o1), to_host(o2)) and f1 == f2
+    cg.close()
+
+
 @pytest.mark.slow
 def test_full_size_sampled_columns():
     """The 192^3 workload (GRF, D 1 / 1e-6, r = 8, n = 200) with 5^3 blocks and
