@@ -243,3 +243,25 @@ def test_node_window_liquid_operator_matches_oracle(prec, tol):
     assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
     assert abs(cff - cff_w) <= tol * abs(cff_w)
     assert np.max(np.abs(hist[:, 0] + hist[:, 1] + 500.0 * hist[:, 2] - m_total)) <= 1e-12 * m_total
+
+
+@pytest.mark.parametrize("B,r,n_sub", [(2, 3, 6), (2, 12, 30)])
+def test_step_is_deterministic(B, r, n_sub):
+    # a big step uses no global atomics (fixed-order product and Eq. 7 sums):
+    # the same handle and input give bit-identical fields and histories, with
+    # the product of K = 2 (one lane per node) and K = 6 (one lane per chunk)
+    label, c0 = _case(n=16, r_p=4.0, seed=98)
+    far = label == synth.PHASE_FAR_LIQUID
+    m_total = c0[~far].sum() + 500.0 * 0.2
+    dom = fd.Domain(label, np.array([1.0, 0.02, 1.0]), r, n_sub, 1.0, 0.5)
+    s = fd.Multiphysics(dom, ROLE, 0.3, 0.01, 1.0, 500.0, a_over_rt=np.array([0.15, 0.5, 0.15]), block=B,
+                        prec=fd.FP16_BANK)
+    assert s.K == -(-r // B)
+    runs = []
+    for _ in range(2):
+        c = to_dev(c0)
+        cff, hist = s.step(c, 0.2, m_total, 3)
+        runs.append((to_host(c), cff, np.array(hist)))
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+    assert np.array_equal(runs[0][2], runs[1][2])
+    s.close()
