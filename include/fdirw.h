@@ -316,7 +316,10 @@ int fdirw_nn_load(void *nn, const char *path);
  * kernels are the flow kernels, generated in chunks of sources; r <= 8 only).  block: 1..256.  d->label is read
  * only here.  *handle
  * receives a handle owning device memory of about 4 N + (2K+1)^3 x N_nodes x
- * element bytes; seconds (host, may be NULL) receives the build time.
+ * element bytes (for K >= 4 N_nodes counts only the nodes of the 16-byte z
+ * groups of P that hold a grouped cell; the build also holds (2K+1)^3 x
+ * N_nodes x 8 bytes for its duration); seconds (host, may be NULL) receives
+ * the build time.
  * Synchronises the stream.  The handle belongs to the current device.
  * Errors: E_ARG (also a block outside 1..256, another precision or K above
  * FDIRW_MAX_COARSE_K), E_UNSUPPORTED (a flow with r above FDIRW_MAX_RADIUS),
