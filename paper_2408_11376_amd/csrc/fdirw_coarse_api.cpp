@@ -210,7 +210,7 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                 h->n_used = (int64_t)ul.size();
                 // P: every chunk of the grid (K < 4) or the listed chunks only,
                 // in list order (K >= 4); entries never written stay 0
-                if (per == 1) {
+                if (h->K >= COARSE_CHUNK_MIN_K) {
                     h->plane = h->n_list * zb;
                     h->slot.assign((size_t)n_ch, -1);
                     for (size_t k = 0; k < gl.size(); ++k) h->slot[(size_t)gl[k]] = (int)k;
