@@ -316,7 +316,7 @@ int fdirw_nn_load(void *nn, const char *path);
  * kernels are the flow kernels, generated in chunks of sources; r <= 8 only).  block: 1..256.  d->label is read
  * only here.  *handle
  * receives a handle owning device memory of about 4 N + (2K+1)^3 x N_nodes x
- * element bytes (for K >= 4 N_nodes counts only the nodes of the 16-byte z
+ * element bytes (for K >= 5 N_nodes counts only the nodes of the 16-byte z
  * groups of P that hold a grouped cell; the build also holds (2K+1)^3 x
  * N_nodes x 8 bytes for its duration); seconds (host, may be NULL) receives
  * the build time.

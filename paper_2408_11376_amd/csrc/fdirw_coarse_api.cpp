@@ -30,8 +30,8 @@ struct Coarse {
     int64_t n_nodes = 0;
     int prec = FDIRW_FP64;          // storage of P: FP64, FP32, FP16_BANK or BF16_BANK
     size_t esz = 8;
-    int64_t plane = 0;              // elements of one offset plane of P (bank layout; compact for K >= 4)
-    std::vector<int> slot;          // K >= 4: chunk -> its place in P's compact layout (-1: not stored)
+    int64_t plane = 0;              // elements of one offset plane of P (bank layout; compact for K >= 5)
+    std::vector<int> slot;          // K >= 5: chunk -> its place in P's compact layout (-1: not stored)
     void *node = nullptr;           // int [N]
     void *count = nullptr;          // double [n_nodes]
     void *P = nullptr;              // esz * (2K+1)^3 * plane bytes
@@ -208,8 +208,8 @@ int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, cons
                 for (int64_t I = 0; I < h->n_nodes; ++I)
                     if (hc[(size_t)I] > 0.0) ul.push_back((int)I);
                 h->n_used = (int64_t)ul.size();
-                // P: every chunk of the grid (K < 4) or the listed chunks only,
-                // in list order (K >= 4); entries never written stay 0
+                // P: every chunk of the grid (K < 5) or the listed chunks only,
+                // in list order (K >= 5); entries never written stay 0
                 if (h->K >= COARSE_CHUNK_MIN_K) {
                     h->plane = h->n_list * zb;
                     h->slot.assign((size_t)n_ch, -1);

@@ -156,7 +156,7 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
 // for K >= COARSE_CHUNK_MIN_K z fastest, with the z extent ncz rounded up to
 // 8, plus 2K (the product with one lane per chunk of P's layout reads one
 // contiguous, 16-byte aligned z column per offset pair).
-constexpr int COARSE_CHUNK_MIN_K = 4;
+constexpr int COARSE_CHUNK_MIN_K = 5;
 struct CoarsePad {
     int K;
     int64_t sx, sy, sz, size;

@@ -43,7 +43,7 @@ def _offset_form(P, cshape, K):
     return out
 
 
-# K = ceil(r / B) from 1 to 5: K >= 4 runs the product with one lane per chunk
+# K = ceil(r / B) from 1 to 5: K >= 5 runs the product with one lane per chunk
 # of P's layout and a second, ordered summing launch (ragged z chunks here)
 CASES = [((6, 7, 5), 2, 6, 2, 11), ((9, 8, 10), 3, 10, 3, 12), ((5, 4, 6), 2, 5, 8, 13), ((7, 6, 8), 2, 8, 1, 14),
          ((3, 1, 70), 2, 4, 5, 15), ((7, 6, 5), 4, 6, 1, 21), ((9, 5, 6), 5, 7, 1, 22), ((11, 5, 6), 8, 6, 2, 23)]
@@ -89,10 +89,10 @@ def test_reduced_precision_p(prec, kind, tol, B, r):
     cg.close()
 
 
-@pytest.mark.parametrize("B,r", [(2, 3), (4, 3), (1, 4)])
+@pytest.mark.parametrize("B,r", [(2, 3), (4, 3), (1, 5)])
 def test_liquid_only_grouping_matches_oracle(B, r):
     # only phase 0 grouped (the other phases keep their values); kernels are
-    # renormalised over the grouped cells.  B = 1, r = 4 (K = 4): many chunks
+    # renormalised over the grouped cells.  B = 1, r = 5 (K = 5): many chunks
     # of P's layout hold no grouped node and are not stored
     d = synth.random_small((9, 10, 11), 3, r=r, n_sub=9, seed=19, d_zero_phase=False)
     grouped = [1, 0, 0]
