@@ -112,11 +112,24 @@ typedef struct fdirw_opts {
     const void *nn;            /* surrogate handle from fdirw_nn_create (GEN_NN) */
     double audit_tol;          /* GEN_NN: largest mean per-kernel L1 error accepted; <= 0: 1e-3 */
     int32_t audit_samples;     /* GEN_NN: sources audited per step; <= 0: 1024 */
-    int32_t deterministic;     /* must be 0 in this build (FP64 atomics reorder sums) */
+    int32_t deterministic;     /* 0 or 1.  1: no floating-point atomics anywhere in the step;
+                                  fdirw_step / fdirw_run results are a function of the inputs
+                                  (bitwise equal on repeat, for n_dom > 1 and n_dom == 1 calls,
+                                  and for a run resumed from its intermediate field).  The
+                                  fused step then takes the source planes in slabs: per slab
+                                  every source line stores its completed output planes to its
+                                  own slot of a library-held buffer of W^2 (slab + 2r) nx ny
+                                  doubles (slab chosen so that it stays <= 4 GiB, at least one
+                                  plane), and a second pass adds the W^2 slots of each cell in
+                                  a fixed order.  With n_dom > 1 the domains run in turn through
+                                  that step instead of the persistent launch.  GEN_NN:
+                                  E_UNSUPPORTED.  0: FP64 atomics (sums of ~1e-16 relative
+                                  order-dependence). */
     size_t bank_budget_bytes;  /* fdirw_run: store every kernel once if the bank fits; 0 = never */
     void *stream;              /* hipStream_t, NULL = default stream */
     int32_t tune;              /* launch shape.  n_dom == 1: > 0 = segments per source line,
-                                  else automatic.  n_dom > 1: 0..5 = batched shape id (item z
+                                  else automatic; with deterministic = 1, > 0 = source planes
+                                  per slab, else automatic.  n_dom > 1: 0..5 = batched shape id (item z
                                   extent and queue order), -1 = autotuned (cached per precision,
                                   radius / sub-step mix, size class and device; the cache file is
                                   named by the environment variable FDIRW_TUNE_CACHE) */

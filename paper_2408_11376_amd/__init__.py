@@ -338,10 +338,11 @@ def _ptr_array(ts):
 
 
 def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = False, tune: int = -1,
-               nn=None, audit_tol: float = 1e-3, audit_samples: int = 1024):
+               nn=None, audit_tol: float = 1e-3, audit_samples: int = 1024, deterministic: bool = False):
     """One big step for one domain or a list of domains.  Returns c_out (and
     a list of stats dicts if ``stats``).  ``nn``: a Surrogate to generate the
-    kernels with (GEN_NN, audited against FD)."""
+    kernels with (GEN_NN, audited against FD).  ``deterministic``: no
+    floating-point atomics (bitwise reproducible results)."""
     torch = _torch()
     single = isinstance(doms, Domain)
     doms = [doms] if single else list(doms)
@@ -356,7 +357,7 @@ def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = Fal
         if a.numel() != d.n or b.numel() != d.n:
             raise ValueError(f"field {i} does not match its domain")
     o = make_opts(prec, stream, tune=tune, gen=GEN_NN if nn is not None else GEN_FD, nn=nn,
-                  audit_tol=audit_tol, audit_samples=audit_samples)
+                  audit_tol=audit_tol, audit_samples=audit_samples, deterministic=int(bool(deterministic)))
     nd = len(doms)
     ds = (fdirw_domain * nd)(*[d.c_struct() for d in doms])
     st = (fdirw_stats * nd)() if stats else None
@@ -370,7 +371,7 @@ def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = Fal
 
 
 def fdirw_run(doms, c, n_steps: int, scratch=None, prec=FP32, stream=None, stats: bool = False,
-              bank_budget_bytes: int = 0, tune: int = -1):
+              bank_budget_bytes: int = 0, tune: int = -1, deterministic: bool = False):
     """``n_steps`` big steps in place on ``c`` (one tensor or a list)."""
     torch = _torch()
     single = isinstance(doms, Domain)
@@ -385,7 +386,8 @@ def fdirw_run(doms, c, n_steps: int, scratch=None, prec=FP32, stream=None, stats
         _dev_tensor(b, torch.float64, f"scratch[{i}]")
         if a.numel() != d.n or b.numel() != d.n:
             raise ValueError(f"field {i} does not match its domain")
-    o = make_opts(prec, stream, bank_budget_bytes=bank_budget_bytes, tune=tune)
+    o = make_opts(prec, stream, bank_budget_bytes=bank_budget_bytes, tune=tune,
+                  deterministic=int(bool(deterministic)))
     nd = len(doms)
     ds = (fdirw_domain * nd)(*[d.c_struct() for d in doms])
     st = (fdirw_stats * nd)() if stats else None

@@ -7,6 +7,7 @@
 // the ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -82,7 +83,7 @@ static void release_all()
         (void)hipSetDevice(kv.first);
         DevCache &c = kv.second;
         for (Buf *b : {&c.lam64, &c.lam32, &c.flags, &c.part, &c.wgk, &c.small, &c.bank, &c.bank_mass, &c.bank_chat, &c.blam,
-                       &c.bsmall, &c.bdoms, &c.bitems}) {
+                       &c.bsmall, &c.bdoms, &c.bitems, &c.det}) {
             if (b->p) (void)hipFree(b->p);
             b->p = nullptr;
             b->cap = 0;
@@ -120,7 +121,10 @@ int check_opts(const fdirw_opts *o)
     if (o->prec < FDIRW_FP64 || o->prec > FDIRW_BF16_BANK) return fail(FDIRW_E_ARG, "unknown precision %d", o->prec);
     if (o->gen != FDIRW_GEN_FD && o->gen != FDIRW_GEN_NN) return fail(FDIRW_E_ARG, "unknown generator %d", o->gen);
     if (o->gen == FDIRW_GEN_NN && !o->nn) return fail(FDIRW_E_ARG, "GEN_NN needs a surrogate handle (opts.nn)");
-    if (o->deterministic) return fail(FDIRW_E_UNSUPPORTED, "deterministic mode is not implemented");
+    if (o->deterministic != 0 && o->deterministic != 1)
+        return fail(FDIRW_E_ARG, "deterministic = %d must be 0 or 1", o->deterministic);
+    if (o->deterministic && o->gen == FDIRW_GEN_NN)
+        return fail(FDIRW_E_UNSUPPORTED, "the surrogate step superposes with FP64 atomics; deterministic needs GEN_FD");
     return FDIRW_OK;
 }
 
@@ -204,6 +208,56 @@ void line_shape(const fdirw_domain *d, int tune, int *seg_len, int *n_seg)
     *n_seg = (d->nz + len - 1) / len;
 }
 
+int det_slab_planes(const fdirw_domain *d, int tune)
+{
+    if (tune > 0) return tune < d->nz ? tune : d->nz;
+    const int64_t W = 2 * d->r + 1;
+    const double plane = (double)(W * W) * (double)d->nx * d->ny * 8.0;   // partial bytes per plane
+    int64_t planes = (int64_t)((double)DET_PART_CAP / plane) - 2 * d->r;
+    if (planes < 1) planes = 1;
+    if (planes > d->nz) planes = d->nz;
+    return (int)planes;
+}
+
+// The deterministic fused step: the source planes are taken in slabs of
+// det_slab_planes; per slab one launch with one workgroup per source line
+// stores every completed plane of every line to its own partial slot, and a
+// second launch adds, for every cell the slab reaches, the partials of its
+// W^2 window columns in a fixed order to c_out.  No floating-point atomics:
+// the result depends on the inputs and the slab size only.
+static int step_det(const fdirw_domain *d, const fdirw_opts *o, LineArgs a, DevCache &dc, hipStream_t stream,
+                    int64_t *nblk_out)
+{
+    int rc;
+    const int slab = det_slab_planes(d, o->tune);
+    const int n_slab = (d->nz + slab - 1) / slab;
+    const int64_t lines = (int64_t)d->nx * d->ny;
+    const int64_t W = 2 * d->r + 1;
+    const int part_planes = slab + 2 * d->r;
+    const size_t part_bytes = (size_t)(W * W) * (size_t)part_planes * (size_t)lines * sizeof(double);
+    if ((rc = ensure(dc.det, part_bytes))) return rc;
+    if ((rc = ensure(dc.wgk, (size_t)n_slab * lines * 2 * sizeof(double)))) return rc;
+    double *c_out = a.c_out;
+    for (int k = 0; k < n_slab; ++k) {
+        const int za = k * slab, zb = std::min(d->nz, za + slab);
+        LineArgs s = a;
+        s.z_begin = za; s.z_end = zb;
+        s.seg_len = zb - za; s.n_seg = 1;
+        s.c_out = nullptr;
+        s.part = (double *)dc.det.p;
+        s.part_z0 = za - d->r;
+        s.part_planes = part_planes;
+        s.wg_kmass = (double *)dc.wgk.p + (size_t)k * lines * 2;
+        hipError_t e = launch_line(o->prec, d->r, s, stream);
+        if (e != hipSuccess) return hip_fail(e, "deterministic step launch");
+        s.c_out = c_out;
+        e = launch_line_reduce(d->r, s, std::max(0, za - d->r), std::min(d->nz, zb + d->r), stream);
+        if (e != hipSuccess) return hip_fail(e, "deterministic reduction launch");
+    }
+    *nblk_out = (int64_t)n_slab * lines;
+    return FDIRW_OK;
+}
+
 int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out,
              fdirw_stats *st, DevCache &dc, hipStream_t stream, bool prepared, const void *lam, Geometry *geo)
 {
@@ -220,9 +274,9 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
         if (!std::isfinite(st->mass_in)) return fail(FDIRW_E_NONFINITE, "input mass is not finite");
     }
     int seg_len, n_seg;
-    line_shape(d, o->tune, &seg_len, &n_seg);
-    const int64_t nblk = (int64_t)d->nx * d->ny * n_seg;
-    if ((rc = ensure(dc.wgk, (size_t)nblk * 2 * sizeof(double)))) return rc;
+    line_shape(d, o->deterministic ? 0 : o->tune, &seg_len, &n_seg);
+    int64_t nblk = (int64_t)d->nx * d->ny * n_seg;
+    if (!o->deterministic && (rc = ensure(dc.wgk, (size_t)nblk * 2 * sizeof(double)))) return rc;
     if ((rc = ensure(dc.small, 64))) return rc;
     unsigned long long *used = (unsigned long long *)dc.small.p;
     hipError_t e = launch_fill(c_out, n, 0.0, stream);
@@ -231,16 +285,23 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     LineArgs a;
     a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.n = n;
     a.n_sub = d->n_sub;
+    a.z_begin = 0; a.z_end = d->nz;
     a.seg_len = seg_len; a.n_seg = n_seg;
     a.lx = lam;
     a.c_in = c_in; a.c_out = c_out;
     a.wg_kmass = (double *)dc.wgk.p;
     a.n_used = used;
+    a.part = nullptr;
+    a.part_z0 = 0; a.part_planes = 0;
     EventPair ev;
     if (st && (e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
     if (st) (void)hipEventRecord(ev.a, stream);
-    e = launch_line(o->prec, d->r, a, stream);
-    if (e != hipSuccess) return hip_fail(e, "fused step launch");
+    if (o->deterministic) {
+        if ((rc = step_det(d, o, a, dc, stream, &nblk))) return rc;
+    } else {
+        e = launch_line(o->prec, d->r, a, stream);
+        if (e != hipSuccess) return hip_fail(e, "fused step launch");
+    }
     if (st) (void)hipEventRecord(ev.b, stream);
     if (st) {
         if ((rc = field_sum_dev(c_out, n, stream, dc, &st->mass_out))) return rc;
@@ -259,7 +320,7 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
         st->audit_l1 = 0.0;
         st->fallback_used = 0;
         st->bank_used = 0;
-        st->tuned_config_id = n_seg;
+        st->tuned_config_id = o->deterministic ? det_slab_planes(d, o->tune) : n_seg;
     }
     return FDIRW_OK;
 }

@@ -197,6 +197,17 @@ int step_batched(const fdirw_domain *d, int n_dom, const fdirw_opts *o, const do
                  double *const *c_out, fdirw_stats *st, DevCache &dc, hipStream_t stream)
 {
     int rc;
+    if (o->deterministic) {
+        // the persistent launch adds with FP64 atomics; the deterministic
+        // form takes the domains in order through the single-domain
+        // deterministic step, so each domain's result is bitwise that of a
+        // call with n_dom = 1
+        for (int i = 0; i < n_dom; ++i)
+            if ((rc = step_one(&d[i], o, c_in[i], c_out[i], st ? &st[i] : nullptr, dc, stream, false, nullptr,
+                               nullptr)))
+                return rc;
+        return FDIRW_OK;
+    }
     const bool f64 = o->prec == FDIRW_FP64;
     const size_t esz = f64 ? 8 : 4;
     std::vector<int64_t> off(n_dom + 1, 0);

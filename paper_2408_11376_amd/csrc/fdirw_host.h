@@ -21,6 +21,7 @@ struct Buf {
 struct DevCache {
     int dev = -1;
     Buf lam64, lam32, flags, part, wgk, small, bank, bank_mass, bank_chat;
+    Buf det;                              // deterministic step: per-column plane partials
     Buf blam, bsmall, bdoms, bitems;      // batched launch
 };
 
@@ -64,6 +65,11 @@ int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double
 int coef_buffers(const fdirw_domain *d, int prec, hipStream_t st, DevCache &dc, Geometry *g, const void **lam);
 int field_sum_dev(const double *c, int64_t n, hipStream_t st, DevCache &dc, double *out_host);
 void line_shape(const fdirw_domain *d, int tune, int *seg_len, int *n_seg);
+// Source planes per launch of the deterministic step (a function of the
+// domain's shape and radius only, or tune > 0 planes).
+int det_slab_planes(const fdirw_domain *d, int tune);
+// Bytes of partials kept by the deterministic step (caps det_slab_planes).
+constexpr size_t DET_PART_CAP = (size_t)4 << 30;
 int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out,
              fdirw_stats *st, DevCache &dc, hipStream_t stream, bool prepared, const void *lam, Geometry *geo);
 int run_one(const fdirw_domain *d, const fdirw_opts *o, int n_steps, double *c, double *scratch,

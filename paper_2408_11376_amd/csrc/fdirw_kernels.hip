@@ -261,6 +261,52 @@ window_kernel(WindowArgs a)
 
 // ----------------------------------------------------------------- fused step
 
+// Adds the completed value v of window column col, plane Z (0 <= Z < nz) of a
+// line to the output: an FP64 atomic into c_out, or in the deterministic form
+// a plain store of its own partial slot (zeros too, so that every slot the
+// reduction reads is written).
+__device__ __forceinline__ void flush_column(const LineArgs &a, double v, bool inxy, int X, int Y, int Z, int col)
+{
+    if (!inxy) return;
+    const int64_t nxy = (int64_t)a.nx * a.ny;
+    if (a.part) {
+        a.part[((int64_t)col * a.part_planes + (Z - a.part_z0)) * nxy + (int64_t)Y * a.nx + X] = v;
+    } else if (v != 0.0) {
+        unsafeAtomicAdd(&a.c_out[(int64_t)Z * nxy + (int64_t)Y * a.nx + X], v);
+    }
+}
+
+// Second pass of the deterministic superposition: one thread per output cell
+// of planes [z_lo, z_hi) adds the partials of the W^2 window columns (cy, cx)
+// whose source line (x + R - cx, y + R - cy) lies in the domain, cy then cx
+// ascending, and adds that sum to c_out.
+template <int R>
+__global__ void line_reduce_kernel(LineArgs a, int z_lo, int z_hi)
+{
+    constexpr int W = 2 * R + 1;
+    const int64_t nxy = (int64_t)a.nx * a.ny;
+    const int64_t total = (int64_t)(z_hi - z_lo) * nxy;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int Z = z_lo + (int)(i / nxy);
+        const int64_t cell = i - (int64_t)(Z - z_lo) * nxy;
+        const int Y = (int)(cell / a.nx), X = (int)(cell - (int64_t)Y * a.nx);
+        const double *p = a.part + (int64_t)(Z - a.part_z0) * nxy + cell;
+        const int64_t colstride = (int64_t)a.part_planes * nxy;
+        double s = 0.0;
+        for (int cy = 0; cy < W; ++cy) {
+            const int sy = Y + R - cy;
+            if (sy < 0 || sy >= a.ny) continue;
+            for (int cx = 0; cx < W; ++cx) {
+                const int sx = X + R - cx;
+                if (sx < 0 || sx >= a.nx) continue;
+                s += p[(int64_t)(cy * W + cx) * colstride];
+            }
+        }
+        a.c_out[(int64_t)Z * nxy + cell] += s;
+    }
+}
+
 // One workgroup walks the sources (sx, sy, z0..z1-1).  c(s) * G_s is
 // accumulated in FP64 into an LDS ring of W planes x W^2 columns indexed by
 // global plane z mod W (touched once per source, so it costs no sub-step
@@ -289,8 +335,8 @@ line_kernel(LineArgs a)
 
     const int line = b / a.n_seg, sgi = b - line * a.n_seg;
     const int sy = line / a.nx, sx = line - sy * a.nx;
-    const int z0 = sgi * a.seg_len;
-    const int z1 = min(a.nz, z0 + a.seg_len);
+    const int z0 = a.z_begin + sgi * a.seg_len;
+    const int z1 = min(a.z_end, z0 + a.seg_len);
     if (z0 >= z1) return;                                   // uniform per block
     const int X = sx - R + p.cx, Y = sy - R + p.cy;
     const bool inxy = p.act && X >= 0 && X < a.nx && Y >= 0 && Y < a.ny;
@@ -327,9 +373,7 @@ line_kernel(LineArgs a)
         if (p.act && p.seg == 0) {
             const int Z = sz - R;
             double &r = ring[((Z + W) % W) * W2 + p.col];
-            const double v = r;
-            if (v != 0.0 && inxy && Z >= 0)
-                unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+            if (Z >= 0) flush_column(a, r, inxy, X, Y, Z, p.col);
             r = 0.0;
         }
     }
@@ -338,8 +382,7 @@ line_kernel(LineArgs a)
         for (int Z = z1 - R; Z < z1 + R; ++Z) {
             if (Z < 0 || Z >= a.nz) continue;
             double &r = ring[((Z + W) % W) * W2 + p.col];
-            const double v = r;
-            if (v != 0.0 && inxy) unsafeAtomicAdd(&a.c_out[((int64_t)Z * a.ny + Y) * a.nx + X], v);
+            flush_column(a, r, inxy, X, Y, Z, p.col);
             r = 0.0;
         }
     }
@@ -550,6 +593,33 @@ static hipError_t launch_line_mr(const LineArgs &a, hipStream_t st)
     const int64_t nblk = (int64_t)a.nx * a.ny * a.n_seg;
     hipLaunchKernelGGL((line_kernel<M, R>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
     return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_reduce_r(const LineArgs &a, int z_lo, int z_hi, hipStream_t st)
+{
+    const int64_t total = (int64_t)(z_hi - z_lo) * a.nx * a.ny;
+    if (total <= 0) return hipSuccess;
+    int64_t g = (total + 255) / 256;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL((line_reduce_kernel<R>), dim3((unsigned)g), dim3(256), 0, st, a, z_lo, z_hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_reduce(int r, const LineArgs &a, int z_lo, int z_hi, hipStream_t st)
+{
+    switch (r) {
+    case 0: return launch_reduce_r<0>(a, z_lo, z_hi, st);
+    case 1: return launch_reduce_r<1>(a, z_lo, z_hi, st);
+    case 2: return launch_reduce_r<2>(a, z_lo, z_hi, st);
+    case 3: return launch_reduce_r<3>(a, z_lo, z_hi, st);
+    case 4: return launch_reduce_r<4>(a, z_lo, z_hi, st);
+    case 5: return launch_reduce_r<5>(a, z_lo, z_hi, st);
+    case 6: return launch_reduce_r<6>(a, z_lo, z_hi, st);
+    case 7: return launch_reduce_r<7>(a, z_lo, z_hi, st);
+    case 8: return launch_reduce_r<8>(a, z_lo, z_hi, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int M, int R>

@@ -15,13 +15,25 @@ struct LineArgs {
     int nx, ny, nz;
     int64_t n;
     int n_sub;
+    int z_begin, z_end;       // source planes of this launch
     int seg_len, n_seg;       // each (x, y) line of sources is cut into n_seg segments
     const void *lx;
     const double *c_in;
-    double *c_out;
+    double *c_out;            // null in the deterministic form
     double *wg_kmass;         // [n_blocks][2] min / max kernel mass, or null
     unsigned long long *n_used;
+    // Deterministic form (n_seg == 1): instead of adding its completed planes
+    // to c_out, the line of source column (sx, sy) stores window column
+    // col = cy W + cx of plane Z to part[(col * part_planes + Z - part_z0) *
+    // nx ny + y nx + x] (zeros included), one writer per entry.
+    double *part;
+    int part_z0, part_planes;
 };
+
+// Deterministic superposition, second pass: for every cell of planes
+// [z_lo, z_hi) c_out += sum of the W^2 partials whose source line lies in the
+// domain, in window-column order.
+hipError_t launch_line_reduce(int r, const LineArgs &a, int z_lo, int z_hi, hipStream_t st);
 
 struct WindowArgs {
     int nx, ny, nz;

@@ -41,7 +41,7 @@ constexpr int NSLAB = (W + TZ - 1) / TZ;
 constexpr int NTHR = 256;
 
 // SiLU with the hardware exp and reciprocal (about 1 ulp each; the result is
-// rounded to BF16, 2^-9 relative, right after)
+// rounded to BF16, 2^-8 relative, right after)
 __device__ __forceinline__ float silu_f(float x) { return x * __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 __device__ __forceinline__ float silu_grad_f(float x)
 {

@@ -48,6 +48,9 @@ int main(void) {
   printf("sizeof.fdirw_domain %zu\n", sizeof(fdirw_domain));
   printf("sizeof.fdirw_opts %zu\n", sizeof(fdirw_opts));
   printf("sizeof.fdirw_stats %zu\n", sizeof(fdirw_stats));
+  printf("sizeof.fdirw_mp_params %zu\n", sizeof(fdirw_mp_params));
+  P(fdirw_mp_params, role) P(fdirw_mp_params, a_over_rt) P(fdirw_mp_params, k) P(fdirw_mp_params, c_eq_liquid)
+  P(fdirw_mp_params, c_eq_solid) P(fdirw_mp_params, n_sub_solid) P(fdirw_mp_params, v_far_field)
   P(fdirw_domain, h) P(fdirw_domain, label) P(fdirw_domain, d_phase) P(fdirw_domain, n_phase)
   P(fdirw_domain, r) P(fdirw_domain, n_sub) P(fdirw_domain, dt)
   P(fdirw_opts, nn) P(fdirw_opts, audit_tol) P(fdirw_opts, bank_budget_bytes) P(fdirw_opts, stream) P(fdirw_opts, tune)
@@ -65,6 +68,7 @@ int main(void) {
     assert int(got["sizeof.fdirw_domain"]) == ctypes.sizeof(fd.fdirw_domain)
     assert int(got["sizeof.fdirw_opts"]) == ctypes.sizeof(fd.fdirw_opts)
     assert int(got["sizeof.fdirw_stats"]) == ctypes.sizeof(fd.fdirw_stats)
+    assert int(got["sizeof.fdirw_mp_params"]) == ctypes.sizeof(fd.fdirw_mp_params)
     for key, val in got.items():
         t, f = key.split(".")
         if t == "sizeof":

@@ -1,14 +1,17 @@
 """GPU parity of the learned kernel generator (features, support, MFMA
 forward, loss, gradients, Adam, the audited surrogate step) against the FP64
-CPU oracle in oracle/surrogate.py.
+CPU oracle in oracle/surrogate.py and against a BF16-rounding emulation of
+the same network (tests/bf16_emulation.py).
 
 Tolerances.  The GPU keeps weights, activations and back-propagated
-gradients in BF16 (unit roundoff u = 2^-9) with FP32 accumulation.  Replaying
-those roundings in an FP64 emulation of the same network and windows gives a
-relative L2 error of 0.6-0.7 % for the last-layer output and 0.5-0.6 % per
-layer for the gradients; the bounds below are four times that (2.5e-2).  The
-loss terms are sums over thousands of cells and agree to ~1e-4 relative in
-that emulation (bound 2e-3).  Support and placement are integer: bit-exact."""
+gradients in BF16 (unit roundoff u = 2^-8) with FP32 accumulation, so against
+the plain FP64 oracle the last-layer output and the per-layer gradients
+differ by a few 1e-3 (relative L2): bound 1e-2.  The emulation replays the
+same roundings in FP64; what is left is accumulation order and width (and the
+rare BF16 rounding that those flip), so the GPU is held to 2e-3 against it --
+a layout or indexing error shows as O(1).  Loss terms are sums over thousands
+of cells: 2e-3 against the oracle.  Support and placement are integer:
+bit-exact."""
 import os
 import tempfile
 
@@ -19,6 +22,7 @@ import oracle
 import synth
 from oracle import surrogate as su
 from helpers import rel_l1, to_dev, to_host
+import bf16_emulation as emu
 
 pytestmark = pytest.mark.gpu
 
@@ -30,8 +34,9 @@ import paper_2408_11376_amd as fd  # noqa: E402
 
 R = 8
 N_SUB = 60
-Z_TOL = 2.5e-2
-GRAD_TOL = 2.5e-2
+Z_TOL = 1e-2
+GRAD_TOL = 1e-2
+EMU_TOL = 2e-3
 LOSS_TOL = 2e-3
 
 
@@ -130,7 +135,12 @@ def test_forward_matches_oracle(dom, prior, seed):
         lo, _ = su.forward(params, f)
         z5o, z5g = lo - prior, L[i].astype(np.float64) - prior
         err = np.linalg.norm(z5g - z5o) / np.linalg.norm(z5o)
+        le, _ = emu.forward(params, emu.features(dom.label, dom.d_phase, s, R, prior), prior)
+        z5e = le - prior
+        err_e = np.linalg.norm(z5g - z5e) / np.linalg.norm(z5e)
+        print(f"source {s}: output rel. L2 vs FP64 oracle {err:.2e}, vs BF16 emulation {err_e:.2e}")
         assert err <= Z_TOL, (s, err)
+        assert err_e <= EMU_TOL, (s, err_e)
         go = su.masked_softmax(lo, S[i])
         assert np.all(G[i][~S[i]] == 0)
         assert abs(G[i].astype(np.float64).sum() - 1.0) <= 1e-5
@@ -170,6 +180,22 @@ def _oracle_grads(params, dom, prior, srcs, targets):
     return acc / len(srcs), kl_l1 / len(srcs), dl_abs / len(srcs)
 
 
+def _emu_grads(params, dom, prior, srcs, targets):
+    """Sum over windows of the emulated gradients (each scaled by 1 / batch)."""
+    P = oracle.Problem.from_domain(dom)
+    acc = None
+    for i, s in enumerate(srcs):
+        sup = P.support(s).astype(bool)
+        q = targets[i].astype(np.float64)
+        q = q / q.sum()
+        lo, cache = emu.forward(params, emu.features(dom.label, dom.d_phase, s, R, prior), prior)
+        g = su.masked_softmax(lo, sup)
+        _, dl = su.loss_and_dlogits(g, q, sup)
+        v = su.flatten(emu.backward(params, cache, dl, 1.0 / len(srcs)))
+        acc = v if acc is None else acc + v
+    return acc
+
+
 def test_gradients_match_oracle(dom, prior):
     params = _params(4)
     nn = _net(params)
@@ -183,14 +209,20 @@ def test_gradients_match_oracle(dom, prior):
     assert kl == pytest.approx(klo, rel=LOSS_TOL)
     assert l1 == pytest.approx(l1o, rel=LOSS_TOL)
     gg = to_host(g).astype(np.float64)
+    ge = _emu_grads(params, dom, prior, srcs, target)
     off = 0
     for l, (ws, bs) in enumerate(su.param_shapes()):
         nw, nb = int(np.prod(ws)), int(np.prod(bs))
-        a, b = gg[off:off + nw], go[off:off + nw]
-        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= GRAD_TOL, ("w", l)
-        a, b = gg[off + nw:off + nw + nb], go[off + nw:off + nw + nb]
+        a, b, e = gg[off:off + nw], go[off:off + nw], ge[off:off + nw]
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        err_e = np.linalg.norm(a - e) / np.linalg.norm(e)
+        print(f"layer {l} weight gradient rel. L2 vs FP64 oracle {err:.2e}, vs BF16 emulation {err_e:.2e}")
+        assert err <= GRAD_TOL, ("w", l, err)
+        assert err_e <= EMU_TOL, ("w emulation", l, err_e)
+        a, b, e = gg[off + nw:off + nw + nb], go[off + nw:off + nw + nb], ge[off + nw:off + nw + nb]
         if l < 4:
             assert np.linalg.norm(a - b) <= GRAD_TOL * np.linalg.norm(b), ("b", l)
+            assert np.linalg.norm(a - e) <= EMU_TOL * np.linalg.norm(e), ("b emulation", l)
         else:
             # the last bias shifts every logit: its exact gradient is 0 (softmax
             # shift invariance); the GPU sums BF16-rounded d loss / d logits, so
@@ -368,4 +400,6 @@ def test_full_size_sampled_windows():
         lo, _ = su.forward(params, su.window_features(d.label, d.d_phase, s, R, prior))
         z5o, z5g = lo - prior, L[i].astype(np.float64) - prior
         assert np.linalg.norm(z5g - z5o) / np.linalg.norm(z5o) <= Z_TOL, s
+        le, _ = emu.forward(params, emu.features(d.label, d.d_phase, s, R, prior), prior)
+        assert np.linalg.norm(z5g - (le - prior)) / np.linalg.norm(le - prior) <= EMU_TOL, s
         assert np.array_equal(S[i], P.support(s).astype(np.uint8)), s
