@@ -201,6 +201,35 @@ int fdirw_kernels_flow(const fdirw_domain *d, const fdirw_opts *o, const double 
 int fdirw_step(const fdirw_domain *d, int32_t n_dom, const fdirw_opts *o,
                const double *const *c_in, double *const *c_out, fdirw_stats *st);
 
+/* fdirw_step for one domain without allocating: for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  It calls no hipMalloc / hipFree and no
+ * allocating library routine, and creates no events.  The result is that of
+ * fdirw_step with n_dom = 1 (same kernels and arithmetic; the face
+ * coefficients are looked up per phase pair instead of being stored per
+ * cell, same values), up to the order of the FP64 atomic additions.
+ *
+ * Scratch: one statically sized device array of FDIRW_NOALLOC_SCRATCH_BYTES
+ * per GPU, held from the library's first use on that GPU until the process
+ * ends: flags, counters, reduction partials, the n_phase^2 coefficient table
+ * and, when st != NULL, one kernel-mass pair per workgroup.  All calls on one
+ * GPU share it and it keeps the last call's contents (every part a call reads
+ * is rewritten or cleared by that call first), so calls that overlap in time
+ * on one GPU (two host threads, or two streams whose work overlaps) race.
+ * The call synchronises o->stream once (label check and Dmax) and again
+ * for the statistics.
+ *
+ * Limits and errors: as fdirw_step (E_ARG, E_UNSTABLE, E_NONFINITE, E_DEVICE);
+ * E_UNSUPPORTED for GEN_NN, deterministic = 1, or a precision other than
+ * FP64, FP32, FP16X32, BF16X32; E_ARG when st != NULL and the launch has more
+ * than FDIRW_NOALLOC_MAX_BLOCKS workgroups (nx * ny * segments per line,
+ * i.e. nx * ny above FDIRW_NOALLOC_MAX_BLOCKS), or c_in == c_out.
+ * st->kernel_seconds is 0 (no events). */
+#define FDIRW_NOALLOC_SCRATCH_BYTES (2 << 20)
+#define FDIRW_NOALLOC_MAX_BLOCKS 65536
+int fdirw_step_noalloc(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out,
+                       fdirw_stats *st);
+
 /* n_steps big steps (the time marching of
  * Eq. 8).  c[i] holds the initial field and receives the final one;
  * scratch[i] is a second buffer of N_i doubles (its content is overwritten).

@@ -81,7 +81,8 @@ class fdirw_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
-ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_run",
+ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_step_noalloc",
+                 "fdirw_run",
                  "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version",
                  "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
@@ -111,6 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_kernels.argtypes = [D, O, P, ctypes.c_int64, P, P]
     lib.fdirw_kernels_flow.argtypes = [D, O, P, P, ctypes.c_int64, P, P]
     lib.fdirw_step.argtypes = [D, ctypes.c_int32, O, PP, PP, S]
+    lib.fdirw_step_noalloc.argtypes = [D, O, P, P, S]
     lib.fdirw_run.argtypes = [D, ctypes.c_int32, O, ctypes.c_int32, PP, PP, S]
     lib.fdirw_field_sum.argtypes = [P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_last_error.argtypes = []
@@ -142,7 +144,8 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_mp_step.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_int32, P, P, S]
     lib.fdirw_mp_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), PP]
     lib.fdirw_mp_destroy.argtypes = [P]
-    for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_run",
+    for f in ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "fdirw_step", "fdirw_step_noalloc",
+              "fdirw_run",
               "fdirw_field_sum",
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
@@ -368,6 +371,24 @@ def fdirw_step(doms, c_in, c_out=None, prec=FP32, stream=None, stats: bool = Fal
         sd = [s.as_dict() for s in st]
         return out, (sd[0] if single else sd)
     return out
+
+
+def fdirw_step_noalloc(dom, c_in, c_out, prec=FP32, stream=None, stats: bool = False, tune: int = -1):
+    """fdirw_step of one domain through the entry point that allocates
+    nothing (its scratch is a fixed device array).  c_out must be given.
+    Returns c_out (and the stats dict if ``stats``)."""
+    torch = _torch()
+    _dev_tensor(c_in, torch.float64, "c_in")
+    _dev_tensor(c_out, torch.float64, "c_out")
+    if c_in.numel() != dom.n or c_out.numel() != dom.n:
+        raise ValueError("field does not match the domain")
+    o = make_opts(prec, stream, tune=tune)
+    ds = dom.c_struct()
+    st = fdirw_stats() if stats else None
+    _check(load_library().fdirw_step_noalloc(ctypes.byref(ds), ctypes.byref(o), ctypes.c_void_p(c_in.data_ptr()),
+                                             ctypes.c_void_p(c_out.data_ptr()),
+                                             ctypes.byref(st) if st is not None else None))
+    return (c_out, st.as_dict()) if stats else c_out
 
 
 def fdirw_run(doms, c, n_steps: int, scratch=None, prec=FP32, stream=None, stats: bool = False,

@@ -128,14 +128,12 @@ int check_opts(const fdirw_opts *o)
     return FDIRW_OK;
 }
 
-// Reads the label range / presence flags, derives Dmax and dt, checks
-// stability and writes the coefficients.  Synchronises the stream once.
-int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double *lam64, float *lam32, Geometry *g)
+// Reads the label range / presence flags (16 unsigned of device memory at
+// flags), derives Dmax and dt, checks stability and fills the per-label
+// diffusivity table.  Synchronises the stream once.
+int geometry_dt(const fdirw_domain *d, hipStream_t st, unsigned *flags, Geometry *g, CoefTable *tab)
 {
     const int64_t n = (int64_t)d->nx * d->ny * d->nz;
-    int rc = ensure(dc.flags, 16 * sizeof(unsigned));
-    if (rc) return rc;
-    unsigned *flags = (unsigned *)dc.flags.p;
     hipError_t e = launch_validate(d->label, n, d->n_phase, flags, st);
     if (e != hipSuccess) return hip_fail(e, "label check launch");
     unsigned h_flags[9];
@@ -154,9 +152,18 @@ int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double
     g->dt = dt;
     g->dmax = dmax;
     g->n = n;
+    for (int l = 0; l < 256; ++l) tab->d[l] = l < d->n_phase ? d->d_phase[l] : 0.0;
+    return FDIRW_OK;
+}
+
+// geometry_dt, then the owned-face coefficients of every cell.
+int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double *lam64, float *lam32, Geometry *g)
+{
+    int rc = ensure(dc.flags, 16 * sizeof(unsigned));
+    if (rc) return rc;
     CoefTable tab;
-    for (int l = 0; l < 256; ++l) tab.d[l] = l < d->n_phase ? d->d_phase[l] : 0.0;
-    e = launch_coef(d->label, d->nx, d->ny, d->nz, tab, dt, d->h, lam64, lam32, st);
+    if ((rc = geometry_dt(d, st, (unsigned *)dc.flags.p, g, &tab))) return rc;
+    hipError_t e = launch_coef(d->label, d->nx, d->ny, d->nz, tab, g->dt, d->h, lam64, lam32, st);
     if (e != hipSuccess) return hip_fail(e, "coefficient launch");
     return FDIRW_OK;
 }
@@ -282,7 +289,7 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     hipError_t e = launch_fill(c_out, n, 0.0, stream);
     if (e == hipSuccess) e = launch_fill_u32((unsigned *)used, 2, 0u, stream);
     if (e != hipSuccess) return hip_fail(e, "output clear");
-    LineArgs a;
+    LineArgs a{};
     a.nx = d->nx; a.ny = d->ny; a.nz = d->nz; a.n = n;
     a.n_sub = d->n_sub;
     a.z_begin = 0; a.z_end = d->nz;

@@ -167,15 +167,41 @@ __device__ __forceinline__ Place make_place(int t)
     return p;
 }
 
+// Owned-face coefficients from the arrays lx / ly / lz ([nz][ny][nx] each):
+// x(i, X) is the face from cell i to its +x neighbour (0 on the last plane of
+// the axis, stored as such), likewise y and z.
+template <typename S> struct FaceArrays {
+    const S *__restrict__ lx;
+    const S *__restrict__ ly;
+    const S *__restrict__ lz;
+    __device__ __forceinline__ S x(int64_t i, int) const { return lx[i]; }
+    __device__ __forceinline__ S y(int64_t i, int) const { return ly[i]; }
+    __device__ __forceinline__ S z(int64_t i, int) const { return lz[i]; }
+};
+
+// Owned-face coefficients from the phase labels and a table of the face
+// coefficient of every ordered phase pair, tab[a * n_phase + b] (the face
+// value depends on the two phases only); faces leaving the domain are 0.
+template <typename S> struct FaceLabels {
+    const uint8_t *__restrict__ label;
+    const S *__restrict__ tab;
+    int n_phase, nx, ny, nz;
+    __device__ __forceinline__ S pair(int64_t i, int64_t j) const { return tab[label[i] * n_phase + label[j]]; }
+    __device__ __forceinline__ S x(int64_t i, int X) const { return X + 1 < nx ? pair(i, i + 1) : S(0); }
+    __device__ __forceinline__ S y(int64_t i, int Y) const { return Y + 1 < ny ? pair(i, i + nx) : S(0); }
+    __device__ __forceinline__ S z(int64_t i, int Z) const
+    {
+        return Z + 1 < nz ? pair(i, i + (int64_t)nx * ny) : S(0);
+    }
+};
+
 // Loads the coefficients of a thread's segment for the window of source
-// (sx, sy, sz) from the owned-face arrays lx / ly / lz ([nz][ny][nx] each).
-// Faces leaving the window or the domain, and every face of a cell outside
-// the domain or past the segment's real cells, are 0.
-template <int M, int R, int SC = FDIRW_SEG_CELLS>
-__device__ __forceinline__ void load_segment(Seg<M, R, SC> &c, const typename Geo<M, R, SC>::S *__restrict__ lx,
-                                             const typename Geo<M, R, SC>::S *__restrict__ ly,
-                                             const typename Geo<M, R, SC>::S *__restrict__ lz,
-                                             int nx, int ny, int nz, int sx, int sy, int sz, const Place &p)
+// (sx, sy, sz) through the owned-face accessor f.  Faces leaving the window
+// or the domain, and every face of a cell outside the domain or past the
+// segment's real cells, are 0.
+template <int M, int R, int SC = FDIRW_SEG_CELLS, typename F>
+__device__ __forceinline__ void load_segment_faces(Seg<M, R, SC> &c, const F &f,
+                                                   int nx, int ny, int nz, int sx, int sy, int sz, const Place &p)
 {
     using G_ = Geo<M, R, SC>;
     using S = typename G_::S;
@@ -190,10 +216,10 @@ __device__ __forceinline__ void load_segment(Seg<M, R, SC> &c, const typename Ge
         S xm = S(0), xp = S(0), ym = S(0), yp = S(0);
         if (in) {
             const int64_t i = ((int64_t)Z * ny + Y) * nx + X;
-            if (p.cx < W - 1) xp = lx[i];
-            if (p.cx > 0 && X > 0) xm = lx[i - 1];
-            if (p.cy < W - 1) yp = ly[i];
-            if (p.cy > 0 && Y > 0) ym = ly[i - nx];
+            if (p.cx < W - 1) xp = f.x(i, X);
+            if (p.cx > 0 && X > 0) xm = f.x(i - 1, X - 1);
+            if (p.cy < W - 1) yp = f.y(i, Y);
+            if (p.cy > 0 && Y > 0) ym = f.y(i - nx, Y - 1);
         }
         c.xm[k] = xm; c.xp[k] = xp; c.ym[k] = ym; c.yp[k] = yp;
     }
@@ -203,9 +229,21 @@ __device__ __forceinline__ void load_segment(Seg<M, R, SC> &c, const typename Ge
         const int Z = sz - R + j;
         S v = S(0);
         if (inxy && k <= p.len && j >= 1 && j <= W - 1 && Z >= 1 && Z < nz)
-            v = lz[((int64_t)(Z - 1) * ny + Y) * nx + X];
+            v = f.z(((int64_t)(Z - 1) * ny + Y) * nx + X, Z - 1);
         c.zf[k] = v;
     }
+}
+
+// The same from the owned-face arrays lx / ly / lz.
+template <int M, int R, int SC = FDIRW_SEG_CELLS>
+__device__ __forceinline__ void load_segment(Seg<M, R, SC> &c, const typename Geo<M, R, SC>::S *__restrict__ lx,
+                                             const typename Geo<M, R, SC>::S *__restrict__ ly,
+                                             const typename Geo<M, R, SC>::S *__restrict__ lz,
+                                             int nx, int ny, int nz, int sx, int sy, int sz, const Place &p)
+{
+    using S = typename Geo<M, R, SC>::S;
+    const FaceArrays<S> f{lx, ly, lz};
+    load_segment_faces<M, R, SC>(c, f, nx, ny, nz, sx, sy, sz, p);
 }
 
 template <bool X32, int M, int R, int SC = FDIRW_SEG_CELLS>

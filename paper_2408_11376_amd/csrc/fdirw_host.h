@@ -11,6 +11,8 @@
 
 namespace fdirw {
 
+struct CoefTable;
+
 struct Buf {
     void *p = nullptr;
     size_t cap = 0;
@@ -61,6 +63,9 @@ std::mutex &cache_mutex();
 
 int check_domain(const fdirw_domain *d, int max_r = FDIRW_MAX_RADIUS);
 int check_opts(const fdirw_opts *o);
+// Label validation (flags: 16 unsigned of device memory), Dmax, dt, the
+// stability check and the per-label diffusivity table; synchronises once.
+int geometry_dt(const fdirw_domain *d, hipStream_t st, unsigned *flags, Geometry *g, CoefTable *tab);
 int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double *lam64, float *lam32, Geometry *g);
 int coef_buffers(const fdirw_domain *d, int prec, hipStream_t st, DevCache &dc, Geometry *g, const void **lam);
 int field_sum_dev(const double *c, int64_t n, hipStream_t st, DevCache &dc, double *out_host);

@@ -76,6 +76,20 @@ __global__ void coef_kernel(const uint8_t *__restrict__ label, int nx, int ny, i
     }
 }
 
+// Face coefficient of every ordered phase pair: tab[a * n_phase + b] =
+// face_lambda(D_a, D_b) (the value coef_kernel gives a face whose lower cell
+// has phase a and upper cell phase b), in FP64 or rounded to FP32.
+__global__ void pair_table_kernel(CoefTable tab, int n_phase, double dt, double h, double *__restrict__ t64,
+                                  float *__restrict__ t32)
+{
+    const int n = n_phase * n_phase;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const double v = face_lambda(tab.d[i / n_phase], tab.d[i % n_phase], dt, h);
+        if (t64) t64[i] = v;
+        if (t32) t32[i] = (float)v;
+    }
+}
+
 // ----------------------------------------------------------------- helpers
 
 __global__ void fill_kernel(double *__restrict__ p, int64_t n, double v)
@@ -313,7 +327,7 @@ __global__ void line_reduce_kernel(LineArgs a, int z_lo, int z_hi)
 // bandwidth and keeps the register file for the sub-step loop).  After source
 // sz the plane z = sz - R can receive nothing more from this line: it is added
 // to c_out with one atomic per window column and cleared.
-template <int M, int R>
+template <int M, int R, bool LAB = false>
 __global__ void __launch_bounds__((Geo<M, R>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, R>::MINW)))
 line_kernel(LineArgs a)
 {
@@ -349,7 +363,12 @@ line_kernel(LineArgs a)
         if (cs != 0.0) {                                    // uniform per block
             ++used;
             Seg<M, R> c;
-            load_segment<M, R>(c, lx, ly, lz, a.nx, a.ny, a.nz, sx, sy, sz, p);
+            if constexpr (LAB) {
+                const FaceLabels<S> f{a.label, (const S *)a.lam_tab, a.n_phase, a.nx, a.ny, a.nz};
+                load_segment_faces<M, R>(c, f, a.nx, a.ny, a.nz, sx, sy, sz, p);
+            } else {
+                load_segment<M, R>(c, lx, ly, lz, a.nx, a.ny, a.nz, sx, sy, sz, p);
+            }
             compute_diag<T::x32, M, R>(c);
             S G[L];
             init_delta<M, R>(G, p);
@@ -587,11 +606,11 @@ hipError_t launch_bank_gather(int prec, int r, const BankArgs &a, hipStream_t st
 
 // ----------------------------------------------------------------- dispatch
 
-template <int M, int R>
+template <int M, int R, bool LAB = false>
 static hipError_t launch_line_mr(const LineArgs &a, hipStream_t st)
 {
     const int64_t nblk = (int64_t)a.nx * a.ny * a.n_seg;
-    hipLaunchKernelGGL((line_kernel<M, R>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
+    hipLaunchKernelGGL((line_kernel<M, R, LAB>), dim3((unsigned)nblk), dim3(Geo<M, R>::NT), 0, st, a);
     return hipGetLastError();
 }
 
@@ -631,19 +650,19 @@ static hipError_t launch_window_mr(const WindowArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int M>
+template <int M, bool LAB = false>
 static hipError_t launch_line_m(int r, const LineArgs &a, hipStream_t st)
 {
     switch (r) {
-    case 0: return launch_line_mr<M, 0>(a, st);
-    case 1: return launch_line_mr<M, 1>(a, st);
-    case 2: return launch_line_mr<M, 2>(a, st);
-    case 3: return launch_line_mr<M, 3>(a, st);
-    case 4: return launch_line_mr<M, 4>(a, st);
-    case 5: return launch_line_mr<M, 5>(a, st);
-    case 6: return launch_line_mr<M, 6>(a, st);
-    case 7: return launch_line_mr<M, 7>(a, st);
-    case 8: return launch_line_mr<M, 8>(a, st);
+    case 0: return launch_line_mr<M, 0, LAB>(a, st);
+    case 1: return launch_line_mr<M, 1, LAB>(a, st);
+    case 2: return launch_line_mr<M, 2, LAB>(a, st);
+    case 3: return launch_line_mr<M, 3, LAB>(a, st);
+    case 4: return launch_line_mr<M, 4, LAB>(a, st);
+    case 5: return launch_line_mr<M, 5, LAB>(a, st);
+    case 6: return launch_line_mr<M, 6, LAB>(a, st);
+    case 7: return launch_line_mr<M, 7, LAB>(a, st);
+    case 8: return launch_line_mr<M, 8, LAB>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -676,6 +695,19 @@ hipError_t launch_line(int mode, int r, const LineArgs &a, hipStream_t st)
     case M_BF16ST: return launch_line_m<M_BF16ST>(r, a, st);
     case M_F16BANK: return launch_line_m<M_F16BANK>(r, a, st);
     case M_BF16BANK: return launch_line_m<M_BF16BANK>(r, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// The fused step with the face coefficients looked up per phase pair
+// (a.label, a.lam_tab, a.n_phase) instead of read from a.lx.
+hipError_t launch_line_labels(int mode, int r, const LineArgs &a, hipStream_t st)
+{
+    switch (mode) {
+    case M_FP64: return launch_line_m<M_FP64, true>(r, a, st);
+    case M_FP32: return launch_line_m<M_FP32, true>(r, a, st);
+    case M_F16X32: return launch_line_m<M_F16X32, true>(r, a, st);
+    case M_BF16X32: return launch_line_m<M_BF16X32, true>(r, a, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -715,6 +747,14 @@ hipError_t launch_coef(const uint8_t *label, int nx, int ny, int nz, const CoefT
 {
     const int64_t n = (int64_t)nx * ny * nz;
     hipLaunchKernelGGL(coef_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, label, nx, ny, nz, tab, dt, h, lam64, lam32);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_table(const CoefTable &tab, int n_phase, double dt, double h, double *t64, float *t32,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(pair_table_kernel, dim3(grid_for((int64_t)n_phase * n_phase, 256)), dim3(256), 0, st, tab,
+                       n_phase, dt, h, t64, t32);
     return hipGetLastError();
 }
 

@@ -28,12 +28,21 @@ struct LineArgs {
     // nx ny + y nx + x] (zeros included), one writer per entry.
     double *part;
     int part_z0, part_planes;
+    // Coefficients by phase pair (launch_line_labels only): the face between
+    // a cell of phase a and its + neighbour of phase b is lam_tab[a * n_phase
+    // + b] (double in FP64 mode, float otherwise); lx is not read.
+    const uint8_t *label;
+    const void *lam_tab;
+    int n_phase;
 };
 
 // Deterministic superposition, second pass: for every cell of planes
 // [z_lo, z_hi) c_out += sum of the W^2 partials whose source line lies in the
 // domain, in window-column order.
 hipError_t launch_line_reduce(int r, const LineArgs &a, int z_lo, int z_hi, hipStream_t st);
+// The fused step reading its coefficients through a.label / a.lam_tab
+// (modes FP64, FP32, FP16X32, BF16X32).
+hipError_t launch_line_labels(int mode, int r, const LineArgs &a, hipStream_t st);
 
 struct WindowArgs {
     int nx, ny, nz;
@@ -128,6 +137,10 @@ hipError_t batched_occupancy(int mode, int *blocks);
 int batch_windows_per_group(int r);
 
 hipError_t launch_validate(const uint8_t *label, int64_t n, int n_phase, unsigned *out, hipStream_t st);
+// tab[a * n_phase + b] = coefficient of a face between phases a and b
+// (t64 and / or t32 may be null).
+hipError_t launch_pair_table(const CoefTable &tab, int n_phase, double dt, double h, double *t64, float *t32,
+                             hipStream_t st);
 hipError_t launch_coef(const uint8_t *label, int nx, int ny, int nz, const CoefTable &tab,
                        double dt, double h, double *lam64, float *lam32, hipStream_t st);
 hipError_t launch_line(int mode, int r, const LineArgs &a, hipStream_t st);
