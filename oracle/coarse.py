@@ -215,3 +215,93 @@ def step_far_field(problem, P, pbc, c, c_ff: float, m_total: float, v_ff: float,
     c_ff_new = (m_total - out.sum()) / v_ff
     out[res] = c_ff_new
     return out, c_ff_new
+
+
+# --------------------------------------------------------------------------
+# Reduced-precision arithmetic of the coarse step (Sec. 3.3, Fig. 3, Table 2).
+#
+# The paper compares four precisions of the FDiRW superposition:
+#   fp64   P, C, products and sums in FP64
+#   fp32   P and C in FP32, products and sums in FP32
+#   mixed  (its FP32/FP16 scheme) C computed in FP32 and converted to FP16,
+#          P stored in FP16, each product P[I, J] C_J taken in FP16, the
+#          products accumulated in FP32, the result widened for the remapping
+#   fp16   as mixed, but the products also accumulated in FP16
+# The far-field term P_BC c_ff is formed the same way as one more product.
+# Reading: the mapping (Eq. 13) is the FP64 group mean rounded to the C
+# precision (the paper maps in FP32; the mean is the same to FP32 rounding and
+# the mapping is memory-bound either way).
+#
+# ARITH_TERMS gives the terms exactly as the precision forms them; the sum is
+# then written out per node: for fp64 / fp32 / mixed the exact FP64 sum of the
+# terms (any FP32 accumulation order differs from it by at most
+# gamma_n(2^-24) times the sum of |terms|), for fp16 the sequential FP16 sum
+# over J in increasing order (the paper's example of why FP16 accumulation
+# fails: a large partial sum absorbs small terms).
+
+ARITH = ("fp64", "fp32", "mixed", "fp16")
+UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "mixed": 2.0 ** -24, "fp16": 2.0 ** -11}
+
+
+def arith_operands(P, C, arith: str):
+    """(P, C) rounded to the storage precision of ``arith``, as FP64 arrays."""
+    P = np.asarray(P, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    if arith == "fp64":
+        return P, C
+    if arith == "fp32":
+        return P.astype(np.float32).astype(np.float64), C.astype(np.float32).astype(np.float64)
+    if arith in ("mixed", "fp16"):
+        return P.astype(np.float16).astype(np.float64), C.astype(np.float16).astype(np.float64)
+    raise ValueError(f"unknown arithmetic {arith!r}")
+
+
+def arith_terms(P, C, arith: str) -> np.ndarray:
+    """terms[I, J] = the product P[I, J] C_J as the precision forms it: exact
+    for fp64 / fp32 (a product of two FP32 numbers is exact in FP64; FP32
+    accumulates it with a fused multiply-add), rounded to FP16 for mixed and
+    fp16 (an FP16 multiply of the FP16 operands)."""
+    Pr, Cr = arith_operands(P, C, arith)
+    t = Pr * Cr[None, :]
+    if arith in ("mixed", "fp16"):
+        t = (Pr.astype(np.float16) * Cr.astype(np.float16)[None, :]).astype(np.float64)
+    return t
+
+
+def arith_sum(terms: np.ndarray, arith: str) -> np.ndarray:
+    """Row sums of ``terms`` in the accumulation precision (see above)."""
+    terms = np.asarray(terms, dtype=np.float64)
+    if arith != "fp16":
+        return terms.sum(axis=1)
+    out = np.zeros(terms.shape[0], dtype=np.float16)
+    t16 = terms.astype(np.float16)
+    for j in range(terms.shape[1]):
+        out = (out + t16[:, j]).astype(np.float16)
+    return out.astype(np.float64)
+
+
+def arith_product(P, C, arith: str, pbc=None, c_ff: float = 0.0):
+    """(C', bound): Eq. 14 in the precision ``arith`` and, per node, the
+    bound gamma_n(u) * sum |terms| (n = number of nonzero terms + 1) within
+    which any summation order of the same terms agrees with C'."""
+    t = arith_terms(P, C, arith)
+    if pbc is not None:
+        t = np.concatenate([t, arith_terms(np.asarray(pbc, dtype=np.float64)[:, None], np.array([c_ff]), arith)],
+                           axis=1)
+    out = arith_sum(t, arith)
+    n = (t != 0).sum(axis=1) + 1
+    u = UNIT_ROUNDOFF[arith]
+    nu = n * u
+    gam = np.where(nu < 1.0, nu / np.maximum(1.0 - nu, 1e-300), np.inf)
+    return out, gam * np.abs(t).sum(axis=1)
+
+
+def step_arith(problem, P, c, B: int, arith: str, grouped=None):
+    """One coarse big step (Eqs. 13-15) in the precision ``arith``; returns
+    (c_new, per-cell bound of the accumulation order, 0 outside the groups)."""
+    C = mapping(c, problem.label, problem.d_phase, B, grouped)
+    Cn, bnd = arith_product(P, C, arith)
+    out = remapping(Cn, c, problem.label, problem.d_phase, B, grouped)
+    bcell = remapping(bnd, np.zeros_like(np.asarray(c, dtype=np.float64)), problem.label, problem.d_phase, B,
+                      grouped)
+    return out, bcell

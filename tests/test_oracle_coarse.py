@@ -198,3 +198,74 @@ def test_node_windows_far_field_covering_equal_source_windows():
     has = count > 0
     out = (count[:, None] * got).sum(axis=0)[has] / count[has]
     assert np.all(out <= 1.0 + 1e-13) and np.any(out < 0.999)
+
+
+# ---------------------------------------------------------------- reduced-precision arithmetic (Sec. 3.3, Table 2)
+
+def test_arith_fp64_is_the_plain_product():
+    rng = np.random.default_rng(3)
+    P = rng.random((30, 40))
+    C = rng.random(40)
+    out, bnd = coarse.arith_product(P, C, "fp64")
+    assert np.max(np.abs(out - P @ C)) <= 1e-14 * np.abs(P @ C).max()
+    assert np.all(bnd < 1e-12 * np.abs(P @ C))
+
+
+def test_arith_exactly_representable_operands_agree():
+    # P entries k / 64 and C small integers: every product is a multiple of
+    # 1/64 below 16 (exact in FP16) and every row sum is exact in FP32, so the
+    # fp32 and mixed steps equal fp64 exactly; FP16 accumulation does not
+    rng = np.random.default_rng(4)
+    P = rng.integers(0, 65, (25, 125)) / 64.0
+    C = rng.integers(0, 17, 125).astype(np.float64)
+    ref, _ = coarse.arith_product(P, C, "fp64")
+    for a in ("fp32", "mixed"):
+        out, _ = coarse.arith_product(P, C, a)
+        assert np.array_equal(out, ref), a
+    out16, bnd16 = coarse.arith_product(P, C, "fp16")
+    assert not np.array_equal(out16, ref)
+    assert np.all(np.abs(out16 - ref) <= bnd16)
+
+
+def test_arith_mixed_rounds_each_product_to_fp16():
+    # 1/3 rounds to 0.333251953125 in FP16; times 3 that is 1 - 2^-12, exactly
+    # half way between the FP16 neighbours 1 - 2^-11 and 1: round to even -> 1
+    out, _ = coarse.arith_product(np.array([[1.0 / 3.0]]), np.array([3.0]), "mixed")
+    assert out[0] == 1.0
+    out, _ = coarse.arith_product(np.array([[1.0 / 3.0]]), np.array([3.0]), "fp32")
+    assert out[0] == np.float64(np.float32(1.0 / 3.0)) * 3.0 != 1.0
+
+
+def test_arith_fp16_accumulation_stalls():
+    # Sec. 3.3: adding small terms to a large sum needs digits FP16 lacks:
+    # 4096 unit terms accumulate to 2048 in FP16 (2048 + 1 rounds back to
+    # 2048) and to 4096 with FP32 accumulation
+    P = np.ones((1, 4096))
+    C = np.ones(4096)
+    assert coarse.arith_product(P, C, "fp16")[0][0] == 2048.0
+    assert coarse.arith_product(P, C, "mixed")[0][0] == 4096.0
+
+
+@pytest.mark.parametrize("arith", ["fp32", "mixed"])
+def test_arith_bound_covers_other_orders(arith):
+    # the per-node bound holds for FP32 accumulation in another order
+    # (reversed, sequential FP32 additions of the same terms)
+    rng = np.random.default_rng(5)
+    P = rng.random((50, 125)) * 10.0 ** rng.integers(-6, 0, (50, 125))
+    C = rng.random(125)
+    out, bnd = coarse.arith_product(P, C, arith)
+    t = coarse.arith_terms(P, C, arith).astype(np.float32)
+    acc = np.zeros(50, dtype=np.float32)
+    for j in range(124, -1, -1):
+        acc = (acc + t[:, j]).astype(np.float32)
+    assert np.all(np.abs(acc.astype(np.float64) - out) <= bnd)
+
+
+def test_arith_step_on_a_grid_conserves_mass_to_the_precision():
+    d = synth.random_small((10, 10, 10), 2, r=3, n_sub=20, seed=7)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, 5)
+    ref = coarse.step(p, P, d.c0, 5)
+    for a, tol in (("fp64", 1e-14), ("fp32", 1e-6), ("mixed", 2e-3), ("fp16", 5e-2)):
+        out, bnd = coarse.step_arith(p, P, d.c0, 5, a)
+        assert abs(out.sum() - ref.sum()) <= tol * ref.sum(), a
