@@ -244,7 +244,8 @@ UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "mixed": 2.0 ** -24, "f
 
 
 def arith_operands(P, C, arith: str):
-    """(P, C) rounded to the storage precision of ``arith``, as FP64 arrays."""
+    """(P, C) rounded to the storage precision of ``arith``, as FP64 arrays
+    (mixed / fp16: C through FP32, as the scheme forms it)."""
     P = np.asarray(P, dtype=np.float64)
     C = np.asarray(C, dtype=np.float64)
     if arith == "fp64":
@@ -252,7 +253,9 @@ def arith_operands(P, C, arith: str):
     if arith == "fp32":
         return P.astype(np.float32).astype(np.float64), C.astype(np.float32).astype(np.float64)
     if arith in ("mixed", "fp16"):
-        return P.astype(np.float16).astype(np.float64), C.astype(np.float16).astype(np.float64)
+        # C is formed in FP32 and then converted to FP16 (Sec. 3.3); P is
+        # stored in FP16 from its FP64 values
+        return P.astype(np.float16).astype(np.float64), C.astype(np.float32).astype(np.float16).astype(np.float64)
     raise ValueError(f"unknown arithmetic {arith!r}")
 
 
