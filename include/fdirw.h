@@ -129,8 +129,12 @@ typedef struct fdirw_opts {
     void *stream;              /* hipStream_t, NULL = default stream */
     int32_t tune;              /* launch shape.  n_dom == 1: > 0 = segments per source line,
                                   else automatic; with deterministic = 1, > 0 = source planes
-                                  per slab, else automatic.  n_dom > 1: 0..5 = batched shape id (item z
-                                  extent and queue order), -1 = autotuned (cached per precision,
+                                  per slab, else automatic.  n_dom > 1: batched shape id, 0..5 = the
+                                  640-thread segment layout (item z extent whole / whole / 64 / 32 /
+                                  16 / 8 planes; natural order for 0, longest first otherwise), 6..9
+                                  = the 256-thread flat layout, FP32 only (one source line per item,
+                                  z extent whole / 64 / 32 / 16, longest first; E_ARG for another
+                                  precision), -1 = autotuned (cached per precision,
                                   radius / sub-step mix, size class and device; the cache file is
                                   named by the environment variable FDIRW_TUNE_CACHE) */
 } fdirw_opts;
@@ -369,6 +373,29 @@ int fdirw_nn_load(void *nn, const char *path);
 int fdirw_coarse_create(const fdirw_domain *d, int32_t block, int32_t prec, const uint8_t *grouped,
                         const uint8_t *reservoir, const double *velocity, void *stream, void **handle,
                         double *seconds);
+
+/* Arithmetic of the coarse product (the precisions compared in Sec. 3.3
+ * and Table 2; the mapping and remapping stay FP64, the group means are
+ * rounded to the C type):
+ *   FP64   C, products and sums in FP64 (the default; P of any storage)
+ *   FP32   C in FP32, fused FP32 multiply-adds (P stored in FP32)
+ *   MIXED  the paper's FP32/FP16 scheme: C rounded to FP32 and then FP16,
+ *          each product P[I][J] C_J taken in FP16 (P stored in FP16), the
+ *          products accumulated in FP32
+ *   FP16   as MIXED with the products accumulated in FP16
+ * The far-field term P_BC c_ff is formed as one more product.  The result is
+ * widened to FP64 for the remapping. */
+enum {
+    FDIRW_COARSE_ARITH_FP64 = 0,
+    FDIRW_COARSE_ARITH_FP32 = 1,
+    FDIRW_COARSE_ARITH_MIXED = 2,
+    FDIRW_COARSE_ARITH_FP16 = 3
+};
+
+/* Selects the arithmetic of the handle's later steps (allocates the reduced
+ * C grid on first use, synchronously).  Errors: E_ARG (unknown id, or a P
+ * storage the arithmetic does not take), E_NOMEM, E_DEVICE. */
+int fdirw_coarse_set_arith(void *handle, int32_t arith);
 
 /* One coarse big step from c_in to c_out (N doubles each, not overlapping).
  * st (may be NULL) receives mass_in / mass_out (compensated FP64 sums, one

@@ -86,7 +86,8 @@ ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "f
                  "fdirw_field_sum", "fdirw_last_error", "fdirw_release", "fdirw_abi_version",
                  "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
-                 "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create", "fdirw_coarse_step",
+                 "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create", "fdirw_coarse_set_arith",
+                 "fdirw_coarse_step",
                  "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_pbc",
                  "fdirw_coarse_destroy", "fdirw_mp_create", "fdirw_mp_step", "fdirw_mp_info", "fdirw_mp_destroy")
 NN_RADIUS = 8
@@ -133,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     lib.fdirw_coarse_create.argtypes = [D, ctypes.c_int32, ctypes.c_int32, P, P, P, P, PP,
                                         ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_coarse_step.argtypes = [P, P, P, P, S]
+    lib.fdirw_coarse_set_arith.argtypes = [P, ctypes.c_int32]
     lib.fdirw_coarse_step_far_field.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                                 ctypes.c_double, P, S]
     lib.fdirw_coarse_pbc.argtypes = [P, P]
@@ -150,7 +152,8 @@ def load_library(path: str = LIB_PATH):
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
               "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create",
-              "fdirw_coarse_step", "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix",
+              "fdirw_coarse_step", "fdirw_coarse_set_arith", "fdirw_coarse_step_far_field", "fdirw_coarse_shape",
+              "fdirw_coarse_matrix",
               "fdirw_coarse_pbc", "fdirw_coarse_destroy", "fdirw_mp_create", "fdirw_mp_step", "fdirw_mp_info",
               "fdirw_mp_destroy"):
         getattr(lib, f).restype = ctypes.c_int
@@ -480,6 +483,14 @@ def fdirw_coarse_pbc(handle, out: np.ndarray):
     return out
 
 
+COARSE_ARITH = {"fp64": 0, "fp32": 1, "mixed": 2, "fp16": 3}
+
+
+def fdirw_coarse_set_arith(handle, arith) -> None:
+    a = COARSE_ARITH[arith] if isinstance(arith, str) else int(arith)
+    _check(load_library().fdirw_coarse_set_arith(handle, a))
+
+
 def fdirw_coarse_step(handle, c_in, c_out, stream=None, stats: bool = False):
     st = fdirw_stats() if stats else None
     _check(load_library().fdirw_coarse_step(handle, ctypes.c_void_p(c_in.data_ptr()),
@@ -517,6 +528,10 @@ class Coarse:
         self.coarse_shape = tuple(shp[:3])
         self.K, self.block = shp[3], shp[4]
         self.n = dom.n
+
+    def set_arith(self, arith):
+        """Arithmetic of the product: "fp64", "fp32", "mixed" or "fp16"."""
+        fdirw_coarse_set_arith(self.handle, arith)
 
     def step(self, c_in, c_out=None, stream=None, stats: bool = False):
         torch = _torch()

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -265,6 +266,18 @@ static int step_det(const fdirw_domain *d, const fdirw_opts *o, LineArgs a, DevC
     return FDIRW_OK;
 }
 
+// The flat-layout fused kernel (fdirw_flat.hip) serves FP32 steps with
+// r = 4..8; the environment variable FDIRW_FUSED_LAYOUT=segments selects the
+// segment-layout kernel instead (same kernels, for comparison).
+bool use_flat_layout(int prec, int r)
+{
+    static const bool segments = [] {
+        const char *v = std::getenv("FDIRW_FUSED_LAYOUT");
+        return v && std::strcmp(v, "segments") == 0;
+    }();
+    return !segments && prec == FDIRW_FP32 && r >= 4 && r <= 8;
+}
+
 int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, double *c_out,
              fdirw_stats *st, DevCache &dc, hipStream_t stream, bool prepared, const void *lam, Geometry *geo)
 {
@@ -306,7 +319,8 @@ int step_one(const fdirw_domain *d, const fdirw_opts *o, const double *c_in, dou
     if (o->deterministic) {
         if ((rc = step_det(d, o, a, dc, stream, &nblk))) return rc;
     } else {
-        e = launch_line(o->prec, d->r, a, stream);
+        e = use_flat_layout(o->prec, d->r) ? launch_line_flat(o->prec, d->r, a, stream)
+                                           : launch_line(o->prec, d->r, a, stream);
         if (e != hipSuccess) return hip_fail(e, "fused step launch");
     }
     if (st) (void)hipEventRecord(ev.b, stream);

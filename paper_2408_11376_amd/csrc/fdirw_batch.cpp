@@ -3,7 +3,10 @@
 //
 // Work items: a domain, a group of consecutive source lines (as many as the
 // radius lets one workgroup hold) and a range of source planes.  Launch shape
-// choices the tuner explores: the z extent of an item (long items amortise the
+// choices the tuner explores: the workgroup layout (the 640-thread segment
+// layout, which packs several small windows per workgroup, or the 256-thread
+// flat layout of the single-domain FP32 step, one window per workgroup and
+// two workgroups per CU), the z extent of an item (long items amortise the
 // per-item LDS setup; short items balance the load at the end of the queue)
 // and the queue order (natural, or longest-processing-time first).  The tuner
 // times each candidate on an evenly spaced sample of the real items, with HIP
@@ -29,11 +32,15 @@ namespace fdirw {
 struct BatchConfig {
     int zlen;       // planes per item, 0 = whole column of sources
     int lpt;        // 1 = longest item first
+    int flat;       // 1 = flat layout (FP32 only): one source line per item
 };
 
 static const BatchConfig kConfigs[] = {
-    {0, 0}, {0, 1}, {64, 1}, {32, 1}, {16, 1}, {8, 1},
+    {0, 0, 0}, {0, 1, 0}, {64, 1, 0}, {32, 1, 0}, {16, 1, 0}, {8, 1, 0},
+    {0, 1, 1}, {64, 1, 1}, {32, 1, 1}, {16, 1, 1},
 };
+
+static bool config_valid(int id, int prec) { return !kConfigs[id].flat || prec == FDIRW_FP32; }
 static const int kNumConfigs = (int)(sizeof(kConfigs) / sizeof(kConfigs[0]));
 
 int batch_config_count() { return kNumConfigs; }
@@ -88,10 +95,12 @@ static std::string tune_key(const fdirw_domain *d, int n_dom, int prec)
     return k;
 }
 
-static double item_cost(const fdirw_domain &d, const BatchItem &it)
+static int lines_per_item(const BatchConfig &cfg, int r) { return cfg.flat ? 1 : batch_windows_per_group(r); }
+
+static double item_cost(const fdirw_domain &d, const BatchItem &it, const BatchConfig &cfg)
 {
     const double W = 2.0 * d.r + 1.0;
-    const int ng = batch_windows_per_group(d.r);
+    const int ng = lines_per_item(cfg, d.r);
     return (double)ng * (it.z1 - it.z0) * W * W * W * (d.n_sub > 0 ? d.n_sub : 1);
 }
 
@@ -100,7 +109,7 @@ static void build_items(const fdirw_domain *d, int n_dom, const BatchConfig &cfg
     items.clear();
     for (int i = 0; i < n_dom; ++i) {
         const int lines = d[i].nx * d[i].ny;
-        const int ng = batch_windows_per_group(d[i].r);
+        const int ng = lines_per_item(cfg, d[i].r);
         const int zl = cfg.zlen > 0 ? cfg.zlen : d[i].nz;
         for (int l0 = 0; l0 < lines; l0 += ng)
             for (int z0 = 0; z0 < d[i].nz; z0 += zl) {
@@ -115,17 +124,17 @@ static void build_items(const fdirw_domain *d, int n_dom, const BatchConfig &cfg
     }
     if (cfg.lpt) {
         std::stable_sort(items.begin(), items.end(), [&](const BatchItem &a, const BatchItem &b) {
-            return item_cost(d[a.dom], a) > item_cost(d[b.dom], b);
+            return item_cost(d[a.dom], a, cfg) > item_cost(d[b.dom], b, cfg);
         });
     }
 }
 
-static int batch_grid(int prec, int *grid)
+static int batch_grid(int prec, int flat, int *grid)
 {
     int dev = 0, cus = 0, occ = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = batched_occupancy(prec, &occ);
+    if (e == hipSuccess) e = flat ? batched_flat_occupancy(&occ) : batched_occupancy(prec, &occ);
     if (e != hipSuccess) return hip_fail(e, "batched occupancy");
     if (occ < 1) occ = 1;
     *grid = cus * occ;
@@ -133,8 +142,8 @@ static int batch_grid(int prec, int *grid)
 }
 
 // Launch the items (already on the device) after clearing the queue counter.
-static int launch_items(int prec, const BatchDom *ddoms, const BatchItem *ditems, int n_items, double *kmass,
-                        DevCache &dc, int grid, hipStream_t st)
+static int launch_items(int prec, int flat, const BatchDom *ddoms, const BatchItem *ditems, int n_items,
+                        double *kmass, DevCache &dc, int grid, hipStream_t st)
 {
     unsigned *head = (unsigned *)dc.small.p + 14;
     hipError_t e = launch_fill_u32(head, 1, 0u, st);
@@ -144,14 +153,14 @@ static int launch_items(int prec, const BatchDom *ddoms, const BatchItem *ditems
     a.n_items = n_items;
     a.head = head;
     a.item_kmass = kmass;
-    if (e == hipSuccess) e = launch_batched(prec, a, grid, st);
+    if (e == hipSuccess) e = flat ? launch_batched_flat(a, grid, st) : launch_batched(prec, a, grid, st);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     return FDIRW_OK;
 }
 
 // Times every candidate on a sample of its own items; returns the best id.
 static int autotune(const fdirw_domain *d, int n_dom, int prec, const BatchDom *ddoms, double *const *c_out,
-                    DevCache &dc, int grid, hipStream_t st, int *best_out)
+                    DevCache &dc, hipStream_t st, int *best_out)
 {
     int rc;
     double best_t = INFINITY;
@@ -161,6 +170,9 @@ static int autotune(const fdirw_domain *d, int n_dom, int prec, const BatchDom *
     hipError_t e = ev.create();
     if (e != hipSuccess) return hip_fail(e, "event create");
     for (int id = 1; id < kNumConfigs; ++id) {
+        if (!config_valid(id, prec)) continue;
+        int grid = 0;
+        if ((rc = batch_grid(prec, kConfigs[id].flat, &grid))) return rc;
         build_items(d, n_dom, kConfigs[id], items);
         const size_t want = (size_t)grid * 3;
         const size_t step = std::max<size_t>(1, items.size() / want);
@@ -168,7 +180,7 @@ static int autotune(const fdirw_domain *d, int n_dom, int prec, const BatchDom *
         double cost = 0.0;
         for (size_t i = 0; i < items.size(); i += step) {
             sample.push_back(items[i]);
-            cost += item_cost(d[items[i].dom], items[i]);
+            cost += item_cost(d[items[i].dom], items[i], kConfigs[id]);
         }
         if ((rc = ensure(dc.bitems, sample.size() * sizeof(BatchItem)))) return rc;
         e = hipMemcpyAsync(dc.bitems.p, sample.data(), sample.size() * sizeof(BatchItem), hipMemcpyHostToDevice, st);
@@ -176,8 +188,8 @@ static int autotune(const fdirw_domain *d, int n_dom, int prec, const BatchDom *
         // warm the kernel once, then time it
         for (int rep = 0; rep < 2; ++rep) {
             if (rep == 1 && (e = hipEventRecord(ev.a, st)) != hipSuccess) return hip_fail(e, "event");
-            if ((rc = launch_items(prec, ddoms, (const BatchItem *)dc.bitems.p, (int)sample.size(), nullptr, dc,
-                                   grid, st)))
+            if ((rc = launch_items(prec, kConfigs[id].flat, ddoms, (const BatchItem *)dc.bitems.p,
+                                   (int)sample.size(), nullptr, dc, grid, st)))
                 return rc;
             if (rep == 1 && (e = hipEventRecord(ev.b, st)) != hipSuccess) return hip_fail(e, "event");
         }
@@ -238,23 +250,24 @@ int step_batched(const fdirw_domain *d, int n_dom, const fdirw_opts *o, const do
     if ((rc = ensure(dc.bdoms, (size_t)n_dom * sizeof(BatchDom)))) return rc;
     hipError_t e = hipMemcpyAsync(dc.bdoms.p, hd.data(), n_dom * sizeof(BatchDom), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "domain upload");
-    int grid = 0;
-    if ((rc = batch_grid(o->prec, &grid))) return rc;
-
     int cfg = o->tune;
-    if (cfg < 0 || cfg >= kNumConfigs) {
+    if (cfg >= kNumConfigs || (cfg >= 0 && !config_valid(cfg, o->prec)))
+        return fail(FDIRW_E_ARG, "batched shape %d is not available for precision %d", cfg, o->prec);
+    if (cfg < 0) {
         load_tune_file();
         const std::string key = tune_key(d, n_dom, o->prec);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             cfg = it->second;
         } else {
-            if ((rc = autotune(d, n_dom, o->prec, (const BatchDom *)dc.bdoms.p, c_out, dc, grid, stream, &cfg)))
+            if ((rc = autotune(d, n_dom, o->prec, (const BatchDom *)dc.bdoms.p, c_out, dc, stream, &cfg)))
                 return rc;
             g_tune_cache[key] = cfg;
             store_tune_file();
         }
     }
+    int grid = 0;
+    if ((rc = batch_grid(o->prec, kConfigs[cfg].flat, &grid))) return rc;
     std::vector<BatchItem> items;
     build_items(d, n_dom, kConfigs[cfg], items);
     if ((rc = ensure(dc.bitems, items.size() * sizeof(BatchItem)))) return rc;
@@ -267,8 +280,8 @@ int step_batched(const fdirw_domain *d, int n_dom, const fdirw_opts *o, const do
     EventPair ev;
     if (st && (e = ev.create()) != hipSuccess) return hip_fail(e, "event create");
     if (st) (void)hipEventRecord(ev.a, stream);
-    if ((rc = launch_items(o->prec, (const BatchDom *)dc.bdoms.p, (const BatchItem *)dc.bitems.p, (int)items.size(),
-                           (double *)dc.wgk.p, dc, grid, stream)))
+    if ((rc = launch_items(o->prec, kConfigs[cfg].flat, (const BatchDom *)dc.bdoms.p, (const BatchItem *)dc.bitems.p,
+                           (int)items.size(), (double *)dc.wgk.p, dc, grid, stream)))
         return rc;
     if (st) (void)hipEventRecord(ev.b, stream);
     if (st) {

@@ -333,6 +333,53 @@ __global__ void coarse_finalize_kernel(const double *__restrict__ S, const doubl
     }
 }
 
+// Arithmetic of the coarse product (Sec. 3.3, Fig. 3, Table 2): the type of
+// the padded C, of the products and of the accumulation.
+//   COARSE_FP64   C FP64; products and sums FP64 (P of any storage, widened)
+//   COARSE_FP32   C FP32; fused FP32 multiply-adds (P stored in FP32)
+//   COARSE_MIXED  C rounded to FP32 then FP16; each product taken in FP16
+//                 (P stored in FP16), the products accumulated in FP32
+//   COARSE_FP16   as MIXED with FP16 accumulation
+template <int A> struct CoarseArith;
+template <> struct CoarseArith<COARSE_FP64> { using C = double; using Acc = double; };
+template <> struct CoarseArith<COARSE_FP32> { using C = float; using Acc = float; };
+template <> struct CoarseArith<COARSE_MIXED> { using C = _Float16; using Acc = float; };
+template <> struct CoarseArith<COARSE_FP16> { using C = _Float16; using Acc = _Float16; };
+
+// A mapped value (FP64 mean) in the C type of the arithmetic (FP16 via FP32).
+template <typename TC> __device__ __forceinline__ TC to_c(double v) { return (TC)v; }
+template <> __device__ __forceinline__ _Float16 to_c<_Float16>(double v) { return (_Float16)(float)v; }
+
+template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
+template <> __device__ __forceinline__ double widen<double>(double v) { return v; }
+
+// acc + p c in the arithmetic A (p: P in its storage type, c: C).
+template <int A, typename T>
+__device__ __forceinline__ typename CoarseArith<A>::Acc coarse_term(typename CoarseArith<A>::Acc acc, T p,
+                                                                    typename CoarseArith<A>::C c)
+{
+    if constexpr (A == COARSE_FP64) {
+        return __builtin_fma(widen<T>(p), c, acc);
+    } else if constexpr (A == COARSE_FP32) {
+        return __builtin_fmaf(p, c, acc);
+    } else {
+        _Float16 pr = p * c;                                      // the FP16 product
+        asm volatile("" : "+v"(pr));                             // rounded before it is added
+        if constexpr (A == COARSE_MIXED) return acc + (float)pr;
+        else return (_Float16)(acc + pr);
+    }
+}
+
+// The far-field term P_BC c_ff (P_BC held in FP64) added in the arithmetic A.
+template <int A>
+__device__ __forceinline__ typename CoarseArith<A>::Acc coarse_bc_term(typename CoarseArith<A>::Acc acc, double pbc,
+                                                                       double cff)
+{
+    if constexpr (A == COARSE_FP64) return __builtin_fma(pbc, cff, acc);
+    else if constexpr (A == COARSE_FP32) return __builtin_fmaf((float)pbc, (float)cff, acc);
+    else return coarse_term<A, _Float16>(acc, (_Float16)pbc, to_c<_Float16>(cff));
+}
+
 // Eq. 13 on the coarse grid padded by K, for grids where most blocks hold
 // grouped cells.  One workgroup per (by, bz) row of blocks: each thread sums
 // one fine x column over the block's B x B (z, y) rows (coalesced across the
@@ -340,11 +387,12 @@ __global__ void coarse_finalize_kernel(const double *__restrict__ S, const doubl
 // columns in x order: a fixed order, so the mapping is deterministic.  Blocks
 // without grouped cells read nothing and keep the 0 written when the handle
 // was built, as does the halo.
+template <typename TC>
 __global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__restrict__ c,
                                                              const int *__restrict__ node,
                                                              const double *__restrict__ count, int nx, int ny, int nz,
                                                              int B, int ncx, int ncy, CoarsePad pad,
-                                                             double *__restrict__ cpad)
+                                                             TC *__restrict__ cpad)
 {
     __shared__ double col[256];
     const int by = blockIdx.x, bz = blockIdx.y;
@@ -386,7 +434,7 @@ __global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__re
             if (nI > 0.0) {
                 double t = 0.0;
                 for (int k = 0; k < B; ++k) t += col[threadIdx.x * B + k];
-                cpad[coarse_pad_at(pad, bx, by, bz)] = t / nI;
+                cpad[coarse_pad_at(pad, bx, by, bz)] = to_c<TC>(t / nI);
             }
         }
     }
@@ -399,10 +447,11 @@ __global__ void __launch_bounds__(256) coarse_map_rows_kernel(const double *__re
 // written when the handle was built.
 constexpr int MAP_NT = 256;
 
+template <typename TC>
 __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__restrict__ c, const int *__restrict__ node,
                                                             const double *__restrict__ count, int nx, int ny, int nz,
                                                             int B, int ncx, int ncy, int ncz, CoarsePad pad,
-                                                            double *__restrict__ cpad, const int *__restrict__ used,
+                                                            TC *__restrict__ cpad, const int *__restrict__ used,
                                                             int64_t n_used)
 {
     const int64_t wv = blockIdx.x * (int64_t)(MAP_NT / 64) + (threadIdx.x >> 6);
@@ -436,7 +485,7 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) cpad[coarse_pad_at(pad, bx, by, bz)] = s / nI;
+    if (lane == 0) cpad[coarse_pad_at(pad, bx, by, bz)] = to_c<TC>(s / nI);
 }
 
 // Eq. 14 on the coarse grid: C'_I = sum over the (2K+1)^3 offsets o of
@@ -463,19 +512,18 @@ __global__ void __launch_bounds__(MAP_NT) coarse_map_kernel(const double *__rest
 // stored compactly: the listed chunks only, in list order.
 //
 // Either way the sum of every node has one fixed order.
-template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
-template <> __device__ __forceinline__ double widen<double>(double v) { return v; }
-
 constexpr int APPLY_MAX_WAVES = 16;
 
 // groups: the 64-position groups of P's layout to run (those that hold a node
 // with cells).
-template <typename T, int KW>
+template <typename T, int KW, int A>
 __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_rows_kernel(
-    const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz,
+    const T *__restrict__ P, const typename CoarseArith<A>::C *__restrict__ cpad, int ncx, int ncy, int ncz,
     const double *__restrict__ pbc_pad, double c_ff, const double *__restrict__ cff_dev,
     const double *__restrict__ count, double *__restrict__ cnew, const int *__restrict__ groups)
 {
+    using TC = typename CoarseArith<A>::C;
+    using TA = typename CoarseArith<A>::Acc;
     constexpr int zb = 16 / (int)sizeof(T);
     constexpr int K = (KW - 1) / 2, kw = KW;                      // the x offsets unrolled: kw loads in flight
     __shared__ double part[APPLY_MAX_WAVES * 64];
@@ -486,7 +534,7 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_rows_kernel
     const int64_t plane = n_chunks * zb;
     const int64_t ch = (int64_t)groups[blockIdx.x] * (64 / zb) + lane / zb;   // (zg, y, x) chunk
     const int j = lane % zb;
-    double acc = 0.0;
+    TA acc = TA(0);
     int x = 0, y = 0, z = ncz;
     if (ch < n_chunks) {
         x = (int)(ch % ncx);
@@ -501,40 +549,42 @@ __global__ void __launch_bounds__(64 * APPLY_MAX_WAVES) coarse_apply_rows_kernel
             int o = 0;
             for (int oy = 0; oy < kw; ++oy) {
                 // source (z - oz + K, y - oy + K, x - ox + K) = padded (z - oz + 2K, ...), x fastest
-                const double *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
+                const TC *crow = cpad + ((int64_t)(z - oz + 2 * K) * py + (y - oy + 2 * K)) * px + (x + 2 * K);
                 T pv[kw];
-                double cv[kw];
+                TC cv[kw];
 #pragma unroll
                 for (int ox = 0; ox < kw; ++ox) {
                     pv[ox] = p[(o + ox) * plane];
                     cv[ox] = crow[-ox];
                 }
 #pragma unroll
-                for (int ox = 0; ox < kw; ++ox) acc = __builtin_fma(widen<T>(pv[ox]), cv[ox], acc);
+                for (int ox = 0; ox < kw; ++ox) acc = coarse_term<A, T>(acc, pv[ox], cv[ox]);
                 o += kw;
             }
         }
     }
-    part[threadIdx.x] = acc;
+    part[threadIdx.x] = (double)acc;                              // exact: acc is a TA value
     __syncthreads();
     if (w == 0 && z < ncz) {
-        double s = 0.0;
-        for (int k = 0; k < nw; ++k) s += part[k * 64 + lane];
+        TA s = TA(0);
+        for (int k = 0; k < nw; ++k) s = (TA)(s + (TA)part[k * 64 + lane]);
         if (pbc_pad)                                              // far-field term of Eq. 14
-            s = __builtin_fma(pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)],
-                              cff_dev ? *cff_dev : c_ff, s);
-        cnew[((int64_t)z * ncy + y) * ncx + x] = s;
+            s = coarse_bc_term<A>(s, pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)],
+                                  cff_dev ? *cff_dev : c_ff);
+        cnew[((int64_t)z * ncy + y) * ncx + x] = (double)s;
     }
 }
 
 constexpr int APPLY_NT = 256;
 
-template <typename T, int KW>
+template <typename T, int KW, int A>
 __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
-    const T *__restrict__ P, const double *__restrict__ cpad, int ncx, int ncy, int ncz,
+    const T *__restrict__ P, const typename CoarseArith<A>::C *__restrict__ cpad, int ncx, int ncy, int ncz,
     const int *__restrict__ chunks, int64_t n_chunks, int64_t n_chunk_pad, int pairs_per_range, int n_split,
     double *__restrict__ part)
 {
+    using TC = typename CoarseArith<A>::C;
+    using TA = typename CoarseArith<A>::Acc;
     constexpr int zb = 16 / (int)sizeof(T);
     constexpr int K = (KW - 1) / 2, NC = zb + 2 * K;               // C column: zb nodes and 2K neighbours
     const int64_t n_waves = (n_chunk_pad / 64) * n_split;
@@ -543,9 +593,9 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
     const int lane = threadIdx.x & 63;
     const int split = (int)(wv % n_split);
     const int64_t ci = (wv / n_split) * 64 + lane;                // slot in the chunk list
-    double acc[zb];
+    TA acc[zb];
 #pragma unroll
-    for (int j = 0; j < zb; ++j) acc[j] = 0.0;
+    for (int j = 0; j < zb; ++j) acc[j] = TA(0);
     if (ci < n_chunks) {
         const int64_t ch = chunks[ci];                            // (zg, y, x) chunk of P's layout
         const int x = (int)(ch % ncx), y = (int)((ch / ncx) % ncy);
@@ -558,13 +608,18 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
         for (int q = q0; q < q1; ++q) {
             const int oy = q / KW, ox = q - oy * KW;
             // padded z of node z0 + j and offset oz: z0 + j - oz + 2K, i.e. column entry j + 2K - oz
-            const double *colp = cpad + coarse_pad_at(pad, x - ox + K, y - oy + K, z0 - K);
-            double col[NC];
+            const TC *colp = cpad + coarse_pad_at(pad, x - ox + K, y - oy + K, z0 - K);
+            TC col[NC];
+            if constexpr (A == COARSE_FP64) {
 #pragma unroll
-            for (int t = 0; t < NC; t += 2) {
-                const double2 v = *(const double2 *)(colp + t);
-                col[t] = v.x;
-                col[t + 1] = v.y;
+                for (int t = 0; t < NC; t += 2) {
+                    const double2 v = *(const double2 *)(colp + t);
+                    col[t] = v.x;
+                    col[t + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NC; ++t) col[t] = colp[t];
             }
             uint4 pv[KW];
 #pragma unroll
@@ -574,13 +629,13 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
                 T e[zb];
                 __builtin_memcpy(e, &pv[oz], 16);
 #pragma unroll
-                for (int j = 0; j < zb; ++j) acc[j] = __builtin_fma(widen<T>(e[j]), col[j + 2 * K - oz], acc[j]);
+                for (int j = 0; j < zb; ++j) acc[j] = coarse_term<A, T>(acc[j], e[j], col[j + 2 * K - oz]);
             }
         }
     }
     double *out = part + ((int64_t)split * n_chunk_pad + ci) * zb;
 #pragma unroll
-    for (int j = 0; j < zb; j += 2) *(double2 *)(out + j) = make_double2(acc[j], acc[j + 1]);
+    for (int j = 0; j < zb; j += 2) *(double2 *)(out + j) = make_double2((double)acc[j], (double)acc[j + 1]);
 }
 
 // C'_I = the ranges' partial sums added in a fixed order, plus P_BC c_ff with
@@ -590,6 +645,7 @@ __global__ void __launch_bounds__(APPLY_NT) coarse_apply_chunks_kernel(
 // first lane adds the SUM_TP block sums in lane order.
 constexpr int SUM_TP = 8;
 
+template <int A>
 __global__ void coarse_apply_sum_kernel(const double *__restrict__ part, const int *__restrict__ chunks,
                                         int64_t n_chunks, int64_t n_chunk_pad, int n_split, int zb, int ncx, int ncy,
                                         int ncz, int K, const double *__restrict__ count,
@@ -616,7 +672,8 @@ __global__ void coarse_apply_sum_kernel(const double *__restrict__ part, const i
             valid = count[I] > 0.0;
         }
     }
-    double s = 0.0;
+    using TA = typename CoarseArith<A>::Acc;
+    TA s = TA(0);
     if (valid) {
         const int per = (n_split + SUM_TP - 1) / SUM_TP;
         const int k0 = sub * per, k1 = k0 + per < n_split ? k0 + per : n_split;
@@ -628,18 +685,18 @@ __global__ void coarse_apply_sum_kernel(const double *__restrict__ part, const i
             for (int u = 0; u < 16; ++u) v[u] = k + u < k1 ? pp[(int64_t)(k + u) * stride] : 0.0;
 #pragma unroll
             for (int u = 0; u < 16; ++u)
-                if (k + u < k1) s += v[u];
+                if (k + u < k1) s = (TA)(s + (TA)v[u]);
         }
     }
     const int base = (int)(threadIdx.x & 63) & ~(SUM_TP - 1);
-    double tot = 0.0;
+    TA tot = TA(0);
 #pragma unroll
-    for (int u = 0; u < SUM_TP; ++u) tot += __shfl(s, base + u, 64);
+    for (int u = 0; u < SUM_TP; ++u) tot = (TA)(tot + (TA)__shfl((double)s, base + u, 64));
     if (!valid || sub != 0) return;
     if (pbc_pad)                                                  // far-field term of Eq. 14
-        tot = __builtin_fma(pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)], cff_dev ? *cff_dev : c_ff,
-                            tot);
-    cnew[I] = tot;
+        tot = coarse_bc_term<A>(tot, pbc_pad[coarse_pad_at(coarse_pad(ncx, ncy, ncz, K), x, y, z)],
+                                cff_dev ? *cff_dev : c_ff);
+    cnew[I] = (double)tot;
 }
 
 // Eq. 15: every grouped cell takes its node's value, the others keep theirs;
@@ -874,22 +931,49 @@ hipError_t launch_coarse_finalize(int prec, const double *S, const double *count
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
-                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense,
-                             const int *used, int64_t n_used)
+template <typename TC>
+static hipError_t coarse_map_t(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
+                               int ncx, int ncy, int ncz, int K, TC *cpad, hipStream_t st, int dense,
+                               const int *used, int64_t n_used)
 {
     if (dense && B <= 256) {
         if (ncx <= 0 || ncy <= 0 || ncz <= 0) return hipSuccess;
-        hipLaunchKernelGGL(coarse_map_rows_kernel, dim3((unsigned)ncy, (unsigned)ncz), dim3(256), 0, st, c, node,
+        hipLaunchKernelGGL(coarse_map_rows_kernel<TC>, dim3((unsigned)ncy, (unsigned)ncz), dim3(256), 0, st, c, node,
                            count, nx, ny, nz, B, ncx, ncy, coarse_pad(ncx, ncy, ncz, K), cpad);
         return hipGetLastError();
     }
     const int64_t waves = used ? n_used : (int64_t)ncx * ncy * ncz;
     const int64_t g = (waves + MAP_NT / 64 - 1) / (MAP_NT / 64);
     if (g <= 0) return hipSuccess;
-    hipLaunchKernelGGL(coarse_map_kernel, dim3((unsigned)g), dim3(MAP_NT), 0, st, c, node, count, nx, ny, nz, B, ncx,
-                       ncy, ncz, coarse_pad(ncx, ncy, ncz, K), cpad, used, n_used);
+    hipLaunchKernelGGL(coarse_map_kernel<TC>, dim3((unsigned)g), dim3(MAP_NT), 0, st, c, node, count, nx, ny, nz, B,
+                       ncx, ncy, ncz, coarse_pad(ncx, ncy, ncz, K), cpad, used, n_used);
     return hipGetLastError();
+}
+
+hipError_t launch_coarse_map(const double *c, const int *node, const double *count, int nx, int ny, int nz, int B,
+                             int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense,
+                             const int *used, int64_t n_used)
+{
+    return coarse_map_t<double>(c, node, count, nx, ny, nz, B, ncx, ncy, ncz, K, cpad, st, dense, used, n_used);
+}
+
+hipError_t launch_coarse_map_arith(int arith, const double *c, const int *node, const double *count, int nx, int ny,
+                                   int nz, int B, int ncx, int ncy, int ncz, int K, void *cpad, hipStream_t st,
+                                   int dense, const int *used, int64_t n_used)
+{
+    switch (arith) {
+    case COARSE_FP64:
+        return coarse_map_t<double>(c, node, count, nx, ny, nz, B, ncx, ncy, ncz, K, (double *)cpad, st, dense, used,
+                                    n_used);
+    case COARSE_FP32:
+        return coarse_map_t<float>(c, node, count, nx, ny, nz, B, ncx, ncy, ncz, K, (float *)cpad, st, dense, used,
+                                   n_used);
+    case COARSE_MIXED:
+    case COARSE_FP16:
+        return coarse_map_t<_Float16>(c, node, count, nx, ny, nz, B, ncx, ncy, ncz, K, (_Float16 *)cpad, st, dense,
+                                      used, n_used);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 int coarse_apply_zb(int prec) { return 16 / (prec == M_FP64 ? 8 : (prec == M_FP32 ? 4 : 2)); }
@@ -925,7 +1009,7 @@ int64_t coarse_apply_part_elems(int prec, int K, int64_t n_chunks)
 // Arguments of either product shape.
 struct ApplyCall {
     const void *P;
-    const double *cpad;
+    const void *cpad;
     int ncx, ncy, ncz;
     const double *pbc_pad;
     double c_ff;
@@ -937,30 +1021,32 @@ struct ApplyCall {
     double *part;
 };
 
-template <typename T, int KW>
+template <typename T, int KW, int A>
 static hipError_t apply_kw(const ApplyCall &a, hipStream_t st)
 {
+    using TC = typename CoarseArith<A>::C;
     constexpr int K = (KW - 1) / 2;
     if constexpr (K < COARSE_CHUNK_MIN_K) {
         constexpr int nw = KW < APPLY_MAX_WAVES ? KW : APPLY_MAX_WAVES;
-        hipLaunchKernelGGL((coarse_apply_rows_kernel<T, KW>), dim3((unsigned)a.n_list), dim3(64 * nw), 0, st,
-                           (const T *)a.P, a.cpad, a.ncx, a.ncy, a.ncz, a.pbc_pad, a.c_ff, a.cff_dev, a.count, a.cnew,
-                           a.list);
+        hipLaunchKernelGGL((coarse_apply_rows_kernel<T, KW, A>), dim3((unsigned)a.n_list), dim3(64 * nw), 0, st,
+                           (const T *)a.P, (const TC *)a.cpad, a.ncx, a.ncy, a.ncz, a.pbc_pad, a.c_ff, a.cff_dev,
+                           a.count, a.cnew, a.list);
     } else {
         const int64_t pad = (a.n_list + 63) / 64 * 64;
         const int64_t waves = pad / 64 * a.ns;
         const int64_t g = (waves + APPLY_NT / 64 - 1) / (APPLY_NT / 64);
-        hipLaunchKernelGGL((coarse_apply_chunks_kernel<T, KW>), dim3((unsigned)g), dim3(APPLY_NT), 0, st,
-                           (const T *)a.P, a.cpad, a.ncx, a.ncy, a.ncz, a.list, a.n_list, pad, a.ppr, a.ns, a.part);
+        hipLaunchKernelGGL((coarse_apply_chunks_kernel<T, KW, A>), dim3((unsigned)g), dim3(APPLY_NT), 0, st,
+                           (const T *)a.P, (const TC *)a.cpad, a.ncx, a.ncy, a.ncz, a.list, a.n_list, pad, a.ppr,
+                           a.ns, a.part);
     }
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int A>
 static hipError_t apply_t(int K, const ApplyCall &a, hipStream_t st)
 {
 #define FDIRW_APPLY_CASE(k)                                                                                        \
-    case k: return apply_kw<T, 2 * k + 1>(a, st);
+    case k: return apply_kw<T, 2 * k + 1, A>(a, st);
     switch (K) {
         FDIRW_APPLY_CASE(0)
         FDIRW_APPLY_CASE(1)
@@ -976,33 +1062,75 @@ static hipError_t apply_t(int K, const ApplyCall &a, hipStream_t st)
 #undef FDIRW_APPLY_CASE
 }
 
-hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
-                               const double *pbc_pad, double c_ff, const double *count, double *cnew,
-                               hipStream_t st, const double *cff_dev, const int *list, int64_t n_list,
-                               int n_split, double *part)
+template <int A>
+static hipError_t launch_sum(const ApplyCall &a, int zb, int K, hipStream_t st)
+{
+    const int64_t nt = a.n_list * zb * SUM_TP;
+    hipLaunchKernelGGL(coarse_apply_sum_kernel<A>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a.part,
+                       a.list, a.n_list, (a.n_list + 63) / 64 * 64, a.ns, zb, a.ncx, a.ncy, a.ncz, K, a.count,
+                       a.pbc_pad, a.c_ff, a.cff_dev, a.cnew);
+    return hipGetLastError();
+}
+
+bool coarse_arith_supported(int arith, int prec)
+{
+    switch (arith) {
+    case COARSE_FP64: return prec == M_FP64 || prec == M_FP32 || prec == M_F16BANK || prec == M_BF16BANK;
+    case COARSE_FP32: return prec == M_FP32;
+    case COARSE_MIXED:
+    case COARSE_FP16: return prec == M_F16BANK;
+    default: return false;
+    }
+}
+
+size_t coarse_c_bytes(int arith)
+{
+    return arith == COARSE_FP64 ? 8 : (arith == COARSE_FP32 ? 4 : 2);
+}
+
+hipError_t launch_coarse_apply_arith(int arith, int prec, const void *P, const void *cpad, int ncx, int ncy, int ncz,
+                                     int K, const double *pbc_pad, double c_ff, const double *count, double *cnew,
+                                     hipStream_t st, const double *cff_dev, const int *list, int64_t n_list,
+                                     int n_split, double *part)
 {
     if (n_list <= 0) return hipSuccess;
-    if (K < 0 || K > 8) return hipErrorInvalidValue;
+    if (K < 0 || K > 8 || !coarse_arith_supported(arith, prec)) return hipErrorInvalidValue;
     ApplyCall a{P, cpad, ncx, ncy, ncz, pbc_pad, c_ff, cff_dev, count, cnew, list, n_list, 0, 1, part};
     if (K >= COARSE_CHUNK_MIN_K) {
         apply_ranges(K, n_list, &a.ppr, &a.ns);
         if (a.ns != n_split) return hipErrorInvalidValue;         // part was sized for another split
     }
     hipError_t e;
-    switch (prec) {
-    case M_FP64: e = apply_t<double>(K, a, st); break;
-    case M_FP32: e = apply_t<float>(K, a, st); break;
-    case M_F16BANK: e = apply_t<_Float16>(K, a, st); break;
-    case M_BF16BANK: e = apply_t<__bf16>(K, a, st); break;
-    default: return hipErrorInvalidValue;
+    switch (arith) {
+    case COARSE_FP64:
+        switch (prec) {
+        case M_FP64: e = apply_t<double, COARSE_FP64>(K, a, st); break;
+        case M_FP32: e = apply_t<float, COARSE_FP64>(K, a, st); break;
+        case M_F16BANK: e = apply_t<_Float16, COARSE_FP64>(K, a, st); break;
+        default: e = apply_t<__bf16, COARSE_FP64>(K, a, st); break;
+        }
+        break;
+    case COARSE_FP32: e = apply_t<float, COARSE_FP32>(K, a, st); break;
+    case COARSE_MIXED: e = apply_t<_Float16, COARSE_MIXED>(K, a, st); break;
+    default: e = apply_t<_Float16, COARSE_FP16>(K, a, st); break;
     }
     if (e != hipSuccess || K < COARSE_CHUNK_MIN_K) return e;
     const int zb = coarse_apply_zb(prec);
-    const int64_t nt = n_list * zb * SUM_TP;
-    hipLaunchKernelGGL(coarse_apply_sum_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, part, list,
-                       n_list, (n_list + 63) / 64 * 64, a.ns, zb, ncx, ncy, ncz, K, count, pbc_pad, c_ff, cff_dev,
-                       cnew);
-    return hipGetLastError();
+    switch (arith) {
+    case COARSE_FP64: return launch_sum<COARSE_FP64>(a, zb, K, st);
+    case COARSE_FP32: return launch_sum<COARSE_FP32>(a, zb, K, st);
+    case COARSE_MIXED: return launch_sum<COARSE_MIXED>(a, zb, K, st);
+    default: return launch_sum<COARSE_FP16>(a, zb, K, st);
+    }
+}
+
+hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int ncx, int ncy, int ncz, int K,
+                               const double *pbc_pad, double c_ff, const double *count, double *cnew,
+                               hipStream_t st, const double *cff_dev, const int *list, int64_t n_list,
+                               int n_split, double *part)
+{
+    return launch_coarse_apply_arith(COARSE_FP64, prec, P, cpad, ncx, ncy, ncz, K, pbc_pad, c_ff, count, cnew, st,
+                                     cff_dev, list, n_list, n_split, part);
 }
 
 hipError_t launch_coarse_remap(const double *c_in, const int *node, const double *cnew, int64_t n, double *c_out,

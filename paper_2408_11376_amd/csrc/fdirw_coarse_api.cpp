@@ -47,10 +47,12 @@ struct Coarse {
     int n_split = 1;
     void *used = nullptr;           // int [n_used]: the nodes with cells (sparse mapping)
     int64_t n_used = 0;
+    int arith = COARSE_FP64;        // arithmetic of the product (fdirw_coarse_set_arith)
+    void *cpad_lp = nullptr;        // the padded coarse grid in the arithmetic's C type (FP32 / FP16)
 
     ~Coarse()
     {
-        for (void *p : {node, count, P, cpad, cnew, part, pbc, list, apart, used})
+        for (void *p : {node, count, P, cpad, cnew, part, pbc, list, apart, used, cpad_lp})
             if (p) (void)hipFree(p);
     }
     int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
@@ -383,14 +385,15 @@ int coarse_apply_all(Coarse *h, const double *c_in, double *c_out, const double 
     EventPair ev;
     hipError_t e = ks ? ev.create() : hipSuccess;
     if (ks && e == hipSuccess) e = hipEventRecord(ev.a, st);
+    void *cp = h->arith == COARSE_FP64 ? h->cpad : h->cpad_lp;
     if (e == hipSuccess)
-        e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
-                              h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense,
-                              (const int *)h->used, h->n_used);
+        e = launch_coarse_map_arith(h->arith, c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny,
+                                    h->nz, h->B, h->ncx, h->ncy, h->ncz, h->K, cp, st, h->dense,
+                                    (const int *)h->used, h->n_used);
     if (e == hipSuccess)
-        e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
-                                (const double *)h->count, (double *)h->cnew, st, cff_dev,
-                                (const int *)h->list, h->n_list, h->n_split, (double *)h->apart);
+        e = launch_coarse_apply_arith(h->arith, h->prec, h->P, cp, h->ncx, h->ncy, h->ncz, h->K, pbc, c_ff,
+                                      (const double *)h->count, (double *)h->cnew, st, cff_dev,
+                                      (const int *)h->list, h->n_list, h->n_split, (double *)h->apart);
     if (e == hipSuccess) e = launch_coarse_remap(c_in, (const int *)h->node, (const double *)h->cnew, h->n, c_out, st);
     if (ks && e == hipSuccess) e = hipEventRecord(ev.b, st);
     if (e != hipSuccess) return hip_fail(e, "coarse step launch");
@@ -414,14 +417,15 @@ int coarse_map_apply(void *handle, const double *c_in, const double *cff_dev, hi
     Coarse *h = (Coarse *)handle;
     int rc = check_handle(h);
     if (rc) return rc;
-    hipError_t e = launch_coarse_map(c_in, (const int *)h->node, (const double *)h->count, h->nx, h->ny, h->nz, h->B,
-                                     h->ncx, h->ncy, h->ncz, h->K, (double *)h->cpad, st, h->dense,
-                              (const int *)h->used, h->n_used);
+    void *cp = h->arith == COARSE_FP64 ? h->cpad : h->cpad_lp;
+    hipError_t e = launch_coarse_map_arith(h->arith, c_in, (const int *)h->node, (const double *)h->count, h->nx,
+                                           h->ny, h->nz, h->B, h->ncx, h->ncy, h->ncz, h->K, cp, st, h->dense,
+                                           (const int *)h->used, h->n_used);
     if (e == hipSuccess)
-        e = launch_coarse_apply(h->prec, h->P, (const double *)h->cpad, h->ncx, h->ncy, h->ncz, h->K,
-                                h->far_field ? (const double *)h->pbc : nullptr, 0.0, (const double *)h->count,
-                                (double *)h->cnew, st, h->far_field ? cff_dev : nullptr,
-                                (const int *)h->list, h->n_list, h->n_split, (double *)h->apart);
+        e = launch_coarse_apply_arith(h->arith, h->prec, h->P, cp, h->ncx, h->ncy, h->ncz, h->K,
+                                      h->far_field ? (const double *)h->pbc : nullptr, 0.0, (const double *)h->count,
+                                      (double *)h->cnew, st, h->far_field ? cff_dev : nullptr,
+                                      (const int *)h->list, h->n_list, h->n_split, (double *)h->apart);
     if (e != hipSuccess) return hip_fail(e, "coarse mapping / product launch");
     *cnew = (const double *)h->cnew;
     return FDIRW_OK;
@@ -432,6 +436,35 @@ const int *coarse_node(const void *handle) { return (const int *)((const Coarse 
 }  // namespace fdirw
 
 extern "C" {
+
+int fdirw_coarse_set_arith(void *handle, int32_t arith)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (arith < FDIRW_COARSE_ARITH_FP64 || arith > FDIRW_COARSE_ARITH_FP16)
+        return fail(FDIRW_E_ARG, "unknown coarse arithmetic %d", arith);
+    static_assert(FDIRW_COARSE_ARITH_FP64 == COARSE_FP64 && FDIRW_COARSE_ARITH_FP32 == COARSE_FP32 &&
+                      FDIRW_COARSE_ARITH_MIXED == COARSE_MIXED && FDIRW_COARSE_ARITH_FP16 == COARSE_FP16,
+                  "arithmetic ids");
+    if (!coarse_arith_supported(arith, h->prec))
+        return fail(FDIRW_E_ARG, "coarse arithmetic %d needs P stored in %s (the handle stores precision %d)", arith,
+                    arith == FDIRW_COARSE_ARITH_FP32 ? "FP32" : "FP16", h->prec);
+    if (arith != COARSE_FP64 && !h->cpad_lp) {
+        // the largest C type (FP32) for either reduced arithmetic; halo and
+        // empty nodes stay 0
+        const size_t bytes = (size_t)coarse_pad(h->ncx, h->ncy, h->ncz, h->K).size * sizeof(float) + 16;
+        if ((rc = coarse_alloc(&h->cpad_lp, bytes))) return rc;
+        hipError_t e = hipMemset(h->cpad_lp, 0, bytes);
+        if (e != hipSuccess) return hip_fail(e, "coarse C clear");
+    } else if (arith != COARSE_FP64 && arith != h->arith) {
+        const size_t bytes = (size_t)coarse_pad(h->ncx, h->ncy, h->ncz, h->K).size * sizeof(float) + 16;
+        hipError_t e = hipMemset(h->cpad_lp, 0, bytes);
+        if (e != hipSuccess) return hip_fail(e, "coarse C clear");
+    }
+    h->arith = arith;
+    return FDIRW_OK;
+}
 
 int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *stream, fdirw_stats *stats)
 {

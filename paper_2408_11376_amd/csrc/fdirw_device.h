@@ -78,6 +78,16 @@ template <> __device__ __forceinline__ float round_to<float>(float x) { return x
 
 constexpr int ru(int a, int b) { return (a + b - 1) / b * b; }
 
+// Spreads consecutive logical workgroups over one XCD: the hardware hands
+// workgroup b to XCD b % 8, so logical index (b % 8) * (g / 8) + b / 8 keeps
+// neighbouring source lines (which share coefficients and output planes) in
+// the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int g)
+{
+    if (g % 8 != 0) return b;
+    return (b % 8) * (g / 8) + b / 8;
+}
+
 #ifndef FDIRW_SEG_CELLS
 #define FDIRW_SEG_CELLS 9          // most cells of a z-column one thread owns
 #endif

@@ -70,6 +70,8 @@ int prepare_geometry(const fdirw_domain *d, hipStream_t st, DevCache &dc, double
 int coef_buffers(const fdirw_domain *d, int prec, hipStream_t st, DevCache &dc, Geometry *g, const void **lam);
 int field_sum_dev(const double *c, int64_t n, hipStream_t st, DevCache &dc, double *out_host);
 void line_shape(const fdirw_domain *d, int tune, int *seg_len, int *n_seg);
+// True when the fused step of this precision and radius runs the flat-layout kernel.
+bool use_flat_layout(int prec, int r);
 // Source planes per launch of the deterministic step (a function of the
 // domain's shape and radius only, or tune > 0 planes).
 int det_slab_planes(const fdirw_domain *d, int tune);

@@ -190,16 +190,6 @@ __global__ void src_check_kernel(const int64_t *__restrict__ src, int64_t n_src,
 
 // ----------------------------------------------------------------- launch geometry
 
-// Spreads consecutive logical workgroups over one XCD: the hardware hands
-// workgroup b to XCD b % 8, so logical index (b % 8) * (g / 8) + b / 8 keeps
-// neighbouring source lines (which share coefficients and output planes) in
-// the same L2.
-__device__ __forceinline__ int xcd_remap(int b, int g)
-{
-    if (g % 8 != 0) return b;
-    return (b % 8) * (g / 8) + b / 8;
-}
-
 template <int M, int R>
 __device__ __forceinline__ void zero_exchange(typename Geo<M, R>::E *xb)
 {

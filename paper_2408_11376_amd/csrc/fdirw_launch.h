@@ -134,6 +134,9 @@ struct BatchArgs {
 
 hipError_t launch_batched(int mode, const BatchArgs &a, int grid, hipStream_t st);
 hipError_t batched_occupancy(int mode, int *blocks);
+// The batched launch with the flat layout (FP32; items of one line each).
+hipError_t launch_batched_flat(const BatchArgs &a, int grid, hipStream_t st);
+hipError_t batched_flat_occupancy(int *blocks);
 int batch_windows_per_group(int r);
 
 hipError_t launch_validate(const uint8_t *label, int64_t n, int n_phase, unsigned *out, hipStream_t st);
@@ -144,6 +147,10 @@ hipError_t launch_pair_table(const CoefTable &tab, int n_phase, double dt, doubl
 hipError_t launch_coef(const uint8_t *label, int nx, int ny, int nz, const CoefTable &tab,
                        double dt, double h, double *lam64, float *lam32, hipStream_t st);
 hipError_t launch_line(int mode, int r, const LineArgs &a, hipStream_t st);
+// Flat-layout fused step (FP32, r = 4..8, atomic superposition only), with
+// the coefficients of a.lx or looked up per phase pair (a.label, a.lam_tab).
+hipError_t launch_line_flat(int mode, int r, const LineArgs &a, hipStream_t st);
+hipError_t launch_line_flat_labels(int mode, int r, const LineArgs &a, hipStream_t st);
 hipError_t launch_window(int mode, int r, const WindowArgs &a, hipStream_t st);
 hipError_t launch_bank_apply(int prec, int r, const BankArgs &a, hipStream_t st);
 int64_t bank_chat_elems(int nx, int ny, int nz, int r);
@@ -231,6 +238,20 @@ hipError_t launch_coarse_apply(int prec, const void *P, const double *cpad, int 
                                const double *pbc_pad, double c_ff, const double *count, double *cnew,
                                hipStream_t st, const double *cff_dev,    // cff_dev set: c_ff read from it
                                const int *list, int64_t n_list, int n_split, double *part);
+// Arithmetic of the coarse product (the precisions of Table 2): C and the
+// products / sums in FP64, in FP32, in FP16 with FP32 accumulation (the
+// mixed scheme of Sec. 3.3), or all in FP16.  The mapping writes the padded
+// C in the arithmetic's C type (FP64, FP32, FP16 rounded through FP32).
+enum CoarseArithId : int { COARSE_FP64 = 0, COARSE_FP32 = 1, COARSE_MIXED = 2, COARSE_FP16 = 3 };
+bool coarse_arith_supported(int arith, int prec);               // P storage the arithmetic takes
+size_t coarse_c_bytes(int arith);                               // bytes of one padded C value
+hipError_t launch_coarse_map_arith(int arith, const double *c, const int *node, const double *count, int nx, int ny,
+                                   int nz, int B, int ncx, int ncy, int ncz, int K, void *cpad, hipStream_t st,
+                                   int dense, const int *used = nullptr, int64_t n_used = 0);
+hipError_t launch_coarse_apply_arith(int arith, int prec, const void *P, const void *cpad, int ncx, int ncy, int ncz,
+                                     int K, const double *pbc_pad, double c_ff, const double *count, double *cnew,
+                                     hipStream_t st, const double *cff_dev, const int *list, int64_t n_list,
+                                     int n_split, double *part);
 int coarse_apply_zb(int prec);                                  // nodes per chunk
 int coarse_apply_split(int K, int64_t n_chunks);                // the number of pair ranges (1 below the chunk K)
 int64_t coarse_apply_part_elems(int prec, int K, int64_t n_chunks);

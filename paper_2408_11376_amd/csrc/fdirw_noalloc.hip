@@ -4,9 +4,10 @@
 //
 // Every piece of device scratch this call needs lives in one file-scope array,
 // `scratch`, of FDIRW_NOALLOC_SCRATCH_BYTES.  The face coefficients are not
-// stored per cell: the line kernel looks them up per phase pair in a table of
-// n_phase^2 entries (launch_line_labels), so the scratch size does not depend
-// on the grid.  Layout (bytes):
+// stored per cell: the fused kernel (the flat layout where fdirw_step uses it,
+// else the segment layout) looks them up per phase pair in a table of
+// n_phase^2 entries (launch_line_flat_labels / launch_line_labels), so the
+// scratch size does not depend on the grid.  Layout (bytes):
 //   [0, 64)        label / presence flags of the label check (16 unsigned)
 //   [64, 80)       sources-used counter (u64)
 //   [128, 144)     min / max kernel mass
@@ -145,7 +146,8 @@ extern "C" int fdirw_step_noalloc(const fdirw_domain *d, const fdirw_opts *o, co
     a.label = d->label;
     a.lam_tab = ptab;
     a.n_phase = d->n_phase;
-    e = launch_line_labels(o->prec, d->r, a, stream);
+    e = use_flat_layout(o->prec, d->r) ? launch_line_flat_labels(o->prec, d->r, a, stream)
+                                       : launch_line_labels(o->prec, d->r, a, stream);
     if (e != hipSuccess) return hip_fail(e, "fused step launch");
     if (st) {
         if ((rc = field_sum_scratch(c_out, n, base, stream, &st->mass_out))) return rc;

@@ -29,10 +29,12 @@ def _mixed_domains(seed=0):
     return [synth.random_small(s, 3, r=r, n_sub=n, seed=seed + i) for i, (s, r, n) in enumerate(specs)]
 
 
-@pytest.mark.parametrize("prec,tol", [(fd.FP64, 1e-12), (fd.FP32, 1e-5)])
-def test_batched_matches_oracle_every_radius(prec, tol):
+@pytest.mark.parametrize("prec,tol,tune", [(fd.FP64, 1e-12, 3), (fd.FP32, 1e-5, 3), (fd.FP32, 1e-5, 6),
+                                           (fd.FP32, 1e-5, 9)])
+def test_batched_matches_oracle_every_radius(prec, tol, tune):
+    # shapes 6..9: the flat layout (one source line per item, every radius 0..8)
     ds = _mixed_domains(100)
-    outs, sts = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=prec, stats=True, tune=3)
+    outs, sts = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=prec, stats=True, tune=tune)
     for d, o, st in zip(ds, outs, sts):
         ref, used, _ = oracle.Problem.from_domain(d).step(d.c0)
         assert np.max(np.abs(to_host(o) - ref)) <= tol, (d.shape, d.r)
@@ -40,7 +42,7 @@ def test_batched_matches_oracle_every_radius(prec, tol):
         assert abs(st["mass_out"] - st["mass_in"]) <= 1e-9 * st["mass_in"]
 
 
-@pytest.mark.parametrize("tune", list(range(6)))
+@pytest.mark.parametrize("tune", list(range(10)))
 def test_batched_shapes_agree(tune):
     ds = _mixed_domains(200)[3:8]
     base = [to_host(fd.fdirw_step(_dev(d), to_dev(d.c0), prec=fd.FP32)) for d in ds]
@@ -74,7 +76,15 @@ def test_autotuner_choice_gives_the_same_field():
     fixed = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=fd.FP32, tune=0)
     for o, f in zip(outs, fixed):
         assert np.max(np.abs(to_host(o) - to_host(f))) <= 1e-12 * to_host(f).max()
-    assert all(0 < s["tuned_config_id"] < 6 for s in sts)
+    assert all(0 < s["tuned_config_id"] < 10 for s in sts)
+
+
+def test_flat_batched_shapes_need_fp32():
+    ds = _mixed_domains(600)[3:5]
+    for tune in (6, 9, 10):
+        with pytest.raises(fd.FdirwError) as e:
+            fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=fd.FP64, tune=tune)
+        assert e.value.status == fd.E_ARG
 
 
 def test_batched_run_multiple_steps():

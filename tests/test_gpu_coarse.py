@@ -85,7 +85,15 @@ def test_reduced_precision_p(prec, kind, tol, B, r):
         assert np.max(np.abs(got - want)) <= tol * np.abs(want).max()
     else:
         assert rel_l1(got, want) <= tol
-    assert abs(st["mass_out"] - st["mass_in"]) <= 1e-2 * st["mass_in"]
+    # every column of the FP64 P conserves mass (sum_I N_I P[I][J] = N_J);
+    # rounding each entry to the storage type moves a column's mass by at
+    # most the unit roundoff u (relative), plus, for FP16, the absolute
+    # rounding of subnormal entries (<= 2^-25 each, at most (2K+1)^3 of them
+    # per column, weighted by N_I / N_J <= B^3); with c >= 0 the field's mass
+    # moves by at most that share
+    u = {fd.FP32: 2.0 ** -24, fd.FP16_BANK: 2.0 ** -11, fd.BF16_BANK: 2.0 ** -8}[prec]
+    sub = (2 * cg.K + 1) ** 3 * B ** 3 * 2.0 ** -25 if prec == fd.FP16_BANK else 0.0
+    assert abs(st["mass_out"] - st["mass_in"]) <= (u + sub + 1e-12) * st["mass_in"]
     cg.close()
 
 
@@ -341,3 +349,93 @@ def test_full_size_node_window_columns():
             want = col[I] / count[I]
             assert abs(got[o, I] - want) <= 1e-5 * max(abs(want), 1e-4), (J, I)
     cg.close()
+
+
+# ---------------------------------------------------------------- arithmetic of the product (Sec. 3.3, Table 2)
+
+ARITH_PREC = {"fp64": fd.FP64, "fp32": fd.FP32, "mixed": fd.FP16_BANK, "fp16": fd.FP16_BANK}
+
+
+def _block_constant(d, B, seed):
+    """A field constant over every B^3 block, with values k / 64 (k < 1024):
+    exact in FP16, so every group mean is the same number on both sides."""
+    ncz, ncy, ncx = coarse.coarse_dims(d.shape, B)
+    v = np.floor(synth.uniform(seed, ncz * ncy * ncx) * 1024.0) / 64.0
+    z, y, x = np.meshgrid(*[np.arange(n) for n in d.shape], indexing="ij")
+    return v[((z // B) * ncy + (y // B)) * ncx + (x // B)]
+
+
+# K < 5 (one lane per node) and K >= 5 (one lane per chunk, ordered range sum)
+ARITH_CASES = [((10, 9, 11), 4, 4, 2, 41), ((9, 10, 8), 5, 3, 1, 42), ((6, 7, 5), 2, 6, 2, 43)]
+
+
+@pytest.mark.parametrize("arith", ["fp64", "fp32", "mixed", "fp16"])
+@pytest.mark.parametrize("shape,r,n_sub,B,seed", ARITH_CASES)
+def test_arith_step_matches_oracle_within_the_accumulation_bound(arith, shape, r, n_sub, B, seed):
+    """Every product formed as the precision forms it (same rounded operands
+    and FP16 products on both sides); only the order of the accumulation
+    differs, so |GPU - oracle| <= gamma_n(u) sum |terms| per node.  The P of
+    both sides must be the same number before its storage rounding, so the
+    geometry is dyadic: D in {1, 0} and dt = 1/8 (lambda = 1/8), whose FD
+    kernels over a few sub-steps are exact in FP32 (the reduced-precision
+    handles build P from FP32 kernels, the oracle from FP64 ones)."""
+    d = synth.random_small(shape, 2, r=r, n_sub=n_sub, seed=seed, dt=0.125)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, B)
+    cg = fd.Coarse(_dev_domain(d), B, ARITH_PREC[arith])
+    cg.set_arith(arith)
+    for c0 in (_block_constant(d, B, seed + 100), d.c0):
+        ref, bnd = coarse.step_arith(p, P, c0, B, arith)
+        got = to_host(cg.step(to_dev(c0)))
+        slack = 1e-14 * np.abs(ref).max()
+        if c0 is d.c0 and arith != "fp64":
+            # group means of a noise field are rounded to the C type on both
+            # sides from FP64 means summed in different orders: they agree
+            # except at a rounding tie (probability ~1e-13 per node)
+            slack += 4.0 * 2.0 ** -53 * np.abs(ref).max()
+        print(f"[coarse arith] {arith} K={cg.K} max |gpu - oracle| / bound = "
+              f"{np.max(np.abs(got - ref) / (bnd + slack)):.3f}", flush=True)
+        assert np.all(np.abs(got - ref) <= bnd + slack)
+    cg.close()
+
+
+def test_arith_rejects_a_mismatched_p_storage():
+    d = synth.random_small((6, 6, 6), 2, r=2, n_sub=4, seed=44)
+    dom = _dev_domain(d)
+    for prec, bad in ((fd.FP64, ("fp32", "mixed", "fp16")), (fd.FP32, ("mixed", "fp16")), (fd.FP16_BANK, ("fp32",))):
+        cg = fd.Coarse(dom, 2, prec)
+        for a in bad:
+            with pytest.raises(fd.FdirwError) as e:
+                cg.set_arith(a)
+            assert e.value.status == fd.E_ARG
+        with pytest.raises(fd.FdirwError):
+            cg.set_arith(7)
+        cg.set_arith("fp64")
+        cg.close()
+
+
+def test_arith_back_and_forth_and_far_field():
+    """Switching the arithmetic of one handle back to FP64 gives the FP64
+    step again bitwise; with a far field the mixed step keeps the Eq. 7
+    balance (c_ff takes what the near field loses)."""
+    d = synth.random_small((8, 9, 10), 3, r=3, n_sub=10, seed=45, d_zero_phase=False)
+    dom = _dev_domain(d)
+    cg = fd.Coarse(dom, 2, fd.FP16_BANK)
+    c0 = to_dev(d.c0)
+    a = to_host(cg.step(c0))
+    cg.set_arith("mixed")
+    m = to_host(cg.step(c0))
+    cg.set_arith("fp64")
+    b = to_host(cg.step(c0))
+    assert np.array_equal(a, b) and not np.array_equal(a, m)
+    cg.close()
+    res = [0, 0, 1]
+    cf = fd.Coarse(dom, 2, fd.FP16_BANK, grouped=[1, 1, 0], reservoir=res)
+    cf.set_arith("mixed")
+    far = d.label == 2
+    v_ff = float(far.sum())
+    m_total = float(d.c0[~far].sum()) + 0.3 * v_ff
+    out, c_ff = cf.step_far_field(c0, 0.3, m_total, v_ff)
+    o = to_host(out)
+    assert abs(o[~far].sum() + c_ff * v_ff - m_total) <= 1e-12 * m_total
+    cf.close()
