@@ -17,14 +17,16 @@ the same way and reported under ``modes`` with their speedup over FP32 and
 their relative L1 difference from the FP32 field.  The ``bank`` leg stores
 every kernel once (in FP32 and in FP16, the paper's stored-P use) and times
 the HBM-streaming apply of one big step; the ``coarse`` leg runs the paper's
-coarse-mesh method (5^3 blocks, mapping / P C / remapping).
+coarse-mesh method (5^3 blocks, mapping / P C / remapping) in the four
+precisions of its Table 2 (FP64, FP32, mixed FP32/FP16, FP16).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32] [--nn-train-steps S]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32] [--nn-epochs E]
 
-The learned generator (surrogate) is trained for S Adam steps on two other
-seeded 64^3 geometries of the same kind and its step is timed under ``modes``
-as "nn": the audited step as the library runs it (audit L1 and fallback
-flag) and the surrogate-only step with its speedup and field error.
+The learned generator (surrogate) is trained for E epochs of its recipe
+(200,000 FD windows of eight other seeded 192^3 geometries of the same kind,
+evaluated on two unseen ones) and its step is timed under ``modes`` as "nn":
+the audited step as the library runs it (audit L1 and fallback flag) and the
+surrogate-only step with its speedup and field error.
 """
 import argparse
 import hashlib
@@ -41,6 +43,9 @@ import numpy as np  # noqa: E402
 
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+# The FP32 FMA rate without packed FP32 instructions (this build does not
+# emit them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # Algorithmic work of one cell-sub-step of the 7-point update: 7 products and
 # 6 additions (13 flop); exchange: one write and four in-plane reads of the
@@ -75,23 +80,45 @@ def kernel_source_hash():
     """Hash of the sources that define the fused line kernel."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2408_11376_amd", "csrc")
-    for f in ("fdirw_device.h", "fdirw_kernels.hip"):
+    for f in ("fdirw_device.h", "fdirw_kernels.hip", "fdirw_flat.hip"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel_tag):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.md")
+def read_profile_values(kernel_tag, suffix, keys):
+    """Values from a committed rocprofv3 counter summary
+    (profiles/<kernel_tag>_<suffix>.md, lines "key: value"), if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_{suffix}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"source_sha:\s*([0-9a-f]+)", text)
-    m_val = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or m_hash.group(1) != kernel_source_hash():
         return None
-    return float(m_val.group(1))
+    out = {}
+    for k in keys:
+        m = re.search(rf"{k}:\s*([0-9.eE+-]+)", text)
+        if not m:
+            return None
+        out[k] = float(m.group(1))
+    return out
+
+
+def read_traffic(kernel_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary."""
+    v = read_profile_values(kernel_tag, "traffic", ["hbm_bytes_per_launch"])
+    return None if v is None else v["hbm_bytes_per_launch"]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(dom, block: int):
@@ -108,6 +135,7 @@ def cpu_baseline(dom, block: int):
     _, used, _ = p.step(c0)
     dt = time.perf_counter() - t
     out = {"value": used / dt, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "cpu_model": cpu_model(),
            "sample": f"{block}^3 = {used} sources of the {dom.shape[0]}^3 step (c0 zeroed elsewhere), {dt:.2f} s"}
     # one core (the paper's CPU reference is one core): a smaller cube of sources
     b1 = max(2, block // 3)
@@ -126,21 +154,29 @@ def cpu_baseline(dom, block: int):
 
 
 def surrogate_mode(fd, d, dom, c0, bufs, stream, args):
-    """Train the learned generator on two other seeded GRF geometries of the
-    same kind (64^3), then time its step on the workload: the audited step as
-    the library runs it (falls back to FD when the mean per-kernel L1 of 1024
-    audited sources exceeds 1e-3) and the surrogate-only step (audit off)."""
+    """Train the learned generator on the surrogate workload's recipe (a fixed
+    set of 200,000 FD windows from eight seeded 192^3 GRF geometries of the
+    benchmark's kind, batch 256, decaying learning rate; ``--nn-epochs``
+    passes), with its per-kernel L1 on two unseen 192^3 geometries next to the
+    prior's; then time its step on the workload: the audited step as the
+    library runs it (falls back to FD when the mean per-kernel L1 of 1024
+    audited sources exceeds 1e-3) and the surrogate-only step (audit off)
+    with its field error against the FP32 FD step."""
     import torch
     import synth
-    from paper_2408_11376_amd.surrogate_train import train
-    log(f"nn: training {args.nn_train_steps} Adam steps on two 64^3 GRF geometries")
+    from paper_2408_11376_amd.surrogate_train import train_recipe
+    log(f"nn: {args.nn_epochs} epochs of the 200k-window recipe on eight 192^3 GRF geometries")
     nn = fd.Surrogate(d.n_sub, seed=0)
-    tdoms = [fd.Domain.from_synth(synth.config2(seed=100 + i, n=64)) for i in range(2)]
+    tdoms = [fd.Domain.from_synth(synth.config2(seed=100 + i, n=192)) for i in range(8)]
+    edoms = [fd.Domain.from_synth(synth.config2(seed=200 + i, n=192)) for i in range(2)]
     t = time.perf_counter()
-    hist = train(nn, tdoms, args.nn_train_steps, batch=32, lr=3e-3, seed=1)
+    rec = train_recipe(nn, tdoms, edoms, windows=200_000, epochs=args.nn_epochs, batch=256, lr=2e-3,
+                       lr_final=1e-4, eval_windows=1024, log=lambda m: log(f"nn: {m}"))
     train_s = time.perf_counter() - t
-    out = {"train_steps": args.nn_train_steps, "train_seconds": train_s,
-           "train_loss_first_last": [list(hist[0]), list(hist[-1])]}
+    del tdoms, edoms
+    out = {"train_epochs": args.nn_epochs, "train_windows": 200_000, "train_seconds": train_s,
+           "eval_l1_unseen": rec[-1]["eval_l1"], "prior_eval_l1_unseen": rec[-1]["prior_eval_l1"],
+           "eval_l1_per_epoch": [r["eval_l1"] for r in rec]}
     # the audited step (what fdirw_step with GEN_NN does)
     _, st = fd.fdirw_step(dom, c0, bufs[0], nn=nn, stats=True)
     out["audit_l1"] = st["audit_l1"]
@@ -270,9 +306,18 @@ def coarse_leg(fd, d, dom, c0, c1, args):
     torch.cuda.synchronize()
     out = {"block": B, "grouped_phases": grouped}
     stream = torch.cuda.current_stream()
-    for prec in ("fp32", "fp16_bank"):
-        log(f"coarse {prec}: building P over {B}^3 blocks")
-        cg = fd.Coarse(dom, B, prec, grouped=grouped)
+    # Table 2's precisions: (P storage, product arithmetic); "fp16_bank" with
+    # FP64 arithmetic is the library's default coarse step
+    legs = (("fp64", "fp64"), ("fp32", "fp32"), ("fp16_bank", "mixed"), ("fp16_bank", "fp16"),
+            ("fp32", "fp64"), ("fp16_bank", "fp64"))
+    handles = {}
+    base = None
+    for prec, arith in legs:
+        if prec not in handles:
+            log(f"coarse {prec}: building P over {B}^3 blocks")
+            handles[prec] = fd.Coarse(dom, B, prec, grouped=grouped)
+        cg = handles[prec]
+        cg.set_arith(arith)
         bufs = [torch.empty_like(c0), torch.empty_like(c0)]
         cg.step(c0, bufs[0])
         torch.cuda.synchronize()
@@ -288,16 +333,22 @@ def coarse_leg(fd, d, dom, c0, c1, args):
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / n
         o0, st = cg.step(c0, stats=True)
-        rec = {"nodes": cg.n_nodes, "K": cg.K, "build_seconds": cg.build_seconds, "ms_per_step": ms,
-               "cells_per_s": d.n / (ms * 1e-3), "kernel_ms": 1e3 * st["kernel_seconds"],
+        rec = {"P": prec, "arith": arith, "nodes": cg.n_nodes, "K": cg.K, "build_seconds": cg.build_seconds,
+               "ms_per_step": ms, "cells_per_s": d.n / (ms * 1e-3), "kernel_ms": 1e3 * st["kernel_seconds"],
                "mass_rel_drift": abs(st["mass_out"] - st["mass_in"]) / st["mass_in"]}
+        if base is None:
+            base = (o0.clone(), ms)
+        rec["rel_l1_vs_coarse_fp64"] = float((o0 - base[0]).abs().sum()) / float(base[0].abs().sum())
+        rec["speedup_vs_coarse_fp64"] = base[1] / ms
         if c1 is not None:
             rec["rel_l1_vs_fp32_from_c0"] = float((o0 - c1).abs().sum()) / float(c1.abs().sum())
             o1 = cg.step(c1)
             rec["rel_l1_vs_fp32_from_c1"] = float((o1 - fine2).abs().sum()) / float(fine2.abs().sum())
-        out[prec] = rec
+        out[f"{prec}/{arith}"] = rec
+        log(f"coarse P {prec}, arithmetic {arith}: {ms:.4f} ms / step, rel L1 vs coarse FP64 "
+            f"{rec['rel_l1_vs_coarse_fp64']:.2e}, mass drift {rec['mass_rel_drift']:.1e}")
+    for cg in handles.values():
         cg.close()
-        log(f"coarse {prec}: {cg.n_nodes} nodes, build {rec['build_seconds']:.2f} s, {ms:.4f} ms / step")
     return out
 
 
@@ -388,8 +439,8 @@ def main():
     ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
     ap.add_argument("--cpu-block", type=int, default=24, help="edge of the oracle's source sample (0: skip)")
     ap.add_argument("--tune", type=int, default=-1)
-    ap.add_argument("--nn-train-steps", type=int, default=2000,
-                    help="Adam steps of the surrogate before its step is timed (0: skip the surrogate)")
+    ap.add_argument("--nn-epochs", type=int, default=4,
+                    help="epochs of the surrogate recipe before its step is timed (0: skip the surrogate)")
     ap.add_argument("--batched", type=int, default=1, help="also time the 64-domain batched step (0: skip)")
     ap.add_argument("--bank", type=int, default=1, help="also time fdirw_run with FP32 and FP16 kernel banks (0: skip)")
     ap.add_argument("--mp-steps", type=int, default=50,
@@ -459,7 +510,7 @@ def main():
         log(f"{mode}: {ms:.1f} ms/step, kernel {results[mode]['kernel_ms']:.1f} ms, "
             f"{results[mode]['cells_per_s'] / 1e6:.3f} Mcells/s")
 
-    if args.nn_train_steps > 0:
+    if args.nn_epochs > 0:
         results["nn"], fields["nn"] = surrogate_mode(fd, d, dom, c0, bufs, stream, args)
 
     extra = {}
@@ -490,15 +541,28 @@ def main():
     # cell-sub-step) and FMA issue time at one FMA per lane per clock
     t_lds = cs * (4 * esize / LDS_READ_B_PER_CLK + esize / LDS_WRITE_B_PER_CLK) / CU_HZ
     t_valu = cs * FMA_PER_CELL_SUBSTEP / (64 * CU_HZ)
-    kernel_tag = f"line_kernel_{args.prec}_grf{args.n}"
+    flat = args.prec == "fp32" and 4 <= d.r <= 8 and os.environ.get("FDIRW_FUSED_LAYOUT") != "segments"
+    kname = "flat_line_kernel" if flat else "line_kernel"
+    kernel_tag = f"{kname}_{args.prec}_grf{args.n}"
     traffic = read_traffic(kernel_tag)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
-                "kernel": f"line_kernel<{args.prec}, r=8>",
+                "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_unpacked_fp32": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+                "kernel": f"{kname}<{args.prec}, r={d.r}>",
                 "cell_substeps_per_launch": cs, "flop_per_cell_substep": FLOP_PER_CELL_SUBSTEP,
-                "lds_exchange_TBps": lds_tbs,
-                "lds_bound_s": t_lds, "lds_frac": t_lds / t_kern,
+                "lds_exchange_TBps_model": lds_tbs,
+                "lds_bound_s_model": t_lds, "lds_frac_model": t_lds / t_kern,
                 "fma_issue_bound_s": t_valu, "fma_issue_frac": t_valu / t_kern}
+    # LDS from the committed counter summary of this kernel (instructions and
+    # bytes per launch, busy fraction of the LDS pipe), when it matches the
+    # sources; the launch's bytes are scaled to the time measured here
+    lds = read_profile_values(kernel_tag, "lds", ["lds_bytes_per_launch", "lds_busy_frac", "valu_busy_frac"])
+    if lds is not None:
+        roofline["lds_bytes_per_launch"] = lds["lds_bytes_per_launch"]
+        roofline["lds_TBps_counters"] = lds["lds_bytes_per_launch"] / t_kern / 1e12
+        roofline["lds_busy_frac_counters"] = lds["lds_busy_frac"]
+        roofline["valu_busy_frac_counters"] = lds["valu_busy_frac"]
 
     cpu = None
     if args.cpu_block > 0:
