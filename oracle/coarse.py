@@ -308,3 +308,48 @@ def step_arith(problem, P, c, B: int, arith: str, grouped=None):
     bcell = remapping(bnd, np.zeros_like(np.asarray(c, dtype=np.float64)), problem.label, problem.d_phase, B,
                       grouped)
     return out, bcell
+
+
+# --------------------------------------------------------------------------
+# Ensemble product (Eq. 14 with several right-hand sides, Sec. 3.3).
+#
+# With E coarse fields C_e over the same geometry the E products P C_e are one
+# matrix product P [C_1 ... C_E], which the matrix cores take in the mixed
+# FP32/FP16 precision: C_e computed in FP32 and converted to FP16, P stored in
+# FP16, every product of two FP16 operands formed exactly (11 x 11 significant
+# bits fit in FP32) and the products summed in FP32.  Reading: the matrix
+# unit's order and rounding of that sum are not specified, so the result is
+# written out as the FP64 sum of the exact products (its own rounding is
+# below 2^-40 relative here) and the bound allows one FP32 ulp (2^-23
+# relative) per addition:
+#     |C'_e[I] - sum_J terms| <= gamma_n(2^-23) * sum_J |terms|
+# (n = number of nonzero terms + 1).  Without a far field (the term P_BC c_ff
+# of Eq. 14 is zero).
+ENSEMBLE_UNIT = 2.0 ** -23
+
+
+def ensemble_operands(P, C):
+    """(P, C) as the ensemble product takes them: P rounded to FP16, every
+    member of C (shape (E, n)) rounded to FP32 and then to FP16; FP64 arrays."""
+    P = np.asarray(P, dtype=np.float64)
+    C = np.atleast_2d(np.asarray(C, dtype=np.float64))
+    return P.astype(np.float16).astype(np.float64), C.astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+def ensemble_product(P, C):
+    """(C', bound) for the ensemble C (shape (E, n), one coarse field per
+    row): C'[e] = P C[e] with the operands of ensemble_operands, the exact
+    products summed in FP64; bound[e, I] as above."""
+    Pr, Cr = ensemble_operands(P, C)
+    E = Cr.shape[0]
+    out = np.empty((E, Pr.shape[0]))
+    bnd = np.empty_like(out)
+    nz = Pr != 0.0
+    for e in range(E):
+        t = Pr * Cr[e][None, :]                  # exact: FP16 x FP16 fits FP64
+        out[e] = t.sum(axis=1)
+        n = (nz & (Cr[e][None, :] != 0.0)).sum(axis=1) + 1
+        nu = n * ENSEMBLE_UNIT
+        gam = np.where(nu < 1.0, nu / np.maximum(1.0 - nu, 1e-300), np.inf)
+        bnd[e] = gam * np.abs(t).sum(axis=1)
+    return out, bnd

@@ -269,3 +269,66 @@ def test_arith_step_on_a_grid_conserves_mass_to_the_precision():
     for a, tol in (("fp64", 1e-14), ("fp32", 1e-6), ("mixed", 2e-3), ("fp16", 5e-2)):
         out, bnd = coarse.step_arith(p, P, d.c0, 5, a)
         assert abs(out.sum() - ref.sum()) <= tol * ref.sum(), a
+
+
+# ---------------------------------------------------------------- ensemble product (Eq. 14, several right-hand sides)
+
+def test_ensemble_representable_operands_are_exact():
+    # P entries k / 64 and C small integers are FP16 numbers, every product
+    # and every row sum is exact: the ensemble product is the plain product
+    rng = np.random.default_rng(11)
+    P = rng.integers(0, 65, (20, 125)) / 64.0
+    C = rng.integers(0, 33, (6, 125)).astype(np.float64)
+    out, bnd = coarse.ensemble_product(P, C)
+    assert np.array_equal(out, C @ P.T)
+    assert np.all(bnd >= 0.0)
+
+
+def test_ensemble_rounds_c_through_fp32():
+    # 1 + 2^-11 + 2^-40 is 1 + 2^-11 in FP32, exactly half way between the
+    # FP16 neighbours 1 and 1 + 2^-10: round to even gives 1 (rounded
+    # directly to FP16 it would be 1 + 2^-10)
+    c = 1.0 + 2.0 ** -11 + 2.0 ** -40
+    assert np.float64(np.float16(c)) == 1.0 + 2.0 ** -10
+    out, _ = coarse.ensemble_product(np.array([[1.0]]), np.array([[c]]))
+    assert out[0, 0] == 1.0
+
+
+def test_ensemble_products_are_exact():
+    # 1/3 in FP16 is 0.333251953125; times 3 that is 0.999755859375 = 1 - 2^-12,
+    # kept as it is (the mixed VALU form rounds that product to 1)
+    out, _ = coarse.ensemble_product(np.array([[1.0 / 3.0]]), np.array([[3.0]]))
+    assert out[0, 0] == 1.0 - 2.0 ** -12
+    assert coarse.arith_product(np.array([[1.0 / 3.0]]), np.array([3.0]), "mixed")[0][0] == 1.0
+
+
+def test_ensemble_bound_covers_fp32_orders():
+    # sequential FP32 sums of the exact products, in reverse and in a random
+    # order, stay within the bound
+    rng = np.random.default_rng(12)
+    P = rng.random((40, 125)) * 10.0 ** rng.integers(-5, 0, (40, 125))
+    C = rng.random((3, 125)) * 10.0 ** rng.integers(-2, 2, (3, 125))
+    out, bnd = coarse.ensemble_product(P, C)
+    Pr, Cr = coarse.ensemble_operands(P, C)
+    for e in range(3):
+        t = (Pr * Cr[e][None, :]).astype(np.float32)
+        assert np.array_equal(t.astype(np.float64), Pr * Cr[e][None, :])       # products exact in FP32
+        for order in (np.arange(124, -1, -1), rng.permutation(125)):
+            acc = np.zeros(40, dtype=np.float32)
+            for j in order:
+                acc = (acc + t[:, j]).astype(np.float32)
+            assert np.all(np.abs(acc.astype(np.float64) - out[e]) <= bnd[e])
+
+
+def test_ensemble_members_are_independent():
+    # each member's result is that member's product alone, in any order of
+    # the members
+    rng = np.random.default_rng(13)
+    P = rng.random((15, 30))
+    C = rng.random((5, 30))
+    out, bnd = coarse.ensemble_product(P, C)
+    perm = np.array([3, 0, 4, 1, 2])
+    out_p, _ = coarse.ensemble_product(P, C[perm])
+    assert np.array_equal(out_p, out[perm])
+    one, _ = coarse.ensemble_product(P, C[2])
+    assert np.array_equal(one[0], out[2])
