@@ -348,7 +348,7 @@ template <> struct CoarseArith<COARSE_FP16> { using C = _Float16; using Acc = _F
 
 // A mapped value (FP64 mean) in the C type of the arithmetic (FP16 via FP32).
 template <typename TC> __device__ __forceinline__ TC to_c(double v) { return (TC)v; }
-template <> __device__ __forceinline__ _Float16 to_c<_Float16>(double v) { return (_Float16)(float)v; }
+template <> __device__ __forceinline__ _Float16 to_c<_Float16>(double v) { return f64_to_f16_via_f32(v); }
 
 template <typename T> __device__ __forceinline__ double widen(T v) { return (double)(float)v; }
 template <> __device__ __forceinline__ double widen<double>(double v) { return v; }

@@ -78,6 +78,17 @@ template <> __device__ __forceinline__ float round_to<float>(float x) { return x
 
 constexpr int ru(int a, int b) { return (a + b - 1) / b * b; }
 
+// v rounded to FP32 and then to FP16 (two roundings, the route of the mixed
+// FP32/FP16 scheme).  The empty asm keeps the compiler from folding the two
+// conversions into one direct FP64 -> FP16 rounding, which differs where the
+// FP32 value is an FP16 tie.
+__device__ __forceinline__ _Float16 f64_to_f16_via_f32(double v)
+{
+    float f = (float)v;
+    asm volatile("" : "+v"(f));
+    return (_Float16)f;
+}
+
 // Spreads consecutive logical workgroups over one XCD: the hardware hands
 // workgroup b to XCD b % 8, so logical index (b % 8) * (g / 8) + b / 8 keeps
 // neighbouring source lines (which share coefficients and output planes) in
