@@ -317,39 +317,73 @@ def step_arith(problem, P, c, B: int, arith: str, grouped=None):
 # matrix product P [C_1 ... C_E], which the matrix cores take in the mixed
 # FP32/FP16 precision: C_e computed in FP32 and converted to FP16, P stored in
 # FP16, every product of two FP16 operands formed exactly (11 x 11 significant
-# bits fit in FP32) and the products summed in FP32.  Reading: the matrix
-# unit's order and rounding of that sum are not specified, so the result is
-# written out as the FP64 sum of the exact products (its own rounding is
-# below 2^-40 relative here) and the bound allows one FP32 ulp (2^-23
-# relative) per addition:
-#     |C'_e[I] - sum_J terms| <= gamma_n(2^-23) * sum_J |terms|
-# (n = number of nonzero terms + 1).  Without a far field (the term P_BC c_ff
-# of Eq. 14 is zero).
+# bits fit in FP32) and the products summed in FP32.
+# Readings:
+#   * FP16 operands are kept in the normal range: P (as stored in FP16) and
+#     each member C_e are scaled by powers of two, 2^s and 2^t_e, that bring
+#     their largest magnitude into [2^14, 2^15); operands still below the
+#     smallest normal FP16 number (2^-14) after the scaling are taken as 0
+#     (they are below 2^-28 of the largest one); the sums are scaled back by
+#     2^-(s + t_e), exactly.  (A matrix unit may sum products of subnormal
+#     operands less accurately than FP32; with the scaling none occur, and the
+#     scaling changes no normal FP16 value's rounding.)
+#   * The unit's order and rounding of the FP32 sum are not specified, so the
+#     result is written out as the FP64 sum of the exact products (its own
+#     rounding is below 2^-40 relative here) and the bound allows one FP32 ulp
+#     (2^-23 relative) per addition:
+#         |C'_e[I] - sum_J terms| <= gamma_n(2^-23) * sum_J |terms|
+#     (n = number of nonzero terms + 1).
+# Without a far field (the term P_BC c_ff of Eq. 14 is zero).
 ENSEMBLE_UNIT = 2.0 ** -23
+F16_MIN_NORMAL = 2.0 ** -14
+
+
+def pow2_scale(m: float) -> int:
+    """t such that m 2^t lies in [2^14, 2^15) (0 for m = 0)."""
+    if m == 0.0:
+        return 0
+    return 15 - int(np.frexp(m)[1])
+
+
+def _f16_normal(x):
+    """FP32 values rounded to FP16, results below the smallest normal FP16
+    number flushed to 0 (as FP64)."""
+    y = np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+    return np.where(np.abs(y) < F16_MIN_NORMAL, 0.0, y)
 
 
 def ensemble_operands(P, C):
-    """(P, C) as the ensemble product takes them: P rounded to FP16, every
-    member of C (shape (E, n)) rounded to FP32 and then to FP16; FP64 arrays."""
+    """(P, C, s, t) as the ensemble product takes them: P16 = P rounded to
+    FP16 (its storage), then scaled by 2^s; every member of C (shape (E, n))
+    rounded to FP32, scaled by 2^t_e and rounded to FP16; operands below
+    2^-14 after the scaling set to 0.  FP64 arrays of the scaled values, s and
+    the vector t."""
     P = np.asarray(P, dtype=np.float64)
     C = np.atleast_2d(np.asarray(C, dtype=np.float64))
-    return P.astype(np.float16).astype(np.float64), C.astype(np.float32).astype(np.float16).astype(np.float64)
+    P16 = P.astype(np.float16).astype(np.float64)
+    s = pow2_scale(float(np.abs(P16).max()) if P16.size else 0.0)
+    Ps = _f16_normal(P16 * 2.0 ** s)
+    C32 = C.astype(np.float32)
+    t = np.array([pow2_scale(float(np.abs(C32[e]).max()) if C32.shape[1] else 0.0) for e in range(C32.shape[0])])
+    Cs = np.stack([_f16_normal(C32[e].astype(np.float64) * 2.0 ** int(t[e])) for e in range(C32.shape[0])])
+    return Ps, Cs, s, t
 
 
 def ensemble_product(P, C):
     """(C', bound) for the ensemble C (shape (E, n), one coarse field per
     row): C'[e] = P C[e] with the operands of ensemble_operands, the exact
-    products summed in FP64; bound[e, I] as above."""
-    Pr, Cr = ensemble_operands(P, C)
-    E = Cr.shape[0]
-    out = np.empty((E, Pr.shape[0]))
+    products summed in FP64 and scaled back; bound[e, I] as above."""
+    Ps, Cs, s, t = ensemble_operands(P, C)
+    E = Cs.shape[0]
+    out = np.empty((E, Ps.shape[0]))
     bnd = np.empty_like(out)
-    nz = Pr != 0.0
+    nz = Ps != 0.0
     for e in range(E):
-        t = Pr * Cr[e][None, :]                  # exact: FP16 x FP16 fits FP64
-        out[e] = t.sum(axis=1)
-        n = (nz & (Cr[e][None, :] != 0.0)).sum(axis=1) + 1
+        back = 2.0 ** -(s + int(t[e]))
+        tm = Ps * Cs[e][None, :]                 # exact: FP16 x FP16 fits FP64
+        out[e] = tm.sum(axis=1) * back
+        n = (nz & (Cs[e][None, :] != 0.0)).sum(axis=1) + 1
         nu = n * ENSEMBLE_UNIT
         gam = np.where(nu < 1.0, nu / np.maximum(1.0 - nu, 1e-300), np.inf)
-        bnd[e] = gam * np.abs(t).sum(axis=1)
+        bnd[e] = gam * np.abs(tm).sum(axis=1) * back
     return out, bnd

@@ -309,15 +309,16 @@ def test_ensemble_bound_covers_fp32_orders():
     P = rng.random((40, 125)) * 10.0 ** rng.integers(-5, 0, (40, 125))
     C = rng.random((3, 125)) * 10.0 ** rng.integers(-2, 2, (3, 125))
     out, bnd = coarse.ensemble_product(P, C)
-    Pr, Cr = coarse.ensemble_operands(P, C)
+    Ps, Cs, sp, tc = coarse.ensemble_operands(P, C)
     for e in range(3):
-        t = (Pr * Cr[e][None, :]).astype(np.float32)
-        assert np.array_equal(t.astype(np.float64), Pr * Cr[e][None, :])       # products exact in FP32
+        back = 2.0 ** -(sp + int(tc[e]))
+        t = (Ps * Cs[e][None, :]).astype(np.float32)
+        assert np.array_equal(t.astype(np.float64), Ps * Cs[e][None, :])       # products exact in FP32
         for order in (np.arange(124, -1, -1), rng.permutation(125)):
             acc = np.zeros(40, dtype=np.float32)
             for j in order:
                 acc = (acc + t[:, j]).astype(np.float32)
-            assert np.all(np.abs(acc.astype(np.float64) - out[e]) <= bnd[e])
+            assert np.all(np.abs(acc.astype(np.float64) * back - out[e]) <= bnd[e])
 
 
 def test_ensemble_members_are_independent():
@@ -332,3 +333,28 @@ def test_ensemble_members_are_independent():
     assert np.array_equal(out_p, out[perm])
     one, _ = coarse.ensemble_product(P, C[2])
     assert np.array_equal(one[0], out[2])
+
+
+def test_ensemble_power_of_two_scaling_is_exact():
+    # a member scaled by 2^k (into what would be FP16's subnormal range or far
+    # above its largest number) gives the same result scaled by 2^k, bitwise
+    rng = np.random.default_rng(14)
+    P = 0.01 + rng.random((30, 50)) * 0.3                   # FP16-normal, also times 8
+    C = rng.random((2, 50))
+    out, bnd = coarse.ensemble_product(P, C)
+    for k in (-40, -20, 9, 30):
+        o2, b2 = coarse.ensemble_product(P, C * 2.0 ** k)
+        assert np.array_equal(o2, out * 2.0 ** k) and np.array_equal(b2, bnd * 2.0 ** k), k
+    o3, _ = coarse.ensemble_product(P * 8.0, C)
+    assert np.array_equal(o3, out * 8.0)
+
+
+def test_ensemble_keeps_operands_normal():
+    # largest |C| = 1 scales by 2^14: a value 2^-27 becomes 2^-13 (normal,
+    # kept), 2^-29 becomes 2^-15 (below the smallest normal FP16, taken as 0)
+    P = np.array([[0.5, 0.25, 0.125]])
+    kept, _ = coarse.ensemble_product(P, np.array([[1.0, 2.0 ** -27, 0.0]]))
+    assert kept[0, 0] == 0.5 + 0.25 * 2.0 ** -27
+    gone, _ = coarse.ensemble_product(P, np.array([[1.0, 2.0 ** -29, 0.0]]))
+    assert gone[0, 0] == 0.5
+    assert coarse.pow2_scale(1.0) == 14 and coarse.pow2_scale(2.0 ** 15 - 1) == 0 and coarse.pow2_scale(0.0) == 0
