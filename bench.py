@@ -347,8 +347,78 @@ def coarse_leg(fd, d, dom, c0, c1, args):
         out[f"{prec}/{arith}"] = rec
         log(f"coarse P {prec}, arithmetic {arith}: {ms:.4f} ms / step, rel L1 vs coarse FP64 "
             f"{rec['rel_l1_vs_coarse_fp64']:.2e}, mass drift {rec['mass_rel_drift']:.1e}")
+    if "fp16_bank" in handles:
+        out["ensemble"] = ensemble_leg(fd, handles["fp16_bank"], args)
     for cg in handles.values():
         cg.close()
+    return out
+
+
+def ensemble_leg(fd, cg, args):
+    """The coarse product for an ensemble of E coarse fields at once (Eq. 14
+    with E right-hand sides, mixed FP32/FP16 on the matrix cores): device
+    time per call (20 chained calls between events) for E = 1, 16, 64, 256,
+    the time per member against E = 1, the achieved HBM rate of the
+    algorithmic bytes (P's fragments once, each member's FP64 C read twice
+    (its largest magnitude, then the scaled FP16 copy) and C' written, its
+    FP16 grid written and read) and, for E = 16, the relative L1
+    difference from the FP64 product of the same members (host)."""
+    import torch
+    import synth
+    kw = 2 * cg.K + 1
+    ncz, ncy, ncx = cg.coarse_shape
+    n = cg.n_nodes
+    tx, ty = (ncx + 3) // 4, (ncy + 3) // 4
+    row = (4 + 2 * cg.K + 7) // 8 * 8
+    kst = (row * (4 + 2 * cg.K) + 31) // 32
+    frag_bytes = tx * ty * ncz * kw * kst * 64 * 16
+    msize = (4 * tx - 4 + row) * (4 * ty + 2 * cg.K) * (ncz + 2 * cg.K)
+    stream = torch.cuda.current_stream()
+    Pm = cg.matrix()                                  # [o, I]: the stored FP16 values, widened
+    nnz = float(np.count_nonzero(Pm))
+    out = {"K": cg.K, "nodes": n, "fragment_bytes": frag_bytes, "nonzeros": nnz}
+    t1 = None
+    for E in (1, 16, 64, 256):
+        C = torch.from_numpy(synth.uniform(900 + E, E * n).reshape(E, n)).cuda()
+        Co = torch.empty_like(C)
+        cg.apply_ensemble(C, Co)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        reps = 20
+        ev0.record(stream)
+        for _ in range(reps):
+            cg.apply_ensemble(C, Co)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        if t1 is None:
+            t1 = ms
+        bytes_ = frag_bytes + E * n * 24 + 2 * ((E + 15) // 16 * 16) * msize * 2
+        rec = {"ms": ms, "us_per_member": 1e3 * ms / E, "speedup_per_member_vs_E1": t1 * E / ms,
+               "hbm_GBps": bytes_ / (ms * 1e-3) / 1e9, "hbm_frac": bytes_ / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        rec["useful_tflops"] = 2.0 * E * nnz / (ms * 1e-3) / 1e12
+        if E == 16:
+            Ch = C.cpu().numpy()
+            ref = np.zeros((E, n))
+            Cg = Ch.reshape(E, ncz, ncy, ncx)
+            for o in range(kw ** 3):
+                oz, rem = divmod(o, kw * kw)
+                oy, ox = divmod(rem, kw)
+                dz, dy, dx = oz - cg.K, oy - cg.K, ox - cg.K
+                # C'[I] += P[o, I] C[I - d]
+                src = np.zeros_like(Cg)
+                zs, ys, xs = slice(max(dz, 0), ncz + min(dz, 0)), slice(max(dy, 0), ncy + min(dy, 0)), \
+                    slice(max(dx, 0), ncx + min(dx, 0))
+                zt, yt, xt = slice(max(-dz, 0), ncz - max(dz, 0)), slice(max(-dy, 0), ncy - max(dy, 0)), \
+                    slice(max(-dx, 0), ncx - max(dx, 0))
+                src[:, zs, ys, xs] = Cg[:, zt, yt, xt]
+                ref += Pm[o][None, :] * src.reshape(E, n)
+            got = Co.cpu().numpy()
+            rec["rel_l1_vs_fp64_product"] = float(np.abs(got - ref).sum() / np.abs(ref).sum())
+        out[f"E{E}"] = rec
+        log(f"coarse ensemble E={E}: {ms:.4f} ms ({1e3 * ms / E:.2f} us / member), "
+            f"{rec['hbm_GBps']:.0f} GB/s")
     return out
 
 
@@ -437,7 +507,7 @@ def main():
     ap.add_argument("--prec", default="fp32", help="headline precision mode")
     ap.add_argument("--modes", default="fp32,fp16x32,bf16x32", help="modes timed for the comparison")
     ap.add_argument("--n", type=int, default=192, help="grid edge (192 = the benchmark workload)")
-    ap.add_argument("--cpu-block", type=int, default=24, help="edge of the oracle's source sample (0: skip)")
+    ap.add_argument("--cpu-block", type=int, default=40, help="edge of the oracle's source sample (0: skip)")
     ap.add_argument("--tune", type=int, default=-1)
     ap.add_argument("--nn-epochs", type=int, default=4,
                     help="epochs of the surrogate recipe before its step is timed (0: skip the surrogate)")

@@ -49,6 +49,7 @@ extern "C" {
 #define FDIRW_MAX_RADIUS 8   /* largest window radius r supported (W = 17) */
 #define FDIRW_MAX_COARSE_RADIUS 128   /* largest r of the coarse operator (node windows beyond 8) */
 #define FDIRW_MAX_COARSE_K 8          /* ... with ceil(r / block) at most this */
+#define FDIRW_MAX_ENSEMBLE 4096       /* members of one ensemble coarse product */
 #define FDIRW_MAX_PHASES 256
 
 typedef enum fdirw_status {
@@ -415,6 +416,31 @@ int fdirw_coarse_step(void *handle, const double *c_in, double *c_out, void *str
  * Synchronises the stream.  Errors: E_ARG, E_NONFINITE, E_DEVICE. */
 int fdirw_coarse_step_far_field(void *handle, const double *c_in, double *c_out, double *c_ff, double m_total,
                                 double v_ff, void *stream, fdirw_stats *st);
+
+/* Ensemble form of the coarse product (Eq. 14 with n_ens right-hand sides,
+ * in the mixed FP32/FP16 precision of Sec. 3.3, on the matrix cores):
+ * C_out[e] = P C_in[e] for e < n_ens.  C_in, C_out: device, n_ens x n_nodes
+ * doubles each, member-major, nodes numbered as in fdirw_coarse_shape; not
+ * overlapping.  Every C value is rounded to FP32, scaled by the power of two
+ * that brings its member's largest |C| into [2^14, 2^15) and rounded to FP16;
+ * P is the handle's FP16 P scaled the same way by its largest entry; scaled
+ * operands below 2^-14 (the smallest normal FP16 number) are taken as 0.  Each
+ * product of two FP16 numbers is exact and the products of a node are summed
+ * in FP32 (in an order the matrix unit fixes; within gamma_n(2^-23) sum |terms|
+ * of the exact sum), scaled back exactly and widened to FP64.  Nodes without
+ * grouped cells get 0.  A member holding a non-finite value gives non-finite
+ * results for that member.  P is read
+ * once per call for all members (as matrix fragments built from it on the
+ * first call, about 10 KB per 16 nodes at K = 2, kept by the handle); the
+ * padded FP16 grids of the members (grown on demand, kept) are written by
+ * every call.  Stream-ordered on `stream`; calls on one handle that overlap
+ * on different streams race.  kernel_seconds (host, may be NULL): device
+ * time of the call (synchronises the stream).
+ * Errors: E_ARG (null, overlap, n_ens outside 1..FDIRW_MAX_ENSEMBLE, P not
+ * stored in FP16, a handle with a far field, another device), E_UNSUPPORTED
+ * (K above 4), E_NOMEM, E_DEVICE. */
+int fdirw_coarse_apply_ensemble(void *handle, const double *C_in, double *C_out, int32_t n_ens, void *stream,
+                                double *kernel_seconds);
 
 /* Copies P_BC (host, n_nodes doubles; zeros without a far field). */
 int fdirw_coarse_pbc(void *handle, double *pbc_host);

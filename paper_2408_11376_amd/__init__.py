@@ -87,7 +87,7 @@ ABI_FUNCTIONS = ("fdirw_coefficients", "fdirw_kernels", "fdirw_kernels_flow", "f
                  "fdirw_nn_num_params", "fdirw_nn_create", "fdirw_nn_destroy", "fdirw_nn_set_params",
                  "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward", "fdirw_nn_adam",
                  "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create", "fdirw_coarse_set_arith",
-                 "fdirw_coarse_step",
+                 "fdirw_coarse_step", "fdirw_coarse_apply_ensemble",
                  "fdirw_coarse_step_far_field", "fdirw_coarse_shape", "fdirw_coarse_matrix", "fdirw_coarse_pbc",
                  "fdirw_coarse_destroy", "fdirw_mp_create", "fdirw_mp_step", "fdirw_mp_info", "fdirw_mp_destroy")
 NN_RADIUS = 8
@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_coarse_step.argtypes = [P, P, P, P, S]
     lib.fdirw_coarse_set_arith.argtypes = [P, ctypes.c_int32]
+    lib.fdirw_coarse_apply_ensemble.argtypes = [P, P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double)]
     lib.fdirw_coarse_step_far_field.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                                 ctypes.c_double, P, S]
     lib.fdirw_coarse_pbc.argtypes = [P, P]
@@ -152,7 +153,8 @@ def load_library(path: str = LIB_PATH):
               "fdirw_release", "fdirw_abi_version", "fdirw_nn_create", "fdirw_nn_destroy",
               "fdirw_nn_set_params", "fdirw_nn_get_params", "fdirw_nn_forward", "fdirw_nn_backward",
               "fdirw_nn_adam", "fdirw_nn_save", "fdirw_nn_load", "fdirw_coarse_create",
-              "fdirw_coarse_step", "fdirw_coarse_set_arith", "fdirw_coarse_step_far_field", "fdirw_coarse_shape",
+              "fdirw_coarse_step", "fdirw_coarse_set_arith", "fdirw_coarse_apply_ensemble",
+              "fdirw_coarse_step_far_field", "fdirw_coarse_shape",
               "fdirw_coarse_matrix",
               "fdirw_coarse_pbc", "fdirw_coarse_destroy", "fdirw_mp_create", "fdirw_mp_step", "fdirw_mp_info",
               "fdirw_mp_destroy"):
@@ -499,6 +501,14 @@ def fdirw_coarse_step(handle, c_in, c_out, stream=None, stats: bool = False):
     return st.as_dict() if st is not None else None
 
 
+def fdirw_coarse_apply_ensemble(handle, C_in, C_out, n_ens: int, stream=None, timed: bool = False):
+    ks = ctypes.c_double(0.0)
+    _check(load_library().fdirw_coarse_apply_ensemble(handle, ctypes.c_void_p(C_in.data_ptr()),
+                                                      ctypes.c_void_p(C_out.data_ptr()), int(n_ens),
+                                                      _stream_ptr(stream), ctypes.byref(ks) if timed else None))
+    return ks.value if timed else None
+
+
 def fdirw_coarse_shape(handle):
     shp = (ctypes.c_int32 * 5)()
     nn = ctypes.c_int64(0)
@@ -556,6 +566,22 @@ class Coarse:
             raise ValueError("field does not match the domain")
         r = fdirw_coarse_step_far_field(self.handle, c_in, c_out, c_ff, m_total, v_ff, stream, stats)
         return (c_out,) + tuple(r) if stats else (c_out, r)
+
+    def apply_ensemble(self, C_in, C_out=None, stream=None, timed: bool = False):
+        """Eq. 14 for an ensemble: C_in (device, float64, [n_ens, n_nodes])
+        -> P C_in[e] per member, mixed FP32/FP16 on the matrix cores.
+        Returns C_out, or (C_out, device seconds) when ``timed``."""
+        torch = _torch()
+        _dev_tensor(C_in, torch.float64, "C_in")
+        if C_in.dim() != 2 or C_in.shape[1] != self.n_nodes:
+            raise ValueError("C_in must be [n_ens, n_nodes]")
+        if C_out is None:
+            C_out = torch.empty_like(C_in)
+        _dev_tensor(C_out, torch.float64, "C_out")
+        if tuple(C_out.shape) != tuple(C_in.shape):
+            raise ValueError("C_out must have C_in's shape")
+        ks = fdirw_coarse_apply_ensemble(self.handle, C_in, C_out, C_in.shape[0], stream, timed)
+        return (C_out, ks) if timed else C_out
 
     def p_bc(self) -> np.ndarray:
         return fdirw_coarse_pbc(self.handle, np.empty(self.n_nodes))

@@ -49,10 +49,15 @@ struct Coarse {
     int64_t n_used = 0;
     int arith = COARSE_FP64;        // arithmetic of the product (fdirw_coarse_set_arith)
     void *cpad_lp = nullptr;        // the padded coarse grid in the arithmetic's C type (FP32 / FP16)
+    void *efrag = nullptr;          // ensemble product: P as matrix fragments (built on first use)
+    void *ecpad = nullptr;          // ensemble product: padded FP16 grids of ecpad_members members
+    void *ecmax = nullptr;          // ensemble product: each member's largest |C| (FP32 bits)
+    int64_t ecpad_members = 0;
+    int esp = 0;                    // ensemble product: P's power-of-two scale
 
     ~Coarse()
     {
-        for (void *p : {node, count, P, cpad, cnew, part, pbc, list, apart, used, cpad_lp})
+        for (void *p : {node, count, P, cpad, cnew, part, pbc, list, apart, used, cpad_lp, efrag, ecpad, ecmax})
             if (p) (void)hipFree(p);
     }
     int nb() const { return (2 * K + 1) * (2 * K + 1) * (2 * K + 1); }
@@ -528,6 +533,82 @@ int fdirw_coarse_step_far_field(void *handle, const double *c_in, double *c_out,
         if (e != hipSuccess) return hip_fail(e, "far-field step");
         loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         *stats = loc;
+    }
+    return FDIRW_OK;
+}
+
+int fdirw_coarse_apply_ensemble(void *handle, const double *C_in, double *C_out, int32_t n_ens, void *stream,
+                                double *kernel_seconds)
+{
+    Coarse *h = (Coarse *)handle;
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!C_in || !C_out) return fail(FDIRW_E_ARG, "C_in and C_out must not be null");
+    if (n_ens < 1 || n_ens > FDIRW_MAX_ENSEMBLE)
+        return fail(FDIRW_E_ARG, "n_ens = %d outside 1..%d", n_ens, FDIRW_MAX_ENSEMBLE);
+    if (h->prec != FDIRW_FP16_BANK)
+        return fail(FDIRW_E_ARG, "the ensemble product needs P stored in FP16 (the handle stores precision %d)",
+                    h->prec);
+    if (h->far_field) return fail(FDIRW_E_ARG, "the ensemble product takes handles without a far field");
+    if (h->K > ENSEMBLE_MAX_K)
+        return fail(FDIRW_E_UNSUPPORTED, "the ensemble product needs K <= %d (the handle has K = %d)", ENSEMBLE_MAX_K,
+                    h->K);
+    const size_t bytes = (size_t)n_ens * h->n_nodes * sizeof(double);
+    const char *a0 = (const char *)C_in, *b0 = (const char *)C_out;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return fail(FDIRW_E_ARG, "C_in and C_out must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    const EnsembleShape s = ensemble_shape(h->ncx, h->ncy, h->ncz, h->K);
+    if (s.n_tiles >= ((int64_t)1 << 31) || (int64_t)h->ncy * h->ncz >= ((int64_t)1 << 31))
+        return fail(FDIRW_E_UNSUPPORTED, "coarse grid too large for the ensemble product");
+    hipError_t e = hipSuccess;
+    if (!h->efrag) {
+        // P's scale from its largest entry (once per handle), then the fragments
+        void *pm = nullptr;
+        if ((rc = coarse_alloc(&pm, 16))) return rc;
+        unsigned bits = 0;
+        e = launch_ensemble_pmax(h->P, (int64_t)h->nb() * h->plane, (unsigned *)pm, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bits, pm, sizeof bits, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(pm);
+        if (e != hipSuccess) return hip_fail(e, "ensemble P scale");
+        h->esp = ensemble_p_scale(bits);
+        if ((rc = coarse_alloc(&h->efrag, (size_t)ensemble_frag_bytes(s)))) return rc;
+        e = launch_ensemble_frags(h->P, h->plane, s, h->esp, h->efrag, st);
+        if (e != hipSuccess) return hip_fail(e, "ensemble fragments");
+    }
+    const int64_t members = ((int64_t)n_ens + 15) / 16 * 16;
+    if (members > h->ecpad_members) {
+        // the halo rows stay zero; interior rows are written by every call
+        e = hipStreamSynchronize(st);                         // earlier calls may still read the old grids
+        if (e != hipSuccess) return hip_fail(e, "ensemble grid");
+        if (h->ecpad) (void)hipFree(h->ecpad);
+        if (h->ecmax) (void)hipFree(h->ecmax);
+        h->ecpad = h->ecmax = nullptr;
+        h->ecpad_members = 0;
+        const size_t gb = (size_t)members * s.msize * sizeof(_Float16);
+        if ((rc = coarse_alloc(&h->ecmax, (size_t)members * sizeof(unsigned)))) return rc;
+        if ((rc = coarse_alloc(&h->ecpad, gb))) return rc;
+        e = launch_fill_u32((unsigned *)h->ecpad, (int64_t)(gb / 4), 0u, st);
+        if (e != hipSuccess) return hip_fail(e, "ensemble grid clear");
+        h->ecpad_members = members;
+    }
+    EventPair ev;
+    if (kernel_seconds) {
+        e = ev.create();
+        if (e == hipSuccess) e = hipEventRecord(ev.a, st);
+    }
+    const int cap = (int)h->ecpad_members;
+    if (e == hipSuccess)
+        e = launch_ensemble_pack(C_in, n_ens, h->n_nodes, s, cap, (unsigned *)h->ecmax, h->ecpad, st);
+    if (e == hipSuccess)
+        e = launch_ensemble_apply(h->efrag, h->ecpad, n_ens, h->n_nodes, s, cap, h->esp, (const unsigned *)h->ecmax,
+                                  C_out, st);
+    if (kernel_seconds && e == hipSuccess) e = hipEventRecord(ev.b, st);
+    if (e != hipSuccess) return hip_fail(e, "ensemble product launch");
+    if (kernel_seconds) {
+        e = hipEventSynchronize(ev.b);
+        if (e != hipSuccess) return hip_fail(e, "ensemble product");
+        *kernel_seconds = ev.seconds();
     }
     return FDIRW_OK;
 }

@@ -252,6 +252,36 @@ hipError_t launch_coarse_apply_arith(int arith, int prec, const void *P, const v
                                      int K, const double *pbc_pad, double c_ff, const double *count, double *cnew,
                                      hipStream_t st, const double *cff_dev, const int *list, int64_t n_list,
                                      int n_split, double *part);
+
+// Ensemble product (several coarse fields at once) on the matrix cores, for
+// P stored in FP16 with K <= ENSEMBLE_MAX_K: tiles of 4 x 4 nodes in (x, y),
+// (2K + 1) z offsets of kst steps of 32 columns; the padded FP16 C grid has
+// px x py x pz positions (pad K) for every member.
+constexpr int ENSEMBLE_MAX_K = 4;
+struct EnsembleShape {
+    int ncx, ncy, ncz, K, kw;
+    int tx, ty;               // tiles along x and y
+    int row;                  // columns per source row (4 + 2K rounded up to 8)
+    int kst;                  // 32-column steps per z offset
+    int64_t n_tiles;
+    int px, py, pz;
+    int64_t msize;            // elements of one member's padded grid
+};
+EnsembleShape ensemble_shape(int ncx, int ncy, int ncz, int K);
+int64_t ensemble_frag_bytes(const EnsembleShape &s);
+// largest |P| (FP32 bits, into *out) and the power-of-two scale it gives
+hipError_t launch_ensemble_pmax(const void *P16, int64_t n, unsigned *out, hipStream_t st);
+int ensemble_p_scale(unsigned pmax_bits);
+hipError_t launch_ensemble_frags(const void *P16, int64_t plane, const EnsembleShape &s, int sp, void *frag,
+                                 hipStream_t st);
+// cap: members the padded grid holds (a multiple of 16, >= n_ens; the
+// grid is cap x msize halves); cmax: n_ens unsigned of scratch (each
+// member's largest |C|)
+hipError_t launch_ensemble_pack(const double *C, int n_ens, int64_t n_nodes, const EnsembleShape &s, int cap,
+                                unsigned *cmax, void *cpad, hipStream_t st);
+hipError_t launch_ensemble_apply(const void *frag, const void *cpad, int n_ens, int64_t n_nodes,
+                                 const EnsembleShape &s, int cap, int sp, const unsigned *cmax, double *out,
+                                 hipStream_t st);
 int coarse_apply_zb(int prec);                                  // nodes per chunk
 int coarse_apply_split(int K, int64_t n_chunks);                // the number of pair ranges (1 below the chunk K)
 int64_t coarse_apply_part_elems(int prec, int K, int64_t n_chunks);

@@ -13,7 +13,8 @@ disabled, so every kernel is the network's) instead of the FD kernels.  With
 kernel once in a bank of the precision ``--prec`` (fp32, fp16_bank, ...) and
 applies it for one big step.  With ``--coarse B`` the coarse-mesh operator
 over B^3 blocks is built once (P stored in ``--prec``) and each repetition is
-one coarse step.  With ``--mp K`` the integrated near-field solver of the
+one coarse step, or with ``--ensemble E1,E2,..`` three ensemble products (P
+in FP16) of each listed member count on seeded node fields.  With ``--mp K`` the integrated near-field solver of the
 particle case (porous particle of radius 50 n / 192, Table 1 values, coarse
 blocks of 5, P in ``--prec``) is built once and each repetition runs K big
 steps (``--mp-r`` / ``--mp-nsub``: window radius and fast sub-steps of the
@@ -42,6 +43,7 @@ def main():
     ap.add_argument("--gen", default="fd", choices=["fd", "nn"])
     ap.add_argument("--bank", type=int, default=0)
     ap.add_argument("--coarse", type=int, default=0)
+    ap.add_argument("--ensemble", default="")
     ap.add_argument("--flow", type=float, default=0.0)
     ap.add_argument("--mp", type=int, default=0)
     ap.add_argument("--mp-r", type=int, default=8)
@@ -94,9 +96,15 @@ def main():
         cg = fd.Coarse(dom, args.coarse, args.prec)
         print(f"[profile_step] n={args.n} coarse block {args.coarse} prec={args.prec}: {cg.n_nodes} nodes, "
               f"build {cg.build_seconds:.2f} s", flush=True)
-        for i in range(args.reps):
+        for i in range(args.reps if not args.ensemble else 0):
             _, st = cg.step(c, out, stats=True)
             print(f"[profile_step] coarse step {i}: kernels {st['kernel_seconds'] * 1e3:.3f} ms", flush=True)
+        for E in [int(v) for v in args.ensemble.split(",") if v]:
+            C = torch.from_numpy(synth.uniform(900 + E, E * cg.n_nodes).reshape(E, cg.n_nodes)).cuda()
+            Co = torch.empty_like(C)
+            for _ in range(3):
+                _, ks = cg.apply_ensemble(C, Co, timed=True)
+            print(f"[profile_step] ensemble E={E}: {ks * 1e3:.4f} ms", flush=True)
         cg.close()
         args.reps = 0
         args.warmup = 0

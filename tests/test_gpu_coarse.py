@@ -439,3 +439,109 @@ def test_arith_back_and_forth_and_far_field():
     o = to_host(out)
     assert abs(o[~far].sum() + c_ff * v_ff - m_total) <= 1e-12 * m_total
     cf.close()
+
+
+# ---------------------------------------------------------------- ensemble product (Eq. 14, several right-hand sides)
+
+def _ensemble_fields(n_ens, n_nodes, seed):
+    """Members of different magnitudes (1e-12 .. 1e6: below FP16's normal
+    range and above its largest number before the scaling), seeded."""
+    v = synth.uniform(seed, n_ens * n_nodes).reshape(n_ens, n_nodes)
+    scale = 10.0 ** (3 * (np.arange(n_ens) % 7) - 12)
+    return v * scale[:, None]
+
+
+# K = 1, 2, 3, 4; ragged 4 x 4 tiles; member counts below, at and above the
+# 16-member column tile and the 128 members of one wave
+ENSEMBLE_CASES = [((7, 9, 6), 2, 6, 2, 1, 70), ((10, 11, 9), 3, 8, 2, 17, 71), ((13, 9, 12), 3, 5, 1, 5, 72),
+                  ((14, 12, 13), 8, 8, 2, 130, 73), ((20, 18, 22), 8, 8, 4, 16, 74)]
+
+
+@pytest.mark.parametrize("shape,r,n_sub,B,n_ens,seed", ENSEMBLE_CASES)
+def test_ensemble_product_matches_oracle(shape, r, n_sub, B, n_ens, seed):
+    """Every member's product within the FP32 accumulation bound of the
+    oracle's exact products of the same FP16 operands (dyadic geometry: P is
+    the same number on both sides before its FP16 rounding)."""
+    d = synth.random_small(shape, 2, r=r, n_sub=n_sub, seed=seed, dt=0.125)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, B)
+    cg = fd.Coarse(_dev_domain(d), B, fd.FP16_BANK)
+    C = _ensemble_fields(n_ens, cg.n_nodes, seed)
+    print(f"[ensemble] shape={shape} r={r} B={B} K={cg.K} n_ens={n_ens}", flush=True)
+    got = to_host(cg.apply_ensemble(to_dev(C)))
+    ref, bnd = coarse.ensemble_product(P, C)
+    ratio = np.max(np.abs(got - ref) / (bnd + 1e-300))
+    print(f"[ensemble] max |gpu - oracle| / bound = {ratio:.3f}", flush=True)
+    assert np.all(np.abs(got - ref) <= bnd)
+    cg.close()
+
+
+def test_ensemble_second_call_with_fewer_members():
+    """Grids kept from a larger call do not leak into a smaller one; the
+    same members give the same results bitwise."""
+    d = synth.random_small((11, 10, 12), 2, r=3, n_sub=6, seed=75, dt=0.125)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, 2)
+    cg = fd.Coarse(_dev_domain(d), 2, fd.FP16_BANK)
+    C = _ensemble_fields(40, cg.n_nodes, 75)
+    big = to_host(cg.apply_ensemble(to_dev(C)))
+    small = to_host(cg.apply_ensemble(to_dev(C[3:10].copy())))
+    assert np.array_equal(small, big[3:10])
+    ref, bnd = coarse.ensemble_product(P, C[3:10])
+    assert np.all(np.abs(small - ref) <= bnd)
+    cg.close()
+
+
+def test_ensemble_grf_blocks_of_five():
+    """The benchmark's coarse shape (r = 8, 5^3 blocks, K = 2) on a 40^3 GRF
+    geometry: each member's product within the bound of the oracle's terms
+    formed from the library's own FP16 P (the oracle's P differs from it by
+    FP32 kernel rounding on this non-dyadic geometry), and members equal to
+    single-member calls bitwise."""
+    d = synth.config2(seed=76, n=40)
+    cg = fd.Coarse(_dev_domain(d), 5, fd.FP16_BANK)
+    Pm = cg.matrix()                                    # [o, I], the stored FP16 values widened
+    K, kw = cg.K, 2 * cg.K + 1
+    ncz, ncy, ncx = cg.coarse_shape
+    n = cg.n_nodes
+    P = np.zeros((n, n))
+    for I in range(n):
+        bz, rem = divmod(I, ncy * ncx)
+        by, bx = divmod(rem, ncx)
+        for o in range(kw ** 3):
+            oz, rem2 = divmod(o, kw * kw)
+            oy, ox = divmod(rem2, kw)
+            jz, jy, jx = bz - (oz - K), by - (oy - K), bx - (ox - K)
+            if 0 <= jz < ncz and 0 <= jy < ncy and 0 <= jx < ncx:
+                P[I, (jz * ncy + jy) * ncx + jx] = Pm[o, I]
+    C = _ensemble_fields(24, n, 76)
+    got = to_host(cg.apply_ensemble(to_dev(C)))
+    ref, bnd = coarse.ensemble_product(P, C)
+    assert np.all(np.abs(got - ref) <= bnd)
+    one = to_host(cg.apply_ensemble(to_dev(C[5:6].copy())))
+    assert np.array_equal(one[0], got[5])
+    cg.close()
+
+
+def test_ensemble_rejections():
+    d = synth.random_small((8, 8, 8), 2, r=3, n_sub=4, seed=77)
+    dom = _dev_domain(d)
+    c32 = fd.Coarse(dom, 2, fd.FP32)
+    C = to_dev(np.ones((2, c32.n_nodes)))
+    with pytest.raises(fd.FdirwError) as e:
+        c32.apply_ensemble(C)
+    assert e.value.status == fd.E_ARG
+    c32.close()
+    c16 = fd.Coarse(dom, 2, fd.FP16_BANK)
+    with pytest.raises(fd.FdirwError) as e:
+        fd.fdirw_coarse_apply_ensemble(c16.handle, C, C, 2)            # in place
+    assert e.value.status == fd.E_ARG
+    with pytest.raises(fd.FdirwError) as e:
+        fd.fdirw_coarse_apply_ensemble(c16.handle, C, torch.empty_like(C), 0)
+    assert e.value.status == fd.E_ARG
+    c16.close()
+    k5 = fd.Coarse(_dev_domain(synth.random_small((7, 7, 7), 2, r=5, n_sub=4, seed=78)), 1, fd.FP16_BANK)
+    with pytest.raises(fd.FdirwError) as e:
+        k5.apply_ensemble(to_dev(np.ones((1, k5.n_nodes))))
+    assert e.value.status == fd.E_UNSUPPORTED
+    k5.close()
