@@ -189,7 +189,9 @@ __global__ void __launch_bounds__(ENS_NT) ensemble_apply_kernel(const half8 *__r
     constexpr int KW = 2 * K + 1, SPAN = 4 + 2 * K, ROW = ru(SPAN, 8), KST = (ROW * SPAN + 31) / 32;
     constexpr int UNR = KST <= 2 ? KST : (KST % 2 ? 1 : 2);   // steps in flight (registers)
     const int lane = threadIdx.x & 63;
-    const int64_t tile = blockIdx.x * (int64_t)(ENS_NT / 64) + (threadIdx.x >> 6);
+    // consecutive tiles (a z-slab) on one XCD: they share their sources' FP16
+    // copies in that XCD's L2
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x) * (int64_t)(ENS_NT / 64) + (threadIdx.x >> 6);
     if (tile >= s.n_tiles) return;                             // uniform per wave (no barrier below)
     const int mt0 = blockIdx.y * ENS_MT;
     const int n_mt = min(ENS_MT, (n_ens + 15) / 16 - mt0);
@@ -314,7 +316,8 @@ hipError_t launch_ensemble_apply(const void *frag, const void *cpad, int n_ens, 
                                  hipStream_t st)
 {
     const int n_mt = (n_ens + 15) / 16;
-    const dim3 grid((unsigned)((s.n_tiles + ENS_NT / 64 - 1) / (ENS_NT / 64)), (unsigned)((n_mt + ENS_MT - 1) / ENS_MT));
+    const int64_t blocks = (s.n_tiles + ENS_NT / 64 - 1) / (ENS_NT / 64);
+    const dim3 grid((unsigned)((blocks + 7) / 8 * 8), (unsigned)((n_mt + ENS_MT - 1) / ENS_MT));
     const half8 *f = (const half8 *)frag;
     const _Float16 *c = (const _Float16 *)cpad;
     switch (s.K) {
