@@ -44,6 +44,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int ENS_NT = 256;           // 4 waves, one tile each
 constexpr int ENS_MT = 8;             // column tiles of 16 members per wave
+constexpr int ENS_SLIDE_MG = 4;       // ... in the plane-walking form
 
 // 2^t that brings m into [2^14, 2^15) (1 for m = 0 or not finite).
 __device__ __forceinline__ int pow2_scale(float m)
@@ -249,6 +250,97 @@ __global__ void __launch_bounds__(ENS_NT) ensemble_apply_kernel(const half8 *__r
     }
 }
 
+// The same product with the source planes walked once (K <= 2, many members):
+// a wave takes one tile column (txi, tyi), ZC consecutive output planes and
+// MG column tiles of 16 members.  Each source plane's operands (every step,
+// every column tile) are loaded once and feed the 2K + 1 output planes whose
+// band covers it (accumulators of all ZC planes live in registers), instead
+// of being reloaded for every output plane: (ZC + 2K) instead of ZC (2K + 1)
+// operand loads.  Same fragments, same sums in the same order per output as
+// ensemble_apply_kernel (z offsets in increasing order, then steps).
+template <int K, int ZC, int MG>
+__global__ void __launch_bounds__(ENS_NT) ensemble_slide_kernel(const half8 *__restrict__ frag,
+                                                                const _Float16 *__restrict__ cpad, int n_ens,
+                                                                int64_t n_nodes, EnsembleShape s, int cap, int sp,
+                                                                const unsigned *__restrict__ cmax,
+                                                                double *__restrict__ out)
+{
+    constexpr int KW = 2 * K + 1, SPAN = 4 + 2 * K, ROW = ru(SPAN, 8), KST = (ROW * SPAN + 31) / 32;
+    const int lane = threadIdx.x & 63;
+    const int ncol = s.tx * s.ty, nzc = (s.ncz + ZC - 1) / ZC;
+    // consecutive waves: consecutive tile columns of one z-chunk (on one XCD)
+    const int w = xcd_remap(blockIdx.x, gridDim.x) * (ENS_NT / 64) + (threadIdx.x >> 6);
+    if (w >= ncol * nzc) return;                               // uniform per wave (no barrier below)
+    const int colt = w % ncol, z0 = (w / ncol) * ZC;
+    const int txi = colt % s.tx, tyi = colt / s.tx;
+    const int x0 = 4 * txi, y0 = 4 * tyi, kb = lane >> 4, col = lane & 15;
+    const int mt0 = blockIdx.y * MG;
+    const int n_mt = min(MG, (n_ens + 15) / 16 - mt0);
+    const int nchunk = s.px / 4;
+    const _Float16 *cbase = cpad + (int64_t)(16 * mt0 + col) * 4;
+    floatx4 acc[ZC][MG];
+#pragma unroll
+    for (int zi = 0; zi < ZC; ++zi)
+#pragma unroll
+        for (int t = 0; t < MG; ++t) acc[zi][t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // the sums of an output plane run over z offsets in increasing order: its
+    // source planes in decreasing order, so walk them downwards
+#pragma unroll
+    for (int j = ZC + 2 * K - 1; j >= 0; --j) {
+        const int zp = z0 + j;                                 // padded z of source plane j
+        if (zp >= s.pz) continue;                              // uniform: feeds no output plane
+        half8 b[KST][MG];
+#pragma unroll
+        for (int step = 0; step < KST; ++step) {
+            const int k = 32 * step + 8 * kb;
+            int jy = k / ROW;
+            const int jx = k - jy * ROW;
+            if (jy >= SPAN) jy = SPAN - 1;                    // padding columns: zero in the fragment
+            const _Float16 *cp = cbase + (((int64_t)zp * s.py + (y0 + jy)) * nchunk + (x0 + jx) / 4) * cap * 4;
+#pragma unroll
+            for (int t = 0; t < MG; ++t) {
+                const _Float16 *c = cp + 64 * (t < n_mt ? t : 0);
+                const uint2 lo = *(const uint2 *)c, hi = *(const uint2 *)(c + (int64_t)cap * 4);
+                __builtin_memcpy(&b[step][t], &lo, 8);
+                __builtin_memcpy((char *)&b[step][t] + 8, &hi, 8);
+            }
+        }
+#pragma unroll
+        for (int oz = 0; oz < KW; ++oz) {
+            const int zi = j + oz - 2 * K;                     // output plane z0 + zi (zp = z - oz + 2K)
+            if (zi < 0 || zi >= ZC) continue;                  // compile time
+            const int z = z0 + zi;
+            if (z >= s.ncz) continue;                          // uniform
+            const half8 *fp = frag + (((int64_t)z * s.ty + tyi) * s.tx + txi) * (KW * KST * 64) + lane;
+#pragma unroll
+            for (int step = 0; step < KST; ++step) {
+                const half8 a = fp[(oz * KST + step) * 64];
+#pragma unroll
+                for (int t = 0; t < MG; ++t)
+                    acc[zi][t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b[step][t], acc[zi][t], 0, 0, 0);
+            }
+        }
+    }
+    const int y = y0 + kb;
+    if (y >= s.ncy) return;
+#pragma unroll
+    for (int zi = 0; zi < ZC; ++zi) {
+        const int z = z0 + zi;
+        if (z >= s.ncz) break;
+#pragma unroll
+        for (int t = 0; t < MG; ++t) {
+            const int m = 16 * (mt0 + t) + col;
+            if (t < n_mt && m < n_ens) {
+                const int back = -(sp + pow2_scale(__uint_as_float(cmax[m])));
+                double *o = out + (int64_t)m * n_nodes + ((int64_t)z * s.ncy + y) * s.ncx + x0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (x0 + u < s.ncx) o[u] = ldexp((double)acc[zi][t][u], back);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 EnsembleShape ensemble_shape(int ncx, int ncy, int ncz, int K)
@@ -316,10 +408,24 @@ hipError_t launch_ensemble_apply(const void *frag, const void *cpad, int n_ens, 
                                  hipStream_t st)
 {
     const int n_mt = (n_ens + 15) / 16;
-    const int64_t blocks = (s.n_tiles + ENS_NT / 64 - 1) / (ENS_NT / 64);
-    const dim3 grid((unsigned)((blocks + 7) / 8 * 8), (unsigned)((n_mt + ENS_MT - 1) / ENS_MT));
     const half8 *f = (const half8 *)frag;
     const _Float16 *c = (const _Float16 *)cpad;
+    // the plane-walking form keeps ZC planes of accumulators (two waves per
+    // SIMD) and has fewer waves: it pays from 8 column tiles (128 members) on
+    if (s.K <= 2 && n_mt >= 2 * ENS_SLIDE_MG) {
+        constexpr int ZC = 8, MG = ENS_SLIDE_MG;
+        const int64_t waves = (int64_t)s.tx * s.ty * ((s.ncz + ZC - 1) / ZC);
+        const int64_t blocks = (waves + ENS_NT / 64 - 1) / (ENS_NT / 64);
+        const dim3 grid((unsigned)((blocks + 7) / 8 * 8), (unsigned)((n_mt + MG - 1) / MG));
+        switch (s.K) {
+        case 0: ensemble_slide_kernel<0, ZC, MG><<<grid, ENS_NT, 0, st>>>(f, c, n_ens, n_nodes, s, cap, sp, cmax, out); break;
+        case 1: ensemble_slide_kernel<1, ZC, MG><<<grid, ENS_NT, 0, st>>>(f, c, n_ens, n_nodes, s, cap, sp, cmax, out); break;
+        default: ensemble_slide_kernel<2, ZC, MG><<<grid, ENS_NT, 0, st>>>(f, c, n_ens, n_nodes, s, cap, sp, cmax, out); break;
+        }
+        return hipGetLastError();
+    }
+    const int64_t blocks = (s.n_tiles + ENS_NT / 64 - 1) / (ENS_NT / 64);
+    const dim3 grid((unsigned)((blocks + 7) / 8 * 8), (unsigned)((n_mt + ENS_MT - 1) / ENS_MT));
     switch (s.K) {
     case 0: ensemble_apply_kernel<0><<<grid, ENS_NT, 0, st>>>(f, c, n_ens, n_nodes, s, cap, sp, cmax, out); break;
     case 1: ensemble_apply_kernel<1><<<grid, ENS_NT, 0, st>>>(f, c, n_ens, n_nodes, s, cap, sp, cmax, out); break;

@@ -454,7 +454,9 @@ def _ensemble_fields(n_ens, n_nodes, seed):
 # K = 1, 2, 3, 4; ragged 4 x 4 tiles; member counts below, at and above the
 # 16-member column tile and the 128 members of one wave
 ENSEMBLE_CASES = [((7, 9, 6), 2, 6, 2, 1, 70), ((10, 11, 9), 3, 8, 2, 17, 71), ((13, 9, 12), 3, 5, 1, 5, 72),
-                  ((14, 12, 13), 8, 8, 2, 130, 73), ((20, 18, 22), 8, 8, 4, 16, 74)]
+                  ((14, 12, 13), 8, 8, 2, 130, 73), ((20, 18, 22), 8, 8, 4, 16, 74),
+                  # 128 or more members at K <= 2: the plane-walking form (ragged z-chunks of 8 planes)
+                  ((12, 9, 21), 3, 6, 2, 130, 79), ((9, 13, 19), 2, 6, 2, 140, 80)]
 
 
 @pytest.mark.parametrize("shape,r,n_sub,B,n_ens,seed", ENSEMBLE_CASES)
@@ -545,3 +547,16 @@ def test_ensemble_rejections():
         k5.apply_ensemble(to_dev(np.ones((1, k5.n_nodes))))
     assert e.value.status == fd.E_UNSUPPORTED
     k5.close()
+
+
+def test_ensemble_forms_agree_bitwise():
+    """128 members go through the plane-walking form, 16 through the
+    per-tile form: the same fragments summed in the same order, so the
+    members they share agree bitwise."""
+    d = synth.random_small((15, 14, 19), 2, r=3, n_sub=6, seed=81, dt=0.125)
+    cg = fd.Coarse(_dev_domain(d), 2, fd.FP16_BANK)
+    C = _ensemble_fields(128, cg.n_nodes, 81)
+    many = to_host(cg.apply_ensemble(to_dev(C)))
+    few = to_host(cg.apply_ensemble(to_dev(C[:16].copy())))
+    assert np.array_equal(few, many[:16])
+    cg.close()
