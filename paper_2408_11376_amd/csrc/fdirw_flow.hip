@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fdirw_host.h"
 #include "fdirw_launch.h"
 
 namespace fdirw {
@@ -195,6 +196,7 @@ static hipError_t launch_flow_sl(int r, const FlowArgs &a, hipStream_t st)
 
 hipError_t launch_flow_window(int fp64, int r, const FlowArgs &a, hipStream_t st)
 {
+    if (!fp64 && use_flat_layout(FDIRW_FP32, r)) return launch_flow_flat(r, a, st);
     return fp64 ? launch_flow_sl<double, double>(r, a, st) : launch_flow_sl<float, float>(r, a, st);
 }
 

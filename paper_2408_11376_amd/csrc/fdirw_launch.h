@@ -223,6 +223,8 @@ hipError_t launch_coarse_map(const double *c, const int *node, const double *cou
                              int ncx, int ncy, int ncz, int K, double *cpad, hipStream_t st, int dense,
                              const int *used = nullptr, int64_t n_used = 0);   // used: the nodes with cells
 hipError_t launch_flow_window(int fp64, int r, const FlowArgs &a, hipStream_t st);
+// FP32 flow window kernels in the flat layout (r = 4..8)
+hipError_t launch_flow_flat(int r, const FlowArgs &a, hipStream_t st);
 hipError_t launch_flow_stability(int fp64, const void *lam, const double *u, int nx, int ny, int nz, double cour,
                                  unsigned long long *out, hipStream_t st);
 hipError_t launch_coarse_bin(int fp64, int sink, int r, const CoarseGenArgs &a, const void *G, int64_t src_base,

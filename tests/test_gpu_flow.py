@@ -58,6 +58,50 @@ def test_flow_kernels_fp32_and_zero_flow():
     assert np.max(np.abs(to_host(G0) - to_host(Gp))) <= 1e-14
 
 
+@pytest.mark.parametrize("shape,r,n_sub,seed", [((10, 9, 11), 4, 16, 47), ((12, 13, 14), 8, 12, 48)])
+def test_flow_kernels_fp32_flat_layout(shape, r, n_sub, seed):
+    """r = 4..8 in FP32 runs the flat-layout flow kernel: against the FP64
+    oracle to 1e-6 (window edges, domain walls, the source near a corner),
+    unit mass without sinks."""
+    d, u, dt = _flow_case(shape, r, n_sub, seed)
+    dom = fd.Domain(d.label, d.d_phase, r, n_sub, d.h, dt)
+    src = np.arange(0, d.label.size, 5)
+    p = oracle.Problem(d.label, d.d_phase, r, n_sub, d.h, dt, velocity=u)
+    Gw, _ = p.kernels(src)
+    G32, m32 = fd.fdirw_kernels_flow(dom, to_dev(u), to_dev(src), prec=fd.FP32)
+    print(f"[flow fp32 flat] r={r} max |gpu - oracle| = {np.max(np.abs(to_host(G32) - Gw)):.2e}", flush=True)
+    assert np.max(np.abs(to_host(G32) - Gw)) <= 1e-6
+    assert np.max(np.abs(to_host(m32) - 1.0)) <= 1e-5
+
+
+def test_coarse_with_flow_fp32_flat_layout_far_field():
+    """The coarse build with a flow at r = 4 (flat-layout kernels with
+    far-field sinks): P and P_BC against the oracle at FP32 accuracy."""
+    d, u, dt = _flow_case((9, 8, 10), 4, 10, 49)
+    label = d.label.copy()
+    dph = np.array(list(d.d_phase) + [1.0])
+    label[:, :, 0] = len(dph) - 1
+    res = [0] * (len(dph) - 1) + [1]
+    p = oracle.Problem(label, dph, 4, 10, d.h, dt, velocity=u)
+    P = coarse.coarse_matrix(p, 3, reservoir=res)
+    cg = fd.Coarse(fd.Domain(label, dph, 4, 10, d.h, dt), 3, fd.FP32, reservoir=res, velocity=to_dev(u))
+    kw = 2 * cg.K + 1
+    got = cg.matrix()
+    ncz, ncy, ncx = cg.coarse_shape
+    ref = np.zeros_like(got)
+    for I in range(P.shape[0]):
+        bz, rem = divmod(I, ncy * ncx)
+        by, bx = divmod(rem, ncx)
+        for o in range(kw ** 3):
+            oz, rem2 = divmod(o, kw * kw)
+            oy, ox = divmod(rem2, kw)
+            jz, jy, jx = bz - (oz - cg.K), by - (oy - cg.K), bx - (ox - cg.K)
+            if 0 <= jz < ncz and 0 <= jy < ncy and 0 <= jx < ncx:
+                ref[o, I] = P[I, (jz * ncy + jy) * ncx + jx]
+    assert np.max(np.abs(got - ref)) <= 2e-6 * np.abs(ref).max()
+    cg.close()
+
+
 def test_flow_instability_and_errors():
     d, u, dt = _flow_case((5, 5, 5), 2, 4, 45)
     dom = fd.Domain(d.label, d.d_phase, 2, 4, d.h, dt)
