@@ -560,3 +560,29 @@ def test_ensemble_forms_agree_bitwise():
     few = to_host(cg.apply_ensemble(to_dev(C[:16].copy())))
     assert np.array_equal(few, many[:16])
     cg.close()
+
+
+def test_ensemble_without_diffusion_is_the_identity_band():
+    """r = 0 (K = 0): P is diagonal (every group keeps its mass), so each
+    member's product is the member itself in the mixed precision: the
+    FP32-then-FP16 rounding of its scaled values, bitwise."""
+    d = synth.random_small((9, 10, 11), 2, r=0, n_sub=3, seed=82, dt=0.125)
+    p = oracle.Problem.from_domain(d)
+    P = coarse.coarse_matrix(p, 2)
+    cg = fd.Coarse(_dev_domain(d), 2, fd.FP16_BANK)
+    assert cg.K == 0
+    C = _ensemble_fields(20, cg.n_nodes, 82)
+    got = to_host(cg.apply_ensemble(to_dev(C)))
+    ref, bnd = coarse.ensemble_product(P, C)
+    assert np.array_equal(got, ref)
+    cg.close()
+
+
+def test_ensemble_member_count_limit():
+    d = synth.random_small((6, 6, 6), 2, r=2, n_sub=3, seed=83)
+    cg = fd.Coarse(_dev_domain(d), 2, fd.FP16_BANK)
+    C = torch.zeros((4097, cg.n_nodes), dtype=torch.float64, device="cuda")
+    with pytest.raises(fd.FdirwError) as e:
+        fd.fdirw_coarse_apply_ensemble(cg.handle, C, torch.empty_like(C), 4097)
+    assert e.value.status == fd.E_ARG
+    cg.close()
