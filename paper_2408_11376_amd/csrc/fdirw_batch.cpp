@@ -5,8 +5,8 @@
 // radius lets one workgroup hold) and a range of source planes.  Launch shape
 // choices the tuner explores: the workgroup layout (the 640-thread segment
 // layout, which packs several small windows per workgroup, or the 256-thread
-// flat layout of the single-domain FP32 step, one window per workgroup and
-// two workgroups per CU), the z extent of an item (long items amortise the
+// flat layout of the single-domain FP32 step, one to four windows per
+// workgroup by radius and two workgroups per CU), the z extent of an item (long items amortise the
 // per-item LDS setup; short items balance the load at the end of the queue)
 // and the queue order (natural, or longest-processing-time first).  The tuner
 // times each candidate on an evenly spaced sample of the real items, with HIP
@@ -32,7 +32,7 @@ namespace fdirw {
 struct BatchConfig {
     int zlen;       // planes per item, 0 = whole column of sources
     int lpt;        // 1 = longest item first
-    int flat;       // 1 = flat layout (FP32 only): one source line per item
+    int flat;       // 1 = flat layout (FP32 only): flat_lines_per_group(r) lines per item
 };
 
 static const BatchConfig kConfigs[] = {
@@ -95,7 +95,10 @@ static std::string tune_key(const fdirw_domain *d, int n_dom, int prec)
     return k;
 }
 
-static int lines_per_item(const BatchConfig &cfg, int r) { return cfg.flat ? 1 : batch_windows_per_group(r); }
+static int lines_per_item(const BatchConfig &cfg, int r)
+{
+    return cfg.flat ? flat_lines_per_group(r) : batch_windows_per_group(r);
+}
 
 static double item_cost(const fdirw_domain &d, const BatchItem &it, const BatchConfig &cfg)
 {

@@ -137,6 +137,9 @@ hipError_t batched_occupancy(int mode, int *blocks);
 // The batched launch with the flat layout (FP32; items of one line each).
 hipError_t launch_batched_flat(const BatchArgs &a, int grid, hipStream_t st);
 hipError_t batched_flat_occupancy(int *blocks);
+// Source lines one flat-layout workgroup runs side by side at radius r
+// (4 at r = 4, 2 at r = 5 and 6, 1 at r = 7 and 8).
+int flat_lines_per_group(int r);
 int batch_windows_per_group(int r);
 
 hipError_t launch_validate(const uint8_t *label, int64_t n, int n_phase, unsigned *out, hipStream_t st);

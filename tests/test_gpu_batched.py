@@ -32,7 +32,8 @@ def _mixed_domains(seed=0):
 @pytest.mark.parametrize("prec,tol,tune", [(fd.FP64, 1e-12, 3), (fd.FP32, 1e-5, 3), (fd.FP32, 1e-5, 6),
                                            (fd.FP32, 1e-5, 9)])
 def test_batched_matches_oracle_every_radius(prec, tol, tune):
-    # shapes 6..9: the flat layout (one source line per item, every radius 0..8)
+    # shapes 6..9: the flat layout (one to four source lines per item by radius,
+    # every radius 0..8)
     ds = _mixed_domains(100)
     outs, sts = fd.fdirw_step([_dev(d) for d in ds], [to_dev(d.c0) for d in ds], prec=prec, stats=True, tune=tune)
     for d, o, st in zip(ds, outs, sts):

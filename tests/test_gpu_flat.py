@@ -11,8 +11,11 @@ shift ring, so its step must equal
     placed at the source (same nonzero pattern, values within 1e-14
     relative: the masses are summed in another grouping).
 Cases cover every radius of the kernel, domains smaller than the window,
-lines cut into several segments, odd and zero sub-step counts, and zero
-sources between nonzero ones (the ring still shifts past them)."""
+lines cut into several segments, odd and zero sub-step counts, zero sources
+between nonzero ones (the ring still shifts past them), and line counts that
+leave the last workgroup's group of lines short (r = 4 runs four lines per
+workgroup, r = 5 and 6 two: 110 and 9 lines at r = 4, 91 at r = 5, 99 at
+r = 6)."""
 import numpy as np
 import pytest
 
@@ -35,7 +38,8 @@ def _dev(d):
 
 CASES = [((9, 10, 11), 4, 21, 901), ((12, 7, 13), 5, 30, 902), ((6, 15, 8), 6, 17, 903),
          ((16, 16, 16), 7, 40, 904), ((19, 18, 20), 8, 45, 905), ((5, 6, 7), 8, 33, 906),
-         ((1, 1, 1), 8, 5, 907), ((3, 20, 2), 8, 0, 908), ((25, 4, 9), 4, 1, 909)]
+         ((1, 1, 1), 8, 5, 907), ((3, 20, 2), 8, 0, 908), ((25, 4, 9), 4, 1, 909),
+         ((10, 9, 11), 6, 23, 910), ((8, 3, 3), 4, 12, 912), ((11, 5, 7), 7, 19, 913)]
 
 
 @pytest.mark.parametrize("shape,r,n_sub,seed", CASES)
@@ -74,7 +78,7 @@ def test_flat_step_lines_in_segments(tune):
     assert np.max(np.abs(to_host(out) - whole)) <= 1e-13 * np.abs(whole).max()
 
 
-@pytest.mark.parametrize("r", [4, 8])
+@pytest.mark.parametrize("r", [4, 5, 6, 8])
 def test_flat_one_hot_is_placed_kernel(r):
     d = synth.random_small((14, 13, 15), 3, r=r, n_sub=37, seed=921 + r)
     dom = _dev(d)
