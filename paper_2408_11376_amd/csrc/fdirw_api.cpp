@@ -228,8 +228,9 @@ int det_slab_planes(const fdirw_domain *d, int tune)
 }
 
 // The deterministic fused step: the source planes are taken in slabs of
-// det_slab_planes; per slab one launch with one workgroup per source line
-// stores every completed plane of every line to its own partial slot, and a
+// det_slab_planes; per slab one launch (the flat layout where the atomic step
+// uses it, else one workgroup per source line) stores every completed plane
+// of every line to its own partial slot, and a
 // second launch adds, for every cell the slab reaches, the partials of its
 // W^2 window columns in a fixed order to c_out.  No floating-point atomics:
 // the result depends on the inputs and the slab size only.
@@ -256,7 +257,8 @@ static int step_det(const fdirw_domain *d, const fdirw_opts *o, LineArgs a, DevC
         s.part_z0 = za - d->r;
         s.part_planes = part_planes;
         s.wg_kmass = (double *)dc.wgk.p + (size_t)k * lines * 2;
-        hipError_t e = launch_line(o->prec, d->r, s, stream);
+        hipError_t e = use_flat_layout(o->prec, d->r) ? launch_line_flat(o->prec, d->r, s, stream)
+                                                      : launch_line(o->prec, d->r, s, stream);
         if (e != hipSuccess) return hip_fail(e, "deterministic step launch");
         s.c_out = c_out;
         e = launch_line_reduce(d->r, s, std::max(0, za - d->r), std::min(d->nz, zb + d->r), stream);

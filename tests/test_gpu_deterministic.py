@@ -4,7 +4,9 @@ The contract (Eq. 8 marched in time): with deterministic = 1 the result of
 fdirw_step / fdirw_run is a function of the inputs, so a repeated call, a
 batched call (n_dom > 1) and single calls, and a run resumed from its
 intermediate field all agree bitwise; every result still matches the FP64
-oracle to the usual bars (L_inf 1e-12 in FP64, 1e-5 in FP32)."""
+oracle to the usual bars (L_inf 1e-12 in FP64, 1e-5 in FP32).  FP32 steps at
+r = 4..8 store their partials from the flat-layout kernel (several lines per
+workgroup at r = 4..6), the other cases from the segment-layout kernel."""
 import numpy as np
 import pytest
 
@@ -28,7 +30,8 @@ def _dev(d):
 @pytest.mark.parametrize("prec,tol", [(fd.FP64, 1e-12), (fd.FP32, 1e-5)])
 @pytest.mark.parametrize("shape,r,n_sub,seed", [((5, 7, 11), 2, 9, 21), ((1, 1, 1), 3, 5, 22), ((3, 4, 2), 8, 12, 23),
                                                  ((17, 3, 9), 4, 25, 24), ((6, 6, 6), 0, 10, 25),
-                                                 ((8, 9, 10), 3, 0, 26), ((19, 18, 20), 8, 40, 27)])
+                                                 ((8, 9, 10), 3, 0, 26), ((19, 18, 20), 8, 40, 27),
+                                                 ((10, 9, 11), 6, 23, 28), ((12, 7, 13), 5, 17, 29)])
 def test_deterministic_step_matches_oracle_and_repeats_bitwise(prec, tol, shape, r, n_sub, seed):
     d = synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=seed)
     ref, used, _ = oracle.Problem.from_domain(d).step(d.c0)
@@ -58,6 +61,23 @@ def test_deterministic_slabs_match_oracle(slab):
     assert np.array_equal(to_host(out), to_host(again))
     assert st["tuned_config_id"] == min(slab, d.shape[0])      # planes along z (nz = 13)
     assert st["kmass_min"] == pytest.approx(kmin, abs=1e-13) and st["kmass_max"] == pytest.approx(kmax, abs=1e-13)
+
+
+@pytest.mark.parametrize("slab", [1, 3, 1000])
+def test_deterministic_flat_layout_slabs(slab):
+    # FP32 at r = 5 (two lines per workgroup of the flat kernel) in slabs of
+    # source planes, the thinnest far below the window
+    d = synth.random_small((14, 9, 7), 3, r=5, n_sub=21, seed=32)
+    ref, used, _ = oracle.Problem.from_domain(d).step(d.c0)
+    dom = _dev(d)
+    out, st = fd.fdirw_step(dom, to_dev(d.c0), prec=fd.FP32, tune=slab, stats=True, deterministic=True)
+    again = fd.fdirw_step(dom, to_dev(d.c0), prec=fd.FP32, tune=slab, deterministic=True)
+    A = to_host(out)
+    assert np.max(np.abs(A - ref)) <= 1e-5
+    assert np.array_equal(A, to_host(again))
+    assert st["n_sources"] == used and st["tuned_config_id"] == min(slab, d.shape[0])
+    atomic = to_host(fd.fdirw_step(dom, to_dev(d.c0), prec=fd.FP32))
+    assert np.max(np.abs(A - atomic)) <= 1e-13 * np.abs(A).max()
 
 
 @pytest.mark.parametrize("prec", [fd.FP64, fd.FP32, fd.FP16X32])
@@ -98,9 +118,9 @@ def test_deterministic_batched_equals_single_bitwise(prec):
         assert np.array_equal(to_host(c), to_host(one))
 
 
-@pytest.mark.parametrize("bank", [0, 1 << 34])
-def test_deterministic_run_resumes_bitwise(bank):
-    d = synth.random_small((12, 11, 10), 3, r=3, n_sub=20, seed=61)
+@pytest.mark.parametrize("bank,r", [(0, 3), (1 << 34, 3), (0, 6)])
+def test_deterministic_run_resumes_bitwise(bank, r):
+    d = synth.random_small((12, 11, 10), 3, r=r, n_sub=20, seed=61)
     dom = _dev(d)
     full = to_dev(d.c0)
     _, st = fd.fdirw_run(dom, full, 3, prec=fd.FP32, stats=True, bank_budget_bytes=bank, deterministic=True)
