@@ -58,11 +58,13 @@ def test_flow_kernels_fp32_and_zero_flow():
     assert np.max(np.abs(to_host(G0) - to_host(Gp))) <= 1e-14
 
 
-@pytest.mark.parametrize("shape,r,n_sub,seed", [((10, 9, 11), 4, 16, 47), ((12, 13, 14), 8, 12, 48)])
+@pytest.mark.parametrize("shape,r,n_sub,seed", [((10, 9, 11), 4, 16, 47), ((12, 13, 14), 8, 12, 48),
+                                                 ((9, 7, 8), 5, 14, 51), ((8, 9, 7), 6, 11, 52)])
 def test_flow_kernels_fp32_flat_layout(shape, r, n_sub, seed):
     """r = 4..8 in FP32 runs the flat-layout flow kernel: against the FP64
     oracle to 1e-6 (window edges, domain walls, the source near a corner),
-    unit mass without sinks."""
+    unit mass without sinks.  r = 4 runs four sources per workgroup, r = 5
+    and 6 two; 198 and 101 sources leave the last workgroup short."""
     d, u, dt = _flow_case(shape, r, n_sub, seed)
     dom = fd.Domain(d.label, d.d_phase, r, n_sub, d.h, dt)
     src = np.arange(0, d.label.size, 5)
