@@ -79,26 +79,46 @@ __global__ void __launch_bounds__(256) ensemble_pmax_kernel(const _Float16 *__re
 }
 
 // Per member m (blockIdx.y) the bits of the largest |FP32(C)| of its nodes,
-// into cmax[m] (zeroed by the caller); four independent loads per thread and
-// trip.
+// into cmax[m] (zeroed by the caller).  The member's row is read as 16-byte
+// pairs from its first 16-byte boundary, eight independent loads per thread
+// and trip; the one value before that boundary and the one after the last
+// pair (rows of odd length or odd start) are taken by the first thread.
+// Workgroups of 256 threads (the reduction below assumes four waves).
 __device__ __forceinline__ float nan_max(float a, float b) { return b > a || b != b ? b : a; }
+
+constexpr int CMAX_UNR = 8;
 
 __global__ void __launch_bounds__(256) ensemble_cmax_kernel(const double *__restrict__ C, int64_t n_nodes,
                                                             unsigned *__restrict__ cmax)
 {
-    const double *c = C + (int64_t)blockIdx.y * n_nodes;
+    const int64_t a0 = (int64_t)blockIdx.y * n_nodes, a1 = a0 + n_nodes;
+    const int64_t b0 = a0 + (((uintptr_t)(C + a0) & 15) ? 1 : 0);   // first 16-byte boundary of the row
+    const int64_t np = (a1 - b0) / 2;                          // whole pairs from there
+    const double2 *c2 = (const double2 *)(C + b0);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     float m = 0.0f;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_nodes; i += 4 * stride) {
-        double v[4];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np; i += CMAX_UNR * stride) {
+        double2 v[CMAX_UNR];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = i + u * stride < n_nodes ? c[i + u * stride] : 0.0;
+        for (int u = 0; u < CMAX_UNR; ++u) v[u] = i + u * stride < np ? c2[i + u * stride] : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) m = nan_max(m, fabsf((float)v[u]));    // a NaN is kept
+        for (int u = 0; u < CMAX_UNR; ++u) {
+            m = nan_max(m, fabsf((float)v[u].x));             // a NaN is kept
+            m = nan_max(m, fabsf((float)v[u].y));
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (b0 > a0) m = nan_max(m, fabsf((float)C[a0]));
+        if (b0 + 2 * np < a1) m = nan_max(m, fabsf((float)C[a1 - 1]));
+    }
+    // one atomic per workgroup: waves through LDS first
+    __shared__ float wm[4];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) m = nan_max(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(cmax + blockIdx.y, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(cmax + blockIdx.y, __float_as_uint(nan_max(nan_max(wm[0], wm[1]), nan_max(wm[2], wm[3]))));
 }
 
 // Matrix fragment of (tile, oz, step) for one lane: row i = lane % 16 (node
@@ -395,7 +415,8 @@ hipError_t launch_ensemble_pack(const double *C, int n_ens, int64_t n_nodes, con
 {
     hipError_t e = launch_fill_u32(cmax, n_ens, 0u, st);
     if (e != hipSuccess) return e;
-    const dim3 gm((unsigned)std::min<int64_t>((n_nodes + 1023) / 1024, 16), (unsigned)n_ens);
+    const int64_t per_block = 2 * 256 * CMAX_UNR;              // values per workgroup and trip
+    const dim3 gm((unsigned)std::min<int64_t>((n_nodes + per_block - 1) / per_block, 16), (unsigned)n_ens);
     ensemble_cmax_kernel<<<gm, 256, 0, st>>>(C, n_nodes, cmax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const dim3 grid((unsigned)(s.ncy * s.ncz), (unsigned)((n_ens + 15) / 16));

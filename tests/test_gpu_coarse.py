@@ -456,7 +456,9 @@ def _ensemble_fields(n_ens, n_nodes, seed):
 ENSEMBLE_CASES = [((7, 9, 6), 2, 6, 2, 1, 70), ((10, 11, 9), 3, 8, 2, 17, 71), ((13, 9, 12), 3, 5, 1, 5, 72),
                   ((14, 12, 13), 8, 8, 2, 130, 73), ((20, 18, 22), 8, 8, 4, 16, 74),
                   # 128 or more members at K <= 2: the plane-walking form (ragged z-chunks of 8 planes)
-                  ((12, 9, 21), 3, 6, 2, 130, 79), ((9, 13, 19), 2, 6, 2, 140, 80)]
+                  ((12, 9, 21), 3, 6, 2, 130, 79), ((9, 13, 19), 2, 6, 2, 140, 80),
+                  # 125 nodes: member rows of odd length (every other one starts off a 16-byte boundary)
+                  ((9, 9, 9), 3, 6, 2, 9, 81)]
 
 
 @pytest.mark.parametrize("shape,r,n_sub,B,n_ens,seed", ENSEMBLE_CASES)
@@ -475,6 +477,21 @@ def test_ensemble_product_matches_oracle(shape, r, n_sub, B, n_ens, seed):
     ratio = np.max(np.abs(got - ref) / (bnd + 1e-300))
     print(f"[ensemble] max |gpu - oracle| / bound = {ratio:.3f}", flush=True)
     assert np.all(np.abs(got - ref) <= bnd)
+    cg.close()
+
+
+def test_ensemble_input_off_16_byte_boundary():
+    """Member fields that start 8 bytes past a 16-byte boundary (a view one
+    double into its allocation) give the same products bitwise."""
+    d = synth.random_small((9, 9, 9), 2, r=3, n_sub=6, seed=82, dt=0.125)
+    cg = fd.Coarse(_dev_domain(d), 2, fd.FP16_BANK)
+    C = _ensemble_fields(6, cg.n_nodes, 82)
+    whole = to_dev(np.concatenate([[7.0], C.ravel()]))
+    view = whole[1:].view(C.shape)
+    assert view.data_ptr() % 16 == 8
+    a = to_host(cg.apply_ensemble(view))
+    b = to_host(cg.apply_ensemble(to_dev(C)))
+    assert np.array_equal(a, b)
     cg.close()
 
 
