@@ -170,7 +170,15 @@ __global__ void flow_stability_kernel(const L *__restrict__ lam, const double *_
         if (!(t <= mx)) mx = t;                                 // NaN propagates as "unstable"
     }
     if (!(mx >= 0.0) || mx != mx) mx = 1e300;
-    atomicMax(out, (unsigned long long)__double_as_longlong(mx));
+    // one atomic per workgroup (256 threads): waves first, then through LDS
+    // (the values are >= 0, so their bit patterns order as the values do)
+    __shared__ double wm[4];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(out, (unsigned long long)__double_as_longlong(fmax(fmax(wm[0], wm[1]), fmax(wm[2], wm[3]))));
 }
 
 template <typename S, typename L>
