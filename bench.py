@@ -14,7 +14,9 @@ chained (output -> next input).  ``value`` = 192^3 cells / seconds per step in
 the headline precision (default FP32, the fastest fused mode on gfx950); the
 mixed precision steps (FP32 state with FP16 or BF16 neighbour copies) are timed
 the same way and reported under ``modes`` with their speedup over FP32 and
-their relative L1 difference from the FP32 field.  The ``bank`` leg stores
+their relative L1 difference from the FP32 field; the ``deterministic`` leg
+times the FP32 step without floating-point atomics (bitwise repeatable).
+The ``bank`` leg stores
 every kernel once (in FP32 and in FP16, the paper's stored-P use) and times
 the HBM-streaming apply of one big step; the ``coarse`` leg runs the paper's
 coarse-mesh method (5^3 blocks, mapping / P C / remapping) in the four
@@ -243,6 +245,39 @@ def batched_leg(fd, args):
     log(f"batched: {ms:.1f} ms/step, {out['cells_per_s'] / 1e6:.3f} Mcells/s, "
         f"{out['cell_substeps_per_s'] / 1e12:.3f} T cell-substeps/s, shape {out['tuned_config_id']}")
     return out
+
+
+def deterministic_leg(fd, d, dom, c0, bufs, stream, ref, args):
+    """The headline step with deterministic = 1 (no floating-point atomics:
+    completed planes to partial slots, then a fixed-order reduction), timed
+    like the modes; its field from c0 twice (bitwise equal) and its relative
+    L1 difference from the atomic FP32 field."""
+    import torch
+    log(f"deterministic fp32: {args.warmup} warm-up + {args.steps} timed steps")
+    for _ in range(args.warmup):
+        fd.fdirw_step(dom, c0, bufs[0], prec="fp32", deterministic=True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    kern = []
+    cur = c0
+    ev0.record(stream)
+    for k in range(args.steps):
+        out = bufs[k % 2]
+        _, st = fd.fdirw_step(dom, cur, out, prec="fp32", stats=True, deterministic=True)
+        kern.append(st["kernel_seconds"])
+        cur = out
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    a = fd.fdirw_step(dom, c0, torch.empty_like(c0), prec="fp32", deterministic=True)
+    b = fd.fdirw_step(dom, c0, torch.empty_like(c0), prec="fp32", deterministic=True)
+    res = {"ms_per_step": ms, "kernel_ms": 1e3 * float(np.mean(kern)), "cells_per_s": d.n / (ms * 1e-3),
+           "repeat_bitwise": bool(torch.equal(a, b))}
+    if ref is not None:
+        res["rel_l1_vs_fp32"] = float((a - ref).abs().sum()) / float(ref.abs().sum())
+    log(f"deterministic fp32: {ms:.1f} ms/step, repeat bitwise {res['repeat_bitwise']}")
+    return res
 
 
 def bank_leg(fd, d, dom, c0, ref, args):
@@ -511,6 +546,7 @@ def main():
     ap.add_argument("--tune", type=int, default=-1)
     ap.add_argument("--nn-epochs", type=int, default=4,
                     help="epochs of the surrogate recipe before its step is timed (0: skip the surrogate)")
+    ap.add_argument("--det", type=int, default=1, help="also time the FP32 step with deterministic = 1 (0: skip)")
     ap.add_argument("--batched", type=int, default=1, help="also time the 64-domain batched step (0: skip)")
     ap.add_argument("--bank", type=int, default=1, help="also time fdirw_run with FP32 and FP16 kernel banks (0: skip)")
     ap.add_argument("--mp-steps", type=int, default=50,
@@ -584,6 +620,8 @@ def main():
         results["nn"], fields["nn"] = surrogate_mode(fd, d, dom, c0, bufs, stream, args)
 
     extra = {}
+    if args.det:
+        extra["deterministic"] = deterministic_leg(fd, d, dom, c0, bufs, stream, fields.get("fp32"), args)
     if args.batched:
         extra["batched"] = batched_leg(fd, args)
     if args.bank:
