@@ -133,7 +133,8 @@ typedef struct fdirw_opts {
                                   per slab, else automatic.  n_dom > 1: batched shape id, 0..5 = the
                                   640-thread segment layout (item z extent whole / whole / 64 / 32 /
                                   16 / 8 planes; natural order for 0, longest first otherwise), 6..9
-                                  = the 256-thread flat layout, FP32 only (one source line per item,
+                                  = the 256-thread flat layout, FP32 only (one source line per item
+                                  at r >= 7, two at r = 5, 6 and r = 3, four at r = 4 and r <= 2;
                                   z extent whole / 64 / 32 / 16, longest first; E_ARG for another
                                   precision), -1 = autotuned (cached per precision,
                                   radius / sub-step mix, size class and device; the cache file is
