@@ -31,7 +31,8 @@ def _dev(d):
 @pytest.mark.parametrize("shape,r,n_sub,seed", [((5, 7, 11), 2, 9, 21), ((1, 1, 1), 3, 5, 22), ((3, 4, 2), 8, 12, 23),
                                                  ((17, 3, 9), 4, 25, 24), ((6, 6, 6), 0, 10, 25),
                                                  ((8, 9, 10), 3, 0, 26), ((19, 18, 20), 8, 40, 27),
-                                                 ((10, 9, 11), 6, 23, 28), ((12, 7, 13), 5, 17, 29)])
+                                                 ((10, 9, 11), 6, 23, 28), ((12, 7, 13), 5, 17, 29),
+                                                 ((4, 1, 2), 4, 7, 30)])
 def test_deterministic_step_matches_oracle_and_repeats_bitwise(prec, tol, shape, r, n_sub, seed):
     d = synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=seed)
     ref, used, _ = oracle.Problem.from_domain(d).step(d.c0)

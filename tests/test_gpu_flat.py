@@ -39,7 +39,9 @@ def _dev(d):
 CASES = [((9, 10, 11), 4, 21, 901), ((12, 7, 13), 5, 30, 902), ((6, 15, 8), 6, 17, 903),
          ((16, 16, 16), 7, 40, 904), ((19, 18, 20), 8, 45, 905), ((5, 6, 7), 8, 33, 906),
          ((1, 1, 1), 8, 5, 907), ((3, 20, 2), 8, 0, 908), ((25, 4, 9), 4, 1, 909),
-         ((10, 9, 11), 6, 23, 910), ((8, 3, 3), 4, 12, 912), ((11, 5, 7), 7, 19, 913)]
+         ((10, 9, 11), 6, 23, 910), ((8, 3, 3), 4, 12, 912), ((11, 5, 7), 7, 19, 913),
+         # one line at r = 4 (three of the workgroup's four line groups empty), three at r = 6
+         ((6, 1, 1), 4, 9, 914), ((5, 1, 3), 6, 8, 915)]
 
 
 @pytest.mark.parametrize("shape,r,n_sub,seed", CASES)
