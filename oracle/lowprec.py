@@ -14,7 +14,9 @@ the device).  Because the two cells of a face use the same two copies, the
 amounts they exchange are equal and opposite, so the kernel keeps its mass
 whatever the rounding (Sec. 3.3 relies on mass conservation to accept reduced
 precision).  The device modes FP16X32 / BF16X32 also divide the kernel by its
-mass at the end; ``kernels`` returns the mass beside the kernel.
+mass at the end; ``kernels`` returns the mass beside the kernel.  With
+``state=True`` the state itself is rounded to the format after every sub-step
+(the FP16_STATE / BF16_STATE control modes: the copies are then the state).
 
 Formats: FP16 (11 significant bits, smallest normal 2^-14, subnormal step
 2^-24) and BF16 (8 significant bits, smallest normal 2^-126, subnormal step
@@ -46,11 +48,12 @@ def round_to_format(x, fmt):
     return np.where(x == 0.0, x, out)
 
 
-def _substeps(g, lx, ly, lz, n_sub, fmt):
+def _substeps(g, lx, ly, lz, n_sub, fmt, state=False):
     """n_sub sub-steps on a box (z, y, x) with no flux through its walls;
     lx / ly / lz: the box's owned +x / +y / +z face coefficients (0 on the
     box's last plane of each axis).  Terms per cell in the order -x, +x, -y,
-    +y, -z, +z, each lambda (copy of the neighbour - copy of the cell)."""
+    +y, -z, +z, each lambda (copy of the neighbour - copy of the cell);
+    state: the new state is rounded to the format as well."""
     for _ in range(n_sub):
         h = round_to_format(g, fmt)
         acc = g.copy()
@@ -60,14 +63,15 @@ def _substeps(g, lx, ly, lz, n_sub, fmt):
         acc[:, :-1, :] += ly[:, :-1, :] * (h[:, 1:, :] - h[:, :-1, :])
         acc[1:, :, :] += lz[:-1, :, :] * (h[:-1, :, :] - h[1:, :, :])
         acc[:-1, :, :] += lz[:-1, :, :] * (h[1:, :, :] - h[:-1, :, :])
-        g = acc
+        g = round_to_format(acc, fmt) if state else acc
     return g
 
 
-def kernels(problem, src, fmt):
+def kernels(problem, src, fmt, state=False):
     """Window kernels of the sources ``src`` of an ``oracle.Problem`` with
-    copies in ``fmt``: G [n_src, W, W, W] (z, y, x relative to s - r, zeros
-    outside the domain) and the masses [n_src] (not divided out)."""
+    copies in ``fmt`` (and the state rounded too if ``state``): G [n_src, W,
+    W, W] (z, y, x relative to s - r, zeros outside the domain) and the
+    masses [n_src] (not divided out)."""
     p = problem
     src = np.asarray(src, dtype=np.int64).ravel()
     W, r = p.W, p.r
@@ -88,18 +92,20 @@ def kernels(problem, src, fmt):
         bz[-1, :, :] = 0.0
         g = np.zeros(tuple(b - a + 1 for a, b in zip(lo, hi)))
         g[sz - lo[0], sy - lo[1], sx - lo[2]] = 1.0
-        g = _substeps(g, bx, by, bz, p.n_sub, fmt)
+        g = _substeps(g, bx, by, bz, p.n_sub, fmt, state)
         w0 = [a - (c - r) for a, c in zip(lo, (sz, sy, sx))]
         G[q, w0[0]:w0[0] + g.shape[0], w0[1]:w0[1] + g.shape[1], w0[2]:w0[2] + g.shape[2]] = g
         mass[q] = math.fsum(g.ravel())
     return G, mass
 
 
-def error_bound(n_sub, lam_max, fmt):
+def error_bound(n_sub, lam_max, fmt, state=False):
     """Largest |G_copies - G_exact| after n_sub sub-steps for kernels inside
     [0, 1]: the exact update is a convex combination (6 lambda <= 1), so it
     carries an earlier difference over without growth, and each sub-step adds
     at most sum_f lambda_f (|copy - value| of both cells) <= 12 lambda_max u,
-    u = 2^-bits the copies' relative rounding bound."""
+    u = 2^-bits the copies' relative rounding bound; rounding the state adds u
+    more per sub-step (values <= 1)."""
     bits, _ = fmt
-    return 12.0 * n_sub * lam_max * 2.0 ** (-bits)
+    u = 2.0 ** (-bits)
+    return n_sub * (12.0 * lam_max * u + (u if state else 0.0))

@@ -1,8 +1,9 @@
 """GPU: the reduced-precision kernel modes against the 16-bit-copy oracle.
 
 FP16X32 and BF16X32 keep the state in FP32 and publish it to the neighbours
-as copies rounded to FP16 / BF16 (ties to even) every sub-step.
-oracle/lowprec.py does the same with an FP64 state.  Two checks per mode:
+as copies rounded to FP16 / BF16 (ties to even) every sub-step; FP16_STATE /
+BF16_STATE round the state itself every sub-step.  oracle/lowprec.py does the
+same with an FP64 state (and an FP64 accumulation).  Two checks per mode:
   * the kernels lie within twice the oracle's bound for the copies, 12 n
     lambda_max 2^-bits (the device's kernel and the oracle's are each that
     close to the exact one), plus the FP32 state's own rounding (per
@@ -31,10 +32,11 @@ if not torch.cuda.is_available():
 import paper_2408_11376_amd as fd  # noqa: E402
 
 
-@pytest.mark.parametrize("prec,fmt", [(fd.FP16X32, lowprec.FP16), (fd.BF16X32, lowprec.BF16)])
+@pytest.mark.parametrize("prec,fmt,state", [(fd.FP16X32, lowprec.FP16, False), (fd.BF16X32, lowprec.BF16, False),
+                                            (fd.FP16_STATE, lowprec.FP16, True), (fd.BF16_STATE, lowprec.BF16, True)])
 @pytest.mark.parametrize("shape,r,n_sub,seed", [((11, 10, 12), 4, 30, 91), ((9, 13, 8), 3, 45, 92),
                                                  ((12, 12, 12), 6, 60, 93)])
-def test_copy_modes_follow_the_copy_oracle(prec, fmt, shape, r, n_sub, seed):
+def test_copy_modes_follow_the_copy_oracle(prec, fmt, state, shape, r, n_sub, seed):
     d = synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=seed)
     dom = fd.Domain(d.label, d.d_phase, d.r, d.n_sub, d.h, d.dt)
     p = oracle.Problem.from_domain(d)
@@ -42,12 +44,12 @@ def test_copy_modes_follow_the_copy_oracle(prec, fmt, shape, r, n_sub, seed):
     print(f"[lowprec] prec={prec} shape={shape} r={r} n_sub={n_sub} sources={src.size}", flush=True)
     G, m = fd.fdirw_kernels(dom, to_dev(src), prec=prec)
     Gd = to_host(G).astype(np.float64).reshape(src.size, -1)
-    Gc, _ = lowprec.kernels(p, src, fmt)
+    Gc, _ = lowprec.kernels(p, src, fmt, state)
     Ge, _ = p.kernels(src)
     Gc = Gc.reshape(src.size, -1)
     Ge = Ge.reshape(src.size, -1)
     lam_max = max(p.lx.max(), p.ly.max(), p.lz.max())
-    bound = 2.0 * lowprec.error_bound(n_sub, lam_max, fmt) + 8.0 * n_sub * 2.0 ** -24
+    bound = 2.0 * lowprec.error_bound(n_sub, lam_max, fmt, state) + 8.0 * n_sub * 2.0 ** -24
     assert np.max(np.abs(Gd - Gc)) <= bound
     to_copy = np.abs(Gd - Gc).sum()
     to_exact = np.abs(Gd - Ge).sum()

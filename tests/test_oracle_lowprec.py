@@ -83,3 +83,19 @@ def test_copies_conserve_mass_and_stay_inside_the_bound(fmt):
     assert 0.0 < err <= bound
     assert Gl.min() >= 0.0 and Gl.max() <= 1.0
 
+
+@pytest.mark.parametrize("fmt", [lowprec.FP16, lowprec.BF16])
+def test_rounded_state_stays_in_the_format_and_inside_its_bound(fmt):
+    d = synth.random_small((9, 10, 8), 3, r=3, n_sub=25, seed=12)
+    p = oracle.Problem.from_domain(d)
+    src = np.arange(2, d.label.size, 41)
+    G, _ = p.kernels(src)
+    Gs, _ = lowprec.kernels(p, src, fmt, state=True)
+    # every value is a number of the format
+    assert np.array_equal(lowprec.round_to_format(Gs, fmt), Gs)
+    lam_max = max(p.lx.max(), p.ly.max(), p.lz.max())
+    assert np.max(np.abs(Gs - G)) <= lowprec.error_bound(p.n_sub, lam_max, fmt, state=True)
+    # with lambda = 1/8 the first sub-steps are exact here too
+    label = np.zeros((7, 7, 7), dtype=np.uint8)
+    q = oracle.Problem(label, np.array([1.0]), 3, 2, 1.0, 0.125)
+    assert np.array_equal(q.kernels([171])[0], lowprec.kernels(q, [171], fmt, state=True)[0])
