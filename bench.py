@@ -45,8 +45,8 @@ import numpy as np  # noqa: E402
 
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3
-# The FP32 FMA rate without packed FP32 instructions (this build does not
-# emit them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+# The FP32 FMA rate without packed FP32 instructions (the library is compiled
+# without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # Algorithmic work of one cell-sub-step of the 7-point update: 7 products and

@@ -58,7 +58,7 @@ typedef enum fdirw_status {
     FDIRW_E_UNSTABLE = -2,     /* 6 Dmax dt / h^2 > 1: explicit scheme unstable */
     FDIRW_E_NOMEM = -3,        /* internal scratch could not be allocated */
     FDIRW_E_DEVICE = -4,       /* a HIP call failed */
-    FDIRW_E_UNSUPPORTED = -5,  /* valid request this build does not implement */
+    FDIRW_E_UNSUPPORTED = -5,  /* valid request the library does not implement */
     FDIRW_E_NONFINITE = -6     /* non-finite input mass */
 } fdirw_status;
 
