@@ -72,6 +72,13 @@ def test_noalloc_window_radius_8_grf():
     _check_pair(d, fd.FP32)
 
 
+def test_noalloc_fp32_line_groups():
+    # FP32 at r = 5 and 6 runs two source lines per workgroup: 45 and 35 lines
+    # leave the last workgroup's second line empty
+    for shape, r, n_sub, seed in [((7, 5, 9), 5, 14, 814), ((9, 7, 5), 6, 11, 815)]:
+        _check_pair(synth.random_small(shape, 3, r=r, n_sub=n_sub, seed=seed), fd.FP32)
+
+
 def test_noalloc_edge_cases():
     # one cell; r = 0; no sub-steps
     for shape, r, n_sub, seed in [((1, 1, 1), 3, 5, 811), ((4, 5, 6), 0, 7, 812), ((6, 5, 4), 2, 0, 813)]:
